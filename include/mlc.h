@@ -1,0 +1,171 @@
+/*
+ * mlc.h -- C ABI of the MI355X (gfx950) library for the multilevel local-and-parallel
+ * finite element eigen-correction of Li, Han, Xie and You (arXiv:1401.4969).
+ *
+ * Problem (Section 3, eigenproblem (Weak_Eigenvalue_Problem) with the operator of
+ * Section 2.2, A = kappa I): find (lambda, u) with -div(kappa grad u) = lambda u in Omega,
+ * u = 0 on the boundary, b(u, u) = 1, discretised by conforming P1 elements on nested
+ * uniform right-triangle meshes (each square cell cut by its lower-left to upper-right
+ * diagonal; regular refinement, beta = 2, Section 6).
+ *
+ * Method (Algorithm 4.2 driving Algorithm 4.1):
+ *   mlc_coarse_setup    -- Algorithm 4.2 step 1: the eigenproblem on the coarse space
+ *                          V_0H (h_1 = H), solved once; its eigenbasis is kept for step 3.
+ *   mlc_level_correct   -- one Correction(V_0H, lambda_hk, u_hk, V_0h_{k+1}) of
+ *                          Algorithm 4.1: (1) independent local solves of equation
+ *                          (Aux_Problem) on every overlapping subdomain Omega_j,
+ *                          (2) partition-of-unity gluing of the corrections into u~,
+ *                          (3) Rayleigh-Ritz (Eigen_Augment_Problem) on V_0H + span{u~}.
+ *   mlc_get_eigenpairs  -- the current (lambda, u), b(u_i, u_j) = delta_ij.
+ *
+ * Conventions
+ *   - Every call returns an mlc_status; no C++ exception or abort crosses the ABI.
+ *   - Device buffers are plain device pointers (hipMalloc'd or any device allocation).
+ *     The caller owns all device memory: the workspace passed to mlc_create and every
+ *     output buffer.  The library allocates no device memory of its own except the
+ *     internal buffers of the dense generalized eigensolver used once by
+ *     mlc_coarse_setup (rocSOLVER).
+ *   - All work is enqueued on the caller's HIP stream (borrowed, never destroyed) and is
+ *     stream-ordered; only calls that return host data synchronise that stream.
+ *   - Grid vectors are full node grids of the bounding box, row-major: the value at node
+ *     (i, j) (x = x0 + i h, y = y0 + j h) is at index j*(N+1)+i, N = n_coarse*2^level
+ *     cells per side; boundary and removed-quadrant nodes hold 0.  q eigenvectors are
+ *     stored one after another.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MLC_H
+#define MLC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mlc_status {
+  MLC_OK = 0,
+  MLC_EINVAL = 1,   /* invalid argument or unsupported problem */
+  MLC_ENOMEM = 2,   /* workspace too small */
+  MLC_EHIP = 3,     /* a HIP runtime or library call failed; see mlc_last_error */
+  MLC_ENOCONV = 4,  /* a local solve did not reach its tolerance within max_it;
+                       results are still written and the stats say which level */
+  MLC_ESTATE = 5    /* call out of order (e.g. level_correct before coarse_setup) */
+} mlc_status;
+
+enum { MLC_DOMAIN_SQUARE = 0,   /* (0,1)^2 */
+       MLC_DOMAIN_LSHAPE = 1 }; /* (-1,1)^2 \ [0,1)x(-1,0] */
+
+enum { MLC_COEF_ONE = 0,        /* kappa == 1 */
+       MLC_COEF_COARSE = 1,     /* one kappa per coarse cell, [n_coarse*n_coarse] */
+       MLC_COEF_FINE = 2 };     /* one kappa per finest square cell, [N_L*N_L] */
+
+enum { MLC_PREC_FP64 = 0,       /* every local solve in FP64 */
+       MLC_PREC_MIXED = 1 };    /* FP32 inner PCG with FP64 residual refinement */
+
+/* Problem description (Section 3 eigenproblem; Section 4 domain decomposition). */
+typedef struct mlc_problem_desc {
+  int32_t domain;      /* MLC_DOMAIN_* */
+  int32_t n_coarse;    /* coarse cells per bounding-box side; H = side/n_coarse (even for the L-shape) */
+  int32_t n_refine;    /* number of corrections L; finest h = H/2^L; level 0 is the coarse mesh */
+  int32_t sub_x;       /* D_j blocks along x: boundaries at floor(b*n_coarse/sub_x) coarse cells */
+  int32_t sub_y;       /* D_j blocks along y */
+  int32_t overlap;     /* Omega_j = D_j grown by this many coarse cells per side (>= 1) */
+  int32_t n_eig;       /* q, number of lowest eigenpairs (1..8) */
+  int32_t coef_kind;   /* MLC_COEF_*; both triangles of a square cell share its value */
+  const double* kappa; /* host pointer, row-major [row along y][col along x]; read during
+                          mlc_create only (copied); NULL for MLC_COEF_ONE.  Must be > 0 and finite. */
+} mlc_problem_desc;
+
+/* Solver options; mlc_default_opts fills the defaults shown. */
+typedef struct mlc_solver_opts {
+  int32_t precision;   /* MLC_PREC_FP64 (default) or MLC_PREC_MIXED */
+  double rtol;         /* local solve: ||r||_2 <= rtol * ||b||_2 from a zero guess (1e-12) */
+  int32_t max_it;      /* PCG iterations per local solve (FP64) or per inner solve (200) */
+  int32_t max_refine;  /* mixed precision: FP64 refinement steps (10) */
+  double inner_rtol;   /* mixed precision: FP32 inner solve relative tolerance (1e-5) */
+  int32_t nu;          /* damped Jacobi sweeps before and after each coarse correction (2) */
+  double omega;        /* Jacobi damping (0.8) */
+  int32_t block;       /* threads per workgroup of the local solver: 256, 512 or 1024 (0 = 1024) */
+  int32_t timing;      /* 1: record HIP events around the local-solve kernel (see mlc_phase_times) */
+} mlc_solver_opts;
+
+/* Per-level statistics, filled by mlc_level_correct when st != NULL (this synchronises
+ * the stream). */
+typedef struct mlc_level_stats {
+  int32_t level;        /* level produced (k+1) */
+  int32_t n_items;      /* local solves launched (kept subdomains x q) */
+  double h;             /* mesh size of that level */
+  int64_t n_dofs;       /* interior nodes of the level */
+  int64_t n_tile_dofs;  /* sum over local solves of their unknowns */
+  int32_t it_max;       /* max PCG iterations over the local solves (inner, for mixed) */
+  int32_t refine_max;   /* mixed precision: max FP64 refinement steps */
+  int64_t it_sum;       /* sum of PCG iterations over the local solves */
+  int64_t it_dofs;      /* sum over local solves of iterations x unknowns */
+  double relres_max;    /* max final ||r||/||b|| over the local solves */
+  double lambda[8];     /* the q eigenvalues after the step */
+} mlc_level_stats;
+
+/* Fill opts with the defaults listed above. */
+mlc_status mlc_default_opts(mlc_solver_opts* opts);
+
+/* Bytes of device workspace mlc_create needs for this problem and these options. */
+mlc_status mlc_workspace_size(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
+                              size_t* bytes);
+
+/* Create a context.  dev_workspace: device buffer of at least mlc_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and kept alive until mlc_destroy.  hip_stream:
+ * a hipStream_t (NULL = default stream).  Uploads geometry tables on the stream.
+ * MLC_EINVAL for: domain/coef_kind out of range, n_coarse < 2, odd n_coarse on the
+ * L-shape, n_refine outside 1..10, sub_x/sub_y outside 1..n_coarse, overlap < 1,
+ * n_eig outside 1..8 or above the number of coarse interior nodes, kappa NULL when
+ * needed or not > 0 and finite, a subdomain whose coarse interior exceeds 64 nodes. */
+mlc_status mlc_create(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
+                      void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                      struct mlc_ctx** out);
+
+/* Algorithm 4.2 step 1 with h_1 = H: coefficients on every level (children means),
+ * coarse stiffness and mass, the full generalized eigendecomposition on V_0H, the
+ * initial eigenpairs (level 0), and the exact coarsest-grid inverses of every
+ * subdomain.  Synchronises the stream. */
+mlc_status mlc_coarse_setup(struct mlc_ctx* ctx);
+
+/* One correction step (Algorithm 4.1) from the current level k to k+1.  Stream-ordered
+ * and asynchronous when st == NULL.  MLC_ESTATE before setup or at the finest level. */
+mlc_status mlc_level_correct(struct mlc_ctx* ctx, mlc_level_stats* st);
+
+/* Run every remaining correction (no statistics). */
+mlc_status mlc_run(struct mlc_ctx* ctx);
+
+/* Step back to the previous level (its eigenpair is still held), so the last
+ * correction can be repeated.  MLC_ESTATE if there is none. */
+mlc_status mlc_rewind(struct mlc_ctx* ctx);
+
+/* Current level k (0 after setup, L at the end). */
+mlc_status mlc_current_level(const struct mlc_ctx* ctx, int32_t* level);
+
+/* The current eigenpairs: lambda_host[q] (host, may be NULL) and u_dev (device,
+ * q*(N_k+1)^2 doubles, may be NULL).  Each eigenvector is signed so that its nodal sum
+ * is >= 0.  Synchronises the stream when lambda_host != NULL. */
+mlc_status mlc_get_eigenpairs(struct mlc_ctx* ctx, double* lambda_host, double* u_dev);
+
+/* Replace the current state by (level, lambda_host[q], u_dev) given on the level grid
+ * (device, q*(N_level+1)^2 doubles, values at non-interior nodes ignored).  Needs setup. */
+mlc_status mlc_set_state(struct mlc_ctx* ctx, int32_t level, const double* lambda_host,
+                         const double* u_dev);
+
+/* Accumulated milliseconds measured with HIP events on the stream since the last call:
+ * ms[0] = local-solve kernel, ms[1] = whole level_correct calls.  Synchronises. */
+mlc_status mlc_phase_times(struct mlc_ctx* ctx, double* ms, int32_t n);
+
+mlc_status mlc_destroy(struct mlc_ctx* ctx);
+
+const char* mlc_status_str(mlc_status s);
+/* Message of the last failure on this context (never NULL; "" if none). */
+const char* mlc_last_error(const struct mlc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLC_H */

@@ -1,0 +1,559 @@
+// Global-grid kernels of one correction step (Algorithm 4.1) and of the coarse setup
+// (Algorithm 4.2 step 1).  One thread per node of a level grid; blockIdx.y selects the
+// problem of a batch.  All are plain streaming sweeps bound by HBM bandwidth.
+#include "mlc_launch.h"
+
+namespace {
+
+constexpr int NTG = 256;
+
+__device__ __forceinline__ double interp2(const double* uc, int nc1, int x, int y) {
+  // P1 nodal interpolation from the grid one level coarser (SW-NE diagonals):
+  // coinciding nodes copy, edge midpoints average the two ends of their edge.
+  const int ix = x >> 1, iy = y >> 1;
+  const double a = uc[iy * nc1 + ix];
+  if (x & 1) {
+    if (y & 1) return 0.5 * (a + uc[(iy + 1) * nc1 + ix + 1]);
+    return 0.5 * (a + uc[iy * nc1 + ix + 1]);
+  }
+  if (y & 1) return 0.5 * (a + uc[(iy + 1) * nc1 + ix]);
+  return a;
+}
+
+// a1 + a2: u_bar = I u_k on level m and the right-hand side of (Aux_Problem),
+// r = lambda_k M u_bar - K u_bar, for each of the q eigenpairs.
+template <int KIND>
+__global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, int m, int src) {
+  const ProbDev& P = probs[blockIdx.y];
+  if (m > P.L) return;
+  const int N = P.n_c << m;
+  const int n1 = N + 1;
+  const int64_t nn = (int64_t)n1 * n1;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nn) return;
+  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int nc1 = (N >> 1) + 1;
+  const bool dof = is_dof(P.domain, N, gx, gy);
+  const double h = P.side / N;
+  const double mh = h * h * (1.0 / 12.0);
+  Weights W;
+  if (dof) W = edge_weights<KIND>(P, m, N, gx, gy);
+  for (int i = 0; i < P.q; ++i) {
+    double* ub = P.ubar + (int64_t)i * nn;
+    double* r = P.res + (int64_t)i * nn;
+    if (!dof) {
+      ub[idx] = 0.0;
+      r[idx] = 0.0;
+      continue;
+    }
+    const double* uc = P.u[src] + (int64_t)i * nc1 * nc1;
+    const double c = interp2(uc, nc1, gx, gy);
+    const double e = interp2(uc, nc1, gx + 1, gy), w = interp2(uc, nc1, gx - 1, gy);
+    const double n = interp2(uc, nc1, gx, gy + 1), s = interp2(uc, nc1, gx, gy - 1);
+    const double ne = interp2(uc, nc1, gx + 1, gy + 1), sw = interp2(uc, nc1, gx - 1, gy - 1);
+    const double Ku = (W.e + W.w + W.n + W.s) * c - W.e * e - W.w * w - W.n * n - W.s * s;
+    const double Mu = mh * (6.0 * c + e + w + n + s + ne + sw);
+    const double lam = P.lam[src * MLC_MAX_Q + i];
+    ub[idx] = c;
+    r[idx] = lam * Mu - Ku;
+  }
+}
+
+__device__ __forceinline__ int axis_candidates(const int32_t* bnd, int nb, int g, int r, int ov,
+                                               int (&id)[MLC_MAX_CAND], double (&rho)[MLC_MAX_CAND]) {
+  // ramp(t; a, b) = clamp(min(t - a + d, b + d - t)/d, 0, 1), d = overlap coarse cells,
+  // here in fine-node units (exact dyadic arithmetic).
+  const int d = ov * r;
+  int n = 0;
+  for (int b = 0; b < nb && n < MLC_MAX_CAND; ++b) {
+    const int lo = bnd[b] * r, hi = bnd[b + 1] * r;
+    const int v = min(g - lo + d, hi + d - g);
+    if (v > 0) {
+      id[n] = b;
+      rho[n] = (double)min(v, d) / (double)d;
+      ++n;
+    }
+  }
+  return n;
+}
+
+// a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
+__global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const TileItem* items,
+                                                   const char* store, int m) {
+  const ProbDev& P = probs[blockIdx.y];
+  if (m > P.L) return;
+  const int N = P.n_c << m;
+  const int n1 = N + 1;
+  const int64_t nn = (int64_t)n1 * n1;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nn) return;
+  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  if (!is_dof(P.domain, N, gx, gy)) {
+    for (int i = 0; i < P.q; ++i) P.ut[(int64_t)i * nn + idx] = 0.0;
+    return;
+  }
+  const int r = 1 << m;
+  int ix[MLC_MAX_CAND], iy[MLC_MAX_CAND];
+  double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
+  const int nxc = axis_candidates(P.bx, P.sub_x, gx, r, P.overlap, ix, rx);
+  const int nyc = axis_candidates(P.by, P.sub_y, gy, r, P.overlap, iy, ry);
+  for (int i = 0; i < P.q; ++i) {
+    double acc = 0.0, tot = 0.0;
+    for (int a = 0; a < nyc; ++a) {
+      for (int b = 0; b < nxc; ++b) {
+        const int item = P.sub_item[(iy[a] * P.sub_x + ix[b]) * P.q + i];
+        if (item < 0) continue;
+        const TileItem& it = items[item];
+        const int nx = it.cw * r - 1;
+        const int lx = gx - (it.cx0 * r + 1), ly = gy - (it.cy0 * r + 1);
+        const double* e = reinterpret_cast<const double*>(store + it.off);
+        const double phi = rx[b] * ry[a];
+        acc += phi * e[(int64_t)ly * nx + lx];
+        tot += phi;
+      }
+    }
+    P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + acc / tot;
+  }
+}
+
+// a5: y_K = K u~ (into res), y_M = M u~ (into ubar), and per-block partial sums of
+// alpha_ij = u~_i . y_K,j, beta_ij = u~_i . y_M,j and s_i = sum u~_i.
+template <int KIND>
+__global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
+  __shared__ double red[NTG / 64];
+  const ProbDev& P = probs[blockIdx.y];
+  if (m > P.L) return;
+  const int N = P.n_c << m;
+  const int n1 = N + 1;
+  const int64_t nn = (int64_t)n1 * n1;
+  const int64_t nblk = (nn + NTG - 1) / NTG;
+  if ((int64_t)blockIdx.x >= nblk) return;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  const int q = P.q;
+  const bool inr = idx < nn;
+  int gx = 0, gy = 0;
+  if (inr) {
+    gy = (int)(idx / n1);
+    gx = (int)(idx - (int64_t)gy * n1);
+  }
+  const bool dof = inr && is_dof(P.domain, N, gx, gy);
+  const double h = P.side / N;
+  const double mh = h * h * (1.0 / 12.0);
+  Weights W;
+  if (dof) W = edge_weights<KIND>(P, m, N, gx, gy);
+  double uv[MLC_MAX_Q], yk[MLC_MAX_Q], ym[MLC_MAX_Q];
+#pragma unroll
+  for (int i = 0; i < MLC_MAX_Q; ++i) {
+    uv[i] = yk[i] = ym[i] = 0.0;
+    if (i < q && dof) {
+      const double* u = P.ut + (int64_t)i * nn;
+      const double c = u[idx], e = u[idx + 1], w = u[idx - 1], n = u[idx + n1], s = u[idx - n1];
+      const double ne = u[idx + n1 + 1], sw = u[idx - n1 - 1];
+      uv[i] = c;
+      yk[i] = (W.e + W.w + W.n + W.s) * c - W.e * e - W.w * w - W.n * n - W.s * s;
+      ym[i] = mh * (6.0 * c + e + w + n + s + ne + sw);
+    }
+    if (i < q && inr) {
+      P.res[(int64_t)i * nn + idx] = yk[i];
+      P.ubar[(int64_t)i * nn + idx] = ym[i];
+    }
+  }
+  const int nv = 2 * q * q + q;
+  double* out = P.partials + (int64_t)blockIdx.x * nv;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    double x = 0.0;
+#pragma unroll
+    for (int i = 0; i < MLC_MAX_Q; ++i) {
+#pragma unroll
+      for (int j = 0; j < MLC_MAX_Q; ++j) {
+        if (i < q && j < q) {
+          if (v == i * q + j) x = uv[i] * yk[j];
+          if (v == q * q + i * q + j) x = uv[i] * ym[j];
+        }
+      }
+      if (i < q && v == 2 * q * q + i) x = uv[i];
+    }
+    x = wave_sum(x);
+    __syncthreads();
+    if (lane == 0) red[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NTG / 64; ++w) s += red[w];
+      out[v] = s;
+    }
+  }
+}
+
+// a5 (continued): one level of the transposed interpolation P^T (full weighting on the
+// SW-NE mesh: centre 1, E/W/N/S/NE/SW 1/2) for the 2q border vectors, level l+1 -> l.
+__global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, int m) {
+  const ProbDev& P = probs[blockIdx.y];
+  if (m > P.L) return;
+  const int Nc = P.n_c << l;
+  const int nc1 = Nc + 1;
+  const int64_t nnc = (int64_t)nc1 * nc1;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nnc) return;
+  const int Iy = (int)(idx / nc1), Ix = (int)(idx - (int64_t)Iy * nc1);
+  const int nf1 = 2 * Nc + 1;
+  const int64_t nnf = (int64_t)nf1 * nf1;
+  const bool dof = is_dof(P.domain, Nc, Ix, Iy);
+  const int q = P.q;
+  double* outb = P.rchain + P.rchain_off[l];
+  for (int v = 0; v < 2 * q; ++v) {
+    const double* f;
+    if (l + 1 == m) {
+      f = (v < q ? P.res + (int64_t)v * nnf : P.ubar + (int64_t)(v - q) * nnf);
+    } else {
+      f = P.rchain + P.rchain_off[l + 1] + (int64_t)v * nnf;
+    }
+    double val = 0.0;
+    if (dof) {
+      const int64_t c = (int64_t)(2 * Iy) * nf1 + 2 * Ix;
+      val = f[c] + 0.5 * (f[c + 1] + f[c - 1] + f[c + nf1] + f[c - nf1] + f[c + nf1 + 1] +
+                          f[c - nf1 - 1]);
+    }
+    outb[(int64_t)v * nnc + idx] = val;
+  }
+}
+
+// a6 (first half): f = V^T a, g = V^T b for the coarse eigenbasis V, one wave per column.
+__global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
+  const ProbDev& P = probs[blockIdx.y];
+  const int c = blockIdx.x * (NTG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= P.nH) return;
+  const int nH = P.nH, q = P.q;
+  const int nc1 = P.n_c + 1;
+  const double* a = P.rchain + P.rchain_off[0];
+  const double* col = P.V + (int64_t)c * nH;
+  for (int v = 0; v < 2 * q; ++v) {
+    const double* src = a + (int64_t)v * nc1 * nc1;
+    double s = 0.0;
+    for (int r = lane; r < nH; r += 64) s += col[r] * src[P.coarse_nodes[r]];
+    s = wave_sum(s);
+    if (lane == 0) P.fg[(int64_t)v * nH + c] = s;
+  }
+}
+
+// a7 (first half): coarse nodal coefficients c_H = V y_hat on the coarse grid.
+__global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
+  const ProbDev& P = probs[blockIdx.y];
+  const int nc1 = P.n_c + 1;
+  const int idx = blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nc1 * nc1) return;
+  const int r = P.coarse_index[idx];
+  const int nH = P.nH;
+  for (int k = 0; k < P.q; ++k) {
+    double s = 0.0;
+    if (r >= 0) {
+      const double* y = P.rr_y + (int64_t)k * nH;
+      for (int c = 0; c < nH; ++c) s += P.V[(int64_t)c * nH + r] * y[c];
+    }
+    P.cH_grid[(int64_t)k * nc1 * nc1 + idx] = s;
+  }
+}
+
+// a7: u_{k+1} = P_{0->m} c_H + sum_i t_i u~_i on level m.
+__global__ __launch_bounds__(NTG) void k_assemble(const ProbDev* probs, int m, int dst) {
+  const ProbDev& P = probs[blockIdx.y];
+  if (m > P.L) return;
+  const int N = P.n_c << m;
+  const int n1 = N + 1;
+  const int64_t nn = (int64_t)n1 * n1;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nn) return;
+  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const bool dof = is_dof(P.domain, N, gx, gy);
+  const int q = P.q;
+  const int nc = P.n_c, nc1 = nc + 1;
+  const int I = min(gx >> m, nc - 1), J = min(gy >> m, nc - 1);
+  const int a = gx - (I << m), b = gy - (J << m);
+  const double inv_r = 1.0 / (double)(1 << m);
+  for (int k = 0; k < q; ++k) {
+    double val = 0.0;
+    if (dof) {
+      const double* c = P.cH_grid + (int64_t)k * nc1 * nc1;
+      const double c00 = c[J * nc1 + I], c10 = c[J * nc1 + I + 1];
+      const double c01 = c[(J + 1) * nc1 + I], c11 = c[(J + 1) * nc1 + I + 1];
+      if (a >= b)
+        val = c00 + (a * (c10 - c00) + b * (c11 - c10)) * inv_r;
+      else
+        val = c00 + (b * (c01 - c00) + a * (c11 - c01)) * inv_r;
+      for (int i = 0; i < q; ++i) val += P.rr_t[k * q + i] * P.ut[(int64_t)i * nn + idx];
+    }
+    P.u[dst][(int64_t)k * nn + idx] = val;
+  }
+}
+
+// ---- setup kernels ----
+
+// kappa on a coarser level: each coarse triangle takes the mean of its four children
+// (exact integration of a(.,.) on the nested spaces).
+__global__ __launch_bounds__(NTG) void k_coarsen_kappa(const double* lo_f, const double* up_f,
+                                                       double* lo_c, double* up_c, int Nc) {
+  const int idx = blockIdx.x * NTG + threadIdx.x;
+  if (idx >= Nc * Nc) return;
+  const int J = idx / Nc, I = idx - J * Nc;
+  const int Nf = 2 * Nc;
+  const int a = (2 * J) * Nf + 2 * I;  // fine cell (2I, 2J)
+  lo_c[idx] = 0.25 * (lo_f[a] + lo_f[a + 1] + up_f[a + 1] + lo_f[a + Nf + 1]);
+  up_c[idx] = 0.25 * (up_f[a] + up_f[a + Nf] + lo_f[a + Nf] + up_f[a + Nf + 1]);
+}
+
+// Coarse stiffness K_H and consistent mass M_H (dense, column-major) on V_0H.
+template <int KIND>
+__global__ __launch_bounds__(NTG) void k_coarse_matrices(const ProbDev* probs) {
+  const ProbDev& P = probs[blockIdx.y];
+  const int r = blockIdx.x * NTG + threadIdx.x;
+  if (r >= P.nH) return;
+  const int nH = P.nH, N = P.n_c, n1 = N + 1;
+  const int node = P.coarse_nodes[r];
+  const int gy = node / n1, gx = node - gy * n1;
+  const Weights W = edge_weights<KIND>(P, 0, N, gx, gy);
+  const double H = P.side / N;
+  const double mh = H * H / 12.0;
+  P.Kc[(int64_t)r * nH + r] = W.e + W.w + W.n + W.s;
+  P.Mc[(int64_t)r * nH + r] = 6.0 * mh;
+  const int dx[6] = {1, -1, 0, 0, 1, -1}, dy[6] = {0, 0, 1, -1, 1, -1};
+  const double kw[6] = {W.e, W.w, W.n, W.s, 0.0, 0.0};
+  for (int t = 0; t < 6; ++t) {
+    const int c = P.coarse_index[(gy + dy[t]) * n1 + gx + dx[t]];
+    if (c < 0) continue;
+    P.Kc[(int64_t)c * nH + r] = -kw[t];
+    P.Mc[(int64_t)c * nH + r] = mh;
+  }
+}
+
+__global__ __launch_bounds__(NTG) void k_init_u0(const ProbDev* probs, int dst) {
+  const ProbDev& P = probs[blockIdx.y];
+  const int nc1 = P.n_c + 1;
+  const int idx = blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nc1 * nc1) return;
+  const int r = P.coarse_index[idx];
+  for (int k = 0; k < P.q; ++k) {
+    P.u[dst][(int64_t)k * nc1 * nc1 + idx] = r >= 0 ? P.V[(int64_t)k * P.nH + r] : 0.0;
+    if (idx == 0) P.lam[dst * MLC_MAX_Q + k] = P.Lam[k];
+  }
+}
+
+// Exact inverse of each subdomain's coarsest-grid operator K_H restricted to the coarse
+// interior nodes of Omega_j (Gauss-Jordan in LDS; SPD so no pivoting).  Nodes outside the
+// domain get identity rows.  One workgroup per subdomain (first item of it).
+template <int KIND>
+__global__ __launch_bounds__(NTG) void k_tile_inverse(const ProbDev* probs, const TileItem* items,
+                                                       double* inv) {
+  __shared__ double A[MLC_MAX_TILE_COARSE * MLC_MAX_TILE_COARSE];
+  constexpr int PER = MLC_MAX_TILE_COARSE * MLC_MAX_TILE_COARSE / NTG;
+  const TileItem it = items[blockIdx.x];
+  if (it.rhs != 0) return;
+  const ProbDev& P = probs[it.prob];
+  const int nx = it.cw - 1, ny = it.ch - 1, n = nx * ny;
+  const int N = P.n_c;
+  for (int e = threadIdx.x; e < n * n; e += NTG) {
+    const int i = e / n, j = e - i * n;
+    const int ix = i % nx, iy = i / nx;
+    const int gx = it.cx0 + 1 + ix, gy = it.cy0 + 1 + iy;
+    const bool di = is_dof(P.domain, N, gx, gy);
+    double v = 0.0;
+    if (!di) {
+      v = (i == j) ? 1.0 : 0.0;
+    } else {
+      const int jx = j % nx, jy = j / nx;
+      const bool dj = is_dof(P.domain, N, it.cx0 + 1 + jx, it.cy0 + 1 + jy);
+      const Weights W = edge_weights<KIND>(P, 0, N, gx, gy);
+      if (i == j)
+        v = W.e + W.w + W.n + W.s;
+      else if (dj && jy == iy && jx == ix + 1)
+        v = -W.e;
+      else if (dj && jy == iy && jx == ix - 1)
+        v = -W.w;
+      else if (dj && jx == ix && jy == iy + 1)
+        v = -W.n;
+      else if (dj && jx == ix && jy == iy - 1)
+        v = -W.s;
+    }
+    A[e] = v;
+  }
+  double tmp[PER];
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    const double pk = 1.0 / A[k * n + k];
+    int c = 0;
+    for (int e = threadIdx.x; e < n * n; e += NTG, ++c) {
+      const int i = e / n, j = e - i * n;
+      double v;
+      if (i == k && j == k)
+        v = pk;
+      else if (i == k)
+        v = A[k * n + j] * pk;
+      else if (j == k)
+        v = -A[i * n + k] * pk;
+      else
+        v = A[e] - A[i * n + k] * A[k * n + j] * pk;
+      tmp[c] = v;
+    }
+    __syncthreads();
+    c = 0;
+    for (int e = threadIdx.x; e < n * n; e += NTG, ++c) A[e] = tmp[c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += NTG) inv[it.inv_off + e] = A[e];
+}
+
+// Output: per-eigenvector nodal sums (two fixed-order stages), then a signed copy.
+__global__ __launch_bounds__(NTG) void k_sum_parts(const double* u, int64_t nn, int q,
+                                                   double* parts, int nblk) {
+  __shared__ double red[NTG / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < q; ++k) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NTG + threadIdx.x; i < nn; i += (int64_t)nblk * NTG)
+      s += u[(int64_t)k * nn + i];
+    s = wave_sum(s);
+    __syncthreads();
+    if (lane == 0) red[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NTG / 64; ++w) t += red[w];
+      parts[k * nblk + blockIdx.x] = t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTG) void k_copy_signed(const double* u, int64_t nn, int q,
+                                                     const double* parts, int nblk, double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nn) return;
+  for (int k = 0; k < q; ++k) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += parts[k * nblk + b];
+    out[(int64_t)k * nn + idx] = (s < 0.0 ? -1.0 : 1.0) * u[(int64_t)k * nn + idx];
+  }
+}
+
+__global__ __launch_bounds__(NTG) void k_set_state(const ProbDev* probs, int level, int dst,
+                                                   const double* in) {
+  const ProbDev& P = probs[0];
+  const int N = P.n_c << level;
+  const int n1 = N + 1;
+  const int64_t nn = (int64_t)n1 * n1;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= nn) return;
+  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const bool dof = is_dof(P.domain, N, gx, gy);
+  for (int k = 0; k < P.q; ++k)
+    P.u[dst][(int64_t)k * nn + idx] = dof ? in[(int64_t)k * nn + idx] : 0.0;
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + NTG - 1) / NTG); }
+
+}  // namespace
+
+hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, int m, int src,
+                                   int64_t max_nodes, hipStream_t s) {
+  dim3 g(nblocks(max_nodes), nprob);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_prolong_residual<0>, g, dim3(NTG), 0, s, probs, m, src);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_prolong_residual<1>, g, dim3(NTG), 0, s, probs, m, src);
+  else
+    hipLaunchKernelGGL(k_prolong_residual<2>, g, dim3(NTG), 0, s, probs, m, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
+                           const char* store, int m, int64_t max_nodes, hipStream_t s) {
+  hipLaunchKernelGGL(k_pou_glue, dim3(nblocks(max_nodes), nprob), dim3(NTG), 0, s, probs, items,
+                     store, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
+                           hipStream_t s) {
+  dim3 g(nblocks(max_nodes), nprob);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_rr_apply<0>, g, dim3(NTG), 0, s, probs, m);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_rr_apply<1>, g, dim3(NTG), 0, s, probs, m);
+  else
+    hipLaunchKernelGGL(k_rr_apply<2>, g, dim3(NTG), 0, s, probs, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3(nblocks(max_nodes_l), nprob), dim3(NTG), 0, s, probs, l, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStream_t s) {
+  hipLaunchKernelGGL(k_rr_project, dim3((max_nH + 3) / 4, nprob), dim3(NTG), 0, s, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s) {
+  hipLaunchKernelGGL(k_rr_combine, dim3(nblocks(max_nc1sq), nprob), dim3(NTG), 0, s, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble, dim3(nblocks(max_nodes), nprob), dim3(NTG), 0, s, probs, m,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen_kappa(const double* lo_f, const double* up_f, double* lo_c,
+                                double* up_c, int Nc, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsen_kappa, dim3(nblocks((int64_t)Nc * Nc)), dim3(NTG), 0, s, lo_f,
+                     up_f, lo_c, up_c, Nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_matrices(int kind, const ProbDev* probs, int nprob, int max_nH,
+                                  hipStream_t s) {
+  dim3 g(nblocks(max_nH), nprob);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_coarse_matrices<0>, g, dim3(NTG), 0, s, probs);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_coarse_matrices<1>, g, dim3(NTG), 0, s, probs);
+  else
+    hipLaunchKernelGGL(k_coarse_matrices<2>, g, dim3(NTG), 0, s, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_u0(const ProbDev* probs, int nprob, int dst, int max_nc1sq, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_u0, dim3(nblocks(max_nc1sq), nprob), dim3(NTG), 0, s, probs, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_inverse(int kind, const ProbDev* probs, const TileItem* items, int nitems,
+                               double* inv, hipStream_t s) {
+  if (kind == 0)
+    hipLaunchKernelGGL(k_tile_inverse<0>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_tile_inverse<1>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
+  else
+    hipLaunchKernelGGL(k_tile_inverse<2>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_output_signed(const double* u, int64_t nn, int q, double* parts, double* out,
+                                hipStream_t s) {
+  const int nblk = 64;
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk), dim3(NTG), 0, s, u, nn, q, parts, nblk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_signed, dim3(nblocks(nn)), dim3(NTG), 0, s, u, nn, q, parts, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const ProbDev* prob, int level, int dst, const double* in,
+                            int64_t nn, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(nblocks(nn)), dim3(NTG), 0, s, prob, level, dst, in);
+  return hipGetLastError();
+}

@@ -1,0 +1,142 @@
+// Device-side data structures and helpers shared by the HIP kernels of libmlc.
+//
+// Geometry: a level-l grid of the bounding box has N_l = n_c * 2^l cells per side and
+// (N_l+1)^2 nodes, node (gx, gy) at index gy*(N_l+1)+gx.  Square cell (I, J) is cut by
+// its SW-NE diagonal into a lower triangle (SW, SE, NE) and an upper one (SW, NE, NW).
+// With P1 elements only the two legs of each triangle couple, so the stiffness is a
+// five-point stencil whose edge weights average the kappa of the two triangles on each
+// side of the edge; the mass is (h^2/12)[6; E, W, N, S, NE, SW].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MLC_MAX_LEVELS 10
+#define MLC_MAX_Q 8
+#define MLC_MAX_TILE_COARSE 64
+#define MLC_MAX_CAND 8
+
+// Per-problem device record.  Pointers are into the caller's workspace.
+struct ProbDev {
+  int32_t domain, n_c, L, q, coef_kind, sub_x, sub_y, overlap;
+  int32_t nH;                 // coarse interior nodes (dofs of V_0H)
+  int32_t nparts;             // blocks of the fine-level reductions at the finest level
+  double side;                // bounding-box side length
+  const double* kH;           // coef kinds 0/1: n_c*n_c per coarse cell
+  const double* kLR[MLC_MAX_LEVELS + 1];  // coef kind 2: per level, N_l*N_l lower-triangle kappa
+  const double* kUL[MLC_MAX_LEVELS + 1];  //                            upper-triangle kappa
+  const int32_t* bx;          // sub_x+1 block boundaries in coarse cells
+  const int32_t* by;          // sub_y+1
+  const int32_t* sub_item;    // (sub_x*sub_y)*q -> item index in the current item table, -1 dropped
+  const int32_t* coarse_nodes;  // nH: grid index (on (n_c+1)^2) of coarse dof r
+  const int32_t* coarse_index;  // (n_c+1)^2: dof index or -1
+  double* u[2];               // eigenvectors, q*(N_L+1)^2 each (ping-pong)
+  double* lam;                // [2][MLC_MAX_Q]
+  double* ubar;               // q*(N_L+1)^2: I u_k, later M u~
+  double* res;                // q*(N_L+1)^2: Aux_Problem right-hand side, later K u~
+  double* ut;                 // q*(N_L+1)^2: glued u~
+  double* rchain;             // restriction chain
+  int64_t rchain_off[MLC_MAX_LEVELS + 1];
+  double* V;                  // nH*nH column-major, M_H-orthonormal coarse eigenvectors
+  double* Lam;                // nH ascending coarse eigenvalues
+  double* Kc;                 // nH*nH coarse stiffness (setup scratch, overwritten by V)
+  double* Mc;                 // nH*nH coarse mass (setup scratch)
+  double* fg;                 // 2*q*nH: f = V^T a, g = V^T b
+  double* partials;           // nparts*(2q^2+q)
+  double* rr_x;               // q*(nH+q) eigenvectors of the reduced problem
+  double* rr_y;               // q*nH coarse eigen-coordinates of the new eigenvectors
+  double* rr_t;               // q*q coefficients of u~
+  double* cH_grid;            // q*(n_c+1)^2 coarse nodal coefficients
+  double* sum_parts;          // output sign partial sums
+};
+
+// One local solve: subdomain Omega_j of problem prob, right-hand side rhs.
+struct TileItem {
+  int32_t prob, sub, rhs, pad;
+  int32_t cx0, cy0, cw, ch;   // Omega_j in coarse cells
+  int64_t off;                // byte offset of the item's storage
+  int64_t inv_off;            // double offset of the subdomain's coarsest-grid inverse
+};
+
+struct ItemStat {
+  int32_t iters, refine;
+  double relres;
+};
+
+__device__ __forceinline__ bool is_dof(int domain, int N, int gx, int gy) {
+  if (gx <= 0 || gy <= 0 || gx >= N || gy >= N) return false;
+  if (domain == 1 && gx >= (N >> 1) && gy <= (N >> 1)) return false;
+  return true;
+}
+
+// Edge weights around node (gx, gy) on a level with N cells, level index l (coarse = 0).
+struct Weights {
+  double e, w, n, s;
+};
+
+template <int KIND>
+__device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, int gx, int gy) {
+  Weights W;
+  if (KIND == 0) {
+    W.e = W.w = W.n = W.s = 1.0;
+  } else if (KIND == 1) {
+    const int nc = P.n_c;
+    const double* k = P.kH;
+    const int cx = gx >> l, cxm = (gx - 1) >> l;
+    const int cy = gy >> l, cym = (gy - 1) >> l;
+    const double k00 = k[cy * nc + cx];      // cell (gx, gy)
+    const double k10 = k[cy * nc + cxm];     // cell (gx-1, gy)
+    const double k01 = k[cym * nc + cx];     // cell (gx, gy-1)
+    const double k11 = k[cym * nc + cxm];    // cell (gx-1, gy-1)
+    W.e = 0.5 * (k00 + k01);
+    W.w = 0.5 * (k10 + k11);
+    W.n = 0.5 * (k00 + k10);
+    W.s = 0.5 * (k01 + k11);
+  } else {
+    const double* lo = P.kLR[l];
+    const double* up = P.kUL[l];
+    const int c = gy * N + gx;
+    // horizontal edge (gx,gy)-(gx+1,gy): lower triangle of cell (gx,gy), upper of (gx,gy-1)
+    W.e = 0.5 * (lo[c] + up[c - N]);
+    W.w = 0.5 * (lo[c - 1] + up[c - N - 1]);
+    // vertical edge (gx,gy)-(gx,gy+1): upper triangle of cell (gx,gy), lower of (gx-1,gy)
+    W.n = 0.5 * (up[c] + lo[c - 1]);
+    W.s = 0.5 * (up[c - N] + lo[c - N - 1]);
+  }
+  return W;
+}
+
+// ---------------------------------------------------------------------------------
+// Workgroup reductions (fixed order: wave butterfly, then waves in index order)
+// ---------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* lds) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[k * NW + wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += lds[k * NW + w];
+    v[k] = s;
+  }
+}
+
+// Kernel launchers (defined in the .hip files).
+struct LaunchCfg {
+  hipStream_t stream;
+};

@@ -1,0 +1,44 @@
+// Kernel launchers of libmlc (host side).  Every launcher enqueues on the given stream
+// and returns the launch status.  Grids span the largest problem of a batch; blocks of
+// problems that are smaller, or that have no level m, exit at once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mlc_device.h"
+
+// ---- one correction step (Algorithm 4.1) at level m, ping-pong src -> dst ----
+hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, int m, int src,
+                                   int64_t max_nodes, hipStream_t s);
+hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
+                            int nitems, char* store, const double* inv, int m, ItemStat* stats,
+                            double rtol, int max_it, int nu, double omega, hipStream_t s);
+hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
+                              int nitems, char* store, const double* inv, int m, ItemStat* stats,
+                              double rtol, int max_it, int max_refine, double inner_rtol, int nu,
+                              double omega, hipStream_t s);
+hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
+                           const char* store, int m, int64_t max_nodes, hipStream_t s);
+hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
+                           hipStream_t s);
+hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
+                           hipStream_t s);
+hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
+hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, int max_nH, int dst,
+                           hipStream_t s);
+hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s);
+hipError_t launch_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
+                           hipStream_t s);
+
+// ---- setup ----
+hipError_t launch_coarsen_kappa(const double* lo_f, const double* up_f, double* lo_c,
+                                double* up_c, int Nc, hipStream_t s);
+hipError_t launch_coarse_matrices(int kind, const ProbDev* probs, int nprob, int max_nH,
+                                  hipStream_t s);
+hipError_t launch_init_u0(const ProbDev* probs, int nprob, int dst, int max_nc1sq, hipStream_t s);
+hipError_t launch_tile_inverse(int kind, const ProbDev* probs, const TileItem* items,
+                               int nitems, double* inv, hipStream_t s);
+
+// ---- state in/out ----
+hipError_t launch_output_signed(const double* u, int64_t nn, int q, double* parts, double* out,
+                                hipStream_t s);
+hipError_t launch_set_state(const ProbDev* prob, int level, int dst, const double* in,
+                            int64_t nn, hipStream_t s);

@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (CPU only: no kernel is launched).
+
+The library must load, export every entry point that include/mlc.h declares, size
+workspaces and reject invalid problems with MLC_EINVAL before touching a GPU.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_1401_4969_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            txt = open(os.path.join(inc, f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mlc_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    declared = _declared()
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared <= set(B.EXPORTS) | declared
+    assert set(B.EXPORTS) == declared
+
+
+def test_status_strings():
+    lib = B.load_library()
+    assert lib.mlc_status_str(0) == b"MLC_OK"
+    assert lib.mlc_status_str(4) == b"MLC_ENOCONV"
+
+
+def test_workspace_size_scales():
+    a = B.workspace_size(W.config1())
+    b = B.workspace_size(W.config1().with_(n_refine=3))
+    assert 0 < a < b
+    assert a % 256 == 0
+
+
+def test_workspace_size_config3_fits_hbm():
+    n = B.workspace_size(W.config3())
+    assert n < 8 * 2 ** 30   # well inside one MI355X's 288 GB
+    m = B.workspace_size(W.config3(), B.default_opts(precision=1))
+    assert m <= n
+
+
+@pytest.mark.parametrize("bad", [
+    dict(domain=3), dict(n_coarse=1), dict(n_refine=0), dict(n_refine=11),
+    dict(sub_x=0), dict(sub_x=9), dict(overlap=0), dict(n_eig=0), dict(n_eig=9),
+    dict(coef_kind=5),
+])
+def test_invalid_descriptors_rejected(bad):
+    p = W.config1().with_(**bad)
+    with pytest.raises(B.MLCError) as e:
+        B.workspace_size(p)
+    assert e.value.status == B.MLC_EINVAL
+
+
+def test_invalid_kappa_rejected():
+    p = W.config1().with_(coef_kind=1, kappa=np.ones((8, 8)))
+    B.workspace_size(p)
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        k = np.ones((8, 8))
+        k[3, 4] = bad
+        with pytest.raises(B.MLCError):
+            B.workspace_size(p.with_(kappa=k))
+
+
+def test_odd_lshape_and_oversized_subdomain_rejected():
+    with pytest.raises(B.MLCError):
+        B.workspace_size(W.Problem(1, 7, 2, 2, 2, 1, 1, 0, None))
+    with pytest.raises(B.MLCError):   # Omega_j of 12x12 coarse cells: 121 coarse interior nodes
+        B.workspace_size(W.Problem(0, 16, 2, 1, 1, 1, 1, 0, None))
+
+
+def test_invalid_options_rejected():
+    for kw in (dict(rtol=0.0), dict(nu=0), dict(omega=1.5), dict(block=128), dict(precision=2)):
+        with pytest.raises(B.MLCError):
+            B.workspace_size(W.config1(), B.default_opts(**kw))
+
+
+def test_create_without_workspace_is_einval():
+    lib = B.load_library()
+    d, _k = B.make_desc(W.config1())
+    o = B.default_opts()
+    ctx = C.c_void_p()
+    st = lib.mlc_create(C.byref(d), C.byref(o), None, 0, None, C.byref(ctx))
+    assert st == B.MLC_EINVAL
+    assert not ctx.value
+
+
+def test_null_context_calls():
+    lib = B.load_library()
+    assert lib.mlc_coarse_setup(None) == B.MLC_EINVAL
+    assert lib.mlc_level_correct(None, None) == B.MLC_EINVAL
+    assert lib.mlc_destroy(None) == B.MLC_EINVAL
+    assert lib.mlc_last_error(None) == b"null context"
