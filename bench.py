@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the multilevel local-and-parallel eigen-correction on one MI355X.
+
+A step is one correction (Algorithm 4.1) at the finest level of the workload, with the
+previous level's eigenpairs already resident in HBM: prolongation and residual of
+(Aux_Problem), every local solve, partition-of-unity gluing, the Rayleigh-Ritz step on
+V_0H + span{u~} and the new eigenvectors.  The library rewinds its ping-pong state
+between steps, so every step repeats exactly the same correction.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3mixed] [--no-cpu-baseline]
+
+Prints one JSON line.  ``value`` is fine interior DOFs corrected per second at the finest
+level (work of every eigenpair included).  ``roofline`` is for the local-solve kernel,
+timed with HIP events the library records on its stream around that kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def tile_levels(cw: int, ch: int, m: int):
+    """Interior node counts of a tile's nested grids, finest first."""
+    return [(cw * (1 << (m - t)) - 1) * (ch * (1 << (m - t)) - 1) for t in range(m + 1)]
+
+
+def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8) -> float:
+    """Bytes the FP64 local-solve kernel schedules per PCG iteration for one tile
+    (each streamed vector read or write counted once per pass):
+      level 0 outside the V-cycle: A p (read p, write q) 2, x/r update 6, r.z 2,
+      p update 3  -> 13 passes;
+      every V-cycle level t above the coarsest: first sweep 2, nu-1 sweeps 3 each,
+      residual 3, restriction read 1 (+ write 1 on level t+1), prolongation add 2
+      (+ read 1 on level t+1), nu post sweeps 3 each;
+      coarsest: read b, write z, and the dense inverse (n^2 values)."""
+    S = tile_levels(cw, ch, m)
+    v = 0.0
+    for t in range(m):
+        v += S[t] * (2 + 3 * (nu - 1) + 3 + 1 + 2 + 3 * nu) + S[t + 1] * 2
+    v += 2 * S[m] + S[m] ** 2
+    return elem * (13 * S[0] + v)
+
+
+def subdomain_shapes(prob):
+    """(cw, ch) of every kept Omega_j, in coarse cells (same layout rule as the library)."""
+    n = prob.n_coarse
+    bx = [(b * n) // prob.sub_x for b in range(prob.sub_x + 1)]
+    by = [(b * n) // prob.sub_y for b in range(prob.sub_y + 1)]
+    out = []
+    ov = prob.overlap
+    for sy in range(prob.sub_y):
+        for sx in range(prob.sub_x):
+            if prob.domain == 1 and bx[sx] >= n // 2 and by[sy + 1] <= n // 2:
+                continue
+            cw = min(n, bx[sx + 1] + ov) - max(0, bx[sx] - ov)
+            ch = min(n, by[sy + 1] + ov) - max(0, by[sy] - ov)
+            out.append((cw, ch))
+    return out
+
+
+def workload(name: str):
+    import workloads as W
+    if name == "c2":
+        return W.config2(), dict(precision=0)
+    if name == "c3":
+        return W.config3(), dict(precision=0)
+    if name == "c3mixed":
+        return W.config3(), dict(precision=1)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def golden_lambda(name: str):
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["lam_levels"][-1]
+
+
+def cpu_baseline(prob, budget_s: float = 30.0):
+    """Time the oracle's finest-level correction (one thread) on a bounded sample."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import mlc as O
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        hier = O.Hierarchy(prob)
+        lam, U = O.coarse_eigs(hier, prob.n_eig)
+        for k in range(prob.n_refine - 1):
+            lam, U, _ = O.correction(hier, k, lam, U)
+        k = prob.n_refine - 1
+        # bounded sample: the local solves of as many subdomains as fit the budget, scaled
+        # to the whole level by tile unknowns; residual, gluing and Rayleigh-Ritz timed whole
+        m = k + 1
+        import scipy.sparse.linalg as spla
+        t0 = time.perf_counter()
+        ubar = hier.P[k] @ U
+        rhs = (hier.M[m] @ ubar) * lam[None, :] - hier.K[m] @ ubar
+        t_rhs = time.perf_counter() - t0
+        total_dofs = sum(hier.tile_dofs(m, s).size for s in hier.subs)
+        t0 = time.perf_counter()
+        sols = []
+        done_dofs = 0
+        for s in hier.subs:
+            idx = hier.tile_dofs(m, s)
+            lu = spla.splu(hier.K[m][idx][:, idx].tocsc())
+            sols.append((idx, lu.solve(np.ascontiguousarray(rhs[idx]))))
+            done_dofs += idx.size
+            if time.perf_counter() - t0 > budget_s:
+                break
+        t_solve = (time.perf_counter() - t0) * total_dofs / done_dofs
+        t1 = time.perf_counter()
+        chi = hier.pou(m)
+        ut = ubar.copy()
+        for (idx, e), c in zip(sols, chi):
+            ut[idx] += c[idx, None] * e
+        O.rayleigh_ritz(hier, m, ut, prob.n_eig)
+        t_rest = time.perf_counter() - t1 + t_rhs
+        done = len(sols)
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    secs = t_solve + t_rest
+    n_dofs = hier.meshes[m].dof.size
+    return dict(value=n_dofs / secs, unit="fine DOFs/s", cores=1, kind="oracle",
+                sample=(f"oracle finest-level correction of {prob.name}: sparse-LU local solves of "
+                        f"{done} of {len(hier.subs)} subdomains timed and scaled by tile unknowns, "
+                        f"gluing + Rayleigh-Ritz timed whole; 1 thread"),
+                seconds_per_step=secs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the subdomain solves of one problem run on one "
+              "MI355X; multi-GPU sharding is a design note, not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1401_4969_amd import binding as B
+
+    prob, okw = workload(args.workload)
+    opts = B.default_opts(timing=1, block=args.block, **okw)
+    s = B.Solver(prob, opts)
+    s.coarse_setup()
+    for _ in range(prob.n_refine):
+        s.level_correct()
+    print(f"[bench] {prob.name}: reached level {s.level}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        s.rewind()
+        s.level_correct()
+    torch.cuda.synchronize()
+    s.phase_times()  # reset the event accumulators
+    stream = s.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        s.rewind()
+        s.level_correct()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    ph = s.phase_times()
+    pcg_ms = ph[0] / args.steps
+    # statistics of the same step (untimed)
+    s.rewind()
+    st = s.level_correct(stats=True)
+    lam = np.array(st["lam"])
+    n_dofs = st["n_dofs"]
+    s.close()
+
+    # algorithmic bytes of one local-solve launch
+    m = prob.n_refine
+    shapes = subdomain_shapes(prob)
+    cw, ch = max(shapes, key=lambda x: x[0] * x[1])
+    S0 = tile_levels(cw, ch, m)[0]
+    per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu) / S0
+    bytes_launch = per_dof_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
+    achieved = bytes_launch / (pcg_ms * 1e-3) / 1e9
+
+    gold = golden_lambda(args.workload.replace("mixed", ""))
+    lam_err = None
+    if gold is not None:
+        lam_err = float(np.max(np.abs(lam - np.array(gold)) / np.abs(np.array(gold))))
+
+    out = {
+        "metric": "fine DOFs corrected/sec per level (1 GPU); lambda1 rel err vs FP64 oracle; HBM GB/s",
+        "value": n_dofs / (ms_step * 1e-3),
+        "unit": "fine DOFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if opts.precision == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "level": m, "h": prob.h(m), "fine_dofs": n_dofs,
+                   "n_eig": prob.n_eig, "subdomains": f"{prob.sub_x}x{prob.sub_y}",
+                   "overlap": prob.overlap, "precision": "fp64" if opts.precision == 0 else "mixed",
+                   "local_rtol": opts.rtol},
+        "lambda": lam.tolist(),
+        "lambda_rel_err_vs_oracle": lam_err,
+        "local_solve": {"ms": pcg_ms, "items": st["n_items"], "tile_dofs": st["n_tile_dofs"],
+                        "it_max": st["it_max"], "it_sum": st["it_sum"],
+                        "relres_max": st["relres_max"], "bytes_per_tile_dof_iter": per_dof_it},
+        "roofline": {"kernel": "k_local_pcg64", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

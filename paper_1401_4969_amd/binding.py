@@ -15,7 +15,8 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "libmlc.so")
+# MLC_LIB may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MLC_LIB") or os.path.join(HERE, "_lib", "libmlc.so")
 
 MLC_OK, MLC_EINVAL, MLC_ENOMEM, MLC_EHIP, MLC_ENOCONV, MLC_ESTATE = range(6)
 STATUS_NAMES = ["MLC_OK", "MLC_EINVAL", "MLC_ENOMEM", "MLC_EHIP", "MLC_ENOCONV", "MLC_ESTATE"]

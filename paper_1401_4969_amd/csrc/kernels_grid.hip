@@ -118,9 +118,11 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
 
 // a5: y_K = K u~ (into res), y_M = M u~ (into ubar), and per-block partial sums of
 // alpha_ij = u~_i . y_K,j, beta_ij = u~_i . y_M,j and s_i = sum u~_i.
+constexpr int RNV = 2 * MLC_MAX_Q * MLC_MAX_Q + MLC_MAX_Q;
+
 template <int KIND>
 __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
-  __shared__ double red[NTG / 64];
+  __shared__ double red[(NTG / 64) * RNV];
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
   const int N = P.n_c << m;
@@ -158,31 +160,33 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
       P.ubar[(int64_t)i * nn + idx] = ym[i];
     }
   }
+  // partial sums: every wave reduces each value with shuffles, one barrier, then the
+  // waves' values are added in a fixed order
   const int nv = 2 * q * q + q;
   double* out = P.partials + (int64_t)blockIdx.x * nv;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int v = 0; v < nv; ++v) {
-    double x = 0.0;
 #pragma unroll
-    for (int i = 0; i < MLC_MAX_Q; ++i) {
+  for (int i = 0; i < MLC_MAX_Q; ++i) {
+    if (i >= q) break;
 #pragma unroll
-      for (int j = 0; j < MLC_MAX_Q; ++j) {
-        if (i < q && j < q) {
-          if (v == i * q + j) x = uv[i] * yk[j];
-          if (v == q * q + i * q + j) x = uv[i] * ym[j];
-        }
+    for (int j = 0; j < MLC_MAX_Q; ++j) {
+      if (j >= q) break;
+      const double a = wave_sum(uv[i] * yk[j]);
+      const double c = wave_sum(uv[i] * ym[j]);
+      if (lane == 0) {
+        red[wid * RNV + i * q + j] = a;
+        red[wid * RNV + q * q + i * q + j] = c;
       }
-      if (i < q && v == 2 * q * q + i) x = uv[i];
     }
-    x = wave_sum(x);
-    __syncthreads();
-    if (lane == 0) red[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < NTG / 64; ++w) s += red[w];
-      out[v] = s;
-    }
+    const double s = wave_sum(uv[i]);
+    if (lane == 0) red[wid * RNV + 2 * q * q + i] = s;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += NTG) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NTG / 64; ++w) s += red[w * RNV + v];
+    out[v] = s;
   }
 }
 
@@ -238,21 +242,25 @@ __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
   }
 }
 
-// a7 (first half): coarse nodal coefficients c_H = V y_hat on the coarse grid.
+// a7 (first half): coarse nodal coefficients c_H = V y_hat on the coarse grid, one wave
+// per coarse node sweeping a row of V^T.
 __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
   const ProbDev& P = probs[blockIdx.y];
   const int nc1 = P.n_c + 1;
-  const int idx = blockIdx.x * NTG + threadIdx.x;
-  if (idx >= nc1 * nc1) return;
-  const int r = P.coarse_index[idx];
+  const int node = blockIdx.x * (NTG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (node >= nc1 * nc1) return;
+  const int r = P.coarse_index[node];
   const int nH = P.nH;
   for (int k = 0; k < P.q; ++k) {
     double s = 0.0;
     if (r >= 0) {
       const double* y = P.rr_y + (int64_t)k * nH;
-      for (int c = 0; c < nH; ++c) s += P.V[(int64_t)c * nH + r] * y[c];
+      const double* row = P.VT + (int64_t)r * nH;
+      for (int c = lane; c < nH; c += 64) s += row[c] * y[c];
+      s = wave_sum(s);
     }
-    P.cH_grid[(int64_t)k * nc1 * nc1 + idx] = s;
+    if (lane == 0) P.cH_grid[(int64_t)k * nc1 * nc1 + node] = s;
   }
 }
 
@@ -496,7 +504,8 @@ hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStr
 }
 
 hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s) {
-  hipLaunchKernelGGL(k_rr_combine, dim3(nblocks(max_nc1sq), nprob), dim3(NTG), 0, s, probs);
+  hipLaunchKernelGGL(k_rr_combine, dim3((max_nc1sq + NTG / 64 - 1) / (NTG / 64), nprob), dim3(NTG),
+                     0, s, probs);
   return hipGetLastError();
 }
 

@@ -341,7 +341,7 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
 
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                            double rtol, int max_it, int nu, double omega, hipStream_t s) {
+                            double rtol, int max_it, int nu, double omega, int64_t, hipStream_t s) {
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), 0, s, probs, items,      \
                      store, inv, m, stats, rtol, max_it, nu, omega)
@@ -363,3 +363,5 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
 #undef MLC_PCG
   return hipGetLastError();
 }
+
+int64_t pcg_lds_bytes(const TileItem*, int, int, int) { return 0; }

@@ -16,6 +16,11 @@
 // and its eigenvectors by inverse iteration with (T - sigma I)^-1 applied through
 // the q x q Schur complement.  Cost O(nH q^2) per evaluation instead of the
 // O((nH+q)^3) of a dense eigensolver.
+//
+// Reductions are batched: each wave reduces its partial sums with shuffles and writes
+// them to LDS, and one barrier later every value is summed over the waves in a fixed
+// order (deterministic).  Multisection evaluates G points per round, GS threads per
+// point (GS consecutive lanes reduce with shuffles inside the wave).
 #include "mlc_launch.h"
 
 namespace {
@@ -23,26 +28,21 @@ namespace {
 constexpr int NTR = 256;
 constexpr int NWR = NTR / 64;
 
-__device__ __forceinline__ double bsum(double x, double* red) {
-  x = wave_sum(x);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < NWR; ++w) s += red[w];
-  return s;
+__device__ __forceinline__ double group_sum(double x, int gs) {
+  for (int o = gs >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
 }
 
-__device__ __forceinline__ double bmin(double x, double* red) {
+// Wave-reduce x and park it in lds[wave * stride + v]; the caller barriers, then sums.
+__device__ __forceinline__ void park(double x, int v, double* lds, int stride) {
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) lds[(threadIdx.x >> 6) * stride + v] = x;
+}
+
+__device__ __forceinline__ double gather(int v, const double* lds, int stride) {
+  double s = 0.0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-  __syncthreads();
-  double s = red[0];
-#pragma unroll
-  for (int w = 1; w < NWR; ++w) s = fmin(s, red[w]);
+  for (int w = 0; w < NWR; ++w) s += lds[w * stride + v];
   return s;
 }
 
@@ -58,38 +58,11 @@ __device__ __forceinline__ int bmin_int(int x, int* red) {
   return s;
 }
 
-// Number of eigenvalues of T below mu (Sylvester inertia through the Schur complement).
+// Number of negative eigenvalues of a symmetric QxQ matrix (LDL^T, Sylvester); an exact
+// zero pivot is nudged.
 template <int Q>
-__device__ int count_below(double mu, const double* Lam, const double* Z, int nH,
-                           const double* W) {
-  double S[Q][Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i)
-#pragma unroll
-    for (int j = 0; j < Q; ++j) S[i][j] = 0.0;
+__device__ int neg_inertia(double (&S)[Q][Q]) {
   int n = 0;
-  for (int r = 0; r < nH; ++r) {
-    double d = Lam[r] - mu;
-    if (d < 0.0) ++n;
-    if (d == 0.0) d = 1e-300;
-    const double inv = 1.0 / d;
-    double z[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) z[i] = Z[r * Q + i];
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-#pragma unroll
-      for (int j = 0; j <= i; ++j) S[i][j] += z[i] * z[j] * inv;
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      S[i][j] = W[i * Q + j] - S[i][j] - (i == j ? mu : 0.0);
-      S[j][i] = S[i][j];
-    }
-  // LDL^T without pivoting: the count of negative pivots is the number of negative
-  // eigenvalues (Sylvester); an exact zero pivot is nudged.
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     double d = S[k][k];
@@ -105,7 +78,7 @@ __device__ int count_below(double mu, const double* Lam, const double* Z, int nH
   return n;
 }
 
-// Solve the small dense system A x = b (Gaussian elimination, partial pivoting).
+// Solve A x = b (Gaussian elimination, partial pivoting), x returned in b.
 template <int Q>
 __device__ void small_solve(double (&A)[Q][Q], double (&b)[Q]) {
 #pragma unroll
@@ -142,72 +115,76 @@ __device__ void small_solve(double (&A)[Q][Q], double (&b)[Q]) {
 
 template <int Q>
 __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, int dst) {
-  __shared__ double red[NWR];
+  constexpr int NV = 3 * Q * Q + Q + 1;
+  __shared__ double park_lds[NWR * NV];
+  __shared__ double vals[NV];
   __shared__ int redi[NWR];
   __shared__ double sAlpha[Q * Q], sBeta[Q * Q];
-  __shared__ double sGG[Q * Q], sGF[Q * Q], sGLG[Q * Q];
   __shared__ double sL[Q * Q], sW[Q * Q];
-  __shared__ double sMu[Q], sS[Q], sT[Q];
+  __shared__ double sMu[Q], sT[Q], sSol[Q];
   __shared__ double sLo, sHi;
   extern __shared__ double dyn[];
   const ProbDev& P = probs[blockIdx.x];
   if (m > P.L) return;
   const int tid = threadIdx.x;
   const int nH = P.nH;
-  double* Lam = dyn;
-  double* Z = dyn + nH;
-  const double* f = P.fg;
-  const double* g = P.fg + (int64_t)Q * nH;
+  double* Lam = dyn;                 // nH
+  double* Z = dyn + nH;              // nH * Q
+  double* f = dyn + nH * (1 + Q);    // Q * nH
+  double* g = f + Q * nH;            // Q * nH
 
-  // 1. finish the fine-grid reductions in a fixed order
+  // 1. finish the fine-grid reductions (alpha, beta) in a fixed order; stage the
+  //    coarse quantities in LDS
   {
     const int N = P.n_c << m;
     const int64_t nn = (int64_t)(N + 1) * (N + 1);
     const int nblk = (int)((nn + 255) / 256);
-    const int nv = 2 * Q * Q + Q;
+    const int nvp = 2 * Q * Q + Q;
     for (int v = 0; v < 2 * Q * Q; ++v) {
       double s = 0.0;
-      for (int b = tid; b < nblk; b += NTR) s += P.partials[(int64_t)b * nv + v];
-      s = bsum(s, red);
-      if (tid == 0) {
-        if (v < Q * Q)
-          sAlpha[v] = s;
-        else
-          sBeta[v - Q * Q] = s;
-      }
+      for (int b = tid; b < nblk; b += NTR) s += P.partials[(int64_t)b * nvp + v];
+      park(s, v, park_lds, NV);
     }
+    for (int r = tid; r < nH; r += NTR) Lam[r] = P.Lam[r];
+    for (int e = tid; e < 2 * Q * nH; e += NTR) f[e] = P.fg[e];
+    __syncthreads();
+    for (int v = tid; v < 2 * Q * Q; v += NTR) {
+      const double s = gather(v, park_lds, NV);
+      if (v < Q * Q)
+        sAlpha[v] = s;
+      else
+        sBeta[v - Q * Q] = s;
+    }
+    __syncthreads();
   }
-  for (int r = tid; r < nH; r += NTR) Lam[r] = P.Lam[r];
-  // 2. g^T g, g^T f, g^T Lambda g
-  for (int i = 0; i < Q; ++i) {
+  // 2. g^T g, g^T f, g^T Lambda g (one batched reduction)
+  for (int i = 0; i < Q; ++i)
     for (int j = 0; j < Q; ++j) {
       double a = 0.0, b = 0.0, c = 0.0;
       for (int r = tid; r < nH; r += NTR) {
-        const double gi = g[(int64_t)i * nH + r];
-        a += gi * g[(int64_t)j * nH + r];
-        b += gi * f[(int64_t)j * nH + r];
-        c += gi * P.Lam[r] * g[(int64_t)j * nH + r];
+        const double gi = g[i * nH + r];
+        a += gi * g[j * nH + r];
+        b += gi * f[j * nH + r];
+        c += gi * Lam[r] * g[j * nH + r];
       }
-      a = bsum(a, red);
-      b = bsum(b, red);
-      c = bsum(c, red);
-      if (tid == 0) {
-        sGG[i * Q + j] = a;
-        sGF[i * Q + j] = b;
-        sGLG[i * Q + j] = c;
-      }
+      park(a, i * Q + j, park_lds, NV);
+      park(b, Q * Q + i * Q + j, park_lds, NV);
+      park(c, 2 * Q * Q + i * Q + j, park_lds, NV);
     }
-  }
   __syncthreads();
-  // 3. Bw = L L^T, W = L^-1 Aw L^-T
+  for (int v = tid; v < 3 * Q * Q; v += NTR) vals[v] = gather(v, park_lds, NV);
+  __syncthreads();
+  // 3. Bw = L L^T, W = L^-1 Aw L^-T (one thread; Q <= 8)
   if (tid == 0) {
+    const double* GG = vals;
+    const double* GF = vals + Q * Q;
+    const double* GLG = vals + 2 * Q * Q;
     double Bw[Q][Q], Aw[Q][Q], L[Q][Q];
     for (int i = 0; i < Q; ++i)
       for (int j = 0; j < Q; ++j) {
-        Bw[i][j] = 0.5 * (sBeta[i * Q + j] + sBeta[j * Q + i]) -
-                   0.5 * (sGG[i * Q + j] + sGG[j * Q + i]);
-        Aw[i][j] = 0.5 * (sAlpha[i * Q + j] + sAlpha[j * Q + i]) - sGF[i * Q + j] -
-                   sGF[j * Q + i] + 0.5 * (sGLG[i * Q + j] + sGLG[j * Q + i]);
+        Bw[i][j] = 0.5 * (sBeta[i * Q + j] + sBeta[j * Q + i]) - 0.5 * (GG[i * Q + j] + GG[j * Q + i]);
+        Aw[i][j] = 0.5 * (sAlpha[i * Q + j] + sAlpha[j * Q + i]) - GF[i * Q + j] - GF[j * Q + i] +
+                   0.5 * (GLG[i * Q + j] + GLG[j * Q + i]);
         L[i][j] = 0.0;
       }
     for (int j = 0; j < Q; ++j) {
@@ -221,15 +198,14 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
         L[i][j] = s / d;
       }
     }
-    // X = L^-1 Aw (forward substitution on columns), W = X L^-T = (L^-1 X^T)^T
-    double X[Q][Q];
+    double X[Q][Q];  // X = L^-1 Aw
     for (int c = 0; c < Q; ++c)
       for (int i = 0; i < Q; ++i) {
         double s = Aw[i][c];
         for (int k = 0; k < i; ++k) s -= L[i][k] * X[k][c];
         X[i][c] = s / L[i][i];
       }
-    double Wm[Q][Q];
+    double Wm[Q][Q];  // Wm = X L^-T
     for (int rI = 0; rI < Q; ++rI)
       for (int i = 0; i < Q; ++i) {
         double s = X[rI][i];
@@ -247,7 +223,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
   for (int r = tid; r < nH; r += NTR) {
     double z[Q];
     for (int i = 0; i < Q; ++i) {
-      double s = f[(int64_t)i * nH + r] - Lam[r] * g[(int64_t)i * nH + r];
+      double s = f[i * nH + r] - Lam[r] * g[i * nH + r];
       for (int k = 0; k < i; ++k) s -= sL[i * Q + k] * z[k];
       z[i] = s / sL[i * Q + i];
     }
@@ -269,40 +245,85 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
       }
       rowmin = fmin(rowmin, Lam[r] - s);
     }
-    lo = bmin(rowmin, red);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rowmin = fmin(rowmin, __shfl_xor(rowmin, o, 64));
+    for (int i = 0; i < Q; ++i) park(cs[i], i, park_lds, NV);
+    if ((tid & 63) == 0) park_lds[(tid >> 6) * NV + Q] = rowmin;
+    __syncthreads();
+    lo = park_lds[Q];
+    for (int w = 1; w < NWR; ++w) lo = fmin(lo, park_lds[w * NV + Q]);
     for (int i = 0; i < Q; ++i) {
-      const double c = bsum(cs[i], red);
-      double w = sW[i * Q + i] - c;
+      double w = sW[i * Q + i] - gather(i, park_lds, NV);
       for (int j = 0; j < Q; ++j)
         if (j != i) w -= fabs(sW[i * Q + j]);
       lo = fmin(lo, w);
     }
+    __syncthreads();
   }
   const double hi0 = Lam[Q - 1] + 1e-12 * fabs(Lam[Q - 1]) + 1e-300;
   lo -= 1e-12 * fabs(lo) + 1e-300;
-  // 6. multisection for each of the lowest Q eigenvalues
+  // 6. multisection: G points per round, GS threads per point
+  int GS = 1;
+  while (GS < 64 && GS * 32 < nH) GS <<= 1;
+  const int G = NTR / GS;
+  const int pnt = tid / GS, gl = tid % GS;
   for (int k = 0; k < Q; ++k) {
     if (tid == 0) {
       sLo = lo;
       sHi = hi0;
     }
     __syncthreads();
-    for (int round = 0; round < 24; ++round) {
+    for (int round = 0; round < 64; ++round) {
       const double a = sLo, b = sHi;
       if (b - a <= 4.0 * 2.220446049250313e-16 * fmax(fabs(a), fabs(b))) break;
-      const double mu = a + (b - a) * (double)(tid + 1) / (double)(NTR + 1);
-      const int c = count_below<Q>(mu, Lam, Z, nH, sW);
-      const int t = bmin_int(c >= k + 1 ? tid : NTR, redi);
-      __syncthreads();
-      if (tid == t) sHi = mu;
-      if (tid == t - 1) sLo = mu;
-      if (t == NTR && tid == NTR - 1) sLo = mu;
+      const double mu = a + (b - a) * (double)(pnt + 1) / (double)(G + 1);
+      double S[Q][Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int j = 0; j < Q; ++j) S[i][j] = 0.0;
+      double nless = 0.0;
+      for (int r = gl; r < nH; r += GS) {
+        double d = Lam[r] - mu;
+        if (d < 0.0) nless += 1.0;
+        if (d == 0.0) d = 1e-300;
+        const double inv = 1.0 / d;
+        double z[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) z[i] = Z[r * Q + i];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j) S[i][j] += z[i] * z[j] * inv;
+      }
+      nless = group_sum(nless, GS);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) S[i][j] = group_sum(S[i][j], GS);
+      int flag = G;
+      if (gl == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j) {
+            S[i][j] = sW[i * Q + j] - S[i][j] - (i == j ? mu : 0.0);
+            S[j][i] = S[i][j];
+          }
+        const int c = (int)nless + neg_inertia<Q>(S);
+        if (c >= k + 1) flag = pnt;
+      }
+      const int t = bmin_int(flag, redi);
+      if (gl == 0 && pnt == t) sHi = mu;
+      if (gl == 0 && pnt == t - 1) sLo = mu;
+      if (t == G && gl == 0 && pnt == G - 1) sLo = mu;
       __syncthreads();
     }
     if (tid == 0) sMu[k] = 0.5 * (sLo + sHi);
     __syncthreads();
   }
-  // 7. eigenvectors by inverse iteration on T - sigma I
+  // 7. eigenvectors by inverse iteration on T - sigma I (two steps), classical
+  //    Gram-Schmidt against the previous ones
   const int n = nH + Q;
   for (int k = 0; k < Q; ++k) {
     double* x = P.rr_x + (int64_t)k * n;
@@ -310,8 +331,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
     const double sigma = mu - fmax(8.0 * 2.220446049250313e-16 * fabs(mu), 1e-300);
     for (int r = tid; r < n; r += NTR) x[r] = 1.0 + 0.01 * (double)((r * 7 + k * 13) % 17);
     __syncthreads();
-    for (int iter = 0; iter < 3; ++iter) {
-      // S(sigma) and the reduced right-hand side, accumulated over r
+    for (int iter = 0; iter < 2; ++iter) {
       double Sp[Q][Q], rp[Q];
       for (int i = 0; i < Q; ++i) {
         rp[i] = 0.0;
@@ -321,40 +341,60 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
         double d = Lam[r] - sigma;
         if (d == 0.0) d = 1e-300;
         const double inv = 1.0 / d;
+        const double xr = x[r];
         for (int i = 0; i < Q; ++i) {
-          rp[i] += Z[r * Q + i] * x[r] * inv;
-          for (int j = 0; j < Q; ++j) Sp[i][j] += Z[r * Q + i] * Z[r * Q + j] * inv;
+          rp[i] += Z[r * Q + i] * xr * inv;
+          for (int j = 0; j <= i; ++j) Sp[i][j] += Z[r * Q + i] * Z[r * Q + j] * inv;
         }
       }
-      double A[Q][Q], bb[Q];
       for (int i = 0; i < Q; ++i) {
-        bb[i] = x[nH + i] - bsum(rp[i], red);
-        for (int j = 0; j < Q; ++j)
-          A[i][j] = sW[i * Q + j] - (i == j ? sigma : 0.0) - bsum(Sp[i][j], red);
+        park(rp[i], i, park_lds, NV);
+        for (int j = 0; j <= i; ++j) park(Sp[i][j], Q + i * Q + j, park_lds, NV);
       }
-      small_solve<Q>(A, bb);  // every thread holds the same s
+      __syncthreads();
+      if (tid == 0) {
+        double A[Q][Q], bb[Q];
+        for (int i = 0; i < Q; ++i) {
+          bb[i] = x[nH + i] - gather(i, park_lds, NV);
+          for (int j = 0; j <= i; ++j) {
+            A[i][j] = sW[i * Q + j] - (i == j ? sigma : 0.0) - gather(Q + i * Q + j, park_lds, NV);
+            A[j][i] = A[i][j];
+          }
+        }
+        small_solve<Q>(A, bb);
+        for (int i = 0; i < Q; ++i) sSol[i] = bb[i];
+      }
       __syncthreads();
       for (int r = tid; r < nH; r += NTR) {
         double d = Lam[r] - sigma;
         if (d == 0.0) d = 1e-300;
         double s = x[r];
-        for (int i = 0; i < Q; ++i) s -= Z[r * Q + i] * bb[i];
+        for (int i = 0; i < Q; ++i) s -= Z[r * Q + i] * sSol[i];
         x[r] = s / d;
       }
-      if (tid < Q) x[nH + tid] = bb[tid];
+      if (tid < Q) x[nH + tid] = sSol[tid];
       __syncthreads();
-      for (int kp = 0; kp < k; ++kp) {
-        const double* xp = P.rr_x + (int64_t)kp * n;
-        double d = 0.0;
-        for (int r = tid; r < n; r += NTR) d += x[r] * xp[r];
-        d = bsum(d, red);
-        for (int r = tid; r < n; r += NTR) x[r] -= d * xp[r];
+      if (k > 0) {
+        for (int kp = 0; kp < k; ++kp) {
+          const double* xp = P.rr_x + (int64_t)kp * n;
+          double d = 0.0;
+          for (int r = tid; r < n; r += NTR) d += x[r] * xp[r];
+          park(d, kp, park_lds, NV);
+        }
+        __syncthreads();
+        for (int r = tid; r < n; r += NTR) {
+          double s = x[r];
+          for (int kp = 0; kp < k; ++kp) s -= gather(kp, park_lds, NV) * P.rr_x[(int64_t)kp * n + r];
+          x[r] = s;
+        }
         __syncthreads();
       }
       double nr = 0.0;
       for (int r = tid; r < n; r += NTR) nr += x[r] * x[r];
-      nr = sqrt(bsum(nr, red));
-      for (int r = tid; r < n; r += NTR) x[r] /= nr;
+      park(nr, 0, park_lds, NV);
+      __syncthreads();
+      const double inv = 1.0 / sqrt(gather(0, park_lds, NV));
+      for (int r = tid; r < n; r += NTR) x[r] *= inv;
       __syncthreads();
     }
     // 8. back to the original basis: u_k = P V (y - g t) + u~ t, t = L^-T s
@@ -374,18 +414,28 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
     __syncthreads();
     for (int r = tid; r < nH; r += NTR) {
       double s = x[r];
-      for (int i = 0; i < Q; ++i) s -= g[(int64_t)i * nH + r] * sT[i];
+      for (int i = 0; i < Q; ++i) s -= g[i * nH + r] * sT[i];
       P.rr_y[(int64_t)k * nH + r] = s;
     }
     __syncthreads();
   }
 }
 
+// V^T stored row-major (VT[r*nH + c] = V[c*nH + r]) for coalesced row sweeps.
+__global__ __launch_bounds__(256) void k_transpose(const ProbDev* probs) {
+  const ProbDev& P = probs[blockIdx.y];
+  const int nH = P.nH;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nH * nH) return;
+  const int r = (int)(e / nH), c = (int)(e - (int64_t)r * nH);
+  P.VT[e] = P.V[(int64_t)c * nH + r];
+}
+
 }  // namespace
 
 hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, int max_nH, int dst,
                            hipStream_t s) {
-  const size_t shm = (size_t)max_nH * (1 + max_q) * sizeof(double);
+  const size_t shm = (size_t)max_nH * (1 + 3 * max_q) * sizeof(double);
   switch (max_q) {
 #define MLC_RR_CASE(QQ)                                                                       \
   case QQ:                                                                                    \
@@ -403,5 +453,11 @@ hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, in
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_v(const ProbDev* probs, int nprob, int max_nH, hipStream_t s) {
+  const int64_t n = (int64_t)max_nH * max_nH;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 255) / 256), nprob), dim3(256), 0, s, probs);
   return hipGetLastError();
 }

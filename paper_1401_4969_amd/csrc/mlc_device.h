@@ -39,7 +39,8 @@ struct ProbDev {
   double* V;                  // nH*nH column-major, M_H-orthonormal coarse eigenvectors
   double* Lam;                // nH ascending coarse eigenvalues
   double* Kc;                 // nH*nH coarse stiffness (setup scratch, overwritten by V)
-  double* Mc;                 // nH*nH coarse mass (setup scratch)
+  double* Mc;                 // nH*nH coarse mass (setup scratch, then V^T)
+  double* VT;                 // nH*nH row-major V^T (aliases Mc after setup)
   double* fg;                 // 2*q*nH: f = V^T a, g = V^T b
   double* partials;           // nparts*(2q^2+q)
   double* rr_x;               // q*(nH+q) eigenvectors of the reduced problem

@@ -110,7 +110,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, const mlc_solver_opts* o, G
       }
   g.nH = (int)g.coarse_nodes.size();
   if (g.q > g.nH) { msg = "n_eig exceeds the number of coarse interior nodes"; return MLC_EINVAL; }
-  if ((int64_t)g.nH * (1 + g.q) > 8192) { msg = "coarse space too large for the device Rayleigh-Ritz solve"; return MLC_EINVAL; }
+  if ((int64_t)g.nH * (1 + 3 * g.q) > 8192) { msg = "coarse space too large for the device Rayleigh-Ritz solve"; return MLC_EINVAL; }
   // subdomains (Section 4): D_j blocks, Omega_j = D_j grown by `overlap` coarse cells
   for (int b = 0; b <= d->sub_x; ++b) g.bx.push_back((b * nc) / d->sub_x);
   for (int b = 0; b <= d->sub_y; ++b) g.by.push_back((b * nc) / d->sub_y);
@@ -405,6 +405,7 @@ mlc_status mlc_create(const mlc_problem_desc* d, const mlc_solver_opts* o, void*
   P.Kc = (double*)(b + L.Kc);
   P.V = P.Kc;
   P.Mc = (double*)(b + L.Mc);
+  P.VT = P.Mc;
   P.Lam = (double*)(b + L.Lam);
   P.fg = (double*)(b + L.fg);
   P.partials = (double*)(b + L.partials);
@@ -496,6 +497,7 @@ mlc_status mlc_coarse_setup(mlc_ctx* c) {
     c->err = std::string("rocsolver_dsygvd: ") + rocblas_status_to_string(rs);
     return MLC_EHIP;
   }
+  MLC_HIP(c, launch_transpose_v(c->dprob, 1, g.nH, st));
   MLC_HIP(c, launch_init_u0(c->dprob, 1, 0, (g.nc + 1) * (g.nc + 1), st));
   MLC_HIP(c, launch_tile_inverse(g.kind, c->dprob, (const TileItem*)(b + L.items[1]),
                                  (int)g.items.size(), (double*)(b + L.inv), st));
@@ -538,9 +540,10 @@ static mlc_status level_correct_impl(mlc_ctx* c) {
   MLC_HIP(c, launch_prolong_residual(g.kind, c->dprob, 1, m, src, nn, st));
   if (timing) MLC_HIP(c, hipEventRecord(ev[1], st));
   if (c->o.precision == 0) {
+    const int64_t lds = pcg_lds_bytes(c->items_lv[m].data(), nitems, m, (int)sizeof(double));
     MLC_HIP(c, launch_local_pcg(g.kind, c->nt, c->dprob, items, nitems, b + L.store,
                                 (const double*)(b + L.inv), m, (ItemStat*)(b + L.stats),
-                                c->o.rtol, c->o.max_it, c->o.nu, c->o.omega, st));
+                                c->o.rtol, c->o.max_it, c->o.nu, c->o.omega, lds, st));
   } else {
     MLC_HIP(c, launch_local_mixed(g.kind, c->nt, c->dprob, items, nitems, b + L.store,
                                   (const double*)(b + L.inv), m, (ItemStat*)(b + L.stats),

@@ -10,7 +10,9 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
                                    int64_t max_nodes, hipStream_t s);
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                            double rtol, int max_it, int nu, double omega, hipStream_t s);
+                            double rtol, int max_it, int nu, double omega, int64_t lds_bytes,
+                            hipStream_t s);
+int64_t pcg_lds_bytes(const TileItem* items, int nitems, int m, int elem_bytes);
 hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
@@ -24,6 +26,7 @@ hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_
 hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
 hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, int max_nH, int dst,
                            hipStream_t s);
+hipError_t launch_transpose_v(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
 hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s);
 hipError_t launch_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
                            hipStream_t s);

@@ -1,0 +1,61 @@
+"""Write the stored oracle values used by the GPU parity tests and the benchmark.
+
+Calls only the CPU oracle (``oracle/``) on the seeded workloads (``workloads.py``); no
+value here comes from the GPU path.  Output: tests/golden/oracle_<name>.json with the
+per-level eigenvalues and, for the finest level, eigenvector values at a seeded sample
+of interior nodes (each vector with non-negative nodal sum).
+
+    python tests/golden/make_golden.py [c1 c2 c3 c5 ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle import solve  # noqa: E402
+
+CONFIGS = {
+    "c1": W.config1,
+    "c2": W.config2,
+    "c3": W.config3,
+    "c5": W.config5,
+}
+
+
+def make(name: str, n_samples: int = 512):
+    prob = CONFIGS[name]()
+    t0 = time.perf_counter()
+    res = solve(prob, keep_levels=False)
+    secs = time.perf_counter() - t0
+    hier = res.hier
+    L = prob.n_refine
+    mesh = hier.meshes[L]
+    rng = np.random.Generator(np.random.PCG64(1234))
+    pick = np.sort(rng.choice(mesh.dof.size, size=min(n_samples, mesh.dof.size), replace=False))
+    out = dict(
+        name=prob.name, n_refine=L, n_eig=prob.n_eig,
+        lam_levels=[l.tolist() for l in res.lam_levels],
+        level_seconds=res.seconds,
+        total_seconds=secs,
+        sample_nodes=mesh.dof[pick].tolist(),
+        sample_values=[res.U[pick, i].tolist() for i in range(prob.n_eig)],
+        u_l2=[float(np.sqrt(res.U[:, i] @ res.U[:, i])) for i in range(prob.n_eig)],
+        u_sum=[float(res.U[:, i].sum()) for i in range(prob.n_eig)],
+        source="oracle.solve (CPU FP64), written by tests/golden/make_golden.py",
+    )
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"{name}: {secs:.1f} s -> {path}", flush=True)
+
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or list(CONFIGS)):
+        make(n)

@@ -175,3 +175,32 @@ def test_set_state_resume():
     d = s.level_correct(stats=True)
     assert abs(d["lam"][0] - ref.lam_levels[2][0]) / ref.lam_levels[2][0] < LAM_RTOL
     s.close()
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"oracle_{name}.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,factory", [("c3", W.config3), ("c5", W.config5)])
+def test_full_size_against_stored_oracle(name, factory):
+    """Configurations 3 (h = 1/2048, 16x16 subdomains) and 5 (h = 1/1024, per-cell
+    log-normal kappa) at full size in FP64: every level's eigenvalue against the stored
+    oracle values, and the finest eigenvector at 512 seeded nodes."""
+    gold = _golden(name)
+    prob = factory()
+    lam, u, levels, stats = gpu_solve(prob)
+    for k, (a, b) in enumerate(zip(levels, gold["lam_levels"])):
+        rel = np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b)))
+        assert rel < LAM_RTOL, (name, k, a, b, rel)
+    ug = u[0].reshape(-1)
+    idx = np.asarray(gold["sample_nodes"])
+    import torch
+    vals = ug[torch.as_tensor(idx, device=ug.device)].cpu().numpy()
+    ref = np.asarray(gold["sample_values"][0])
+    assert np.max(np.abs(vals - ref)) < 1e-8 * np.max(np.abs(ref))
+    for s in stats:
+        assert s["relres_max"] <= 1e-12 * 1.0000001
