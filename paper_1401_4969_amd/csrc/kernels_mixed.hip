@@ -1,11 +1,123 @@
-// Mixed-precision local solves (FP32 inner PCG, FP64 residual refinement).
-#include "mlc_launch.h"
+// Mixed-precision local solves of Algorithm 4.1 step 1 (equation (Aux_Problem)):
+// FP32 preconditioned conjugate gradients with the FP32 V-cycle, wrapped in FP64
+// iterative refinement.  The correction e and the residual b - K e stay in FP64:
+//   e = 0; repeat { r = b - K e (FP64 stencil); stop when ||r|| <= rtol ||b||;
+//                   solve K d = r in FP32 to inner_rtol; e += d (FP64) }.
+// Only the inner iterations run in FP32, so they stream half the bytes of the FP64
+// solver; the accuracy of e is that of the FP64 residual.
+#include "pcg_ops.h"
 
-int64_t item_bytes_fp64(int cw, int ch, int m);
+namespace {
 
-int64_t item_bytes_mixed(int cw, int ch, int m) { return item_bytes_fp64(cw, ch, m); }
+template <int NT, int KIND>
+__global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const TileItem* items,
+                                                    char* store, const double* inv, int m,
+                                                    ItemStat* stats, double rtol, int max_it,
+                                                    int max_refine, double inner_rtol, int nu,
+                                                    double omega) {
+  __shared__ LevelDesc lev[MLC_MAX_LEVELS + 1];
+  __shared__ double red[2 * (NT / 64)];
+  const TileItem it = items[blockIdx.x];
+  const ProbDev& P = probs[it.prob];
+  if (threadIdx.x == 0) fill_levels(it, P, m, 2, lev);
+  __syncthreads();
+  const LevelDesc& l0 = lev[0];
+  const int64_t S0 = (int64_t)l0.nx * l0.ny;
+  double* E = reinterpret_cast<double*>(store + it.off);      // FP64 correction, read by the gluing
+  float* base = reinterpret_cast<float*>(store + it.off + 8 * S0);
+  float* X = base;
+  float* R = base + l0.ob;
+  const double* Kinv = inv + it.inv_off;
+  const int n1 = l0.N + 1;
+  const double* bglob = P.res + (int64_t)it.rhs * n1 * n1;
+  auto bat = [&](int ix, int iy) -> double {
+    return bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
+  };
+  double acc[2] = {0.0, 0.0};
+  FOR_TILE(l0) {
+    const int64_t i = (int64_t)iy * l0.nx + ix;
+    const double v = bat(ix, iy);
+    E[i] = 0.0;
+    R[i] = (float)v;
+    X[i] = 0.0f;
+    acc[0] += v * v;
+  }
+  block_sum<NT, 2>(acc, red);
+  const double bb = acc[0];
+  double rr = bb;
+  int total = 0, refine = 0;
+  while (rr > rtol * rtol * bb && refine < max_refine) {
+    ++refine;
+    double rr_inner;
+    total += pcg_solve<NT, KIND, float>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
+                                        max_it, nu, omega, red, rr_inner);
+    FOR_TILE(l0) {
+      const int64_t i = (int64_t)iy * l0.nx + ix;
+      E[i] += (double)X[i];
+    }
+    __syncthreads();
+    // FP64 residual of the accumulated correction, handed to the next FP32 solve
+    acc[0] = acc[1] = 0.0;
+    FOR_TILE(l0) {
+      const int64_t i = (int64_t)iy * l0.nx + ix;
+      double r = 0.0;
+      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
+        double d;
+        r = bat(ix, iy) - stencil<KIND, double>(P, l0, E, ix, iy, i, d);
+      }
+      R[i] = (float)r;
+      X[i] = 0.0f;
+      acc[0] += r * r;
+    }
+    block_sum<NT, 2>(acc, red);
+    rr = acc[0];
+  }
+  if (threadIdx.x == 0) {
+    ItemStat s;
+    s.iters = total;
+    s.refine = refine;
+    s.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    stats[blockIdx.x] = s;
+  }
+}
 
-hipError_t launch_local_mixed(int, int, const ProbDev*, const TileItem*, int, char*, const double*,
-                              int, ItemStat*, double, int, int, double, int, double, hipStream_t) {
-  return hipErrorNotSupported;
+}  // namespace
+
+// Storage (bytes) of one item at level m: the FP64 correction, then the FP32 tile buffers
+// (X, R, Z, Tmp, P, Q on the tile level and B, Z, Tmp on every coarser level).
+int64_t item_bytes_mixed(int cw, int ch, int m) {
+  int64_t fl = 0, S0 = 0;
+  for (int t = 0; t <= m; ++t) {
+    const int r = 1 << (m - t);
+    const int64_t S = (int64_t)(cw * r - 1) * (ch * r - 1);
+    if (t == 0) S0 = S;
+    fl += (t == 0 ? 6 : 3) * S;
+  }
+  return 8 * S0 + ((4 * fl + 7) / 8) * 8;
+}
+
+hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
+                              int nitems, char* store, const double* inv, int m, ItemStat* stats,
+                              double rtol, int max_it, int max_refine, double inner_rtol, int nu,
+                              double omega, hipStream_t s) {
+#define MLC_MIX(NTV, KV)                                                                     \
+  hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), 0, s, probs, items,   \
+                     store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega)
+#define MLC_MIX_NT(NTV) \
+  if (kind == 0)        \
+    MLC_MIX(NTV, 0);    \
+  else if (kind == 1)   \
+    MLC_MIX(NTV, 1);    \
+  else                  \
+    MLC_MIX(NTV, 2);
+  if (nt == 256) {
+    MLC_MIX_NT(256)
+  } else if (nt == 512) {
+    MLC_MIX_NT(512)
+  } else {
+    MLC_MIX_NT(1024)
+  }
+#undef MLC_MIX_NT
+#undef MLC_MIX
+  return hipGetLastError();
 }
