@@ -49,6 +49,43 @@ def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8) ->
     return elem * (13 * S[0] + v)
 
 
+def mixed_bytes(cw: int, ch: int, m: int, nu: int, it_dofs: int, refine_dofs: int,
+                tile_dofs: int) -> float:
+    """Bytes of one mixed-precision local-solve launch: the FP32 inner iterations (the FP64
+    schedule above with 4-byte elements, plus one pass per inner solve), and per
+    refinement step the FP64 passes e += d (read e 8, d 4, write e 8) and r = b - K e
+    (read b 8, e 8, write r 4, clear d 4); plus the first pass (read b, write e, r, d)."""
+    S0 = tile_levels(cw, ch, m)[0]
+    per_it = pcg_bytes_per_iteration(cw, ch, m, nu, elem=4) / S0
+    return per_it * it_dofs + (44.0 + 4.0) * refine_dofs + 24.0 * tile_dofs
+
+
+def source_sha(kernel: str) -> str:
+    import hashlib
+    c = os.path.join(ROOT, "paper_1401_4969_amd", "csrc")
+    files = {"k_local_pcg64": ["kernels_pcg.hip", "pcg_ops.h", "mlc_device.h"],
+             "k_local_mixed": ["kernels_mixed.hip", "pcg_ops.h", "mlc_device.h"]}[kernel]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(c, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """Counter-derived HBM bytes per launch from profiles/traffic.json, or None when the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    rec = tab.get(f"{kernel}:{workload}")
+    if not rec or rec.get("source_sha") != source_sha(kernel):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def subdomain_shapes(prob):
     """(cw, ch) of every kept Omega_j, in coarse cells (same layout rule as the library)."""
     n = prob.n_coarse
@@ -148,6 +185,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run 4 plain device copies of 256 MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the subdomain solves of one problem run on one "
@@ -158,6 +197,15 @@ def main():
     import torch
     from paper_1401_4969_amd import binding as B
 
+    if args.calibrate_copy:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration: 4 copies of {src.numel() * 8} bytes", file=sys.stderr,
+              flush=True)
+        del src, dst
     prob, okw = workload(args.workload)
     opts = B.default_opts(timing=1, block=args.block, **okw)
     s = B.Solver(prob, opts)
@@ -195,9 +243,17 @@ def main():
     shapes = subdomain_shapes(prob)
     cw, ch = max(shapes, key=lambda x: x[0] * x[1])
     S0 = tile_levels(cw, ch, m)[0]
-    per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu) / S0
-    bytes_launch = per_dof_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
+    if opts.precision == 0:
+        kernel = "k_local_pcg64"
+        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu) / S0
+        bytes_launch = per_dof_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
+    else:
+        kernel = "k_local_mixed"
+        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4) / S0
+        bytes_launch = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
+                                   st["n_tile_dofs"])
     achieved = bytes_launch / (pcg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kernel, prob.name)
 
     gold = golden_lambda(args.workload.replace("mixed", ""))
     lam_err = None
@@ -225,10 +281,11 @@ def main():
         "lambda_rel_err_vs_oracle": lam_err,
         "local_solve": {"ms": pcg_ms, "items": st["n_items"], "tile_dofs": st["n_tile_dofs"],
                         "it_max": st["it_max"], "it_sum": st["it_sum"],
-                        "relres_max": st["relres_max"], "bytes_per_tile_dof_iter": per_dof_it},
-        "roofline": {"kernel": "k_local_pcg64", "bound": "hbm", "achieved": achieved,
+                        "refine_max": st["refine_max"], "relres_max": st["relres_max"],
+                        "bytes_per_tile_dof_iter": per_dof_it, "bytes_per_launch": bytes_launch},
+        "roofline": {"kernel": kernel, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": traffic},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)

@@ -104,6 +104,7 @@ typedef struct mlc_level_stats {
   int64_t it_dofs;      /* sum over local solves of iterations x unknowns */
   double relres_max;    /* max final ||r||/||b|| over the local solves */
   double lambda[8];     /* the q eigenvalues after the step */
+  int64_t refine_dofs;  /* mixed precision: sum over local solves of refinement steps x unknowns */
 } mlc_level_stats;
 
 /* Fill opts with the defaults listed above. */

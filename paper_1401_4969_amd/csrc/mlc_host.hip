@@ -601,6 +601,7 @@ mlc_status mlc_level_correct(mlc_ctx* c, mlc_level_stats* stt) {
     stt->refine_max = std::max(stt->refine_max, is[k].refine);
     stt->it_sum += is[k].iters;
     stt->it_dofs += (int64_t)is[k].iters * S;
+    stt->refine_dofs += (int64_t)is[k].refine * S;
     stt->relres_max = std::max(stt->relres_max, is[k].relres);
   }
   for (int i = 0; i < g.q; ++i) stt->lambda[i] = lam[c->cur * MLC_MAX_Q + i];
