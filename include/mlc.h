@@ -161,6 +161,68 @@ mlc_status mlc_phase_times(struct mlc_ctx* ctx, double* ms, int32_t n);
 
 mlc_status mlc_destroy(struct mlc_ctx* ctx);
 
+/* ---- Batches: many independent problems, one launch per kernel and level step ----
+ *
+ * All problems of a batch share q (n_eig) and coef_kind; domains, meshes, subdomain
+ * grids, coefficients and numbers of levels may differ.  Step s produces level s of every
+ * problem with n_refine >= s; the local solves of all those problems (of uneven sizes)
+ * run in one launch, ordered largest tile first.  Same conventions as above: caller-owned
+ * workspace, borrowed stream, statuses. */
+typedef struct mlc_batch mlc_batch;
+
+/* Workspace bytes for n problems (descs[0..n-1]); MLC_EINVAL as for mlc_create, or for
+ * n < 1 or mixed q / coef_kind. */
+mlc_status mlc_batch_workspace_size(int32_t n, const mlc_problem_desc* descs,
+                                    const mlc_solver_opts* opts, size_t* bytes);
+
+/* Create a batch context over a caller-owned device workspace (256-byte aligned). */
+mlc_status mlc_batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solver_opts* opts,
+                            void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                            mlc_batch** out);
+
+/* Algorithm 4.2 step 1 for every problem (as mlc_coarse_setup).  Synchronises. */
+mlc_status mlc_batch_setup(mlc_batch* b);
+
+/* One level step for every problem that has it.  use_graph = 1 captures the step's
+ * launch sequence in a hipGraph on first use and replays it afterwards.  MLC_ESTATE
+ * before setup or after the last step. */
+mlc_status mlc_batch_step(mlc_batch* b, int32_t use_graph);
+
+/* All remaining steps (Algorithm 4.2 for every problem). */
+mlc_status mlc_batch_run(mlc_batch* b, int32_t use_graph);
+
+/* Step back once (the previous eigenpairs are still held), so a step can be repeated. */
+mlc_status mlc_batch_rewind(mlc_batch* b);
+
+/* Current step (0 after setup). */
+mlc_status mlc_batch_current_step(const mlc_batch* b, int32_t* step);
+
+/* Eigenpairs of problem i at its current level (min(step, n_refine_i)): lambda_host[q]
+ * (host, may be NULL), u_dev (device, q*(N+1)^2, may be NULL), signed as in
+ * mlc_get_eigenpairs.  Synchronises when lambda_host != NULL. */
+mlc_status mlc_batch_get(mlc_batch* b, int32_t i, double* lambda_host, double* u_dev);
+
+/* Statistics of the last step aggregated over the batch (synchronises): st->level is the
+ * step, n_dofs the interior nodes of all problems at that step, lambda[] unused. */
+mlc_status mlc_batch_step_stats(mlc_batch* b, mlc_level_stats* st);
+
+/* Autotuner: for every step, time the local-solve launch with 256, 512 and 1024 threads
+ * per workgroup (HIP events, full runs from level 0) and keep the fastest; blocks_out
+ * (may be NULL) receives the choice per step (index s-1, n entries).  Leaves the batch at
+ * step 0.  Synchronises. */
+mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n);
+
+/* Use these workgroup sizes per step (index s-1; 256, 512 or 1024), e.g. a cached
+ * autotuner result.  Drops captured graphs. */
+mlc_status mlc_batch_set_blocks(mlc_batch* b, const int32_t* blocks, int32_t n);
+
+/* As mlc_phase_times, for steps run without graphs. */
+mlc_status mlc_batch_phase_times(mlc_batch* b, double* ms, int32_t n);
+
+mlc_status mlc_batch_destroy(mlc_batch* b);
+const char* mlc_batch_last_error(const mlc_batch* b);
+
+
 const char* mlc_status_str(mlc_status s);
 /* Message of the last failure on this context (never NULL; "" if none). */
 const char* mlc_last_error(const struct mlc_ctx* ctx);

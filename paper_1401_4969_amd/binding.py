@@ -26,6 +26,10 @@ EXPORTS = [
     "mlc_default_opts", "mlc_workspace_size", "mlc_create", "mlc_coarse_setup",
     "mlc_level_correct", "mlc_run", "mlc_rewind", "mlc_current_level", "mlc_get_eigenpairs",
     "mlc_set_state", "mlc_phase_times", "mlc_destroy", "mlc_status_str", "mlc_last_error",
+    "mlc_batch_workspace_size", "mlc_batch_create", "mlc_batch_setup", "mlc_batch_step",
+    "mlc_batch_run", "mlc_batch_rewind", "mlc_batch_current_step", "mlc_batch_get",
+    "mlc_batch_step_stats", "mlc_batch_autotune", "mlc_batch_set_blocks",
+    "mlc_batch_phase_times", "mlc_batch_destroy", "mlc_batch_last_error",
 ]
 
 
@@ -94,8 +98,25 @@ def load_library() -> C.CDLL:
     lib.mlc_status_str.restype = C.c_char_p
     lib.mlc_last_error.argtypes = [P]
     lib.mlc_last_error.restype = C.c_char_p
+    lib.mlc_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(ProblemDesc),
+                                             C.POINTER(SolverOpts), C.POINTER(C.c_size_t)]
+    lib.mlc_batch_create.argtypes = [C.c_int32, C.POINTER(ProblemDesc), C.POINTER(SolverOpts), P,
+                                     C.c_size_t, P, C.POINTER(P)]
+    lib.mlc_batch_setup.argtypes = [P]
+    lib.mlc_batch_step.argtypes = [P, C.c_int32]
+    lib.mlc_batch_run.argtypes = [P, C.c_int32]
+    lib.mlc_batch_rewind.argtypes = [P]
+    lib.mlc_batch_current_step.argtypes = [P, C.POINTER(C.c_int32)]
+    lib.mlc_batch_get.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P]
+    lib.mlc_batch_step_stats.argtypes = [P, C.POINTER(LevelStats)]
+    lib.mlc_batch_autotune.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    lib.mlc_batch_set_blocks.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    lib.mlc_batch_phase_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
+    lib.mlc_batch_destroy.argtypes = [P]
+    lib.mlc_batch_last_error.argtypes = [P]
+    lib.mlc_batch_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("mlc_status_str", "mlc_last_error"):
+        if name not in ("mlc_status_str", "mlc_last_error", "mlc_batch_last_error"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -247,3 +268,123 @@ def solve(prob, opts: Optional[SolverOpts] = None, device: str = "cuda:0", stats
         levels.append(lam)
     s.close()
     return lam, u, levels, st
+
+
+def batch_workspace_size(probs, opts: Optional[SolverOpts] = None) -> int:
+    lib = load_library()
+    opts = opts or default_opts()
+    descs, _keep = _desc_array(probs)
+    n = C.c_size_t(0)
+    st = lib.mlc_batch_workspace_size(len(probs), descs, C.byref(opts), C.byref(n))
+    if st != MLC_OK:
+        raise MLCError(st, "mlc_batch_workspace_size rejected the batch")
+    return int(n.value)
+
+
+def _desc_array(probs):
+    arr = (ProblemDesc * len(probs))()
+    keep = []
+    for i, p in enumerate(probs):
+        d, k = make_desc(p)
+        arr[i] = d
+        keep.append(k)
+    return arr, keep
+
+
+class BatchSolver:
+    """Many independent problems on one GPU: one launch per kernel and level step."""
+
+    def __init__(self, probs, opts: Optional[SolverOpts] = None, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        self.lib = load_library()
+        self.probs = list(probs)
+        self.opts = opts or default_opts()
+        self.device = torch.device(device)
+        self.q = int(self.probs[0].n_eig)
+        self._descs, self._keep = _desc_array(self.probs)
+        self.ws_bytes = batch_workspace_size(self.probs, self.opts)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.b = C.c_void_p()
+        st = self.lib.mlc_batch_create(len(self.probs), self._descs, C.byref(self.opts),
+                                       C.c_void_p(self.ws.data_ptr()), C.c_size_t(self.ws_bytes),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(self.b))
+        if st != MLC_OK:
+            raise MLCError(st, "mlc_batch_create failed (see stderr)")
+
+    def _check(self, st: int, what: str):
+        if st != MLC_OK:
+            raise MLCError(st, f"{what}: {self.lib.mlc_batch_last_error(self.b).decode()}")
+
+    @property
+    def n_steps(self) -> int:
+        return max(p.n_refine for p in self.probs)
+
+    def setup(self):
+        self._check(self.lib.mlc_batch_setup(self.b), "mlc_batch_setup")
+
+    def step(self, use_graph: bool = False):
+        self._check(self.lib.mlc_batch_step(self.b, int(use_graph)), "mlc_batch_step")
+
+    def run(self, use_graph: bool = False):
+        self._check(self.lib.mlc_batch_run(self.b, int(use_graph)), "mlc_batch_run")
+
+    def rewind(self):
+        self._check(self.lib.mlc_batch_rewind(self.b), "mlc_batch_rewind")
+
+    @property
+    def current_step(self) -> int:
+        v = C.c_int32(0)
+        self._check(self.lib.mlc_batch_current_step(self.b, C.byref(v)), "mlc_batch_current_step")
+        return int(v.value)
+
+    def stats(self) -> dict:
+        s = LevelStats()
+        st = self.lib.mlc_batch_step_stats(self.b, C.byref(s))
+        d = s.as_dict(self.q)
+        if st == MLC_ENOCONV:
+            d["enoconv"] = True
+            return d
+        self._check(st, "mlc_batch_step_stats")
+        return d
+
+    def get(self, i: int, with_vectors: bool = True):
+        import torch
+        lam = np.zeros(self.q)
+        u = None
+        uptr = None
+        if with_vectors:
+            p = self.probs[i]
+            lvl = min(self.current_step, p.n_refine)
+            n1 = (p.n_coarse << lvl) + 1
+            u = torch.empty((self.q, n1, n1), dtype=torch.float64, device=self.device)
+            uptr = C.c_void_p(u.data_ptr())
+        self._check(self.lib.mlc_batch_get(self.b, int(i), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                           uptr), "mlc_batch_get")
+        return lam, u
+
+    def autotune(self) -> List[int]:
+        out = (C.c_int32 * self.n_steps)()
+        self._check(self.lib.mlc_batch_autotune(self.b, out, self.n_steps), "mlc_batch_autotune")
+        return list(out)
+
+    def set_blocks(self, blocks: List[int]):
+        arr = (C.c_int32 * len(blocks))(*blocks)
+        self._check(self.lib.mlc_batch_set_blocks(self.b, arr, len(blocks)), "mlc_batch_set_blocks")
+
+    def phase_times(self) -> List[float]:
+        ms = (C.c_double * 2)()
+        self._check(self.lib.mlc_batch_phase_times(self.b, ms, 2), "mlc_batch_phase_times")
+        return [ms[0], ms[1]]
+
+    def close(self):
+        if self.b:
+            self.lib.mlc_batch_destroy(self.b)
+            self.b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

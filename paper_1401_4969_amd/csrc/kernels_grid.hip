@@ -79,7 +79,8 @@ __device__ __forceinline__ int axis_candidates(const int32_t* bnd, int nb, int g
 
 // a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
 __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const TileItem* items,
-                                                   const char* store, int m) {
+                                                   const int32_t* sub_item, const char* store,
+                                                   int m) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
   const int N = P.n_c << m;
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
     double acc = 0.0, tot = 0.0;
     for (int a = 0; a < nyc; ++a) {
       for (int b = 0; b < nxc; ++b) {
-        const int item = P.sub_item[(iy[a] * P.sub_x + ix[b]) * P.q + i];
+        const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q + i];
         if (item < 0) continue;
         const TileItem& it = items[item];
         const int nx = it.cw * r - 1;
@@ -474,9 +475,10 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
 }
 
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
-                           const char* store, int m, int64_t max_nodes, hipStream_t s) {
+                           const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
+                           hipStream_t s) {
   hipLaunchKernelGGL(k_pou_glue, dim3(nblocks(max_nodes), nprob), dim3(NTG), 0, s, probs, items,
-                     store, m);
+                     sub_item, store, m);
   return hipGetLastError();
 }
 

@@ -26,7 +26,9 @@ struct ProbDev {
   const double* kUL[MLC_MAX_LEVELS + 1];  //                            upper-triangle kappa
   const int32_t* bx;          // sub_x+1 block boundaries in coarse cells
   const int32_t* by;          // sub_y+1
-  const int32_t* sub_item;    // (sub_x*sub_y)*q -> item index in the current item table, -1 dropped
+  int32_t sub_item_off;       // offset of this problem's (sub_x*sub_y)*q block in a step's
+                              // subdomain -> item table (-1 entries: dropped or inactive)
+  int32_t pad0;
   const int32_t* coarse_nodes;  // nH: grid index (on (n_c+1)^2) of coarse dof r
   const int32_t* coarse_index;  // (n_c+1)^2: dof index or -1
   double* u[2];               // eigenvectors, q*(N_L+1)^2 each (ping-pong)

@@ -1,6 +1,11 @@
 // Host side of libmlc: argument checking, geometry tables, workspace layout and the
-// launch sequence of one correction step.  No arithmetic of the method runs here:
-// every step of Algorithms 4.1/4.2 is a kernel on the caller's stream.
+// launch sequence of a correction step.  No arithmetic of the method runs here: every
+// step of Algorithms 4.1/4.2 is a kernel on the caller's stream.
+//
+// Every context is a batch of independent problems (a single-problem context is a batch
+// of one).  Per problem the workspace holds its grids and coarse data; the local-solve
+// item tables, the subdomain -> item maps and the local-solve storage are per level step
+// and shared by all problems, so one launch per kernel serves the whole batch.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -26,23 +31,20 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct SubBox {
-  int id;          // sy * sub_x + sx
-  int D[4];        // x0, x1, y0, y1 (coarse cells)
+  int id;    // sy * sub_x + sx
+  int D[4];  // x0, x1, y0, y1 (coarse cells)
   int Om[4];
 };
 
-// Geometry derived from a problem description (host tables only).
+// Geometry derived from one problem description (host tables only).
 struct Geometry {
-  int L = 0, q = 0, nc = 0, nH = 0, kind = 0, domain = 0;
+  int L = 0, q = 0, nc = 0, nH = 0, kind = 0, domain = 0, sub_x = 1, sub_y = 1, overlap = 1;
   double side = 1.0;
   std::vector<int> bx, by;
-  std::vector<SubBox> subs;              // kept subdomains
+  std::vector<SubBox> subs;     // kept subdomains, largest first
   std::vector<int> coarse_nodes, coarse_index;
-  std::vector<TileItem> items;           // order shared by every level
-  std::vector<int> sub_item;             // (sub_x*sub_y)*q -> item, -1 dropped
-  std::vector<int64_t> inv_off;          // per kept subdomain (doubles)
+  std::vector<int64_t> inv_off; // per kept subdomain (doubles, relative to the problem)
   int64_t inv_total = 0;
-
   int64_t N(int l) const { return (int64_t)nc << l; }
   int64_t nodes(int l) const { return (N(l) + 1) * (N(l) + 1); }
 };
@@ -53,24 +55,8 @@ bool is_dof_host(int domain, int N, int gx, int gy) {
   return true;
 }
 
-mlc_status build_geometry(const mlc_problem_desc* d, const mlc_solver_opts* o, Geometry& g,
-                          std::string& msg) {
-  if (!d || !o) {
-    msg = "null descriptor or options";
-    return MLC_EINVAL;
-  }
-  if (d->domain != 0 && d->domain != 1) { msg = "domain must be 0 or 1"; return MLC_EINVAL; }
-  if (d->coef_kind < 0 || d->coef_kind > 2) { msg = "coef_kind must be 0, 1 or 2"; return MLC_EINVAL; }
-  if (d->n_coarse < 2 || d->n_coarse > 4096) { msg = "n_coarse must be in 2..4096"; return MLC_EINVAL; }
-  if (d->domain == 1 && (d->n_coarse & 1)) { msg = "the L-shape needs an even n_coarse"; return MLC_EINVAL; }
-  if (d->n_refine < 1 || d->n_refine > MLC_MAX_LEVELS) { msg = "n_refine must be in 1..10"; return MLC_EINVAL; }
-  if ((int64_t)d->n_coarse << d->n_refine > 32768) { msg = "finest grid above 32768 cells per side"; return MLC_EINVAL; }
-  if (d->sub_x < 1 || d->sub_x > d->n_coarse || d->sub_y < 1 || d->sub_y > d->n_coarse) {
-    msg = "sub_x and sub_y must be in 1..n_coarse";
-    return MLC_EINVAL;
-  }
-  if (d->overlap < 1 || d->overlap > d->n_coarse) { msg = "overlap must be in 1..n_coarse"; return MLC_EINVAL; }
-  if (d->n_eig < 1 || d->n_eig > MLC_MAX_Q) { msg = "n_eig must be in 1..8"; return MLC_EINVAL; }
+mlc_status check_opts(const mlc_solver_opts* o, std::string& msg) {
+  if (!o) { msg = "null options"; return MLC_EINVAL; }
   if (o->precision != 0 && o->precision != 1) { msg = "precision must be 0 or 1"; return MLC_EINVAL; }
   if (!(o->rtol > 0.0 && o->rtol < 1.0)) { msg = "rtol must be in (0,1)"; return MLC_EINVAL; }
   if (o->max_it < 1 || o->nu < 1 || o->nu > 8 || !(o->omega > 0.0 && o->omega < 1.0)) {
@@ -85,11 +71,31 @@ mlc_status build_geometry(const mlc_problem_desc* d, const mlc_solver_opts* o, G
     msg = "block must be 0, 256, 512 or 1024";
     return MLC_EINVAL;
   }
+  return MLC_OK;
+}
+
+mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& msg) {
+  if (!d) { msg = "null descriptor"; return MLC_EINVAL; }
+  if (d->domain != 0 && d->domain != 1) { msg = "domain must be 0 or 1"; return MLC_EINVAL; }
+  if (d->coef_kind < 0 || d->coef_kind > 2) { msg = "coef_kind must be 0, 1 or 2"; return MLC_EINVAL; }
+  if (d->n_coarse < 2 || d->n_coarse > 4096) { msg = "n_coarse must be in 2..4096"; return MLC_EINVAL; }
+  if (d->domain == 1 && (d->n_coarse & 1)) { msg = "the L-shape needs an even n_coarse"; return MLC_EINVAL; }
+  if (d->n_refine < 1 || d->n_refine > MLC_MAX_LEVELS) { msg = "n_refine must be in 1..10"; return MLC_EINVAL; }
+  if ((int64_t)d->n_coarse << d->n_refine > 32768) { msg = "finest grid above 32768 cells per side"; return MLC_EINVAL; }
+  if (d->sub_x < 1 || d->sub_x > d->n_coarse || d->sub_y < 1 || d->sub_y > d->n_coarse) {
+    msg = "sub_x and sub_y must be in 1..n_coarse";
+    return MLC_EINVAL;
+  }
+  if (d->overlap < 1 || d->overlap > d->n_coarse) { msg = "overlap must be in 1..n_coarse"; return MLC_EINVAL; }
+  if (d->n_eig < 1 || d->n_eig > MLC_MAX_Q) { msg = "n_eig must be in 1..8"; return MLC_EINVAL; }
   g.L = d->n_refine;
   g.q = d->n_eig;
   g.nc = d->n_coarse;
   g.kind = d->coef_kind;
   g.domain = d->domain;
+  g.sub_x = d->sub_x;
+  g.sub_y = d->sub_y;
+  g.overlap = d->overlap;
   g.side = d->domain == 0 ? 1.0 : 2.0;
   const int nc = g.nc;
   if (g.kind != 0) {
@@ -100,7 +106,6 @@ mlc_status build_geometry(const mlc_problem_desc* d, const mlc_solver_opts* o, G
       if (!(k > 0.0) || !std::isfinite(k)) { msg = "kappa must be positive and finite"; return MLC_EINVAL; }
     }
   }
-  // coarse dofs
   g.coarse_index.assign((size_t)(nc + 1) * (nc + 1), -1);
   for (int j = 0; j <= nc; ++j)
     for (int i = 0; i <= nc; ++i)
@@ -131,176 +136,235 @@ mlc_status build_geometry(const mlc_problem_desc* d, const mlc_solver_opts* o, G
       }
       g.subs.push_back(s);
     }
-  if (d->sub_x * d->sub_y * 3 > MLC_MAX_CAND * MLC_MAX_CAND * 1000) { msg = "too many subdomains"; return MLC_EINVAL; }
   // candidate bound of the gluing kernel: blocks reaching a node along one axis
-  {
-    auto max_cand = [&](const std::vector<int>& b) {
-      int best = 0;
-      for (int t = 0; t <= 2 * nc; ++t) {  // half-cell resolution is enough to find maxima
-        int c = 0;
-        for (size_t k = 0; k + 1 < b.size(); ++k)
-          if (2 * b[k] - 2 * ov < t && t < 2 * b[k + 1] + 2 * ov) ++c;
-        best = std::max(best, c);
-      }
-      return best;
-    };
-    if (max_cand(g.bx) > MLC_MAX_CAND || max_cand(g.by) > MLC_MAX_CAND) {
-      msg = "overlap too wide for the subdomain width (more than 8 overlapping blocks)";
-      return MLC_EINVAL;
+  auto max_cand = [&](const std::vector<int>& b) {
+    int best = 0;
+    for (int t = 0; t <= 2 * nc; ++t) {  // half-cell resolution finds the maxima
+      int c = 0;
+      for (size_t k = 0; k + 1 < b.size(); ++k)
+        if (2 * b[k] - 2 * ov < t && t < 2 * b[k + 1] + 2 * ov) ++c;
+      best = std::max(best, c);
     }
+    return best;
+  };
+  if (max_cand(g.bx) > MLC_MAX_CAND || max_cand(g.by) > MLC_MAX_CAND) {
+    msg = "overlap too wide for the subdomain width (more than 8 overlapping blocks)";
+    return MLC_EINVAL;
   }
-  // items: every kept subdomain x every eigenpair, largest tiles first
-  std::vector<SubBox> order = g.subs;
-  std::stable_sort(order.begin(), order.end(), [](const SubBox& a, const SubBox& b) {
+  std::stable_sort(g.subs.begin(), g.subs.end(), [](const SubBox& a, const SubBox& b) {
     return (a.Om[1] - a.Om[0]) * (a.Om[3] - a.Om[2]) > (b.Om[1] - b.Om[0]) * (b.Om[3] - b.Om[2]);
   });
-  g.sub_item.assign((size_t)d->sub_x * d->sub_y * g.q, -1);
-  std::vector<int64_t> inv_of_id((size_t)d->sub_x * d->sub_y, -1);
   for (const SubBox& s : g.subs) {
     const int n = (s.Om[1] - s.Om[0] - 1) * (s.Om[3] - s.Om[2] - 1);
-    inv_of_id[s.id] = g.inv_total;
+    g.inv_off.push_back(g.inv_total);
     g.inv_total += (int64_t)n * n;
   }
-  for (const SubBox& s : order)
-    for (int i = 0; i < g.q; ++i) {
-      TileItem it;
-      std::memset(&it, 0, sizeof(it));
-      it.prob = 0;
-      it.sub = s.id;
-      it.rhs = i;
-      it.cx0 = s.Om[0];
-      it.cy0 = s.Om[2];
-      it.cw = s.Om[1] - s.Om[0];
-      it.ch = s.Om[3] - s.Om[2];
-      it.inv_off = inv_of_id[s.id];
-      g.sub_item[(size_t)s.id * g.q + i] = (int)g.items.size();
-      g.items.push_back(it);
-    }
   return MLC_OK;
 }
 
-// Workspace layout: byte offsets from the workspace base.
-struct Layout {
-  size_t prob, bx, by, sub_item, coarse_nodes, coarse_index, kH;
+// Byte offsets (from the workspace base) of one problem's buffers.
+struct ProbLayout {
+  size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
+      E, info, fg, partials, rr_x, rr_y, rr_t, cH, out_parts;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
-  size_t u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam, E, info, fg, partials, rr_x, rr_y, rr_t,
-      cH, out_parts, stats, inv, store;
-  size_t items[MLC_MAX_LEVELS + 1];
   int64_t rchain_off[MLC_MAX_LEVELS + 1];
-  std::vector<std::vector<int64_t>> item_off;  // [m][item] byte offsets within store
-  size_t store_bytes = 0;
-  size_t total = 0;
+  int64_t inv_base;      // doubles, into the batch inverse region
+  int32_t sub_item_off;  // into every step's subdomain -> item table
 };
 
-void plan_layout(const Geometry& g, int precision, Layout& Lo) {
+// One level step of the batch: its local solves and where their storage lives.
+struct StepTables {
+  std::vector<TileItem> items;
+  std::vector<int32_t> sub_item;
+  size_t items_off = 0, sub_item_off = 0;
+  int64_t max_nodes = 0;         // largest (N_s+1)^2 among the active problems
+  std::vector<int64_t> nodes_l;  // per coarser level l < s: largest (N_l+1)^2
+};
+
+struct Plan {
+  std::vector<Geometry> geo;
+  std::vector<ProbLayout> pl;
+  std::vector<StepTables> steps;  // index s (1..Lmax); steps[0] unused
+  int n = 0, q = 0, kind = 0, Lmax = 0, max_nH = 0, max_nc1sq = 0, precision = 0;
+  size_t probdev = 0, stats = 0, inv = 0, store = 0, store_bytes = 0, total = 0;
+  int64_t max_items = 0, inv_total = 0;
+};
+
+mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_opts* o, Plan& P,
+                     std::string& msg) {
+  if (n < 1 || !descs) { msg = "need at least one problem"; return MLC_EINVAL; }
+  mlc_status st = check_opts(o, msg);
+  if (st != MLC_OK) return st;
+  P.n = n;
+  P.precision = o->precision;
+  P.geo.resize(n);
+  for (int i = 0; i < n; ++i) {
+    st = build_geometry(&descs[i], P.geo[i], msg);
+    if (st != MLC_OK) {
+      if (n > 1) msg = "problem " + std::to_string(i) + ": " + msg;
+      return st;
+    }
+  }
+  P.q = P.geo[0].q;
+  P.kind = P.geo[0].kind;
+  for (const Geometry& g : P.geo) {
+    if (g.q != P.q || g.kind != P.kind) { msg = "all problems of a batch need the same n_eig and coef_kind"; return MLC_EINVAL; }
+    P.Lmax = std::max(P.Lmax, g.L);
+    P.max_nH = std::max(P.max_nH, g.nH);
+    P.max_nc1sq = std::max(P.max_nc1sq, (g.nc + 1) * (g.nc + 1));
+  }
   size_t p = 0;
   auto take = [&](size_t bytes) {
     const size_t at = p;
     p = align_up(p + std::max<size_t>(bytes, 1));
     return at;
   };
-  const size_t q = (size_t)g.q;
-  const size_t nnL = (size_t)g.nodes(g.L);
-  const size_t ncs = (size_t)(g.nc + 1) * (g.nc + 1);
-  const size_t nsub = g.sub_item.size() / q;
-  Lo.prob = take(sizeof(ProbDev));
-  Lo.bx = take(g.bx.size() * 4);
-  Lo.by = take(g.by.size() * 4);
-  Lo.sub_item = take(nsub * q * 4);
-  Lo.coarse_nodes = take((size_t)g.nH * 4);
-  Lo.coarse_index = take(ncs * 4);
-  Lo.kH = take((size_t)g.nc * g.nc * 8);
-  for (int l = 0; l <= g.L; ++l) {
-    Lo.kLR[l] = Lo.kUL[l] = 0;
-    if (g.kind == 2) {
-      const size_t c = (size_t)(g.N(l) * g.N(l)) * 8;
-      Lo.kLR[l] = take(c);
-      Lo.kUL[l] = (l == g.L) ? Lo.kLR[l] : take(c);
+  const size_t q = (size_t)P.q;
+  P.probdev = take((size_t)n * sizeof(ProbDev));
+  P.pl.resize(n);
+  int32_t sub_off = 0;
+  for (int i = 0; i < n; ++i) {
+    const Geometry& g = P.geo[i];
+    ProbLayout& L = P.pl[i];
+    const size_t nnL = (size_t)g.nodes(g.L);
+    const size_t ncs = (size_t)(g.nc + 1) * (g.nc + 1);
+    L.bx = take(g.bx.size() * 4);
+    L.by = take(g.by.size() * 4);
+    L.coarse_nodes = take((size_t)g.nH * 4);
+    L.coarse_index = take(ncs * 4);
+    L.kH = take((size_t)g.nc * g.nc * 8);
+    for (int l = 0; l <= MLC_MAX_LEVELS; ++l) L.kLR[l] = L.kUL[l] = 0;
+    if (g.kind == 2)
+      for (int l = 0; l <= g.L; ++l) {
+        const size_t c = (size_t)(g.N(l) * g.N(l)) * 8;
+        L.kLR[l] = take(c);
+        L.kUL[l] = (l == g.L) ? L.kLR[l] : take(c);
+      }
+    L.u[0] = take(q * nnL * 8);
+    L.u[1] = take(q * nnL * 8);
+    L.lam = take(2 * MLC_MAX_Q * 8);
+    L.ubar = take(q * nnL * 8);
+    L.res = take(q * nnL * 8);
+    L.ut = take(q * nnL * 8);
+    int64_t rc = 0;
+    for (int l = 0; l <= g.L; ++l) {
+      L.rchain_off[l] = rc;
+      if (l < g.L) rc += (int64_t)(2 * q * g.nodes(l));
     }
+    L.rchain = take((size_t)rc * 8);
+    const size_t nH = (size_t)g.nH;
+    L.Kc = take(nH * nH * 8);
+    L.Mc = take(nH * nH * 8);
+    L.Lam = take(nH * 8);
+    L.E = take(nH * 8);
+    L.info = take(4);
+    L.fg = take(2 * q * nH * 8);
+    L.partials = take(((nnL + 255) / 256) * (2 * q * q + q) * 8);
+    L.rr_x = take(q * (nH + q) * 8);
+    L.rr_y = take(q * nH * 8);
+    L.rr_t = take(q * q * 8);
+    L.cH = take(q * ncs * 8);
+    L.out_parts = take(64 * q * 8);
+    L.inv_base = P.inv_total;
+    P.inv_total += g.inv_total;
+    L.sub_item_off = sub_off;
+    sub_off += g.sub_x * g.sub_y * (int)q;
   }
-  Lo.u[0] = take(q * nnL * 8);
-  Lo.u[1] = take(q * nnL * 8);
-  Lo.lam = take(2 * MLC_MAX_Q * 8);
-  Lo.ubar = take(q * nnL * 8);
-  Lo.res = take(q * nnL * 8);
-  Lo.ut = take(q * nnL * 8);
-  int64_t rc = 0;
-  for (int l = 0; l < g.L; ++l) {
-    Lo.rchain_off[l] = rc;
-    rc += (int64_t)(2 * q * g.nodes(l));
-  }
-  Lo.rchain_off[g.L] = rc;
-  Lo.rchain = take((size_t)rc * 8);
-  const size_t nH = (size_t)g.nH;
-  Lo.Kc = take(nH * nH * 8);
-  Lo.Mc = take(nH * nH * 8);
-  Lo.Lam = take(nH * 8);
-  Lo.E = take(nH * 8);
-  Lo.info = take(4);
-  Lo.fg = take(2 * q * nH * 8);
-  const size_t nblk = (nnL + 255) / 256;
-  Lo.partials = take(nblk * (2 * q * q + q) * 8);
-  Lo.rr_x = take(q * (nH + q) * 8);
-  Lo.rr_y = take(q * nH * 8);
-  Lo.rr_t = take(q * q * 8);
-  Lo.cH = take(q * ncs * 8);
-  Lo.out_parts = take(64 * q * 8);
-  Lo.stats = take(g.items.size() * sizeof(ItemStat));
-  Lo.inv = take((size_t)g.inv_total * 8);
-  for (int m = 0; m <= g.L; ++m) Lo.items[m] = take(g.items.size() * sizeof(TileItem));
-  Lo.item_off.assign(g.L + 1, std::vector<int64_t>(g.items.size(), 0));
-  size_t sb = 0;
-  for (int m = 1; m <= g.L; ++m) {
+  // per-step item tables: every active problem's subdomains x eigenpairs, largest first
+  P.steps.assign(P.Lmax + 1, StepTables());
+  size_t store_bytes = 0;
+  for (int s = 1; s <= P.Lmax; ++s) {
+    StepTables& T = P.steps[s];
+    T.sub_item.assign((size_t)sub_off, -1);
+    T.nodes_l.assign(s, 0);
+    std::vector<TileItem> all;
+    for (int i = 0; i < n; ++i) {
+      const Geometry& g = P.geo[i];
+      if (g.L < s) continue;
+      T.max_nodes = std::max(T.max_nodes, g.nodes(s));
+      for (int l = 0; l < s; ++l) T.nodes_l[l] = std::max(T.nodes_l[l], g.nodes(l));
+      for (size_t k = 0; k < g.subs.size(); ++k) {
+        const SubBox& sb = g.subs[k];
+        for (int r = 0; r < P.q; ++r) {
+          TileItem it;
+          std::memset(&it, 0, sizeof(it));
+          it.prob = i;
+          it.sub = sb.id;
+          it.rhs = r;
+          it.cx0 = sb.Om[0];
+          it.cy0 = sb.Om[2];
+          it.cw = sb.Om[1] - sb.Om[0];
+          it.ch = sb.Om[3] - sb.Om[2];
+          it.inv_off = P.pl[i].inv_base + g.inv_off[k];
+          all.push_back(it);
+        }
+      }
+    }
+    std::stable_sort(all.begin(), all.end(), [](const TileItem& a, const TileItem& b) {
+      return a.cw * a.ch > b.cw * b.ch;
+    });
     size_t o = 0;
-    for (size_t k = 0; k < g.items.size(); ++k) {
-      Lo.item_off[m][k] = (int64_t)o;
-      const TileItem& it = g.items[k];
-      const int64_t b = precision == 0 ? item_bytes_fp64(it.cw, it.ch, m)
-                                       : item_bytes_mixed(it.cw, it.ch, m);
+    for (size_t k = 0; k < all.size(); ++k) {
+      TileItem& it = all[k];
+      it.off = (int64_t)o;
+      const int64_t b = P.precision == 0 ? item_bytes_fp64(it.cw, it.ch, s)
+                                         : item_bytes_mixed(it.cw, it.ch, s);
       o = align_up(o + (size_t)b);
+      T.sub_item[(size_t)P.pl[it.prob].sub_item_off + (size_t)it.sub * P.q + it.rhs] = (int32_t)k;
     }
-    sb = std::max(sb, o);
+    store_bytes = std::max(store_bytes, o);
+    T.items = all;
+    P.max_items = std::max<int64_t>(P.max_items, (int64_t)all.size());
+    T.items_off = take(all.size() * sizeof(TileItem));
+    T.sub_item_off = take(T.sub_item.size() * 4);
   }
-  Lo.store_bytes = sb;
-  Lo.store = take(sb);
-  Lo.total = p;
+  P.stats = take((size_t)P.max_items * sizeof(ItemStat));
+  P.inv = take((size_t)P.inv_total * 8);
+  P.store_bytes = store_bytes;
+  P.store = take(store_bytes);
+  P.total = p;
+  return MLC_OK;
 }
 
 }  // namespace
 
-struct mlc_ctx {
-  mlc_problem_desc d{};
+struct mlc_batch {
+  Plan plan;
   mlc_solver_opts o{};
-  std::vector<double> kappa;
-  Geometry g;
-  Layout lo;
+  std::vector<std::vector<double>> kappa;
+  std::vector<ProbDev> hp;
   hipStream_t st = nullptr;
   char* ws = nullptr;
-  size_t ws_bytes = 0;
-  ProbDev hp{};
   ProbDev* dprob = nullptr;
-  std::vector<std::vector<TileItem>> items_lv;  // host copies uploaded per level
-  int level = -1, cur = 0;
-  bool setup = false, can_rewind = false;
+  int step = -1;              // current step (-1 before setup)
+  bool can_rewind = false;
+  std::vector<int> shift;     // per problem: eigenvector buffer = (level + shift) & 1
+  std::vector<int> blocks;    // workgroup size of the local solves per step (index s)
+  std::vector<hipGraphExec_t> graphs;  // per step
+  std::vector<hipGraph_t> graph_defs;
+  hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
   std::string err;
   rocblas_handle rb = nullptr;
   std::vector<hipEvent_t> ev_free;
   std::vector<std::array<hipEvent_t, 4>> ev_pending;
-  int nt = 1024;
+};
+
+struct mlc_ctx {
+  mlc_batch* b = nullptr;
 };
 
 namespace {
 
-#define MLC_HIP(ctx, expr)                                                        \
+#define MLC_HIP(bt, expr)                                                         \
   do {                                                                            \
     hipError_t e_ = (expr);                                                       \
     if (e_ != hipSuccess) {                                                       \
-      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+      (bt)->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
       return MLC_EHIP;                                                            \
     }                                                                             \
   } while (0)
 
-hipEvent_t get_event(mlc_ctx* c) {
+hipEvent_t get_event(mlc_batch* c) {
   if (!c->ev_free.empty()) {
     hipEvent_t e = c->ev_free.back();
     c->ev_free.pop_back();
@@ -309,6 +373,372 @@ hipEvent_t get_event(mlc_ctx* c) {
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
+}
+
+void drop_graphs(mlc_batch* b) {
+  for (auto& g : b->graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& g : b->graph_defs)
+    if (g) (void)hipGraphDestroy(g);
+  std::fill(b->graphs.begin(), b->graphs.end(), nullptr);
+  std::fill(b->graph_defs.begin(), b->graph_defs.end(), nullptr);
+}
+
+int problem_level(const mlc_batch* b, int i) { return std::min(b->step, b->plan.geo[i].L); }
+
+mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solver_opts* o,
+                        void* ws, size_t bytes, void* stream, mlc_batch** out) {
+  if (!out) return MLC_EINVAL;
+  *out = nullptr;
+  mlc_batch* b = new (std::nothrow) mlc_batch();
+  if (!b) return MLC_ENOMEM;
+  mlc_status s = make_plan(n, descs, o, b->plan, b->err);
+  if (s != MLC_OK) {
+    std::fprintf(stderr, "mlc: %s\n", b->err.c_str());
+    delete b;
+    return s;
+  }
+  const Plan& P = b->plan;
+  if (!ws || bytes < P.total || ((uintptr_t)ws % kAlign) != 0) {
+    std::fprintf(stderr, "mlc: workspace missing, misaligned or smaller than %zu bytes\n", P.total);
+    delete b;
+    return ws && bytes < P.total ? MLC_ENOMEM : MLC_EINVAL;
+  }
+  b->o = *o;
+  b->st = (hipStream_t)stream;
+  b->ws = (char*)ws;
+  char* w = b->ws;
+  b->shift.assign(n, 0);
+  b->blocks.assign(P.Lmax + 1, o->block ? o->block : 1024);
+  b->graphs.assign(P.Lmax + 1, nullptr);
+  b->graph_defs.assign(P.Lmax + 1, nullptr);
+  b->kappa.resize(n);
+  b->hp.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const Geometry& g = P.geo[i];
+    const ProbLayout& L = P.pl[i];
+    if (g.kind == 1) b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)g.nc * g.nc);
+    if (g.kind == 0) b->kappa[i].assign((size_t)g.nc * g.nc, 1.0);
+    if (g.kind == 2) b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(g.N(g.L) * g.N(g.L)));
+    ProbDev& D = b->hp[i];
+    std::memset(&D, 0, sizeof(D));
+    D.domain = g.domain;
+    D.n_c = g.nc;
+    D.L = g.L;
+    D.q = g.q;
+    D.coef_kind = g.kind;
+    D.sub_x = g.sub_x;
+    D.sub_y = g.sub_y;
+    D.overlap = g.overlap;
+    D.nH = g.nH;
+    D.side = g.side;
+    D.kH = (const double*)(w + L.kH);
+    for (int l = 0; l <= g.L; ++l) {
+      D.kLR[l] = g.kind == 2 ? (const double*)(w + L.kLR[l]) : nullptr;
+      D.kUL[l] = g.kind == 2 ? (const double*)(w + L.kUL[l]) : nullptr;
+    }
+    D.bx = (const int32_t*)(w + L.bx);
+    D.by = (const int32_t*)(w + L.by);
+    D.sub_item_off = L.sub_item_off;
+    D.coarse_nodes = (const int32_t*)(w + L.coarse_nodes);
+    D.coarse_index = (const int32_t*)(w + L.coarse_index);
+    D.u[0] = (double*)(w + L.u[0]);
+    D.u[1] = (double*)(w + L.u[1]);
+    D.lam = (double*)(w + L.lam);
+    D.ubar = (double*)(w + L.ubar);
+    D.res = (double*)(w + L.res);
+    D.ut = (double*)(w + L.ut);
+    D.rchain = (double*)(w + L.rchain);
+    for (int l = 0; l <= g.L; ++l) D.rchain_off[l] = L.rchain_off[l];
+    D.Kc = (double*)(w + L.Kc);
+    D.V = D.Kc;
+    D.Mc = (double*)(w + L.Mc);
+    D.VT = D.Mc;
+    D.Lam = (double*)(w + L.Lam);
+    D.fg = (double*)(w + L.fg);
+    D.partials = (double*)(w + L.partials);
+    D.nparts = (int)((g.nodes(g.L) + 255) / 256);
+    D.rr_x = (double*)(w + L.rr_x);
+    D.rr_y = (double*)(w + L.rr_y);
+    D.rr_t = (double*)(w + L.rr_t);
+    D.cH_grid = (double*)(w + L.cH);
+    D.sum_parts = (double*)(w + L.out_parts);
+  }
+  b->dprob = (ProbDev*)(w + P.probdev);
+  hipStream_t st = b->st;
+  auto up = [&](size_t dst, const void* src, size_t nbytes) -> bool {
+    return nbytes == 0 ||
+           hipMemcpyAsync(w + dst, src, nbytes, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  bool ok = true;
+  for (int i = 0; i < n && ok; ++i) {
+    const Geometry& g = P.geo[i];
+    const ProbLayout& L = P.pl[i];
+    ok = ok && up(L.bx, g.bx.data(), g.bx.size() * 4);
+    ok = ok && up(L.by, g.by.data(), g.by.size() * 4);
+    ok = ok && up(L.coarse_nodes, g.coarse_nodes.data(), g.coarse_nodes.size() * 4);
+    ok = ok && up(L.coarse_index, g.coarse_index.data(), g.coarse_index.size() * 4);
+    if (g.kind == 2)
+      ok = ok && up(L.kLR[g.L], b->kappa[i].data(), b->kappa[i].size() * 8);
+    else
+      ok = ok && up(L.kH, b->kappa[i].data(), b->kappa[i].size() * 8);
+  }
+  for (int s = 1; s <= P.Lmax && ok; ++s) {
+    const StepTables& T = P.steps[s];
+    ok = ok && up(T.items_off, T.items.data(), T.items.size() * sizeof(TileItem));
+    ok = ok && up(T.sub_item_off, T.sub_item.data(), T.sub_item.size() * 4);
+  }
+  ok = ok && up(P.probdev, b->hp.data(), b->hp.size() * sizeof(ProbDev));
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    std::fprintf(stderr, "mlc: upload of the geometry tables failed\n");
+    delete b;
+    return MLC_EHIP;
+  }
+  *out = b;
+  return MLC_OK;
+}
+
+mlc_status batch_setup(mlc_batch* b) {
+  const Plan& P = b->plan;
+  char* w = b->ws;
+  hipStream_t st = b->st;
+  drop_graphs(b);
+  for (int i = 0; i < P.n; ++i) {
+    const Geometry& g = P.geo[i];
+    const ProbLayout& L = P.pl[i];
+    if (g.kind == 2)  // coefficients on every level: children means
+      for (int l = g.L - 1; l >= 0; --l)
+        MLC_HIP(b, launch_coarsen_kappa(b->hp[i].kLR[l + 1], b->hp[i].kUL[l + 1],
+                                        (double*)(w + L.kLR[l]), (double*)(w + L.kUL[l]),
+                                        (int)g.N(l), st));
+    const size_t nH = (size_t)g.nH;
+    MLC_HIP(b, hipMemsetAsync(w + L.Kc, 0, nH * nH * 8, st));
+    MLC_HIP(b, hipMemsetAsync(w + L.Mc, 0, nH * nH * 8, st));
+  }
+  MLC_HIP(b, launch_coarse_matrices(P.kind, b->dprob, P.n, P.max_nH, st));
+  if (!b->rb && rocblas_create_handle(&b->rb) != rocblas_status_success) {
+    b->err = "rocblas_create_handle failed";
+    return MLC_EHIP;
+  }
+  if (rocblas_set_stream(b->rb, st) != rocblas_status_success) {
+    b->err = "rocblas_set_stream failed";
+    return MLC_EHIP;
+  }
+  // Algorithm 4.2 step 1 on V_0H: K_H V = M_H V Lambda, V^T M_H V = I (full spectrum)
+  for (int i = 0; i < P.n; ++i) {
+    const Geometry& g = P.geo[i];
+    const ProbLayout& L = P.pl[i];
+    rocblas_status rs = rocsolver_dsygvd(b->rb, rocblas_eform_ax, rocblas_evect_original,
+                                         rocblas_fill_upper, g.nH, (double*)(w + L.Kc), g.nH,
+                                         (double*)(w + L.Mc), g.nH, (double*)(w + L.Lam),
+                                         (double*)(w + L.E), (rocblas_int*)(w + L.info));
+    if (rs != rocblas_status_success) {
+      b->err = std::string("rocsolver_dsygvd: ") + rocblas_status_to_string(rs);
+      return MLC_EHIP;
+    }
+  }
+  MLC_HIP(b, launch_transpose_v(b->dprob, P.n, P.max_nH, st));
+  MLC_HIP(b, launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, st));
+  MLC_HIP(b, launch_tile_inverse(P.kind, b->dprob, (const TileItem*)(w + P.steps[1].items_off),
+                                 (int)P.steps[1].items.size(), (double*)(w + P.inv), st));
+  MLC_HIP(b, hipStreamSynchronize(st));
+  for (int i = 0; i < P.n; ++i) {
+    int info = 0;
+    MLC_HIP(b, hipMemcpy(&info, w + P.pl[i].info, 4, hipMemcpyDeviceToHost));
+    if (info != 0) {
+      b->err = "coarse generalized eigensolve failed (problem " + std::to_string(i) + ", info " +
+               std::to_string(info) + ")";
+      return MLC_EHIP;
+    }
+  }
+  b->step = 0;
+  b->can_rewind = false;
+  std::fill(b->shift.begin(), b->shift.end(), 0);
+  return MLC_OK;
+}
+
+// Enqueue one level step s (src/dst: eigenvector buffers of levels s-1 and s).
+mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipStream_t st) {
+  const Plan& P = b->plan;
+  const StepTables& T = P.steps[s];
+  char* w = b->ws;
+  const TileItem* items = (const TileItem*)(w + T.items_off);
+  const int32_t* sub_item = (const int32_t*)(w + T.sub_item_off);
+  const int nitems = (int)T.items.size();
+  std::array<hipEvent_t, 4> ev{};
+  if (timing) {
+    for (auto& e : ev) {
+      e = get_event(b);
+      if (!e) {
+        b->err = "hipEventCreate failed";
+        return MLC_EHIP;
+      }
+    }
+    MLC_HIP(b, hipEventRecord(ev[0], st));
+  }
+  MLC_HIP(b, launch_prolong_residual(P.kind, b->dprob, P.n, s, src, T.max_nodes, st));
+  if (timing) MLC_HIP(b, hipEventRecord(ev[1], st));
+  if (P.precision == 0) {
+    MLC_HIP(b, launch_local_pcg(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
+                                (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
+                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 0, st));
+  } else {
+    MLC_HIP(b, launch_local_mixed(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
+                                  (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
+                                  b->o.rtol, b->o.max_it, b->o.max_refine, b->o.inner_rtol,
+                                  b->o.nu, b->o.omega, st));
+  }
+  if (timing) MLC_HIP(b, hipEventRecord(ev[2], st));
+  MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, st));
+  MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, st));
+  for (int l = s - 1; l >= 0; --l)
+    MLC_HIP(b, launch_restrict(b->dprob, P.n, l, s, T.nodes_l[l], st));
+  MLC_HIP(b, launch_rr_project(b->dprob, P.n, P.max_nH, st));
+  MLC_HIP(b, launch_rr_solve(P.q, b->dprob, P.n, s, P.max_nH, dst, st));
+  MLC_HIP(b, launch_rr_combine(b->dprob, P.n, P.max_nc1sq, st));
+  MLC_HIP(b, launch_assemble(b->dprob, P.n, s, dst, T.max_nodes, st));
+  if (timing) {
+    MLC_HIP(b, hipEventRecord(ev[3], st));
+    b->ev_pending.push_back(ev);
+  }
+  return MLC_OK;
+}
+
+mlc_status batch_step(mlc_batch* b, int use_graph) {
+  const Plan& P = b->plan;
+  if (b->step < 0 || b->step >= P.Lmax) {
+    b->err = "a step needs setup and a level below the finest";
+    return MLC_ESTATE;
+  }
+  const int s = b->step + 1;
+  // every problem stepping here holds level s-1 in buffer (s-1+shift)&1; the shift is
+  // zero except after mlc_set_state on a single-problem context
+  const int src = (s - 1 + b->shift[0]) & 1, dst = 1 - src;
+  if (use_graph) {
+    if (!b->graphs[s]) {
+      // capture on a private stream (default priority); the instantiated graph is then
+      // launched on the caller's stream, which orders it with the caller's work
+      if (!b->cap) MLC_HIP(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+      MLC_HIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      mlc_status e = enqueue_step(b, s, src, dst, false, b->cap);
+      hipGraph_t g = nullptr;
+      hipError_t he = hipStreamEndCapture(b->cap, &g);
+      if (e != MLC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+      }
+      if (he != hipSuccess) {
+        b->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(he);
+        return MLC_EHIP;
+      }
+      hipGraphExec_t ex = nullptr;
+      he = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (he != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        b->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(he);
+        return MLC_EHIP;
+      }
+      b->graph_defs[s] = g;
+      b->graphs[s] = ex;
+    }
+    MLC_HIP(b, hipGraphLaunch(b->graphs[s], b->st));
+  } else {
+    mlc_status e = enqueue_step(b, s, src, dst, b->o.timing != 0, b->st);
+    if (e != MLC_OK) return e;
+  }
+  b->step = s;
+  b->can_rewind = true;
+  return MLC_OK;
+}
+
+mlc_status step_stats(mlc_batch* b, mlc_level_stats* stt) {
+  const Plan& P = b->plan;
+  const int s = b->step;
+  if (s < 1) {
+    b->err = "no step has run";
+    return MLC_ESTATE;
+  }
+  const StepTables& T = P.steps[s];
+  MLC_HIP(b, hipStreamSynchronize(b->st));
+  std::vector<ItemStat> is(T.items.size());
+  MLC_HIP(b, hipMemcpy(is.data(), b->ws + P.stats, is.size() * sizeof(ItemStat),
+                       hipMemcpyDeviceToHost));
+  std::memset(stt, 0, sizeof(*stt));
+  stt->level = s;
+  stt->n_items = (int)T.items.size();
+  for (int i = 0; i < P.n; ++i) {
+    const Geometry& g = P.geo[i];
+    if (g.L < s) continue;
+    const int N = (int)g.N(s);
+    for (int j = 1; j < N; ++j)
+      for (int x = 1; x < N; ++x) stt->n_dofs += is_dof_host(g.domain, N, x, j) ? 1 : 0;
+    stt->h = g.side / (double)N;
+  }
+  for (size_t k = 0; k < T.items.size(); ++k) {
+    const TileItem& it = T.items[k];
+    const int64_t S = (int64_t)(it.cw * (1 << s) - 1) * (it.ch * (1 << s) - 1);
+    stt->n_tile_dofs += S;
+    stt->it_max = std::max(stt->it_max, is[k].iters);
+    stt->refine_max = std::max(stt->refine_max, is[k].refine);
+    stt->it_sum += is[k].iters;
+    stt->it_dofs += (int64_t)is[k].iters * S;
+    stt->refine_dofs += (int64_t)is[k].refine * S;
+    stt->relres_max = std::max(stt->relres_max, is[k].relres);
+  }
+  if (stt->relres_max > b->o.rtol * 1.0000001) {
+    b->err = "a local solve did not converge within max_it";
+    return MLC_ENOCONV;
+  }
+  return MLC_OK;
+}
+
+mlc_status batch_get(mlc_batch* b, int i, double* lam_host, double* u_dev) {
+  const Plan& P = b->plan;
+  if (b->step < 0) {
+    b->err = "no eigenpairs before setup";
+    return MLC_ESTATE;
+  }
+  if (i < 0 || i >= P.n) return MLC_EINVAL;
+  const Geometry& g = P.geo[i];
+  const int lvl = problem_level(b, i);
+  const int buf = (lvl + b->shift[i]) & 1;
+  if (u_dev)
+    MLC_HIP(b, launch_output_signed(b->hp[i].u[buf], g.nodes(lvl), g.q,
+                                    (double*)(b->ws + P.pl[i].out_parts), u_dev, b->st));
+  if (lam_host) {
+    MLC_HIP(b, hipStreamSynchronize(b->st));
+    MLC_HIP(b, hipMemcpy(lam_host, b->ws + P.pl[i].lam + (size_t)buf * MLC_MAX_Q * 8,
+                         (size_t)g.q * 8, hipMemcpyDeviceToHost));
+  }
+  return MLC_OK;
+}
+
+mlc_status phase_times(mlc_batch* b, double* ms, int32_t n) {
+  MLC_HIP(b, hipStreamSynchronize(b->st));
+  double acc[2] = {0.0, 0.0};
+  for (auto& ev : b->ev_pending) {
+    float a = 0.f, t = 0.f;
+    MLC_HIP(b, hipEventElapsedTime(&a, ev[1], ev[2]));
+    MLC_HIP(b, hipEventElapsedTime(&t, ev[0], ev[3]));
+    acc[0] += a;
+    acc[1] += t;
+    for (auto e : ev) b->ev_free.push_back(e);
+  }
+  b->ev_pending.clear();
+  for (int i = 0; ms && i < n; ++i) ms[i] = i < 2 ? acc[i] : 0.0;
+  return MLC_OK;
+}
+
+void batch_destroy(mlc_batch* b) {
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  drop_graphs(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (auto& ev : b->ev_pending)
+    for (auto e : ev) b->ev_free.push_back(e);
+  for (auto e : b->ev_free) (void)hipEventDestroy(e);
+  if (b->rb) rocblas_destroy_handle(b->rb);
+  delete b;
 }
 
 }  // namespace
@@ -329,15 +759,15 @@ mlc_status mlc_default_opts(mlc_solver_opts* o) {
   return MLC_OK;
 }
 
+// ---------------- single problem ----------------
+
 mlc_status mlc_workspace_size(const mlc_problem_desc* d, const mlc_solver_opts* o, size_t* bytes) {
   if (!bytes) return MLC_EINVAL;
-  Geometry g;
+  Plan P;
   std::string msg;
-  mlc_status s = build_geometry(d, o, g, msg);
+  mlc_status s = make_plan(1, d, o, P, msg);
   if (s != MLC_OK) return s;
-  Layout lo;
-  plan_layout(g, o->precision, lo);
-  *bytes = lo.total;
+  *bytes = P.total;
   return MLC_OK;
 }
 
@@ -345,278 +775,47 @@ mlc_status mlc_create(const mlc_problem_desc* d, const mlc_solver_opts* o, void*
                       void* stream, mlc_ctx** out) {
   if (!out) return MLC_EINVAL;
   *out = nullptr;
+  mlc_batch* b = nullptr;
+  mlc_status s = batch_create(1, d, o, ws, bytes, stream, &b);
+  if (s != MLC_OK) return s;
   mlc_ctx* c = new (std::nothrow) mlc_ctx();
-  if (!c) return MLC_ENOMEM;
-  mlc_status s = build_geometry(d, o, c->g, c->err);
-  if (s != MLC_OK) {
-    std::fprintf(stderr, "mlc_create: %s\n", c->err.c_str());
-    delete c;
-    return s;
+  if (!c) {
+    batch_destroy(b);
+    return MLC_ENOMEM;
   }
-  plan_layout(c->g, o->precision, c->lo);
-  if (!ws || bytes < c->lo.total || ((uintptr_t)ws % kAlign) != 0) {
-    std::fprintf(stderr, "mlc_create: workspace missing, misaligned or smaller than %zu bytes\n",
-                 c->lo.total);
-    delete c;
-    return ws && bytes < c->lo.total ? MLC_ENOMEM : MLC_EINVAL;
-  }
-  c->d = *d;
-  c->o = *o;
-  c->st = (hipStream_t)stream;
-  c->ws = (char*)ws;
-  c->ws_bytes = bytes;
-  c->nt = o->block ? o->block : 1024;
-  const Geometry& g = c->g;
-  const Layout& L = c->lo;
-  char* b = c->ws;
-  if (g.kind == 1) c->kappa.assign(d->kappa, d->kappa + (size_t)g.nc * g.nc);
-  if (g.kind == 0) c->kappa.assign((size_t)g.nc * g.nc, 1.0);
-  if (g.kind == 2) c->kappa.assign(d->kappa, d->kappa + (size_t)(g.N(g.L) * g.N(g.L)));
-  ProbDev& P = c->hp;
-  std::memset(&P, 0, sizeof(P));
-  P.domain = g.domain;
-  P.n_c = g.nc;
-  P.L = g.L;
-  P.q = g.q;
-  P.coef_kind = g.kind;
-  P.sub_x = d->sub_x;
-  P.sub_y = d->sub_y;
-  P.overlap = d->overlap;
-  P.nH = g.nH;
-  P.side = g.side;
-  P.kH = (const double*)(b + L.kH);
-  for (int l = 0; l <= g.L; ++l) {
-    P.kLR[l] = g.kind == 2 ? (const double*)(b + L.kLR[l]) : nullptr;
-    P.kUL[l] = g.kind == 2 ? (const double*)(b + L.kUL[l]) : nullptr;
-  }
-  P.bx = (const int32_t*)(b + L.bx);
-  P.by = (const int32_t*)(b + L.by);
-  P.sub_item = (const int32_t*)(b + L.sub_item);
-  P.coarse_nodes = (const int32_t*)(b + L.coarse_nodes);
-  P.coarse_index = (const int32_t*)(b + L.coarse_index);
-  P.u[0] = (double*)(b + L.u[0]);
-  P.u[1] = (double*)(b + L.u[1]);
-  P.lam = (double*)(b + L.lam);
-  P.ubar = (double*)(b + L.ubar);
-  P.res = (double*)(b + L.res);
-  P.ut = (double*)(b + L.ut);
-  P.rchain = (double*)(b + L.rchain);
-  for (int l = 0; l <= g.L; ++l) P.rchain_off[l] = L.rchain_off[l];
-  P.Kc = (double*)(b + L.Kc);
-  P.V = P.Kc;
-  P.Mc = (double*)(b + L.Mc);
-  P.VT = P.Mc;
-  P.Lam = (double*)(b + L.Lam);
-  P.fg = (double*)(b + L.fg);
-  P.partials = (double*)(b + L.partials);
-  P.nparts = (int)((g.nodes(g.L) + 255) / 256);
-  P.rr_x = (double*)(b + L.rr_x);
-  P.rr_y = (double*)(b + L.rr_y);
-  P.rr_t = (double*)(b + L.rr_t);
-  P.cH_grid = (double*)(b + L.cH);
-  P.sum_parts = (double*)(b + L.out_parts);
-  c->dprob = (ProbDev*)(b + L.prob);
-  // per-level item tables (storage offsets differ per level)
-  c->items_lv.assign(g.L + 1, g.items);
-  for (int m = 1; m <= g.L; ++m)
-    for (size_t k = 0; k < g.items.size(); ++k) c->items_lv[m][k].off = L.item_off[m][k];
-  hipStream_t st = c->st;
-  auto fail = [&](mlc_status e) {
-    std::fprintf(stderr, "mlc_create: %s\n", c->err.c_str());
-    delete c;
-    return e;
-  };
-#define MLC_UP(dst, vec)                                                                    \
-  do {                                                                                      \
-    hipError_t e_ = hipMemcpyAsync(b + (dst), (vec).data(), (vec).size() * sizeof((vec)[0]), \
-                                   hipMemcpyHostToDevice, st);                              \
-    if (e_ != hipSuccess) {                                                                 \
-      c->err = std::string("upload: ") + hipGetErrorString(e_);                             \
-      return fail(MLC_EHIP);                                                                \
-    }                                                                                       \
-  } while (0)
-  MLC_UP(L.bx, g.bx);
-  MLC_UP(L.by, g.by);
-  MLC_UP(L.sub_item, g.sub_item);
-  MLC_UP(L.coarse_nodes, g.coarse_nodes);
-  MLC_UP(L.coarse_index, g.coarse_index);
-  if (g.kind == 2) {
-    MLC_UP(L.kLR[g.L], c->kappa);
-    const std::vector<double> ones((size_t)g.nc * g.nc, 1.0);
-    MLC_UP(L.kH, ones);
-    if (hipStreamSynchronize(st) != hipSuccess) return fail(MLC_EHIP);
-  } else {
-    MLC_UP(L.kH, c->kappa);
-  }
-  for (int m = 1; m <= g.L; ++m) MLC_UP(L.items[m], c->items_lv[m]);
-  {
-    std::vector<ProbDev> one(1, P);
-    MLC_UP(L.prob, one);
-    if (hipStreamSynchronize(st) != hipSuccess) {
-      c->err = "stream synchronize after upload failed";
-      return fail(MLC_EHIP);
-    }
-  }
-#undef MLC_UP
+  c->b = b;
   *out = c;
   return MLC_OK;
 }
 
 mlc_status mlc_coarse_setup(mlc_ctx* c) {
   if (!c) return MLC_EINVAL;
-  const Geometry& g = c->g;
-  const Layout& L = c->lo;
-  char* b = c->ws;
-  hipStream_t st = c->st;
-  // coefficients on every level: children means (kind 2 only; kinds 0/1 are per coarse cell)
-  if (g.kind == 2) {
-    for (int l = g.L - 1; l >= 0; --l)
-      MLC_HIP(c, launch_coarsen_kappa(c->hp.kLR[l + 1], c->hp.kUL[l + 1], (double*)(b + L.kLR[l]),
-                                      (double*)(b + L.kUL[l]), (int)g.N(l), st));
-  }
-  const size_t nH = (size_t)g.nH;
-  MLC_HIP(c, hipMemsetAsync(b + L.Kc, 0, nH * nH * 8, st));
-  MLC_HIP(c, hipMemsetAsync(b + L.Mc, 0, nH * nH * 8, st));
-  MLC_HIP(c, launch_coarse_matrices(g.kind, c->dprob, 1, g.nH, st));
-  if (!c->rb) {
-    if (rocblas_create_handle(&c->rb) != rocblas_status_success) {
-      c->err = "rocblas_create_handle failed";
-      return MLC_EHIP;
-    }
-  }
-  if (rocblas_set_stream(c->rb, st) != rocblas_status_success) {
-    c->err = "rocblas_set_stream failed";
-    return MLC_EHIP;
-  }
-  // Algorithm 4.2 step 1 on V_0H: K_H V = M_H V Lambda, V^T M_H V = I (full spectrum)
-  rocblas_status rs = rocsolver_dsygvd(c->rb, rocblas_eform_ax, rocblas_evect_original,
-                                       rocblas_fill_upper, g.nH, (double*)(b + L.Kc), g.nH,
-                                       (double*)(b + L.Mc), g.nH, (double*)(b + L.Lam),
-                                       (double*)(b + L.E), (rocblas_int*)(b + L.info));
-  if (rs != rocblas_status_success) {
-    c->err = std::string("rocsolver_dsygvd: ") + rocblas_status_to_string(rs);
-    return MLC_EHIP;
-  }
-  MLC_HIP(c, launch_transpose_v(c->dprob, 1, g.nH, st));
-  MLC_HIP(c, launch_init_u0(c->dprob, 1, 0, (g.nc + 1) * (g.nc + 1), st));
-  MLC_HIP(c, launch_tile_inverse(g.kind, c->dprob, (const TileItem*)(b + L.items[1]),
-                                 (int)g.items.size(), (double*)(b + L.inv), st));
-  MLC_HIP(c, hipStreamSynchronize(st));
-  int info = 0;
-  MLC_HIP(c, hipMemcpy(&info, b + L.info, 4, hipMemcpyDeviceToHost));
-  if (info != 0) {
-    c->err = "coarse generalized eigensolve failed (info " + std::to_string(info) + ")";
-    return MLC_EHIP;
-  }
-  c->level = 0;
-  c->cur = 0;
-  c->setup = true;
-  c->can_rewind = false;
-  return MLC_OK;
-}
-
-static mlc_status level_correct_impl(mlc_ctx* c) {
-  const Geometry& g = c->g;
-  const Layout& L = c->lo;
-  char* b = c->ws;
-  hipStream_t st = c->st;
-  const int m = c->level + 1;
-  const int src = c->cur, dst = 1 - c->cur;
-  const int64_t nn = g.nodes(m);
-  const TileItem* items = (const TileItem*)(b + L.items[m]);
-  const int nitems = (int)g.items.size();
-  std::array<hipEvent_t, 4> ev{};
-  const bool timing = c->o.timing != 0;
-  if (timing) {
-    for (auto& e : ev) {
-      e = get_event(c);
-      if (!e) {
-        c->err = "hipEventCreate failed";
-        return MLC_EHIP;
-      }
-    }
-    MLC_HIP(c, hipEventRecord(ev[0], st));
-  }
-  MLC_HIP(c, launch_prolong_residual(g.kind, c->dprob, 1, m, src, nn, st));
-  if (timing) MLC_HIP(c, hipEventRecord(ev[1], st));
-  if (c->o.precision == 0) {
-    const int64_t lds = pcg_lds_bytes(c->items_lv[m].data(), nitems, m, (int)sizeof(double));
-    MLC_HIP(c, launch_local_pcg(g.kind, c->nt, c->dprob, items, nitems, b + L.store,
-                                (const double*)(b + L.inv), m, (ItemStat*)(b + L.stats),
-                                c->o.rtol, c->o.max_it, c->o.nu, c->o.omega, lds, st));
-  } else {
-    MLC_HIP(c, launch_local_mixed(g.kind, c->nt, c->dprob, items, nitems, b + L.store,
-                                  (const double*)(b + L.inv), m, (ItemStat*)(b + L.stats),
-                                  c->o.rtol, c->o.max_it, c->o.max_refine, c->o.inner_rtol,
-                                  c->o.nu, c->o.omega, st));
-  }
-  if (timing) MLC_HIP(c, hipEventRecord(ev[2], st));
-  MLC_HIP(c, launch_pou_glue(c->dprob, 1, items, b + L.store, m, nn, st));
-  MLC_HIP(c, launch_rr_apply(g.kind, c->dprob, 1, m, nn, st));
-  for (int l = m - 1; l >= 0; --l) MLC_HIP(c, launch_restrict(c->dprob, 1, l, m, g.nodes(l), st));
-  MLC_HIP(c, launch_rr_project(c->dprob, 1, g.nH, st));
-  MLC_HIP(c, launch_rr_solve(g.q, c->dprob, 1, m, g.nH, dst, st));
-  MLC_HIP(c, launch_rr_combine(c->dprob, 1, (g.nc + 1) * (g.nc + 1), st));
-  MLC_HIP(c, launch_assemble(c->dprob, 1, m, dst, nn, st));
-  if (timing) {
-    MLC_HIP(c, hipEventRecord(ev[3], st));
-    c->ev_pending.push_back(ev);
-  }
-  c->cur = dst;
-  c->level = m;
-  c->can_rewind = true;
-  return MLC_OK;
+  return batch_setup(c->b);
 }
 
 mlc_status mlc_level_correct(mlc_ctx* c, mlc_level_stats* stt) {
   if (!c) return MLC_EINVAL;
-  if (!c->setup || c->level < 0 || c->level >= c->g.L) {
-    c->err = "level_correct needs coarse_setup and a level below the finest";
-    return MLC_ESTATE;
-  }
-  mlc_status s = level_correct_impl(c);
+  mlc_batch* b = c->b;
+  mlc_status s = batch_step(b, 0);
   if (s != MLC_OK || !stt) return s;
-  const Geometry& g = c->g;
-  MLC_HIP(c, hipStreamSynchronize(c->st));
-  std::vector<ItemStat> is(g.items.size());
-  MLC_HIP(c, hipMemcpy(is.data(), c->ws + c->lo.stats, is.size() * sizeof(ItemStat),
-                       hipMemcpyDeviceToHost));
-  double lam[2 * MLC_MAX_Q];
-  MLC_HIP(c, hipMemcpy(lam, c->ws + c->lo.lam, sizeof(lam), hipMemcpyDeviceToHost));
-  std::memset(stt, 0, sizeof(*stt));
-  const int m = c->level;
-  stt->level = m;
-  stt->n_items = (int)g.items.size();
-  stt->h = g.side / (double)g.N(m);
-  int64_t ndof = 0;
-  const int N = (int)g.N(m);
-  for (int j = 1; j < N; ++j)
-    for (int i = 1; i < N; ++i) ndof += is_dof_host(g.domain, N, i, j) ? 1 : 0;
-  stt->n_dofs = ndof;
-  for (size_t k = 0; k < g.items.size(); ++k) {
-    const TileItem& it = g.items[k];
-    const int64_t S = (int64_t)(it.cw * (1 << m) - 1) * (it.ch * (1 << m) - 1);
-    stt->n_tile_dofs += S;
-    stt->it_max = std::max(stt->it_max, is[k].iters);
-    stt->refine_max = std::max(stt->refine_max, is[k].refine);
-    stt->it_sum += is[k].iters;
-    stt->it_dofs += (int64_t)is[k].iters * S;
-    stt->refine_dofs += (int64_t)is[k].refine * S;
-    stt->relres_max = std::max(stt->relres_max, is[k].relres);
-  }
-  for (int i = 0; i < g.q; ++i) stt->lambda[i] = lam[c->cur * MLC_MAX_Q + i];
-  if (stt->relres_max > c->o.rtol * 1.0000001) {
-    c->err = "a local solve did not converge within max_it";
-    return MLC_ENOCONV;
-  }
-  return MLC_OK;
+  s = step_stats(b, stt);
+  if (s != MLC_OK && s != MLC_ENOCONV) return s;
+  double lam[MLC_MAX_Q];
+  const int buf = (b->step + b->shift[0]) & 1;
+  MLC_HIP(b, hipMemcpy(lam, b->ws + b->plan.pl[0].lam + (size_t)buf * MLC_MAX_Q * 8,
+                       (size_t)b->plan.q * 8, hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->plan.q; ++i) stt->lambda[i] = lam[i];
+  return s;
 }
 
 mlc_status mlc_run(mlc_ctx* c) {
   if (!c) return MLC_EINVAL;
-  if (!c->setup) return MLC_ESTATE;
-  while (c->level < c->g.L) {
-    mlc_status s = level_correct_impl(c);
+  if (c->b->step < 0) {
+    c->b->err = "run needs coarse_setup";
+    return MLC_ESTATE;
+  }
+  while (c->b->step < c->b->plan.Lmax) {
+    mlc_status s = batch_step(c->b, 0);
     if (s != MLC_OK) return s;
   }
   return MLC_OK;
@@ -624,84 +823,51 @@ mlc_status mlc_run(mlc_ctx* c) {
 
 mlc_status mlc_rewind(mlc_ctx* c) {
   if (!c) return MLC_EINVAL;
-  if (!c->setup || !c->can_rewind || c->level < 1) {
-    c->err = "nothing to rewind";
-    return MLC_ESTATE;
-  }
-  c->cur = 1 - c->cur;
-  c->level -= 1;
-  c->can_rewind = false;
-  return MLC_OK;
+  return mlc_batch_rewind(c->b);
 }
 
 mlc_status mlc_current_level(const mlc_ctx* c, int32_t* level) {
   if (!c || !level) return MLC_EINVAL;
-  *level = c->level;
+  *level = c->b->step;
   return MLC_OK;
 }
 
 mlc_status mlc_get_eigenpairs(mlc_ctx* c, double* lam_host, double* u_dev) {
   if (!c) return MLC_EINVAL;
-  if (!c->setup) {
-    c->err = "no eigenpairs before coarse_setup";
-    return MLC_ESTATE;
-  }
-  const Geometry& g = c->g;
-  if (u_dev) {
-    MLC_HIP(c, launch_output_signed(c->hp.u[c->cur], g.nodes(c->level), g.q,
-                                    (double*)(c->ws + c->lo.out_parts), u_dev, c->st));
-  }
-  if (lam_host) {
-    MLC_HIP(c, hipStreamSynchronize(c->st));
-    MLC_HIP(c, hipMemcpy(lam_host, c->ws + c->lo.lam + (size_t)c->cur * MLC_MAX_Q * 8,
-                         (size_t)g.q * 8, hipMemcpyDeviceToHost));
-  }
-  return MLC_OK;
+  return batch_get(c->b, 0, lam_host, u_dev);
 }
 
 mlc_status mlc_set_state(mlc_ctx* c, int32_t level, const double* lam_host, const double* u_dev) {
   if (!c || !lam_host || !u_dev) return MLC_EINVAL;
-  if (!c->setup) {
-    c->err = "set_state needs coarse_setup";
+  mlc_batch* b = c->b;
+  if (b->step < 0) {
+    b->err = "set_state needs coarse_setup";
     return MLC_ESTATE;
   }
-  if (level < 0 || level > c->g.L) {
-    c->err = "level out of range";
+  if (level < 0 || level > b->plan.Lmax) {
+    b->err = "level out of range";
     return MLC_EINVAL;
   }
-  MLC_HIP(c, launch_set_state(c->dprob, level, 0, u_dev, c->g.nodes(level), c->st));
-  MLC_HIP(c, hipStreamSynchronize(c->st));
-  MLC_HIP(c, hipMemcpy(c->ws + c->lo.lam, lam_host, (size_t)c->g.q * 8, hipMemcpyHostToDevice));
-  c->level = level;
-  c->cur = 0;
-  c->can_rewind = false;
+  const Geometry& g = b->plan.geo[0];
+  // the state goes to buffer 0; the shift makes (level + shift) & 1 == 0
+  MLC_HIP(b, launch_set_state(b->dprob, level, 0, u_dev, g.nodes(level), b->st));
+  MLC_HIP(b, hipStreamSynchronize(b->st));
+  MLC_HIP(b, hipMemcpy(b->ws + b->plan.pl[0].lam, lam_host, (size_t)g.q * 8, hipMemcpyHostToDevice));
+  b->step = level;
+  b->shift[0] = level & 1;
+  b->can_rewind = false;
+  drop_graphs(b);
   return MLC_OK;
 }
 
 mlc_status mlc_phase_times(mlc_ctx* c, double* ms, int32_t n) {
   if (!c || !ms || n < 1) return MLC_EINVAL;
-  MLC_HIP(c, hipStreamSynchronize(c->st));
-  double acc[2] = {0.0, 0.0};
-  for (auto& ev : c->ev_pending) {
-    float a = 0.f, t = 0.f;
-    MLC_HIP(c, hipEventElapsedTime(&a, ev[1], ev[2]));
-    MLC_HIP(c, hipEventElapsedTime(&t, ev[0], ev[3]));
-    acc[0] += a;
-    acc[1] += t;
-    for (auto e : ev) c->ev_free.push_back(e);
-  }
-  c->ev_pending.clear();
-  for (int i = 0; i < n; ++i) ms[i] = i < 2 ? acc[i] : 0.0;
-  return MLC_OK;
+  return phase_times(c->b, ms, n);
 }
 
 mlc_status mlc_destroy(mlc_ctx* c) {
   if (!c) return MLC_EINVAL;
-  if (c->st) (void)hipStreamSynchronize(c->st);
-  for (auto& ev : c->ev_pending)
-    for (auto e : ev) c->ev_free.push_back(e);
-  for (auto e : c->ev_free) (void)hipEventDestroy(e);
-  if (c->rb) rocblas_destroy_handle(c->rb);
+  batch_destroy(c->b);
   delete c;
   return MLC_OK;
 }
@@ -718,6 +884,141 @@ const char* mlc_status_str(mlc_status s) {
   return "MLC_UNKNOWN";
 }
 
-const char* mlc_last_error(const mlc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* mlc_last_error(const mlc_ctx* c) { return c ? c->b->err.c_str() : "null context"; }
+
+// ---------------- batches ----------------
+
+mlc_status mlc_batch_workspace_size(int32_t n, const mlc_problem_desc* descs,
+                                    const mlc_solver_opts* o, size_t* bytes) {
+  if (!bytes) return MLC_EINVAL;
+  Plan P;
+  std::string msg;
+  mlc_status s = make_plan(n, descs, o, P, msg);
+  if (s != MLC_OK) return s;
+  *bytes = P.total;
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solver_opts* o,
+                            void* ws, size_t bytes, void* stream, mlc_batch** out) {
+  return batch_create(n, descs, o, ws, bytes, stream, out);
+}
+
+mlc_status mlc_batch_setup(mlc_batch* b) { return b ? batch_setup(b) : MLC_EINVAL; }
+
+mlc_status mlc_batch_step(mlc_batch* b, int32_t use_graph) {
+  return b ? batch_step(b, use_graph) : MLC_EINVAL;
+}
+
+mlc_status mlc_batch_run(mlc_batch* b, int32_t use_graph) {
+  if (!b) return MLC_EINVAL;
+  if (b->step < 0) {
+    b->err = "run needs setup";
+    return MLC_ESTATE;
+  }
+  while (b->step < b->plan.Lmax) {
+    mlc_status s = batch_step(b, use_graph);
+    if (s != MLC_OK) return s;
+  }
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_rewind(mlc_batch* b) {
+  if (!b) return MLC_EINVAL;
+  if (b->step < 1 || !b->can_rewind) {
+    b->err = "nothing to rewind";
+    return MLC_ESTATE;
+  }
+  b->step -= 1;
+  b->can_rewind = false;
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_current_step(const mlc_batch* b, int32_t* step) {
+  if (!b || !step) return MLC_EINVAL;
+  *step = b->step;
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_get(mlc_batch* b, int32_t i, double* lam_host, double* u_dev) {
+  return b ? batch_get(b, i, lam_host, u_dev) : MLC_EINVAL;
+}
+
+mlc_status mlc_batch_step_stats(mlc_batch* b, mlc_level_stats* st) {
+  if (!b || !st) return MLC_EINVAL;
+  return step_stats(b, st);
+}
+
+mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n) {
+  if (!b) return MLC_EINVAL;
+  if (b->step < 0) {
+    b->err = "autotune needs setup";
+    return MLC_ESTATE;
+  }
+  const Plan& P = b->plan;
+  const int cand[3] = {256, 512, 1024};
+  std::vector<double> best(P.Lmax + 1, 1e300);
+  std::vector<int> choice(P.Lmax + 1, 1024);
+  const int saved_timing = b->o.timing;
+  b->o.timing = 1;
+  drop_graphs(b);
+  mlc_status e = phase_times(b, nullptr, 0);  // drop stale events
+  for (int c = 0; c < 3 && e == MLC_OK; ++c) {
+    std::fill(b->blocks.begin(), b->blocks.end(), cand[c]);
+    // back to level 0 from the stored coarse eigenbasis, then every step once
+    if (launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st) != hipSuccess) {
+      b->err = "launch_init_u0 failed";
+      e = MLC_EHIP;
+      break;
+    }
+    b->step = 0;
+    std::fill(b->shift.begin(), b->shift.end(), 0);
+    for (int s = 1; s <= P.Lmax && e == MLC_OK; ++s) {
+      e = batch_step(b, 0);
+      double ms[2] = {0.0, 0.0};
+      if (e == MLC_OK) e = phase_times(b, ms, 2);
+      if (e == MLC_OK && ms[0] < best[s]) {
+        best[s] = ms[0];
+        choice[s] = cand[c];
+      }
+    }
+  }
+  b->o.timing = saved_timing;
+  if (e != MLC_OK) return e;
+  for (int s = 1; s <= P.Lmax; ++s) b->blocks[s] = choice[s];
+  for (int s = 1; s <= P.Lmax && blocks_out && s - 1 < n; ++s) blocks_out[s - 1] = choice[s];
+  MLC_HIP(b, launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st));
+  MLC_HIP(b, hipStreamSynchronize(b->st));
+  b->step = 0;
+  b->can_rewind = false;
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_set_blocks(mlc_batch* b, const int32_t* blocks, int32_t n) {
+  if (!b || !blocks) return MLC_EINVAL;
+  for (int s = 1; s <= b->plan.Lmax && s - 1 < n; ++s) {
+    const int v = blocks[s - 1];
+    if (v != 256 && v != 512 && v != 1024) {
+      b->err = "block sizes must be 256, 512 or 1024";
+      return MLC_EINVAL;
+    }
+  }
+  for (int s = 1; s <= b->plan.Lmax && s - 1 < n; ++s) b->blocks[s] = blocks[s - 1];
+  drop_graphs(b);
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_phase_times(mlc_batch* b, double* ms, int32_t n) {
+  if (!b || !ms || n < 1) return MLC_EINVAL;
+  return phase_times(b, ms, n);
+}
+
+mlc_status mlc_batch_destroy(mlc_batch* b) {
+  if (!b) return MLC_EINVAL;
+  batch_destroy(b);
+  return MLC_OK;
+}
+
+const char* mlc_batch_last_error(const mlc_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
 }  // extern "C"

@@ -18,7 +18,8 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
                               double omega, hipStream_t s);
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
-                           const char* store, int m, int64_t max_nodes, hipStream_t s);
+                           const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
+                           hipStream_t s);
 hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
                            hipStream_t s);
 hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,

@@ -56,6 +56,30 @@ def make(name: str, n_samples: int = 512):
     print(f"{name}: {secs:.1f} s -> {path}", flush=True)
 
 
+def _one_batch_problem(i):
+    prob = W.config4()[i]
+    res = solve(prob, keep_levels=False)
+    return dict(name=prob.name, lam_levels=[l.tolist() for l in res.lam_levels],
+                seconds=float(sum(res.seconds)))
+
+
+def make_batch(workers: int = 6):
+    """Configuration 4: all 256 problems, per-level eigenvalues (oracle, process pool)."""
+    from multiprocessing import Pool
+    n = len(W.config4())
+    t0 = time.perf_counter()
+    with Pool(workers) as pool:
+        out = pool.map(_one_batch_problem, range(n), chunksize=1)
+    path = os.path.join(HERE, "oracle_c4.json")
+    with open(path, "w") as f:
+        json.dump(dict(problems=out, source="oracle.solve (CPU FP64), written by "
+                       "tests/golden/make_golden.py from the oracle only"), f)
+    print(f"c4: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
+
+
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CONFIGS)):
-        make(n)
+    for n in (sys.argv[1:] or list(CONFIGS) + ["c4"]):
+        if n == "c4":
+            make_batch()
+        else:
+            make(n)

@@ -1,0 +1,168 @@
+"""GPU tests of the batched path: many independent problems, one launch per kernel and
+level step, optionally captured in a hipGraph, with an autotuned workgroup size.
+
+The local solves of different problems are independent work items, so a problem's
+results in a batch must be bitwise identical to a single-problem run with the same
+workgroup size, and agree with the CPU oracle to 1e-10.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import solve as oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _small_batch(kind=1, q=1, n=7, seed0=100):
+    rng = np.random.Generator(np.random.PCG64(seed0))
+    out = []
+    for i in range(n):
+        dom = int(rng.integers(0, 2))
+        nc = int(rng.choice([4, 6, 8]))
+        L = int(rng.integers(1, 4))
+        s = int(rng.integers(1, min(nc, 4) + 1))
+        kap = None
+        if kind == 1:
+            kap = W.loguniform_coarse_kappa(nc, rng)
+        elif kind == 2:
+            kap = np.exp(rng.uniform(-1, 1, size=(nc << L, nc << L)))
+        out.append(W.Problem(dom, nc, L, s, s, 1, q, kind, kap, f"b{i}"))
+    return out
+
+
+def _single(prob, **kw):
+    from paper_1401_4969_amd import binding as B
+    s = B.Solver(prob, B.default_opts(**kw))
+    s.coarse_setup()
+    s.run()
+    lam, u = s.eigenpairs()
+    s.close()
+    return lam, u
+
+
+@pytest.mark.parametrize("kind,q,precision", [(1, 1, 0), (2, 1, 0), (0, 2, 0), (1, 1, 1)])
+def test_batch_matches_single_and_oracle(kind, q, precision):
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    probs = _small_batch(kind, q)
+    bs = B.BatchSolver(probs, B.default_opts(precision=precision))
+    bs.setup()
+    bs.run()
+    st = bs.stats()
+    assert st["relres_max"] <= 1e-12 * 1.0000001
+    for i, p in enumerate(probs):
+        lam, u = bs.get(i)
+        lam1, u1 = _single(p, precision=precision)
+        assert np.array_equal(lam, lam1), (i, lam, lam1)
+        assert torch.equal(u, u1)
+        ref = oracle_solve(p)
+        assert np.allclose(lam, ref.lam, rtol=1e-10, atol=0), (i, lam, ref.lam)
+    bs.close()
+
+
+def test_graph_replays_match_eager():
+    """Every graph replay, with eager work and synchronisations in between, reproduces
+    the eager step bitwise."""
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    probs = _small_batch(1, 1)
+    eager = B.BatchSolver(probs)
+    eager.setup()
+    eager.run(use_graph=False)
+    ref = [eager.get(i) for i in range(len(probs))]
+    graph = B.BatchSolver(probs)
+    graph.setup()
+    graph.run(use_graph=True)
+    for replay in range(3):
+        for i in range(len(probs)):
+            lam, u = graph.get(i)
+            assert np.array_equal(lam, ref[i][0])
+            assert torch.equal(u, ref[i][1])
+        # eager work on the same stream between replays
+        x = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+        (x * 2).sum().item()
+        torch.cuda.synchronize()
+        graph.rewind()
+        graph.step(use_graph=True)
+    eager.close()
+    graph.close()
+
+
+def test_autotune_choices_and_results():
+    _torch()
+    from paper_1401_4969_amd import binding as B
+    probs = _small_batch(1, 1)
+    bs = B.BatchSolver(probs)
+    bs.setup()
+    blocks = bs.autotune()
+    assert len(blocks) == bs.n_steps and all(b in (256, 512, 1024) for b in blocks)
+    assert bs.current_step == 0
+    bs.run()
+    for i, p in enumerate(probs):
+        lam, _ = bs.get(i, with_vectors=False)
+        ref = oracle_solve(p)
+        assert np.allclose(lam, ref.lam, rtol=1e-10, atol=0)
+    bs.set_blocks(blocks)
+    bs.close()
+
+
+def test_batch_rejects_mixed_q_or_kind():
+    _torch()
+    from paper_1401_4969_amd import binding as B
+    a = W.config1()
+    with pytest.raises(B.MLCError):
+        B.batch_workspace_size([a, a.with_(n_eig=2)])
+    with pytest.raises(B.MLCError):
+        B.batch_workspace_size([a, a.with_(coef_kind=1, kappa=np.ones((8, 8)))])
+
+
+def _golden_c4():
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_c4.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values for configuration 4 not generated")
+    with open(path) as f:
+        return json.load(f)["problems"]
+
+
+def test_config4_full_batch():
+    """Configuration 4: 256 problems (square and L-shape, h = 1/128..1/512 of the unit
+    length, 4x4..8x8 uneven subdomains, log-uniform kappa), mixed precision, one graph
+    per level step.  Every problem's every level against the stored oracle values; a
+    sample of problems bitwise against single-problem runs."""
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    gold = _golden_c4()
+    probs = W.config4()
+    bs = B.BatchSolver(probs, B.default_opts(precision=1))
+    bs.setup()
+    lams = [[bs.get(i, with_vectors=False)[0]] for i in range(len(probs))]
+    for s in range(bs.n_steps):
+        bs.step(use_graph=True)
+        for i, p in enumerate(probs):
+            if p.n_refine >= s + 1:
+                lams[i].append(bs.get(i, with_vectors=False)[0])
+        st = bs.stats()
+        assert st["relres_max"] <= 1e-12 * 1.0000001
+    worst = 0.0
+    for i, g in enumerate(gold):
+        assert g["name"] == probs[i].name
+        for a, b in zip(lams[i], g["lam_levels"]):
+            worst = max(worst, float(np.max(np.abs(a - np.asarray(b)) / np.abs(np.asarray(b)))))
+    assert worst < 1e-10, worst
+    for i in (0, 17, 100, 255):
+        lam, u = bs.get(i)
+        lam1, u1 = _single(probs[i], precision=1)
+        assert np.array_equal(lam, lam1)
+        assert torch.equal(u, u1)
+    bs.close()
