@@ -88,6 +88,8 @@ typedef struct mlc_solver_opts {
   double omega;        /* Jacobi damping (0.8) */
   int32_t block;       /* threads per workgroup of the local solver: 256, 512 or 1024 (0 = 1024) */
   int32_t timing;      /* 1: record HIP events around the local-solve kernel (see mlc_phase_times) */
+  int32_t record_tape; /* 1: keep every level's forward state for mlc_backward (single problem,
+                          q = 1, coef_kind 1 or 2; enlarges the workspace) */
 } mlc_solver_opts;
 
 /* Per-level statistics, filled by mlc_level_correct when st != NULL (this synchronises
@@ -159,6 +161,22 @@ mlc_status mlc_set_state(struct mlc_ctx* ctx, int32_t level, const double* lambd
  * ms[0] = local-solve kernel, ms[1] = whole level_correct calls.  Synchronises. */
 mlc_status mlc_phase_times(struct mlc_ctx* ctx, double* ms, int32_t n);
 
+/* Exact reverse-mode derivative of the computed finest eigenvalue lambda_1 with respect to
+ * the coefficient, through every level: the coarse eigenproblem (Algorithm 4.2 step 1),
+ * every correction step (local solves, gluing, Rayleigh-Ritz of Algorithm 4.1) and the
+ * children-mean coefficients of coarser levels.  kappa_bar_dev (device, written) receives
+ * lambda_bar * d lambda_1 / d kappa in the layout of desc->kappa: per finest cell
+ * (coef_kind 2) or per coarse cell (coef_kind 1).  Needs opts.record_tape = 1 (else
+ * MLC_EINVAL) and a complete forward run (else MLC_ESTATE).  Runs one adjoint local solve
+ * per subdomain and level.  Synchronises. */
+mlc_status mlc_backward(struct mlc_ctx* ctx, double lambda_bar, double* kappa_bar_dev);
+
+/* Hellmann-Feynman reference gradient: (u, dK/dkappa u) for the finest eigenvector
+ * (b(u,u) = 1), same layout and requirements as mlc_backward.  It ignores how the
+ * multilevel approximation itself depends on kappa, so it differs from mlc_backward by
+ * the approximation error; it is a reference, not the derivative. */
+mlc_status mlc_hf_gradient(struct mlc_ctx* ctx, double* kappa_bar_dev);
+
 mlc_status mlc_destroy(struct mlc_ctx* ctx);
 
 /* ---- Batches: many independent problems, one launch per kernel and level step ----
@@ -193,6 +211,10 @@ mlc_status mlc_batch_run(mlc_batch* b, int32_t use_graph);
 
 /* Step back once (the previous eigenpairs are still held), so a step can be repeated. */
 mlc_status mlc_batch_rewind(mlc_batch* b);
+
+/* Back to step 0 (the level-0 eigenpairs from the stored coarse eigenbasis) without
+ * redoing the setup, e.g. to time repeated full runs.  Stream-ordered. */
+mlc_status mlc_batch_restart(mlc_batch* b);
 
 /* Current step (0 after setup). */
 mlc_status mlc_batch_current_step(const mlc_batch* b, int32_t* step);

@@ -26,8 +26,8 @@ EXPORTS = [
     "mlc_default_opts", "mlc_workspace_size", "mlc_create", "mlc_coarse_setup",
     "mlc_level_correct", "mlc_run", "mlc_rewind", "mlc_current_level", "mlc_get_eigenpairs",
     "mlc_set_state", "mlc_phase_times", "mlc_destroy", "mlc_status_str", "mlc_last_error",
-    "mlc_batch_workspace_size", "mlc_batch_create", "mlc_batch_setup", "mlc_batch_step",
-    "mlc_batch_run", "mlc_batch_rewind", "mlc_batch_current_step", "mlc_batch_get",
+    "mlc_backward", "mlc_hf_gradient", "mlc_batch_workspace_size", "mlc_batch_create", "mlc_batch_setup", "mlc_batch_step",
+    "mlc_batch_run", "mlc_batch_rewind", "mlc_batch_restart", "mlc_batch_current_step", "mlc_batch_get",
     "mlc_batch_step_stats", "mlc_batch_autotune", "mlc_batch_set_blocks",
     "mlc_batch_phase_times", "mlc_batch_destroy", "mlc_batch_last_error",
 ]
@@ -43,7 +43,8 @@ class ProblemDesc(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_it", C.c_int32),
                 ("max_refine", C.c_int32), ("inner_rtol", C.c_double), ("nu", C.c_int32),
-                ("omega", C.c_double), ("block", C.c_int32), ("timing", C.c_int32)]
+                ("omega", C.c_double), ("block", C.c_int32), ("timing", C.c_int32),
+                ("record_tape", C.c_int32)]
 
 
 class LevelStats(C.Structure):
@@ -94,6 +95,8 @@ def load_library() -> C.CDLL:
     lib.mlc_set_state.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P]
     lib.mlc_phase_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
     lib.mlc_destroy.argtypes = [P]
+    lib.mlc_backward.argtypes = [P, C.c_double, P]
+    lib.mlc_hf_gradient.argtypes = [P, P]
     lib.mlc_status_str.argtypes = [C.c_int]
     lib.mlc_status_str.restype = C.c_char_p
     lib.mlc_last_error.argtypes = [P]
@@ -106,6 +109,7 @@ def load_library() -> C.CDLL:
     lib.mlc_batch_step.argtypes = [P, C.c_int32]
     lib.mlc_batch_run.argtypes = [P, C.c_int32]
     lib.mlc_batch_rewind.argtypes = [P]
+    lib.mlc_batch_restart.argtypes = [P]
     lib.mlc_batch_current_step.argtypes = [P, C.POINTER(C.c_int32)]
     lib.mlc_batch_get.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P]
     lib.mlc_batch_step_stats.argtypes = [P, C.POINTER(LevelStats)]
@@ -239,6 +243,28 @@ class Solver:
         self._check(self.lib.mlc_phase_times(self.ctx, ms, 2), "mlc_phase_times")
         return [ms[0], ms[1]]
 
+    def _kappa_shape(self):
+        p = self.prob
+        if p.coef_kind == 2:
+            n = p.n_coarse << p.n_refine
+            return (n, n)
+        return (p.n_coarse, p.n_coarse)
+
+    def backward(self, lambda_bar: float = 1.0):
+        """lambda_bar * d lambda_1 / d kappa (torch float64 on the device, kappa's layout)."""
+        import torch
+        out = torch.empty(self._kappa_shape(), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mlc_backward(self.ctx, C.c_double(lambda_bar), C.c_void_p(out.data_ptr())),
+                    "mlc_backward")
+        return out
+
+    def hf_gradient(self):
+        import torch
+        out = torch.empty(self._kappa_shape(), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mlc_hf_gradient(self.ctx, C.c_void_p(out.data_ptr())),
+                    "mlc_hf_gradient")
+        return out
+
     def close(self):
         if self.ctx:
             self.lib.mlc_destroy(self.ctx)
@@ -332,6 +358,9 @@ class BatchSolver:
 
     def rewind(self):
         self._check(self.lib.mlc_batch_rewind(self.b), "mlc_batch_rewind")
+
+    def restart(self):
+        self._check(self.lib.mlc_batch_restart(self.b), "mlc_batch_restart")
 
     @property
     def current_step(self) -> int:

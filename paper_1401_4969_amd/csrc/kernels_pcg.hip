@@ -20,7 +20,7 @@ template <int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const TileItem* items,
                                                      char* store, const double* inv, int m,
                                                      ItemStat* stats, double rtol, int max_it,
-                                                     int nu, double omega) {
+                                                     int nu, double omega, int rhs_in_tile) {
   __shared__ LevelDesc lev[MLC_MAX_LEVELS + 1];
   __shared__ double red[2 * (NT / 64)];
   const TileItem it = items[blockIdx.x];
@@ -36,7 +36,8 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   double acc[2] = {0.0, 0.0};
   FOR_TILE(l0) {
     const int64_t i = (int64_t)iy * l0.nx + ix;
-    const double v = bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
+    // right-hand side: the global residual window, or (adjoint solves) already in R
+    const double v = rhs_in_tile ? R[i] : bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
     R[i] = v;
     X[i] = 0.0;
     acc[0] += v * v;
@@ -70,10 +71,11 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
 
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                            double rtol, int max_it, int nu, double omega, int64_t, hipStream_t s) {
+                            double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
+                            hipStream_t s) {
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), 0, s, probs, items,      \
-                     store, inv, m, stats, rtol, max_it, nu, omega)
+                     store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \
     MLC_PCG(NTV, 0);       \
@@ -93,4 +95,3 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
   return hipGetLastError();
 }
 
-int64_t pcg_lds_bytes(const TileItem*, int, int, int) { return 0; }

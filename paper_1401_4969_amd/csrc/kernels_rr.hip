@@ -154,6 +154,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
         sAlpha[v] = s;
       else
         sBeta[v - Q * Q] = s;
+      if (Q == 1) P.rr_ab[v] = s;
     }
     __syncthreads();
   }

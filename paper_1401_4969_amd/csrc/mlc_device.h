@@ -48,6 +48,7 @@ struct ProbDev {
   double* rr_x;               // q*(nH+q) eigenvectors of the reduced problem
   double* rr_y;               // q*nH coarse eigen-coordinates of the new eigenvectors
   double* rr_t;               // q*q coefficients of u~
+  double* rr_ab;              // alpha = u~^T K u~, beta = u~^T M u~ (q = 1: 2 values)
   double* cH_grid;            // q*(n_c+1)^2 coarse nodal coefficients
   double* sum_parts;          // output sign partial sums
 };

@@ -165,7 +165,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
 // Byte offsets (from the workspace base) of one problem's buffers.
 struct ProbLayout {
   size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
-      E, info, fg, partials, rr_x, rr_y, rr_t, cH, out_parts;
+      E, info, fg, partials, rr_x, rr_y, rr_t, rr_ab, cH, out_parts;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
   int64_t rchain_off[MLC_MAX_LEVELS + 1];
   int64_t inv_base;      // doubles, into the batch inverse region
@@ -181,7 +181,21 @@ struct StepTables {
   std::vector<int64_t> nodes_l;  // per coarser level l < s: largest (N_l+1)^2
 };
 
+// Forward tape and reverse-sweep buffers (single problem, q = 1): per level m the
+// eigenvector, u~, the local corrections e_j (item order) and the Rayleigh-Ritz data
+// (c_H, c_u, f, g, alpha, beta, mu); per level the triangle adjoints; grid scratch.
+struct TapeLayout {
+  bool on = false;
+  size_t tu[MLC_MAX_LEVELS + 1], tut[MLC_MAX_LEVELS + 1], te[MLC_MAX_LEVELS + 1],
+      te_off[MLC_MAX_LEVELS + 1], trr[MLC_MAX_LEVELS + 1];
+  size_t klo[MLC_MAX_LEVELS + 1], kup[MLC_MAX_LEVELS + 1];
+  size_t adj_u, adj_next, utbar, shat, rbar, ubar, cbar_H, scal, ycoef, coef, parts, a0, e0, ygrid,
+      v0grid;
+  std::vector<std::vector<int64_t>> te_offsets;  // per level, per item (doubles)
+};
+
 struct Plan {
+  TapeLayout tape;
   std::vector<Geometry> geo;
   std::vector<ProbLayout> pl;
   std::vector<StepTables> steps;  // index s (1..Lmax); steps[0] unused
@@ -263,6 +277,7 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.rr_x = take(q * (nH + q) * 8);
     L.rr_y = take(q * nH * 8);
     L.rr_t = take(q * q * 8);
+    L.rr_ab = take(2 * 8);
     L.cH = take(q * ncs * 8);
     L.out_parts = take(64 * q * 8);
     L.inv_base = P.inv_total;
@@ -273,6 +288,9 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
   // per-step item tables: every active problem's subdomains x eigenpairs, largest first
   P.steps.assign(P.Lmax + 1, StepTables());
   size_t store_bytes = 0;
+  // the reverse sweep runs FP64 solves in the forward pass's items, so a recorded tape
+  // sizes them for FP64 whatever the forward precision
+  const bool fp64_items = P.precision == 0 || o->record_tape != 0;
   for (int s = 1; s <= P.Lmax; ++s) {
     StepTables& T = P.steps[s];
     T.sub_item.assign((size_t)sub_off, -1);
@@ -307,8 +325,8 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     for (size_t k = 0; k < all.size(); ++k) {
       TileItem& it = all[k];
       it.off = (int64_t)o;
-      const int64_t b = P.precision == 0 ? item_bytes_fp64(it.cw, it.ch, s)
-                                         : item_bytes_mixed(it.cw, it.ch, s);
+      const int64_t b = fp64_items ? item_bytes_fp64(it.cw, it.ch, s)
+                                   : item_bytes_mixed(it.cw, it.ch, s);
       o = align_up(o + (size_t)b);
       T.sub_item[(size_t)P.pl[it.prob].sub_item_off + (size_t)it.sub * P.q + it.rhs] = (int32_t)k;
     }
@@ -320,6 +338,48 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
   }
   P.stats = take((size_t)P.max_items * sizeof(ItemStat));
   P.inv = take((size_t)P.inv_total * 8);
+  if (o->record_tape) {
+    const Geometry& g = P.geo[0];
+    if (n != 1 || P.q != 1 || (P.kind != 1 && P.kind != 2)) {
+      msg = "record_tape needs a single problem with n_eig = 1 and coef_kind 1 or 2";
+      return MLC_EINVAL;
+    }
+    TapeLayout& T = P.tape;
+    T.on = true;
+    T.te_offsets.assign(g.L + 1, {});
+    for (int m = 1; m <= g.L; ++m) {
+      T.tu[m] = take((size_t)g.nodes(m) * 8);
+      T.tut[m] = take((size_t)g.nodes(m) * 8);
+      int64_t o = 0;
+      for (const TileItem& it : P.steps[m].items) {
+        T.te_offsets[m].push_back(o);
+        o += (int64_t)(it.cw * (1 << m) - 1) * (it.ch * (1 << m) - 1);
+      }
+      T.te[m] = take((size_t)o * 8);
+      T.te_off[m] = take(P.steps[m].items.size() * 8);
+      T.trr[m] = take((size_t)(3 * g.nH + 4) * 8);
+    }
+    for (int l = 0; l <= g.L; ++l) {
+      T.klo[l] = take((size_t)(g.N(l) * g.N(l)) * 8);
+      T.kup[l] = take((size_t)(g.N(l) * g.N(l)) * 8);
+    }
+    const size_t nnL = (size_t)g.nodes(g.L);
+    T.adj_u = take(nnL * 8);
+    T.adj_next = take(nnL * 8);
+    T.utbar = take(nnL * 8);
+    T.shat = take(nnL * 8);
+    T.rbar = take(nnL * 8);
+    T.ubar = take(nnL * 8);
+    T.cbar_H = take((size_t)g.nH * 8);
+    T.scal = take((size_t)(g.L + 8) * 8);  // [0] c_bar_u, [1..] lambda_bar per level
+    T.ycoef = take((size_t)g.nH * 8);
+    T.coef = take(8 * 8);
+    T.parts = take(((nnL + 255) / 256) * 8);
+    T.a0 = take((size_t)g.nH * 8);
+    T.e0 = take((size_t)g.nH * 8);
+    T.ygrid = take((size_t)(g.nc + 1) * (g.nc + 1) * 8);
+    T.v0grid = take((size_t)(g.nc + 1) * (g.nc + 1) * 8);
+  }
   P.store_bytes = store_bytes;
   P.store = take(store_bytes);
   P.total = p;
@@ -347,6 +407,7 @@ struct mlc_batch {
   rocblas_handle rb = nullptr;
   std::vector<hipEvent_t> ev_free;
   std::vector<std::array<hipEvent_t, 4>> ev_pending;
+  std::vector<double> e0;  // unit coefficient vector (host copy kept for the async upload)
 };
 
 struct mlc_ctx {
@@ -461,6 +522,7 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     D.rr_x = (double*)(w + L.rr_x);
     D.rr_y = (double*)(w + L.rr_y);
     D.rr_t = (double*)(w + L.rr_t);
+    D.rr_ab = (double*)(w + L.rr_ab);
     D.cH_grid = (double*)(w + L.cH);
     D.sum_parts = (double*)(w + L.out_parts);
   }
@@ -487,6 +549,13 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     const StepTables& T = P.steps[s];
     ok = ok && up(T.items_off, T.items.data(), T.items.size() * sizeof(TileItem));
     ok = ok && up(T.sub_item_off, T.sub_item.data(), T.sub_item.size() * 4);
+  }
+  if (P.tape.on) {
+    for (int m = 1; m <= P.Lmax && ok; ++m)
+      ok = ok && up(P.tape.te_off[m], P.tape.te_offsets[m].data(), P.tape.te_offsets[m].size() * 8);
+    b->e0.assign((size_t)P.geo[0].nH, 0.0);
+    b->e0[0] = 1.0;
+    ok = ok && up(P.tape.e0, b->e0.data(), b->e0.size() * 8);
   }
   ok = ok && up(P.probdev, b->hp.data(), b->hp.size() * sizeof(ProbDev));
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
@@ -598,6 +667,23 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
   MLC_HIP(b, launch_rr_solve(P.q, b->dprob, P.n, s, P.max_nH, dst, st));
   MLC_HIP(b, launch_rr_combine(b->dprob, P.n, P.max_nc1sq, st));
   MLC_HIP(b, launch_assemble(b->dprob, P.n, s, dst, T.max_nodes, st));
+  if (P.tape.on) {  // keep this level's forward state for the reverse sweep
+    const TapeLayout& TL = P.tape;
+    const ProbDev& D = b->hp[0];
+    const int nH = P.geo[0].nH;
+    const size_t nn = (size_t)P.geo[0].nodes(s);
+    double* rr = (double*)(w + TL.trr[s]);
+    MLC_HIP(b, hipMemcpyAsync(w + TL.tu[s], D.u[dst], nn * 8, hipMemcpyDeviceToDevice, st));
+    MLC_HIP(b, hipMemcpyAsync(w + TL.tut[s], D.ut, nn * 8, hipMemcpyDeviceToDevice, st));
+    MLC_HIP(b, launch_tape_tiles(items, nitems, w + P.store, s, (double*)(w + TL.te[s]),
+                                 (const int64_t*)(w + TL.te_off[s]), st));
+    MLC_HIP(b, hipMemcpyAsync(rr, D.rr_y, (size_t)nH * 8, hipMemcpyDeviceToDevice, st));
+    MLC_HIP(b, hipMemcpyAsync(rr + nH, D.rr_t, 8, hipMemcpyDeviceToDevice, st));
+    MLC_HIP(b, hipMemcpyAsync(rr + nH + 1, D.fg, (size_t)2 * nH * 8, hipMemcpyDeviceToDevice, st));
+    MLC_HIP(b, hipMemcpyAsync(rr + 3 * nH + 1, D.rr_ab, 16, hipMemcpyDeviceToDevice, st));
+    MLC_HIP(b, hipMemcpyAsync(rr + 3 * nH + 3, D.lam + (size_t)dst * MLC_MAX_Q, 8,
+                              hipMemcpyDeviceToDevice, st));
+  }
   if (timing) {
     MLC_HIP(b, hipEventRecord(ev[3], st));
     b->ev_pending.push_back(ev);
@@ -756,6 +842,7 @@ mlc_status mlc_default_opts(mlc_solver_opts* o) {
   o->omega = 0.8;
   o->block = 0;
   o->timing = 0;
+  o->record_tape = 0;
   return MLC_OK;
 }
 
@@ -860,6 +947,118 @@ mlc_status mlc_set_state(mlc_ctx* c, int32_t level, const double* lam_host, cons
   return MLC_OK;
 }
 
+// Reverse sweep over every level (see kernels_adj.hip for the formulas).
+static mlc_status backward_impl(mlc_batch* b, double lambda_bar, double* out, bool hf_only) {
+  const Plan& P = b->plan;
+  const TapeLayout& T = P.tape;
+  const Geometry& g = P.geo[0];
+  char* w = b->ws;
+  hipStream_t st = b->st;
+  const ProbDev* dp = b->dprob;
+  const int L = g.L, nH = g.nH;
+  const int nc1sq = (g.nc + 1) * (g.nc + 1);
+  auto D = [&](size_t off) { return (double*)(w + off); };
+  double* scal = D(T.scal);  // [0] c_bar_u, [1 + l] lambda_bar of level l
+  for (int l = 0; l <= L; ++l) {
+    MLC_HIP(b, hipMemsetAsync(w + T.klo[l], 0, (size_t)(g.N(l) * g.N(l)) * 8, st));
+    MLC_HIP(b, hipMemsetAsync(w + T.kup[l], 0, (size_t)(g.N(l) * g.N(l)) * 8, st));
+  }
+  MLC_HIP(b, hipMemsetAsync(w + T.adj_u, 0, (size_t)g.nodes(L) * 8, st));
+  MLC_HIP(b, hipStreamSynchronize(st));
+  MLC_HIP(b, hipMemcpy(scal + 1 + L, &lambda_bar, 8, hipMemcpyHostToDevice));
+  if (hf_only) {  // Hellmann-Feynman reference: lambda_bar (u, dK u) on the finest level
+    MLC_HIP(b, launch_adj_products(dp, L, g.N(L) * g.N(L), D(T.tu[L]), scal + 1 + L, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   D(T.klo[L]), D(T.kup[L]), st));
+    MLC_HIP(b, launch_adj_out(D(T.klo[L]), D(T.kup[L]), (int)g.N(L), g.kind, g.nc, out, st));
+    MLC_HIP(b, hipStreamSynchronize(st));
+    return MLC_OK;
+  }
+  MLC_HIP(b, launch_coarse_combine(dp, nc1sq, D(T.e0), D(T.v0grid), st));
+  double* rchain = b->hp[0].rchain;
+  for (int m = L; m >= 1; --m) {
+    const int k = m - 1;
+    const StepTables& S = P.steps[m];
+    const TileItem* items = (const TileItem*)(w + S.items_off);
+    const int32_t* sub_item = (const int32_t*)(w + S.sub_item_off);
+    const int nitems = (int)S.items.size();
+    const int64_t nn = g.nodes(m);
+    const double* rr = D(T.trr[m]);
+    const double* u_m = D(T.tu[m]);
+    const double* ut_m = D(T.tut[m]);
+    // c_bar = S^T u_bar: restriction of u_bar to the coarse grid, then V^T; and u~ . u_bar
+    const double* src = D(T.adj_u);
+    for (int l = m - 1; l >= 0; --l) {
+      double* dst = rchain + P.pl[0].rchain_off[l];
+      MLC_HIP(b, launch_restrict1(dp, src, dst, l, g.nodes(l), st));
+      src = dst;
+    }
+    MLC_HIP(b, launch_coarse_project(dp, nH, src, D(T.cbar_H), st));
+    MLC_HIP(b, launch_dot_sum(dp, m, nn, ut_m, D(T.adj_u), false, D(T.parts), scal, st));
+    MLC_HIP(b, launch_adj_rr(dp, rr, D(T.cbar_H), scal, scal + 1 + m, D(T.ycoef), D(T.coef), st));
+    MLC_HIP(b, launch_coarse_combine(dp, nc1sq, D(T.ycoef), D(T.ygrid), st));
+    MLC_HIP(b, launch_adj_shat(dp, m, nn, D(T.ygrid), D(T.coef), ut_m, D(T.shat), st));
+    MLC_HIP(b, launch_adj_utbar(g.kind, dp, m, nn, u_m, D(T.shat), D(T.adj_u), D(T.coef), rr,
+                                D(T.utbar), st));
+    // adjoint local solves z_j = K_j^-1 (chi_j u~_bar)
+    MLC_HIP(b, launch_adj_tile_rhs(dp, items, nitems, sub_item, w + P.store, m, D(T.utbar), st));
+    MLC_HIP(b, launch_local_pcg(g.kind, b->blocks[m], dp, items, nitems, w + P.store,
+                                (const double*)(w + P.inv), m, (ItemStat*)(w + P.stats),
+                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 1, st));
+    MLC_HIP(b, launch_adj_rbar(dp, items, sub_item, w + P.store, m, nn, D(T.rbar), st));
+    const double* u_k = (k == 0) ? D(T.v0grid) : D(T.tu[k]);
+    const double* lam_k = (k == 0) ? b->hp[0].Lam : D(T.trr[k]) + 3 * nH + 3;
+    MLC_HIP(b, launch_adj_next(g.kind, dp, m, nn, u_k, lam_k, D(T.utbar), D(T.rbar), D(T.ubar),
+                               D(T.adj_next), st));
+    MLC_HIP(b, launch_dot_sum(dp, m, nn, D(T.rbar), D(T.ubar), true, D(T.parts), scal + 1 + k, st));
+    MLC_HIP(b, launch_adj_products(dp, m, g.N(m) * g.N(m), u_m, scal + 1 + m, D(T.shat), D(T.rbar),
+                                   D(T.ubar), items, sub_item, w + P.store, D(T.te[m]),
+                                   (const int64_t*)(w + T.te_off[m]), D(T.klo[m]), D(T.kup[m]), st));
+    MLC_HIP(b, launch_restrict1(dp, D(T.adj_next), D(T.adj_u), k, g.nodes(k), st));
+  }
+  // level 0: the coarse eigenpair (lambda_0, v_0) of the full eigendecomposition
+  MLC_HIP(b, launch_adj_level0(dp, nH, D(T.adj_u), D(T.a0), st));
+  MLC_HIP(b, launch_coarse_combine(dp, nc1sq, D(T.a0), D(T.ygrid), st));
+  MLC_HIP(b, launch_adj_products(dp, 0, g.N(0) * g.N(0), D(T.v0grid), scal + 1, D(T.ygrid),
+                                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 D(T.klo[0]), D(T.kup[0]), st));
+  // children-mean coefficients: every triangle passes 1/4 of its adjoint to its children
+  for (int l = 1; l <= L; ++l)
+    MLC_HIP(b, launch_adj_down(D(T.klo[l - 1]), D(T.kup[l - 1]), D(T.klo[l]), D(T.kup[l]),
+                               (int)g.N(l - 1), st));
+  MLC_HIP(b, launch_adj_out(D(T.klo[L]), D(T.kup[L]), (int)g.N(L), g.kind, g.nc, out, st));
+  MLC_HIP(b, hipStreamSynchronize(st));
+  return MLC_OK;
+}
+
+mlc_status mlc_backward(mlc_ctx* c, double lambda_bar, double* kappa_bar_dev) {
+  if (!c || !kappa_bar_dev) return MLC_EINVAL;
+  mlc_batch* b = c->b;
+  if (!b->plan.tape.on) {
+    b->err = "backward needs opts.record_tape = 1";
+    return MLC_EINVAL;
+  }
+  if (b->step != b->plan.Lmax || b->shift[0] != 0) {
+    b->err = "backward needs a complete forward run (coarse_setup, then every level_correct)";
+    return MLC_ESTATE;
+  }
+  return backward_impl(b, lambda_bar, kappa_bar_dev, false);
+}
+
+mlc_status mlc_hf_gradient(mlc_ctx* c, double* kappa_bar_dev) {
+  if (!c || !kappa_bar_dev) return MLC_EINVAL;
+  mlc_batch* b = c->b;
+  if (!b->plan.tape.on) {
+    b->err = "the Hellmann-Feynman gradient needs opts.record_tape = 1";
+    return MLC_EINVAL;
+  }
+  if (b->step != b->plan.Lmax || b->shift[0] != 0) {
+    b->err = "the Hellmann-Feynman gradient needs a complete forward run";
+    return MLC_ESTATE;
+  }
+  return backward_impl(b, 1.0, kappa_bar_dev, true);
+}
+
 mlc_status mlc_phase_times(mlc_ctx* c, double* ms, int32_t n) {
   if (!c || !ms || n < 1) return MLC_EINVAL;
   return phase_times(c->b, ms, n);
@@ -931,6 +1130,19 @@ mlc_status mlc_batch_rewind(mlc_batch* b) {
   }
   b->step -= 1;
   b->can_rewind = false;
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_restart(mlc_batch* b) {
+  if (!b) return MLC_EINVAL;
+  if (b->step < 0) {
+    b->err = "restart needs setup";
+    return MLC_ESTATE;
+  }
+  MLC_HIP(b, launch_init_u0(b->dprob, b->plan.n, 0, b->plan.max_nc1sq, b->st));
+  b->step = 0;
+  b->can_rewind = false;
+  std::fill(b->shift.begin(), b->shift.end(), 0);
   return MLC_OK;
 }
 

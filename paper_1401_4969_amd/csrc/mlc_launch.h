@@ -10,9 +10,8 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
                                    int64_t max_nodes, hipStream_t s);
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                            double rtol, int max_it, int nu, double omega, int64_t lds_bytes,
+                            double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
                             hipStream_t s);
-int64_t pcg_lds_bytes(const TileItem* items, int nitems, int m, int elem_bytes);
 hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
@@ -46,3 +45,42 @@ hipError_t launch_output_signed(const double* u, int64_t nn, int q, double* part
                                 hipStream_t s);
 hipError_t launch_set_state(const ProbDev* prob, int level, int dst, const double* in,
                             int64_t nn, hipStream_t s);
+
+// ---- adjoint (reverse sweep) ----
+hipError_t launch_tape_tiles(const TileItem* items, int nitems, const char* store, int m, double* te,
+                             const int64_t* te_off, hipStream_t s);
+hipError_t launch_restrict1(const ProbDev* p, const double* in, double* out, int l, int64_t nodes_l,
+                            hipStream_t s);
+hipError_t launch_coarse_project(const ProbDev* p, int nH, const double* a, double* out,
+                                 hipStream_t s);
+hipError_t launch_coarse_combine(const ProbDev* p, int nc1sq, const double* y, double* grid,
+                                 hipStream_t s);
+hipError_t launch_dot_sum(const ProbDev* p, int m, int64_t nodes, const double* a, const double* b,
+                          bool mass, double* parts, double* out, hipStream_t s);
+hipError_t launch_adj_rr(const ProbDev* p, const double* rr, const double* cbar_H,
+                         const double* cbar_u, const double* lam_bar, double* y, double* coef,
+                         hipStream_t s);
+hipError_t launch_adj_shat(const ProbDev* p, int m, int64_t nodes, const double* ygrid,
+                           const double* coef, const double* ut, double* shat, hipStream_t s);
+hipError_t launch_adj_utbar(int kind, const ProbDev* p, int m, int64_t nodes, const double* u,
+                            const double* shat, const double* ubar_m, const double* coef,
+                            const double* rr, double* out, hipStream_t s);
+hipError_t launch_adj_tile_rhs(const ProbDev* p, const TileItem* items, int nitems,
+                               const int32_t* sub_item, char* store, int m, const double* utbar,
+                               hipStream_t s);
+hipError_t launch_adj_rbar(const ProbDev* p, const TileItem* items, const int32_t* sub_item,
+                           const char* store, int m, int64_t nodes, double* rbar, hipStream_t s);
+hipError_t launch_adj_next(int kind, const ProbDev* p, int m, int64_t nodes, const double* uk,
+                           const double* lam_k, const double* utbar, const double* rbar,
+                           double* ubar, double* next, hipStream_t s);
+hipError_t launch_adj_products(const ProbDev* p, int m, int64_t cells, const double* u,
+                               const double* c_uu, const double* shat, const double* rbar,
+                               const double* ubar, const TileItem* items, const int32_t* sub_item,
+                               const char* store, const double* te, const int64_t* te_off,
+                               double* klo, double* kup, hipStream_t s);
+hipError_t launch_adj_level0(const ProbDev* p, int nH, const double* ubar0, double* a,
+                             hipStream_t s);
+hipError_t launch_adj_down(const double* plo, const double* pup, double* clo, double* cup, int Nc,
+                           hipStream_t s);
+hipError_t launch_adj_out(const double* lo, const double* up, int N, int kind, int nc, double* out,
+                          hipStream_t s);

@@ -3,9 +3,11 @@
 Calls only the CPU oracle (``oracle/``) on the seeded workloads (``workloads.py``); no
 value here comes from the GPU path.  Output: tests/golden/oracle_<name>.json with the
 per-level eigenvalues and, for the finest level, eigenvector values at a seeded sample
-of interior nodes (each vector with non-negative nodal sum).
+of interior nodes (each vector with non-negative nodal sum); configuration 4's per-level
+eigenvalues for all 256 problems; and for configuration 5, central differences of the
+finest eigenvalue along seeded kappa directions (checks of the reverse sweep).
 
-    python tests/golden/make_golden.py [c1 c2 c3 c5 ...]
+    python tests/golden/make_golden.py [c1 c2 c3 c5 c4 c5_fd ...]
 """
 import json
 import os
@@ -77,9 +79,37 @@ def make_batch(workers: int = 6):
     print(f"c4: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
 
 
+def _lam_along(args):
+    name, j, t = args
+    prob = CONFIGS[name]()
+    d = W.kappa_directions(prob.kappa)[j]
+    return solve(prob.with_(kappa=prob.kappa + t * d), keep_levels=False).lam[0]
+
+
+def make_fd(name: str = "c5", t: float = 1e-4, workers: int = 6):
+    """Central differences (lambda(kappa + t d) - lambda(kappa - t d)) / (2 t) of the
+    oracle's finest eigenvalue along the seeded directions of W.kappa_directions."""
+    from multiprocessing import Pool
+    nd = len(W.kappa_directions(CONFIGS[name]().kappa))
+    jobs = [(name, j, s * t) for j in range(nd) for s in (1.0, -1.0)]
+    t0 = time.perf_counter()
+    with Pool(min(workers, len(jobs))) as pool:
+        lam = pool.map(_lam_along, jobs, chunksize=1)
+    fd = [(lam[2 * j] - lam[2 * j + 1]) / (2 * t) for j in range(nd)]
+    path = os.path.join(HERE, f"oracle_{name}_fd.json")
+    with open(path, "w") as f:
+        json.dump(dict(name=CONFIGS[name]().name, t=t, lam_plus=lam[0::2], lam_minus=lam[1::2],
+                       directional_fd=fd, directions="workloads.kappa_directions(kappa), seed 501",
+                       source="oracle.solve (CPU FP64), written by tests/golden/make_golden.py"),
+                  f, indent=1)
+    print(f"{name} fd: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
+
+
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CONFIGS) + ["c4"]):
+    for n in (sys.argv[1:] or list(CONFIGS) + ["c4", "c5_fd"]):
         if n == "c4":
             make_batch()
+        elif n == "c5_fd":
+            make_fd("c5")
         else:
             make(n)

@@ -148,6 +148,23 @@ def config5(seed: int = 5) -> Problem:
                    "c5_square_H16_h1024_8x8_grf")
 
 
+def kappa_directions(kappa: np.ndarray, seed: int = 501) -> List[np.ndarray]:
+    """Seeded perturbation directions d for directional derivatives of lambda_1 along
+    kappa + t d: a cellwise Gaussian scaling, a block patch of cells, and a smooth
+    sinusoid, each multiplied by kappa so that t is a relative step."""
+    k = np.asarray(kappa, dtype=np.float64)
+    ny, nx = k.shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d1 = k * rng.standard_normal(k.shape)
+    d2 = np.zeros_like(k)
+    d2[ny * 5 // 16:ny * 9 // 16, nx * 3 // 16:nx * 7 // 16] = 1.0
+    d2 *= k
+    y = (np.arange(ny) + 0.5) / ny
+    x = (np.arange(nx) + 0.5) / nx
+    d3 = k * np.outer(np.sin(np.pi * y), np.cos(2 * np.pi * x))
+    return [d1, d2, d3]
+
+
 def small_ragged(seed: int = 11) -> Problem:
     """Small L-shape with uneven subdomain splits and random per-coarse-cell kappa."""
     rng = np.random.Generator(np.random.PCG64(seed))
