@@ -296,6 +296,71 @@ def solve(prob, opts: Optional[SolverOpts] = None, device: str = "cuda:0", stats
     return lam, u, levels, st
 
 
+def _problem_with_kappa(prob, kappa: np.ndarray):
+    """A Problem-like record equal to ``prob`` with ``kappa`` replaced."""
+    from types import SimpleNamespace
+    f = {k: getattr(prob, k) for k in ("domain", "n_coarse", "n_refine", "sub_x", "sub_y",
+                                       "overlap", "n_eig", "coef_kind")}
+    return SimpleNamespace(kappa=kappa, **f)
+
+
+_autograd_cls = None
+
+
+def _multilevel_eigen_cls():
+    global _autograd_cls
+    if _autograd_cls is not None:
+        return _autograd_cls
+    import torch
+
+    class MultilevelEigen(torch.autograd.Function):
+        """lambda_1 of the multilevel correction as a function of the coefficient kappa
+        (per coarse cell or per finest cell, float64); the backward pass is the library's
+        reverse sweep (mlc_backward).  ``prob`` supplies everything but kappa."""
+
+        @staticmethod
+        def forward(ctx, kappa, prob, opts=None):
+            if int(prob.n_eig) != 1 or int(prob.coef_kind) not in (1, 2):
+                raise ValueError("MultilevelEigen needs n_eig = 1 and coef_kind 1 or 2")
+            k = np.ascontiguousarray(kappa.detach().to("cpu", torch.float64).numpy())
+            p = _problem_with_kappa(prob, k)
+            o = SolverOpts.from_buffer_copy(opts if opts is not None else default_opts())
+            o.record_tape = 1 if ctx.needs_input_grad[0] else 0
+            dev = kappa.device if kappa.is_cuda else torch.device("cuda:0")
+            s = Solver(p, o, device=str(dev))
+            s.coarse_setup()
+            s.run()
+            lam, _ = s.eigenpairs(with_vectors=False)
+            if o.record_tape:
+                ctx.solver = s
+            else:
+                s.close()
+            ctx.kappa_device = kappa.device
+            return torch.tensor(lam[0], dtype=torch.float64, device=kappa.device)
+
+        @staticmethod
+        def backward(ctx, grad_lam):
+            s = ctx.solver
+            g = s.backward(float(grad_lam))
+            s.close()
+            ctx.solver = None
+            return g.to(ctx.kappa_device), None, None
+
+    _autograd_cls = MultilevelEigen
+    return _autograd_cls
+
+
+def __getattr__(name):
+    if name == "MultilevelEigen":
+        return _multilevel_eigen_cls()
+    raise AttributeError(name)
+
+
+def eigenvalue(kappa, prob, opts: Optional[SolverOpts] = None):
+    """Differentiable lambda_1(kappa): ``MultilevelEigen.apply(kappa, prob, opts)``."""
+    return _multilevel_eigen_cls().apply(kappa, prob, opts)
+
+
 def batch_workspace_size(probs, opts: Optional[SolverOpts] = None) -> int:
     lib = load_library()
     opts = opts or default_opts()

@@ -5,9 +5,10 @@ value here comes from the GPU path.  Output: tests/golden/oracle_<name>.json wit
 per-level eigenvalues and, for the finest level, eigenvector values at a seeded sample
 of interior nodes (each vector with non-negative nodal sum); configuration 4's per-level
 eigenvalues for all 256 problems; and for configuration 5, central differences of the
-finest eigenvalue along seeded kappa directions (checks of the reverse sweep).
+finest eigenvalue along seeded kappa directions and with respect to 32 seeded single
+cells (checks of the reverse sweep).
 
-    python tests/golden/make_golden.py [c1 c2 c3 c5 c4 c5_fd ...]
+    python tests/golden/make_golden.py [c1 c2 c3 c5 c4 c5_fd c5_cells ...]
 """
 import json
 import os
@@ -105,11 +106,50 @@ def make_fd(name: str = "c5", t: float = 1e-4, workers: int = 6):
     print(f"{name} fd: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
 
 
+def _lam_cell(args):
+    name, cell, rel = args
+    prob = CONFIGS[name]()
+    k = prob.kappa.copy()
+    k.flat[cell] *= 1.0 + rel
+    return solve(prob.with_(kappa=k), keep_levels=False).lam[0]
+
+
+def make_cell_fd(name: str = "c5", n_cells: int = 32, seed: int = 55,
+                 steps=(1e-3, 1e-2), workers: int = 6):
+    """Central differences of the oracle's finest eigenvalue with respect to single
+    kappa entries (cells drawn with numpy PCG64(seed)), at two relative steps."""
+    from multiprocessing import Pool
+    prob = CONFIGS[name]()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cells = np.sort(rng.choice(prob.kappa.size, size=n_cells, replace=False)).tolist()
+    jobs = [(name, c, sg * t) for t in steps for c in cells for sg in (1.0, -1.0)]
+    t0 = time.perf_counter()
+    with Pool(workers) as pool:
+        lam = pool.map(_lam_cell, jobs, chunksize=1)
+    fd = {}
+    i = 0
+    for t in steps:
+        vals = []
+        for c in cells:
+            h = t * prob.kappa.flat[c]
+            vals.append((lam[i] - lam[i + 1]) / (2 * h))
+            i += 2
+        fd[repr(t)] = vals
+    path = os.path.join(HERE, f"oracle_{name}_cells.json")
+    with open(path, "w") as f:
+        json.dump(dict(name=prob.name, seed=seed, cells=cells, steps=list(steps), fd=fd,
+                       source="oracle.solve (CPU FP64), written by tests/golden/make_golden.py"),
+                  f, indent=1)
+    print(f"{name} cell fd: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
+
+
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CONFIGS) + ["c4", "c5_fd"]):
+    for n in (sys.argv[1:] or list(CONFIGS) + ["c4", "c5_fd", "c5_cells"]):
         if n == "c4":
             make_batch()
         elif n == "c5_fd":
             make_fd("c5")
+        elif n == "c5_cells":
+            make_cell_fd("c5")
         else:
             make(n)

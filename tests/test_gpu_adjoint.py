@@ -151,3 +151,24 @@ def test_config5_gradient():
     for d, fd in zip(W.kappa_directions(prob.kappa), gold["directional_fd"]):
         got = float(np.sum(g * d))
         assert abs(got - fd) < 1e-5 * abs(fd), (got, fd)
+
+
+def test_autograd_function():
+    """MultilevelEigen.apply: forward equals the solver's lambda_1; backward equals
+    mlc_backward scaled by the incoming gradient, for device and host kappa."""
+    torch = _torch()
+    import paper_1401_4969_amd as mlc
+    prob = W.small_field()
+    lam, g, _ = gpu_grad(prob)
+    for dev in ("cuda:0", "cpu"):
+        kappa = torch.tensor(prob.kappa, dtype=torch.float64, device=dev, requires_grad=True)
+        lam_t = mlc.MultilevelEigen.apply(kappa, prob)
+        assert lam_t.device == kappa.device and lam_t.item() == lam
+        (3.0 * lam_t).backward()
+        assert kappa.grad.device == kappa.device
+        assert np.max(np.abs(kappa.grad.cpu().numpy() - 3.0 * g)) <= 1e-13 * np.max(np.abs(g))
+    with torch.no_grad():
+        v = mlc.eigenvalue(torch.tensor(prob.kappa, dtype=torch.float64), prob)
+    assert v.item() == lam
+    with pytest.raises(ValueError):
+        mlc.eigenvalue(torch.ones(4, 4, dtype=torch.float64), W.config1())
