@@ -83,7 +83,7 @@ typedef struct mlc_solver_opts {
   double rtol;         /* local solve: ||r||_2 <= rtol * ||b||_2 from a zero guess (1e-12) */
   int32_t max_it;      /* PCG iterations per local solve (FP64) or per inner solve (200) */
   int32_t max_refine;  /* mixed precision: FP64 refinement steps (10) */
-  double inner_rtol;   /* mixed precision: FP32 inner solve relative tolerance (1e-5) */
+  double inner_rtol;   /* mixed precision: FP32 inner solve relative tolerance (1e-4) */
   int32_t nu;          /* damped Jacobi sweeps before and after each coarse correction (2) */
   double omega;        /* Jacobi damping (0.8) */
   int32_t block;       /* threads per workgroup of the local solver: 256, 512 or 1024 (0 = 1024) */

@@ -14,14 +14,13 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
                                                     char* store, const double* inv, int m,
                                                     ItemStat* stats, double rtol, int max_it,
                                                     int max_refine, double inner_rtol, int nu,
-                                                    double omega) {
-  __shared__ LevelDesc lev[MLC_MAX_LEVELS + 1];
+                                                    double omega, int ring_on) {
   __shared__ double red[2 * (NT / 64)];
+  extern __shared__ float ring_lds_f[];  // banded post-smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
   const ProbDev& P = probs[it.prob];
-  if (threadIdx.x == 0) fill_levels(it, P, m, 2, lev);
-  __syncthreads();
-  const LevelDesc& l0 = lev[0];
+  const Levels lev(it, P, m, 2);
+  const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
   double* E = reinterpret_cast<double*>(store + it.off);      // FP64 correction, read by the gluing
   float* base = reinterpret_cast<float*>(store + it.off + 8 * S0);
@@ -35,7 +34,7 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   };
   double acc[2] = {0.0, 0.0};
   FOR_TILE(l0) {
-    const int64_t i = (int64_t)iy * l0.nx + ix;
+    const unsigned i = (unsigned)(iy * l0.nx + ix);
     const double v = bat(ix, iy);
     E[i] = 0.0;
     R[i] = (float)v;
@@ -50,16 +49,17 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     ++refine;
     double rr_inner;
     total += pcg_solve<NT, KIND, float>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
-                                        max_it, nu, omega, red, rr_inner);
+                                        max_it, nu, omega, red, ring_on ? ring_lds_f : nullptr,
+                                        rr_inner);
     FOR_TILE(l0) {
-      const int64_t i = (int64_t)iy * l0.nx + ix;
+      const unsigned i = (unsigned)(iy * l0.nx + ix);
       E[i] += (double)X[i];
     }
     __syncthreads();
     // FP64 residual of the accumulated correction, handed to the next FP32 solve
     acc[0] = acc[1] = 0.0;
     FOR_TILE(l0) {
-      const int64_t i = (int64_t)iy * l0.nx + ix;
+      const unsigned i = (unsigned)(iy * l0.nx + ix);
       double r = 0.0;
       if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
         double d;
@@ -99,10 +99,14 @@ int64_t item_bytes_mixed(int cw, int ch, int m) {
 hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
-                              double omega, hipStream_t s) {
+                              double omega, int max_tile_nx, hipStream_t s) {
+  // the ring is sized for the workgroup size actually launched
+  const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
+  const size_t lds = nu == 2 ? post_ring_bytes(ntv, max_tile_nx, 4) : 0;
 #define MLC_MIX(NTV, KV)                                                                     \
-  hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), 0, s, probs, items,   \
-                     store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega)
+  hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
+                     store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \
+                     lds > 0 ? 1 : 0)
 #define MLC_MIX_NT(NTV) \
   if (kind == 0)        \
     MLC_MIX(NTV, 0);    \

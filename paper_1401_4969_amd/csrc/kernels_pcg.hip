@@ -20,22 +20,22 @@ template <int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const TileItem* items,
                                                      char* store, const double* inv, int m,
                                                      ItemStat* stats, double rtol, int max_it,
-                                                     int nu, double omega, int rhs_in_tile) {
-  __shared__ LevelDesc lev[MLC_MAX_LEVELS + 1];
+                                                     int nu, double omega, int rhs_in_tile,
+                                                     int ring_on) {
   __shared__ double red[2 * (NT / 64)];
+  extern __shared__ double ring_lds[];  // banded post-smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
   const ProbDev& P = probs[it.prob];
-  if (threadIdx.x == 0) fill_levels(it, P, m, 2, lev);
-  __syncthreads();
+  const Levels lev(it, P, m, 2);
   double* base = reinterpret_cast<double*>(store + it.off);
-  const LevelDesc& l0 = lev[0];
+  const LevelDesc l0 = lev[0];
   double* X = base;
   double* R = base + l0.ob;
   const int n1 = l0.N + 1;
   const double* bglob = P.res + (int64_t)it.rhs * n1 * n1;
   double acc[2] = {0.0, 0.0};
   FOR_TILE(l0) {
-    const int64_t i = (int64_t)iy * l0.nx + ix;
+    const unsigned i = (unsigned)(iy * l0.nx + ix);
     // right-hand side: the global residual window, or (adjoint solves) already in R
     const double v = rhs_in_tile ? R[i] : bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
     R[i] = v;
@@ -46,7 +46,8 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   const double bb = acc[0];
   double rr = bb;
   const int iters = pcg_solve<NT, KIND, double>(P, lev, base, m, inv + it.inv_off, bb,
-                                                rtol * rtol * bb, max_it, nu, omega, red, rr);
+                                                rtol * rtol * bb, max_it, nu, omega, red,
+                                                ring_on ? ring_lds : nullptr, rr);
   if (threadIdx.x == 0) {
     ItemStat s;
     s.iters = iters;
@@ -69,13 +70,31 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
   return total * (int64_t)sizeof(double);
 }
 
+size_t post_ring_bytes(int nt, int max_tile_nx, int elem_bytes) {
+  static int limit = -1;
+  if (limit < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 0;
+    limit = v;
+  }
+  const size_t bytes = (size_t)2 * (nt / 64 + 2) * (size_t)max_tile_nx * elem_bytes;
+  // keep room for the reduction buffer and the compiler's own LDS
+  return bytes + 4096 <= (size_t)limit ? bytes : 0;
+}
+
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
                             double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
-                            hipStream_t s) {
+                            int max_tile_nx, hipStream_t s) {
+  // the ring is sized for the workgroup size actually launched
+  const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
+  const size_t lds = nu == 2 ? post_ring_bytes(ntv, max_tile_nx, 8) : 0;
 #define MLC_PCG(NTV, KV)                                                                        \
-  hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), 0, s, probs, items,      \
-                     store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile)
+  hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
+                     store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile,           \
+                     lds > 0 ? 1 : 0)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \
     MLC_PCG(NTV, 0);       \
@@ -94,4 +113,3 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
 #undef MLC_PCG
   return hipGetLastError();
 }
-

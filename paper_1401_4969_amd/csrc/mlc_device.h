@@ -77,6 +77,10 @@ struct Weights {
   double e, w, n, s;
 };
 
+// Coefficient arrays are reached through pointers held in ProbDev; the cast to the
+// global address space lets the compiler emit global (not flat) loads for them.
+typedef __attribute__((address_space(1))) const double gconst_double;
+
 template <int KIND>
 __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, int gx, int gy) {
   Weights W;
@@ -84,7 +88,7 @@ __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, 
     W.e = W.w = W.n = W.s = 1.0;
   } else if (KIND == 1) {
     const int nc = P.n_c;
-    const double* k = P.kH;
+    const gconst_double* k = (const gconst_double*)P.kH;
     const int cx = gx >> l, cxm = (gx - 1) >> l;
     const int cy = gy >> l, cym = (gy - 1) >> l;
     const double k00 = k[cy * nc + cx];      // cell (gx, gy)
@@ -96,8 +100,8 @@ __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, 
     W.n = 0.5 * (k00 + k10);
     W.s = 0.5 * (k01 + k11);
   } else {
-    const double* lo = P.kLR[l];
-    const double* up = P.kUL[l];
+    const gconst_double* lo = (const gconst_double*)P.kLR[l];
+    const gconst_double* up = (const gconst_double*)P.kUL[l];
     const int c = gy * N + gx;
     // horizontal edge (gx,gy)-(gx+1,gy): lower triangle of cell (gx,gy), upper of (gx,gy-1)
     W.e = 0.5 * (lo[c] + up[c - N]);
@@ -112,6 +116,14 @@ __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, 
 // ---------------------------------------------------------------------------------
 // Workgroup reductions (fixed order: wave butterfly, then waves in index order)
 // ---------------------------------------------------------------------------------
+// A value every lane holds equally, moved to a scalar register.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -136,7 +148,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* lds) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) s += lds[k * NW + w];
-    v[k] = s;
+    v[k] = uniform_f64(s);  // every lane summed the same values in the same order
   }
 }
 

@@ -178,6 +178,7 @@ struct StepTables {
   std::vector<int32_t> sub_item;
   size_t items_off = 0, sub_item_off = 0;
   int64_t max_nodes = 0;         // largest (N_s+1)^2 among the active problems
+  int32_t max_tile_nx = 0;       // widest tile row (interior nodes) among the items
   std::vector<int64_t> nodes_l;  // per coarser level l < s: largest (N_l+1)^2
 };
 
@@ -325,6 +326,7 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     for (size_t k = 0; k < all.size(); ++k) {
       TileItem& it = all[k];
       it.off = (int64_t)o;
+      T.max_tile_nx = std::max(T.max_tile_nx, it.cw * (1 << s) - 1);
       const int64_t b = fp64_items ? item_bytes_fp64(it.cw, it.ch, s)
                                    : item_bytes_mixed(it.cw, it.ch, s);
       o = align_up(o + (size_t)b);
@@ -651,12 +653,13 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
   if (P.precision == 0) {
     MLC_HIP(b, launch_local_pcg(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                 (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
-                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 0, st));
+                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 0, T.max_tile_nx,
+                                st));
   } else {
     MLC_HIP(b, launch_local_mixed(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                   (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
                                   b->o.rtol, b->o.max_it, b->o.max_refine, b->o.inner_rtol,
-                                  b->o.nu, b->o.omega, st));
+                                  b->o.nu, b->o.omega, T.max_tile_nx, st));
   }
   if (timing) MLC_HIP(b, hipEventRecord(ev[2], st));
   MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, st));
@@ -837,7 +840,7 @@ mlc_status mlc_default_opts(mlc_solver_opts* o) {
   o->rtol = 1e-12;
   o->max_it = 200;
   o->max_refine = 10;
-  o->inner_rtol = 1e-5;
+  o->inner_rtol = 1e-4;
   o->nu = 2;
   o->omega = 0.8;
   o->block = 0;
@@ -1004,7 +1007,8 @@ static mlc_status backward_impl(mlc_batch* b, double lambda_bar, double* out, bo
     MLC_HIP(b, launch_adj_tile_rhs(dp, items, nitems, sub_item, w + P.store, m, D(T.utbar), st));
     MLC_HIP(b, launch_local_pcg(g.kind, b->blocks[m], dp, items, nitems, w + P.store,
                                 (const double*)(w + P.inv), m, (ItemStat*)(w + P.stats),
-                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 1, st));
+                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 1,
+                                P.steps[m].max_tile_nx, st));
     MLC_HIP(b, launch_adj_rbar(dp, items, sub_item, w + P.store, m, nn, D(T.rbar), st));
     const double* u_k = (k == 0) ? D(T.v0grid) : D(T.tu[k]);
     const double* lam_k = (k == 0) ? b->hp[0].Lam : D(T.trr[k]) + 3 * nH + 3;

@@ -11,11 +11,14 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
                             double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
-                            hipStream_t s);
+                            int max_tile_nx, hipStream_t s);
 hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
-                              double omega, hipStream_t s);
+                              double omega, int max_tile_nx, hipStream_t s);
+// LDS bytes of the banded post-smoothing rings for nt threads and the widest tile row,
+// or 0 when they do not fit the device's per-workgroup LDS (then the sweeps run apart).
+size_t post_ring_bytes(int nt, int max_tile_nx, int elem_bytes);
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
                            const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
                            hipStream_t s);

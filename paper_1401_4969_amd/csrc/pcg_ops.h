@@ -6,6 +6,14 @@
 // Vectors of an item live in its slice of the workspace, row-major over the tile's
 // interior nodes (no halo: outside the tile is the Dirichlet boundary, read as 0).
 // Waves sweep rows, 64 consecutive nodes per wave, so every access is coalesced.
+//
+// The tile vectors do not fit in cache (hundreds of items are live at once), so every
+// pass streams from HBM; passes are merged where that removes a whole vector read or
+// write without a second copy of any vector:
+//   - the first two Jacobi sweeps from a zero iterate are one pass over b;
+//   - r.z is accumulated in the last post-smoothing sweep on the tile level;
+//   - the direction update p = z + beta p and A p are one pass (A p is not stored:
+//     the x/r update applies the stencil to p again).
 #pragma once
 #include "mlc_launch.h"
 
@@ -16,19 +24,28 @@ struct LevelDesc {
   int64_t ob, oz, ot;  // element offsets of right-hand side, iterate, temporary
 };
 
+// Tile indices are 32-bit (the finest grid has at most 32768 cells per side, so a tile
+// has fewer than 2^30 nodes): with a uniform vector base the loads take a scalar base
+// and a 32-bit vector offset instead of a 64-bit address per lane.
 #define FOR_TILE(lv)                                                  \
   for (int iy = threadIdx.x >> 6; iy < (lv).ny; iy += NT / 64)       \
     for (int ix = threadIdx.x & 63; ix < (lv).nx; ix += 64)
 
+// Every load of a sweep is issued unconditionally, from an index clamped into the tile
+// (the node itself stands in for a neighbour off the tile), and the value is then
+// selected: a load behind a branch would be waited for inside that branch, so a stencil
+// would cost several memory round trips instead of one.
 template <int KIND, typename T>
 __device__ __forceinline__ T stencil(const ProbDev& P, const LevelDesc& lv, const T* u, int ix,
-                                     int iy, int64_t i, T& diag) {
+                                     int iy, unsigned i, T& diag) {
   const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+  const bool he = ix + 1 < lv.nx, hw = ix > 0, hn = iy + 1 < lv.ny, hs = iy > 0;
   const T c = u[i];
-  const T e = (ix + 1 < lv.nx) ? u[i + 1] : T(0);
-  const T w = (ix > 0) ? u[i - 1] : T(0);
-  const T n = (iy + 1 < lv.ny) ? u[i + lv.nx] : T(0);
-  const T s = (iy > 0) ? u[i - lv.nx] : T(0);
+  const T e0 = u[he ? i + 1 : i];
+  const T w0 = u[hw ? i - 1 : i];
+  const T n0 = u[hn ? i + lv.nx : i];
+  const T s0 = u[hs ? i - lv.nx : i];
+  const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = hn ? n0 : T(0), s = hs ? s0 : T(0);
   const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
   diag = we + ww + wn + ws;
   return diag * c - we * e - ww * w - wn * n - ws * s;
@@ -38,7 +55,7 @@ __device__ __forceinline__ T stencil(const ProbDev& P, const LevelDesc& lv, cons
 template <int NT, int KIND, typename T>
 __device__ void op_first(const ProbDev& P, const LevelDesc& lv, const T* b, T* z, T omega) {
   FOR_TILE(lv) {
-    const int64_t i = (int64_t)iy * lv.nx + ix;
+    const unsigned i = (unsigned)(iy * lv.nx + ix);
     T v = T(0);
     if (is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy)) {
       const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
@@ -48,17 +65,55 @@ __device__ void op_first(const ProbDev& P, const LevelDesc& lv, const T* b, T* z
   }
 }
 
-// zo = zi + omega D^-1 (b - A zi)
+// z = two damped-Jacobi sweeps from a zero iterate in one pass:
+//   z1 = omega D^-1 b,  z = z1 + omega D^-1 (b - A z1),
+// with z1 formed on the fly at the node and its four neighbours (zero off the tile and
+// on nodes outside the domain, where b is zero and the diagonal need not exist).
+template <int KIND>
+__device__ __forceinline__ double diag_at(const ProbDev& P, const LevelDesc& lv, int ix, int iy) {
+  const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+  return W.e + W.w + W.n + W.s;
+}
+
 template <int NT, int KIND, typename T>
-__device__ void op_jacobi(const ProbDev& P, const LevelDesc& lv, const T* b, const T* zi, T* zo,
-                          T omega) {
+__device__ void op_first2(const ProbDev& P, const LevelDesc& lv, const T* b, T* z, T omega) {
   FOR_TILE(lv) {
-    const int64_t i = (int64_t)iy * lv.nx + ix;
+    const unsigned i = (unsigned)(iy * lv.nx + ix);
+    // first-sweep value at tile node (jx, jy) = index j, zero when `in` is false
+    auto z1 = [&](bool in, int jx, int jy, unsigned j) -> T {
+      const T bj = b[in ? j : i];
+      const T dj = T(diag_at<KIND>(P, lv, in ? jx : ix, in ? jy : iy));
+      const bool ok = in && is_dof(P.domain, lv.N, lv.gx0 + jx, lv.gy0 + jy);
+      return ok ? omega * bj / dj : T(0);
+    };
+    const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+    const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+    const T d = we + ww + wn + ws;
+    const T bc = b[i];
+    const T zc = omega * bc / d;
+    const T ze = z1(ix + 1 < lv.nx, ix + 1, iy, i + 1);
+    const T zw = z1(ix > 0, ix - 1, iy, i - 1);
+    const T zn = z1(iy + 1 < lv.ny, ix, iy + 1, i + lv.nx);
+    const T zs = z1(iy > 0, ix, iy - 1, i - lv.nx);
+    const T az = d * zc - we * ze - ww * zw - wn * zn - ws * zs;
+    const T v = zc + omega * (bc - az) / d;
+    z[i] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy) ? v : T(0);
+  }
+}
+
+// zo = zi + omega D^-1 (b - A zi); with DOT, also acc += b . zo
+template <int NT, int KIND, typename T, bool DOT = false>
+__device__ void op_jacobi(const ProbDev& P, const LevelDesc& lv, const T* b, const T* zi, T* zo,
+                          T omega, double* acc = nullptr) {
+  FOR_TILE(lv) {
+    const unsigned i = (unsigned)(iy * lv.nx + ix);
     T v = T(0);
     if (is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy)) {
       T d;
       const T az = stencil<KIND, T>(P, lv, zi, ix, iy, i, d);
-      v = zi[i] + omega * (b[i] - az) / d;
+      const T bi = b[i];
+      v = zi[i] + omega * (bi - az) / d;
+      if (DOT) *acc += (double)bi * (double)v;
     }
     zo[i] = v;
   }
@@ -68,7 +123,7 @@ __device__ void op_jacobi(const ProbDev& P, const LevelDesc& lv, const T* b, con
 template <int NT, int KIND, typename T>
 __device__ void op_residual(const ProbDev& P, const LevelDesc& lv, const T* b, const T* z, T* ro) {
   FOR_TILE(lv) {
-    const int64_t i = (int64_t)iy * lv.nx + ix;
+    const unsigned i = (unsigned)(iy * lv.nx + ix);
     T v = T(0);
     if (is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy)) {
       T d;
@@ -84,10 +139,10 @@ __device__ void op_restrict(const ProbDev& P, const LevelDesc& lf, const LevelDe
                             const T* rf, T* bc) {
   const int nf = lf.nx;
   FOR_TILE(lc) {
-    const int64_t i = (int64_t)iy * lc.nx + ix;
+    const unsigned i = (unsigned)(iy * lc.nx + ix);
     T v = T(0);
     if (is_dof(P.domain, lc.N, lc.gx0 + ix, lc.gy0 + iy)) {
-      const int64_t c = (int64_t)(2 * iy + 1) * nf + (2 * ix + 1);
+      const unsigned c = (unsigned)((2 * iy + 1) * nf + (2 * ix + 1));
       v = rf[c] + T(0.5) * (rf[c + 1] + rf[c - 1] + rf[c + nf] + rf[c - nf] + rf[c + nf + 1] +
                             rf[c - nf - 1]);
     }
@@ -95,28 +150,120 @@ __device__ void op_restrict(const ProbDev& P, const LevelDesc& lf, const LevelDe
   }
 }
 
-// zf += P zc (P1 interpolation on the SW-NE mesh; coarse nodes outside the tile are 0)
+// zf += P zc (P1 interpolation on the SW-NE mesh; coarse nodes outside the tile are 0).
+// Odd tile indices are even global indices, i.e. coarse nodes.  Every fine node takes
+// half the sum of two coarse values: the same node twice (odd, odd), the W-E pair (even,
+// odd), the S-N pair (odd, even) or the SW-NE pair (even, even).
 template <int NT, typename T>
 __device__ void op_prolong_add(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lf,
                                const T* zc, T* zf) {
   const int ncx = lc.nx, ncy = lc.ny;
+  auto at = [&](int cx, int cy) -> T {
+    const bool in = cx >= 0 && cy >= 0 && cx < ncx && cy < ncy;
+    const T v = zc[in ? (unsigned)(cy * ncx + cx) : 0u];
+    return in ? v : T(0);
+  };
   FOR_TILE(lf) {
-    if (!is_dof(P.domain, lf.N, lf.gx0 + ix, lf.gy0 + iy)) continue;
-    const int64_t i = (int64_t)iy * lf.nx + ix;
-    auto at = [&](int cx, int cy) -> T {
-      return (cx >= 0 && cy >= 0 && cx < ncx && cy < ncy) ? zc[(int64_t)cy * ncx + cx] : T(0);
-    };
-    T v;
-    const bool ox = ix & 1, oy = iy & 1;  // odd tile index = even global index = coarse node
-    if (ox && oy)
-      v = at(ix >> 1, iy >> 1);
-    else if (!ox && oy)
-      v = T(0.5) * (at((ix >> 1) - 1, iy >> 1) + at(ix >> 1, iy >> 1));
-    else if (ox && !oy)
-      v = T(0.5) * (at(ix >> 1, (iy >> 1) - 1) + at(ix >> 1, iy >> 1));
-    else
-      v = T(0.5) * (at((ix >> 1) - 1, (iy >> 1) - 1) + at(ix >> 1, iy >> 1));
-    zf[i] += v;
+    const unsigned i = (unsigned)(iy * lf.nx + ix);
+    const int cx = ix >> 1, cy = iy >> 1;
+    const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((iy & 1) ^ 1);
+    const T v = T(0.5) * (at(ax, ay) + at(cx, cy));
+    const T old = zf[i];
+    zf[i] = is_dof(P.domain, lf.N, lf.gx0 + ix, lf.gy0 + iy) ? old + v : old;
+  }
+}
+
+// One damped-Jacobi update at tile node (ix, y) from three consecutive rows held in LDS
+// (rows -1 and ny are stored as zeros, the Dirichlet values).
+template <int KIND, typename T>
+__device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, const T* rs,
+                                         const T* rc, const T* rn, T bi, int ix, int y, T omega) {
+  const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + y);
+  const bool he = ix + 1 < lv.nx, hw = ix > 0;
+  const T c = rc[ix];
+  const T e0 = rc[he ? ix + 1 : ix], w0 = rc[hw ? ix - 1 : ix];
+  const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = rn[ix], s = rs[ix];
+  const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+  const T d = we + ww + wn + ws;
+  const T az = d * c - we * e - ww * w - wn * n - ws * s;
+  return c + omega * (bi - az) / d;
+}
+
+// Post-smoothing of a V-cycle level with nu = 2 as one pass over the tile:
+//   za <- J(J(za + P zc)),   J(z) = z + omega D^-1 (b - A z).
+// The workgroup walks the tile in bands of NW rows, one row per wave.  The prolonged
+// iterate and the first sweep pass through two LDS rings of NW + 2 rows each, so za is
+// read once and written once and b is read twice (the second time from cache), instead
+// of the 8 passes of a separate interpolation and two sweeps.  At step k wave w forms
+// row k NW + w - 1 of za + P zc (stage A), the first sweep on the row below (stage B)
+// and the second sweep two rows below (stage C, written into za in place: no later stage
+// reads za at or below that row).  A row of a ring is overwritten only after the barrier
+// that follows its last reader.
+template <int NT, int KIND, typename T, bool DOT>
+__device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
+                              const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
+  constexpr int NW = NT / 64, RING = NW + 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = lv.nx, ny = lv.ny;
+  T* ringA = ring;
+  T* ringB = ring + RING * nx;
+  auto row = [&](T* r, int y) -> T* { return r + ((y + 1) % RING) * nx; };
+  const int ncx = lc.nx, ncy = lc.ny;
+  auto at = [&](int cx, int cy) -> T {
+    const bool in = cx >= 0 && cy >= 0 && cx < ncx && cy < ncy;
+    const T v = zc[in ? (unsigned)(cy * ncx + cx) : 0u];
+    return in ? v : T(0);
+  };
+  for (int k = 0; k * NW - 3 < ny; ++k) {
+    const int ya = k * NW + w - 1;
+    if (ya >= -1 && ya <= ny) {
+      T* dst = row(ringA, ya);
+      const bool inside = ya >= 0 && ya < ny;
+      for (int ix = lane; ix < nx; ix += 64) {
+        T v = T(0);
+        if (inside) {
+          const unsigned i = (unsigned)(ya * nx + ix);
+          const int cx = ix >> 1, cy = ya >> 1;
+          const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
+          const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
+          const T old = za[i];
+          v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
+        }
+        dst[ix] = v;
+      }
+    }
+    __syncthreads();
+    const int yb = ya - 1;
+    if (yb >= -1 && yb <= ny) {
+      T* dst = row(ringB, yb);
+      if (yb >= 0 && yb < ny) {
+        const T* rs = row(ringA, yb - 1);
+        const T* rc = row(ringA, yb);
+        const T* rn = row(ringA, yb + 1);
+        for (int ix = lane; ix < nx; ix += 64) {
+          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[(unsigned)(yb * nx + ix)], ix, yb,
+                                           omega);
+          dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+        }
+      } else {
+        for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
+      }
+    }
+    __syncthreads();
+    const int yc = ya - 2;
+    if (yc >= 0 && yc < ny) {
+      const T* rs = row(ringB, yc - 1);
+      const T* rc = row(ringB, yc);
+      const T* rn = row(ringB, yc + 1);
+      for (int ix = lane; ix < nx; ix += 64) {
+        const unsigned i = (unsigned)(yc * nx + ix);
+        const T bi = b[i];
+        const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega);
+        const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
+        za[i] = dof ? v : T(0);
+        if (DOT && dof) *acc += (double)bi * (double)v;
+      }
+    }
   }
 }
 
@@ -132,19 +279,63 @@ __device__ void op_coarse_solve(const LevelDesc& lc, const double* Kinv, const T
   }
 }
 
+// Level descriptors of an item: t = 0 is the tile on level m, t = m its coarse-cell grid.
+// Level-0 buffers: X, R(=rhs of the V-cycle), Z, Tmp, then `extra` vectors; coarser
+// levels: B, Z, Tmp each.  Descriptors are computed on demand from the item; every
+// input is uniform over the workgroup, so they stay in scalar registers (a table in LDS
+// would put every field, and every address formed from it, in vector registers).
+struct Levels {
+  int cw, ch, cx0, cy0, n_c, m, extra;
+  __device__ __forceinline__ Levels(const TileItem& it, const ProbDev& P, int m_, int extra_)
+      : cw(it.cw), ch(it.ch), cx0(it.cx0), cy0(it.cy0), n_c(P.n_c), m(m_), extra(extra_) {}
+  __device__ __forceinline__ int64_t size(int t) const {
+    const int r = 1 << (m - t);
+    return (int64_t)(cw * r - 1) * (ch * r - 1);
+  }
+  __device__ __forceinline__ LevelDesc operator[](int t) const {
+    const int l = m - t;
+    const int r = 1 << l;
+    LevelDesc d;
+    d.nx = cw * r - 1;
+    d.ny = ch * r - 1;
+    d.gx0 = cx0 * r + 1;
+    d.gy0 = cy0 * r + 1;
+    d.N = n_c << l;
+    d.l = l;
+    const int64_t S = (int64_t)d.nx * d.ny;
+    if (t == 0) {
+      d.ob = S;
+      d.oz = 2 * S;
+      d.ot = 3 * S;
+    } else {
+      int64_t off = (4 + extra) * size(0);
+      for (int u = 1; u < t; ++u) off += 3 * size(u);
+      d.ob = off;
+      d.oz = off + S;
+      d.ot = off + 2 * S;
+    }
+    return d;
+  }
+};
+
 // One symmetric V-cycle applied to the level-0 right-hand side at lev[0].ob; returns
-// the buffer that holds the result.
+// the buffer that holds the result z and adds this thread's share of b.z to *rz.  With
+// an LDS ring (non-null `ring`, sized for the tile level) and nu = 2 the post-smoothing
+// of every level runs as one banded pass.
 template <int NT, int KIND, typename T>
-__device__ T* vcycle(const ProbDev& P, const LevelDesc* lev, T* base, int m, const double* Kinv,
-                     int nu, T omega) {
+__device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
+                     int nu, T omega, double* rz, T* ring) {
   for (int t = 0; t < m; ++t) {
-    const LevelDesc& lv = lev[t];
+    const LevelDesc lv = lev[t];
     const T* b = base + lv.ob;
     T* za = base + lv.oz;
     T* zb = base + lv.ot;
-    op_first<NT, KIND, T>(P, lv, b, za, omega);
+    if (nu >= 2)
+      op_first2<NT, KIND, T>(P, lv, b, za, omega);
+    else
+      op_first<NT, KIND, T>(P, lv, b, za, omega);
     __syncthreads();
-    for (int s = 1; s < nu; ++s) {
+    for (int s = 2; s < nu; ++s) {
       op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
       __syncthreads();
       T* tmp = za;
@@ -160,19 +351,34 @@ __device__ T* vcycle(const ProbDev& P, const LevelDesc* lev, T* base, int m, con
   __syncthreads();
   T* zc = base + lev[m].oz;
   for (int t = m - 1; t >= 0; --t) {
-    const LevelDesc& lv = lev[t];
+    const LevelDesc lv = lev[t];
     const T* b = base + lv.ob;
     T* za = base + lv.oz;
     T* zb = base + lv.ot;
-    if ((nu - 1) & 1) {
+    // the pre-smoothed iterate is in za when an even number of single sweeps followed
+    // the first pass (two sweeps for nu >= 2, one for nu = 1)
+    const int singles = nu >= 2 ? nu - 2 : 0;
+    if (singles & 1) {
       T* tmp = za;
       za = zb;
       zb = tmp;
     }
+    if (ring != nullptr && nu == 2) {
+      if (t == 0)
+        op_post_fused<NT, KIND, T, true>(P, lev[t + 1], lv, zc, b, za, omega, ring, rz);
+      else
+        op_post_fused<NT, KIND, T, false>(P, lev[t + 1], lv, zc, b, za, omega, ring, nullptr);
+      __syncthreads();
+      zc = za;
+      continue;
+    }
     op_prolong_add<NT, T>(P, lev[t + 1], lv, zc, za);
     __syncthreads();
     for (int s = 0; s < nu; ++s) {
-      op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+      if (t == 0 && s == nu - 1)
+        op_jacobi<NT, KIND, T, true>(P, lv, b, za, zb, omega, rz);
+      else
+        op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
       __syncthreads();
       T* tmp = za;
       za = zb;
@@ -183,107 +389,82 @@ __device__ T* vcycle(const ProbDev& P, const LevelDesc* lev, T* base, int m, con
   return zc;
 }
 
-// Level descriptors of an item: t = 0 is the tile on level m, t = m its coarse-cell grid.
-// Level-0 buffers: X, R(=rhs of the V-cycle), Z, Tmp, then extra vectors; coarser levels:
-// B, Z, Tmp each.  Returns the element count of the item's storage.
-__device__ inline int64_t fill_levels(const TileItem& it, const ProbDev& P, int m, int extra,
-                               LevelDesc* lev) {
-  int64_t off = 0;
-  for (int t = 0; t <= m; ++t) {
-    const int l = m - t;
-    const int r = 1 << l;
-    LevelDesc d;
-    d.nx = it.cw * r - 1;
-    d.ny = it.ch * r - 1;
-    d.gx0 = it.cx0 * r + 1;
-    d.gy0 = it.cy0 * r + 1;
-    d.N = P.n_c << l;
-    d.l = l;
-    const int64_t S = (int64_t)d.nx * d.ny;
-    if (t == 0) {
-      d.ob = S;
-      d.oz = 2 * S;
-      d.ot = 3 * S;
-      off = (4 + extra) * S;
-    } else {
-      d.ob = off;
-      d.oz = off + S;
-      d.ot = off + 2 * S;
-      off += 3 * S;
-    }
-    lev[t] = d;
-  }
-  return off;
-}
-
 // Preconditioned conjugate gradients on K_j x = r with the V-cycle preconditioner, in
 // the vector type T of the tile buffers (reductions in FP64).  On entry R (level-0
 // right-hand side buffer) holds r and X is zero; bb = ||r||^2.  Iterates until
 // ||r_k||^2 <= tol2 or max_it; returns the iteration count and the final ||r_k||^2 in rr.
+// The search direction alternates between two buffers (the new one is formed from the
+// old one and the preconditioned residual while neighbours still read the old one).
 template <int NT, int KIND, typename T>
-__device__ int pcg_solve(const ProbDev& P, const LevelDesc* lev, T* base, int m, const double* Kinv,
+__device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
                          double bb, double tol2, int max_it, int nu, double omega, double* red,
-                         double& rr) {
-  const LevelDesc& l0 = lev[0];
+                         T* ring, double& rr) {
+  const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
   T* X = base;
   T* R = base + l0.ob;
-  T* Pd = base + 4 * S0;
-  T* Qd = base + 5 * S0;
+  T* Po = base + 4 * S0;
+  T* Pn = base + 5 * S0;
   const T om = T(omega);
   int iters = 0;
   rr = bb;
   if (!(bb > 0.0)) return 0;
   double acc[2];
-  T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om);
   acc[0] = acc[1] = 0.0;
-  FOR_TILE(l0) {
-    const int64_t i = (int64_t)iy * l0.nx + ix;
-    Pd[i] = Z[i];
-    acc[0] += (double)R[i] * (double)Z[i];
-  }
+  const T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring);
   block_sum<NT, 2>(acc, red);
   double rho = acc[0];
+  T beta = T(0);
+  bool first = true;
   while (iters < max_it) {
     ++iters;
+    // p_new = z + beta p_old and p_new . A p_new, with A p_new formed from p_new at the
+    // node and its neighbours
     acc[0] = acc[1] = 0.0;
+    const T bet = first ? T(0) : beta;
+    const T* Pold = first ? Z : Po;  // any valid vector: its value is multiplied by 0
+    auto pv = [&](unsigned j) -> T { return Z[j] + bet * Pold[j]; };
     FOR_TILE(l0) {
-      const int64_t i = (int64_t)iy * l0.nx + ix;
-      T q = T(0);
-      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
-        T d;
-        q = stencil<KIND, T>(P, l0, Pd, ix, iy, i, d);
-      }
-      Qd[i] = q;
-      acc[0] += (double)Pd[i] * (double)q;
+      const unsigned i = (unsigned)(iy * l0.nx + ix);
+      const bool he = ix + 1 < l0.nx, hw = ix > 0, hn = iy + 1 < l0.ny, hs = iy > 0;
+      const T pc = pv(i);
+      const T e0 = pv(he ? i + 1 : i), w0 = pv(hw ? i - 1 : i);
+      const T n0 = pv(hn ? i + l0.nx : i), s0 = pv(hs ? i - l0.nx : i);
+      const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = hn ? n0 : T(0), s = hs ? s0 : T(0);
+      const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+      const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+      const T q = (we + ww + wn + ws) * pc - we * e - ww * w - wn * n - ws * s;
+      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) acc[0] += (double)pc * (double)q;
+      Pn[i] = pc;
     }
     block_sum<NT, 2>(acc, red);
     const T alpha = T(rho / acc[0]);
+    // x += alpha p, r -= alpha A p, ||r||^2
     acc[0] = acc[1] = 0.0;
     FOR_TILE(l0) {
-      const int64_t i = (int64_t)iy * l0.nx + ix;
-      X[i] += alpha * Pd[i];
-      const T r = R[i] - alpha * Qd[i];
+      const unsigned i = (unsigned)(iy * l0.nx + ix);
+      T q = T(0);
+      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
+        T d;
+        q = stencil<KIND, T>(P, l0, Pn, ix, iy, i, d);
+      }
+      X[i] += alpha * Pn[i];
+      const T r = R[i] - alpha * q;
       R[i] = r;
       acc[0] += (double)r * (double)r;
     }
     block_sum<NT, 2>(acc, red);
     rr = acc[0];
     if (rr <= tol2) break;
-    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om);
     acc[0] = acc[1] = 0.0;
-    FOR_TILE(l0) {
-      const int64_t i = (int64_t)iy * l0.nx + ix;
-      acc[0] += (double)R[i] * (double)Z[i];
-    }
+    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring);
     block_sum<NT, 2>(acc, red);
-    const T beta = T(acc[0] / rho);
+    beta = T(acc[0] / rho);
     rho = acc[0];
-    FOR_TILE(l0) {
-      const int64_t i = (int64_t)iy * l0.nx + ix;
-      Pd[i] = Z[i] + beta * Pd[i];
-    }
-    __syncthreads();
+    first = false;
+    T* tmp = Po;
+    Po = Pn;
+    Pn = tmp;
   }
   return iters;
 }
