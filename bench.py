@@ -32,43 +32,51 @@ def tile_levels(cw: int, ch: int, m: int):
     return [(cw * (1 << (m - t)) - 1) * (ch * (1 << (m - t)) - 1) for t in range(m + 1)]
 
 
-def post_fused(nt: int, tile_nx: int, nu: int, elem: int = 8, lds_limit: int = 163840) -> bool:
-    """Whether the kernel runs the post-smoothing as one banded pass: nu = 2 and two LDS
-    rings of nt/64 + 2 tile rows fit the per-workgroup LDS (the library's own rule)."""
-    return nu == 2 and 2 * (nt // 64 + 2) * tile_nx * elem + 4096 <= lds_limit
+def ring_mode(nt: int, tile_nx: int, nu: int, elem: int = 8, lds_limit: int = 163840) -> int:
+    """The library's rule for the banded smoothing passes: with nu = 2, mode 2 (pre- and
+    post-smoothing banded) when three LDS rings of nt/64 + 2 tile rows fit the
+    per-workgroup LDS, mode 1 (post-smoothing only) when two fit, else 0."""
+    if nu != 2:
+        return 0
+    for rings, mode in ((3, 2), (2, 1)):
+        if rings * (nt // 64 + 2) * tile_nx * elem + 4096 <= lds_limit:
+            return mode
+    return 0
 
 
 def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
-                            fused_post: bool = True) -> float:
+                            mode: int = 2) -> float:
     """Bytes the local-solve kernel schedules per PCG iteration for one tile (each
-    streamed vector read or write counted once per pass):
+    streamed vector read or write counted once per pass, cache re-reads included):
       level 0 outside the V-cycle: p = z + beta p with p.Ap (read z, p_old, write p) 3,
       x/r update with A p recomputed (read x, r, p, write x, r) 5  -> 8 passes;
-      every V-cycle level t above the coarsest: the first two sweeps from zero 2 (one
-      sweep 2 when nu = 1), nu-2 further sweeps 3 each, residual 3, restriction read 1
-      (+ write 1 on level t+1);
-      post-smoothing, banded (nu = 2): read z 1, read b twice 2, write z 1 (+ read the
-      coarse correction 1 on level t+1); otherwise interpolation add 2 (+ read 1 on level
-      t+1) and nu sweeps 3 each; r.z rides on the last sweep of level 0;
+      every V-cycle level t above the coarsest:
+        pre-smoothing, residual and restriction: banded (mode 2) read b three times,
+        write z 1 -> 4; otherwise the first two sweeps from zero 2 (one sweep 2 when
+        nu = 1), nu-2 further sweeps 3 each, residual 3, restriction read 1;
+        post-smoothing: banded (mode >= 1) read z 1, read b twice 2, write z 1 -> 4;
+        otherwise interpolation add 2 and nu sweeps 3 each;
+        plus on level t+1 the restriction write 1 and the correction read 1;
+      r.z rides on the last sweep of level 0;
       coarsest: read b, write z, and the dense inverse (n^2 values)."""
     S = tile_levels(cw, ch, m)
     v = 0.0
-    pre = 2 + 3 * max(nu - 2, 0)
-    post = 4 if (fused_post and nu == 2) else 2 + 3 * nu
+    pre = 4 if (mode >= 2 and nu == 2) else 2 + 3 * max(nu - 2, 0) + 3 + 1
+    post = 4 if (mode >= 1 and nu == 2) else 2 + 3 * nu
     for t in range(m):
-        v += S[t] * (pre + 3 + 1 + post) + S[t + 1] * 2
+        v += S[t] * (pre + post) + S[t + 1] * 2
     v += 2 * S[m] + S[m] ** 2
     return elem * (8 * S[0] + v)
 
 
 def mixed_bytes(cw: int, ch: int, m: int, nu: int, it_dofs: int, refine_dofs: int,
-                tile_dofs: int, fused_post: bool = True) -> float:
+                tile_dofs: int, mode: int = 2) -> float:
     """Bytes of one mixed-precision local-solve launch: the FP32 inner iterations (the FP64
     schedule above with 4-byte elements, plus one pass per inner solve), and per
     refinement step the FP64 passes e += d (read e 8, d 4, write e 8) and r = b - K e
     (read b 8, e 8, write r 4, clear d 4); plus the first pass (read b, write e, r, d)."""
     S0 = tile_levels(cw, ch, m)[0]
-    per_it = pcg_bytes_per_iteration(cw, ch, m, nu, elem=4, fused_post=fused_post) / S0
+    per_it = pcg_bytes_per_iteration(cw, ch, m, nu, elem=4, mode=mode) / S0
     return per_it * it_dofs + (44.0 + 4.0) * refine_dofs + 24.0 * tile_dofs
 
 
@@ -332,16 +340,16 @@ def main():
     lds_limit = getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", 65536)
     tile_nx = max(c for c, _ in shapes) * (1 << m) - 1
     elem = 8 if opts.precision == 0 else 4
-    fused = post_fused(nt, tile_nx, opts.nu, elem, lds_limit)
+    rmode = ring_mode(nt, tile_nx, opts.nu, elem, lds_limit)
     if opts.precision == 0:
         kernel = "k_local_pcg64"
-        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, fused_post=fused) / S0
+        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode) / S0
         bytes_launch = per_dof_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
     else:
         kernel = "k_local_mixed"
-        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, fused_post=fused) / S0
+        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode) / S0
         bytes_launch = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
-                                   st["n_tile_dofs"], fused_post=fused)
+                                   st["n_tile_dofs"], mode=rmode)
     achieved = bytes_launch / (pcg_ms * 1e-3) / 1e9
     traffic = measured_traffic(kernel, prob.name)
 

@@ -14,9 +14,9 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
                                                     char* store, const double* inv, int m,
                                                     ItemStat* stats, double rtol, int max_it,
                                                     int max_refine, double inner_rtol, int nu,
-                                                    double omega, int ring_on) {
+                                                    double omega, int ring_mode) {
   __shared__ double red[2 * (NT / 64)];
-  extern __shared__ float ring_lds_f[];  // banded post-smoothing rings (dynamic size)
+  extern __shared__ float ring_lds_f[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
   const ProbDev& P = probs[it.prob];
   const Levels lev(it, P, m, 2);
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     ++refine;
     double rr_inner;
     total += pcg_solve<NT, KIND, float>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
-                                        max_it, nu, omega, red, ring_on ? ring_lds_f : nullptr,
+                                        max_it, nu, omega, red, ring_lds_f, ring_mode,
                                         rr_inner);
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
@@ -102,11 +102,12 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
                               double omega, int max_tile_nx, hipStream_t s) {
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
-  const size_t lds = nu == 2 ? post_ring_bytes(ntv, max_tile_nx, 4) : 0;
+  size_t lds = 0;
+  const int mode = ring_mode_for(ntv, nu, max_tile_nx, 4, &lds);
 #define MLC_MIX(NTV, KV)                                                                     \
   hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
                      store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \
-                     lds > 0 ? 1 : 0)
+                     mode)
 #define MLC_MIX_NT(NTV) \
   if (kind == 0)        \
     MLC_MIX(NTV, 0);    \

@@ -21,9 +21,9 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
                                                      char* store, const double* inv, int m,
                                                      ItemStat* stats, double rtol, int max_it,
                                                      int nu, double omega, int rhs_in_tile,
-                                                     int ring_on) {
+                                                     int ring_mode) {
   __shared__ double red[2 * (NT / 64)];
-  extern __shared__ double ring_lds[];  // banded post-smoothing rings (dynamic size)
+  extern __shared__ double ring_lds[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
   const ProbDev& P = probs[it.prob];
   const Levels lev(it, P, m, 2);
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   double rr = bb;
   const int iters = pcg_solve<NT, KIND, double>(P, lev, base, m, inv + it.inv_off, bb,
                                                 rtol * rtol * bb, max_it, nu, omega, red,
-                                                ring_on ? ring_lds : nullptr, rr);
+                                                ring_lds, ring_mode, rr);
   if (threadIdx.x == 0) {
     ItemStat s;
     s.iters = iters;
@@ -70,7 +70,7 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
   return total * (int64_t)sizeof(double);
 }
 
-size_t post_ring_bytes(int nt, int max_tile_nx, int elem_bytes) {
+size_t ring_bytes(int nt, int max_tile_nx, int elem_bytes, int rings) {
   static int limit = -1;
   if (limit < 0) {
     int dev = 0, v = 0;
@@ -79,9 +79,17 @@ size_t post_ring_bytes(int nt, int max_tile_nx, int elem_bytes) {
       v = 0;
     limit = v;
   }
-  const size_t bytes = (size_t)2 * (nt / 64 + 2) * (size_t)max_tile_nx * elem_bytes;
+  const size_t bytes = (size_t)rings * (nt / 64 + 2) * (size_t)max_tile_nx * elem_bytes;
   // keep room for the reduction buffer and the compiler's own LDS
   return bytes + 4096 <= (size_t)limit ? bytes : 0;
+}
+
+int ring_mode_for(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds) {
+  *lds = 0;
+  if (nu != 2) return 0;
+  if ((*lds = ring_bytes(nt, max_tile_nx, elem_bytes, 3)) > 0) return 2;
+  if ((*lds = ring_bytes(nt, max_tile_nx, elem_bytes, 2)) > 0) return 1;
+  return 0;
 }
 
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
@@ -90,11 +98,12 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
                             int max_tile_nx, hipStream_t s) {
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
-  const size_t lds = nu == 2 ? post_ring_bytes(ntv, max_tile_nx, 8) : 0;
+  size_t lds = 0;
+  const int mode = ring_mode_for(ntv, nu, max_tile_nx, 8, &lds);
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
                      store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile,           \
-                     lds > 0 ? 1 : 0)
+                     mode)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \
     MLC_PCG(NTV, 0);       \

@@ -176,17 +176,111 @@ __device__ void op_prolong_add(const ProbDev& P, const LevelDesc& lc, const Leve
 // One damped-Jacobi update at tile node (ix, y) from three consecutive rows held in LDS
 // (rows -1 and ny are stored as zeros, the Dirichlet values).
 template <int KIND, typename T>
-__device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, const T* rs,
-                                         const T* rc, const T* rn, T bi, int ix, int y, T omega) {
+__device__ __forceinline__ T apply_rows(const ProbDev& P, const LevelDesc& lv, const T* rs,
+                                        const T* rc, const T* rn, int ix, int y, T& d) {
   const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + y);
   const bool he = ix + 1 < lv.nx, hw = ix > 0;
   const T c = rc[ix];
   const T e0 = rc[he ? ix + 1 : ix], w0 = rc[hw ? ix - 1 : ix];
   const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = rn[ix], s = rs[ix];
   const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
-  const T d = we + ww + wn + ws;
-  const T az = d * c - we * e - ww * w - wn * n - ws * s;
-  return c + omega * (bi - az) / d;
+  d = we + ww + wn + ws;
+  return d * c - we * e - ww * w - wn * n - ws * s;
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, const T* rs,
+                                         const T* rc, const T* rn, T bi, int ix, int y, T omega) {
+  T d;
+  const T az = apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, y, d);
+  return rc[ix] + omega * (bi - az) / d;
+}
+
+// Pre-smoothing, residual and restriction of a V-cycle level with nu = 2 as one pass:
+//   z = J(J(0)) (two damped-Jacobi sweeps from zero), r = b - A z, bc = P^T r.
+// Same banded walk as the post-smoothing below, with three LDS rings of NW + 2 rows
+// (first sweep, second sweep, residual): at step k wave w forms the first sweep on row
+// k NW + w - 1 (stage A), the second sweep one row below, also written to za (B), the
+// residual two rows below (C), and waves w < NW/2 restrict the three residual rows
+// 2cy .. 2cy+2 into coarse row cy = k NW/2 + w - 2 (D).  b is read three times (twice
+// from cache); z and bc are written once, instead of the 6 passes of separate sweeps.
+template <int NT, int KIND, typename T>
+__device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
+                             const T* b, T* za, T* bc, T omega, T* ring) {
+  constexpr int NW = NT / 64, RING = NW + 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = lv.nx, ny = lv.ny, ncx = lc.nx, ncy = lc.ny;
+  T* r1 = ring;
+  T* r2 = ring + RING * nx;
+  T* rr = ring + 2 * RING * nx;
+  auto row = [&](T* r, int y) -> T* { return r + ((y + 1) % RING) * nx; };
+  for (int k = 0; k * NW - 3 < ny || k * (NW / 2) - 2 < ncy; ++k) {
+    const int ya = k * NW + w - 1;
+    if (ya >= -1 && ya <= ny) {
+      T* dst = row(r1, ya);
+      const bool inside = ya >= 0 && ya < ny;
+      for (int ix = lane; ix < nx; ix += 64) {
+        T v = T(0);
+        if (inside) {
+          const T bi = b[(unsigned)(ya * nx + ix)];
+          const T d = T(diag_at<KIND>(P, lv, ix, ya));
+          v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bi / d : T(0);
+        }
+        dst[ix] = v;
+      }
+    }
+    __syncthreads();
+    const int yb = ya - 1;
+    if (yb >= -1 && yb <= ny) {
+      T* dst = row(r2, yb);
+      if (yb >= 0 && yb < ny) {
+        const T* rs = row(r1, yb - 1);
+        const T* rc = row(r1, yb);
+        const T* rn = row(r1, yb + 1);
+        for (int ix = lane; ix < nx; ix += 64) {
+          const unsigned i = (unsigned)(yb * nx + ix);
+          T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega);
+          v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+          dst[ix] = v;
+          za[i] = v;
+        }
+      } else {
+        for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
+      }
+    }
+    __syncthreads();
+    const int yc = ya - 2;
+    if (yc >= -1 && yc <= ny) {
+      T* dst = row(rr, yc);
+      if (yc >= 0 && yc < ny) {
+        const T* rs = row(r2, yc - 1);
+        const T* rc = row(r2, yc);
+        const T* rn = row(r2, yc + 1);
+        for (int ix = lane; ix < nx; ix += 64) {
+          T d;
+          const T v = b[(unsigned)(yc * nx + ix)] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
+          dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
+        }
+      } else {
+        for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
+      }
+    }
+    __syncthreads();
+    if (w < NW / 2) {
+      const int y = k * NW - 2 + 2 * w;  // even: the top fine row 2cy + 2 of coarse row cy
+      const int cy = (y - 2) / 2;
+      if (cy >= 0 && cy < ncy) {
+        const T* rs = row(rr, y - 2);
+        const T* rc = row(rr, y - 1);
+        const T* rn = row(rr, y);
+        for (int cx = lane; cx < ncx; cx += 64) {
+          const int x = 2 * cx + 1;
+          const T v = rc[x] + T(0.5) * (rc[x + 1] + rc[x - 1] + rn[x] + rs[x] + rn[x + 1] + rs[x - 1]);
+          bc[(unsigned)(cy * ncx + cx)] = is_dof(P.domain, lc.N, lc.gx0 + cx, lc.gy0 + cy) ? v : T(0);
+        }
+      }
+    }
+  }
 }
 
 // Post-smoothing of a V-cycle level with nu = 2 as one pass over the tile:
@@ -320,16 +414,22 @@ struct Levels {
 
 // One symmetric V-cycle applied to the level-0 right-hand side at lev[0].ob; returns
 // the buffer that holds the result z and adds this thread's share of b.z to *rz.  With
-// an LDS ring (non-null `ring`, sized for the tile level) and nu = 2 the post-smoothing
-// of every level runs as one banded pass.
+// nu = 2 and LDS rings sized for the tile level, ring_mode 1 runs the post-smoothing of
+// every level as one banded pass and ring_mode 2 also the pre-smoothing with residual
+// and restriction.
 template <int NT, int KIND, typename T>
 __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
-                     int nu, T omega, double* rz, T* ring) {
+                     int nu, T omega, double* rz, T* ring, int ring_mode) {
   for (int t = 0; t < m; ++t) {
     const LevelDesc lv = lev[t];
     const T* b = base + lv.ob;
     T* za = base + lv.oz;
     T* zb = base + lv.ot;
+    if (ring_mode >= 2 && nu == 2) {
+      op_pre_fused<NT, KIND, T>(P, lv, lev[t + 1], b, za, base + lev[t + 1].ob, omega, ring);
+      __syncthreads();
+      continue;
+    }
     if (nu >= 2)
       op_first2<NT, KIND, T>(P, lv, b, za, omega);
     else
@@ -363,7 +463,7 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
       za = zb;
       zb = tmp;
     }
-    if (ring != nullptr && nu == 2) {
+    if (ring_mode >= 1 && nu == 2) {
       if (t == 0)
         op_post_fused<NT, KIND, T, true>(P, lev[t + 1], lv, zc, b, za, omega, ring, rz);
       else
@@ -398,7 +498,7 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
 template <int NT, int KIND, typename T>
 __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
                          double bb, double tol2, int max_it, int nu, double omega, double* red,
-                         T* ring, double& rr) {
+                         T* ring, int ring_mode, double& rr) {
   const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
   T* X = base;
@@ -411,7 +511,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   if (!(bb > 0.0)) return 0;
   double acc[2];
   acc[0] = acc[1] = 0.0;
-  const T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring);
+  const T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_mode);
   block_sum<NT, 2>(acc, red);
   double rho = acc[0];
   T beta = T(0);
@@ -457,7 +557,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
     rr = acc[0];
     if (rr <= tol2) break;
     acc[0] = acc[1] = 0.0;
-    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring);
+    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_mode);
     block_sum<NT, 2>(acc, red);
     beta = T(acc[0] / rho);
     rho = acc[0];
