@@ -33,36 +33,34 @@ def tile_levels(cw: int, ch: int, m: int):
 
 
 def ring_mode(nt: int, tile_nx: int, nu: int, elem: int = 8, lds_limit: int = 163840) -> int:
-    """The library's rule for the banded smoothing passes: with nu = 2, mode 2 (pre- and
-    post-smoothing banded) when three LDS rings of nt/64 + 2 tile rows fit the
-    per-workgroup LDS, mode 1 (post-smoothing only) when two fit, else 0."""
+    """The library's rule for the banded smoothing passes of a tile: with nu = 2 they run
+    (mode 2) when three LDS rings of nt/64 + 2 rows of the tile fit the per-workgroup
+    LDS, else the sweeps run apart (mode 0)."""
     if nu != 2:
         return 0
-    for rings, mode in ((3, 2), (2, 1)):
-        if rings * (nt // 64 + 2) * tile_nx * elem + 4096 <= lds_limit:
-            return mode
-    return 0
+    return 2 if 3 * (nt // 64 + 2) * tile_nx * elem + 4096 <= lds_limit else 0
 
 
 def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
                             mode: int = 2) -> float:
-    """Bytes the local-solve kernel schedules per PCG iteration for one tile (each
-    streamed vector read or write counted once per pass, cache re-reads included):
+    """Bytes the local-solve kernel must move per PCG iteration for one tile: every
+    vector a pass reads or writes counted once per pass (a vector read at several
+    stages of one banded pass counts once; the later reads are served from cache):
       level 0 outside the V-cycle: p = z + beta p with p.Ap (read z, p_old, write p) 3,
       x/r update with A p recomputed (read x, r, p, write x, r) 5  -> 8 passes;
       every V-cycle level t above the coarsest:
-        pre-smoothing, residual and restriction: banded (mode 2) read b three times,
-        write z 1 -> 4; otherwise the first two sweeps from zero 2 (one sweep 2 when
-        nu = 1), nu-2 further sweeps 3 each, residual 3, restriction read 1;
-        post-smoothing: banded (mode >= 1) read z 1, read b twice 2, write z 1 -> 4;
-        otherwise interpolation add 2 and nu sweeps 3 each;
+        pre-smoothing, residual and restriction: banded (mode 2) read b, write z -> 2;
+        otherwise the first two sweeps from zero 2 (one sweep 2 when nu = 1), nu-2
+        further sweeps 3 each, residual 3, restriction read 1;
+        post-smoothing: banded (mode 2) read z, read b, write z -> 3; otherwise
+        interpolation add 2 and nu sweeps 3 each;
         plus on level t+1 the restriction write 1 and the correction read 1;
       r.z rides on the last sweep of level 0;
       coarsest: read b, write z, and the dense inverse (n^2 values)."""
     S = tile_levels(cw, ch, m)
     v = 0.0
-    pre = 4 if (mode >= 2 and nu == 2) else 2 + 3 * max(nu - 2, 0) + 3 + 1
-    post = 4 if (mode >= 1 and nu == 2) else 2 + 3 * nu
+    pre = 2 if (mode >= 2 and nu == 2) else 2 + 3 * max(nu - 2, 0) + 3 + 1
+    post = 3 if (mode >= 2 and nu == 2) else 2 + 3 * nu
     for t in range(m):
         v += S[t] * (pre + post) + S[t + 1] * 2
     v += 2 * S[m] + S[m] ** 2

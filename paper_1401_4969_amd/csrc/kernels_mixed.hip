@@ -14,7 +14,7 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
                                                     char* store, const double* inv, int m,
                                                     ItemStat* stats, double rtol, int max_it,
                                                     int max_refine, double inner_rtol, int nu,
-                                                    double omega, int ring_mode) {
+                                                    double omega, int ring_cap) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ float ring_lds_f[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
@@ -45,11 +45,12 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   const double bb = acc[0];
   double rr = bb;
   int total = 0, refine = 0;
+  float* ring = l0.nx <= ring_cap ? ring_lds_f : nullptr;  // banded passes (per item)
   while (rr > rtol * rtol * bb && refine < max_refine) {
     ++refine;
     double rr_inner;
     total += pcg_solve<NT, KIND, float>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
-                                        max_it, nu, omega, red, ring_lds_f, ring_mode,
+                                        max_it, nu, omega, red, ring,
                                         rr_inner);
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
@@ -103,11 +104,11 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  const int mode = ring_mode_for(ntv, nu, max_tile_nx, 4, &lds);
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, &lds);
 #define MLC_MIX(NTV, KV)                                                                     \
   hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
                      store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \
-                     mode)
+                     cap)
 #define MLC_MIX_NT(NTV) \
   if (kind == 0)        \
     MLC_MIX(NTV, 0);    \

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
                                                      char* store, const double* inv, int m,
                                                      ItemStat* stats, double rtol, int max_it,
                                                      int nu, double omega, int rhs_in_tile,
-                                                     int ring_mode) {
+                                                     int ring_cap) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ double ring_lds[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
@@ -45,9 +45,12 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   block_sum<NT, 2>(acc, red);
   const double bb = acc[0];
   double rr = bb;
+  // banded passes when this tile's rows fit the rings (a per-item decision, so the
+  // arithmetic of an item does not depend on the other items of the launch)
+  double* ring = l0.nx <= ring_cap ? ring_lds : nullptr;
   const int iters = pcg_solve<NT, KIND, double>(P, lev, base, m, inv + it.inv_off, bb,
-                                                rtol * rtol * bb, max_it, nu, omega, red,
-                                                ring_lds, ring_mode, rr);
+                                                rtol * rtol * bb, max_it, nu, omega, red, ring,
+                                                rr);
   if (threadIdx.x == 0) {
     ItemStat s;
     s.iters = iters;
@@ -70,7 +73,7 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
   return total * (int64_t)sizeof(double);
 }
 
-size_t ring_bytes(int nt, int max_tile_nx, int elem_bytes, int rings) {
+int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds) {
   static int limit = -1;
   if (limit < 0) {
     int dev = 0, v = 0;
@@ -79,17 +82,16 @@ size_t ring_bytes(int nt, int max_tile_nx, int elem_bytes, int rings) {
       v = 0;
     limit = v;
   }
-  const size_t bytes = (size_t)rings * (nt / 64 + 2) * (size_t)max_tile_nx * elem_bytes;
-  // keep room for the reduction buffer and the compiler's own LDS
-  return bytes + 4096 <= (size_t)limit ? bytes : 0;
-}
-
-int ring_mode_for(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds) {
   *lds = 0;
   if (nu != 2) return 0;
-  if ((*lds = ring_bytes(nt, max_tile_nx, elem_bytes, 3)) > 0) return 2;
-  if ((*lds = ring_bytes(nt, max_tile_nx, elem_bytes, 2)) > 0) return 1;
-  return 0;
+  // three rings of nt/64 + 2 rows; keep room for the reduction buffer and the compiler's
+  // own LDS.  The cap depends on the device only, unless every tile is narrower.
+  const long per_node = 3L * (nt / 64 + 2) * elem_bytes;
+  const long fit = (limit - 4096L) / per_node;
+  const int cap = (int)(fit < max_tile_nx ? fit : max_tile_nx);
+  if (cap < 1) return 0;
+  *lds = (size_t)cap * per_node;
+  return cap;
 }
 
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
@@ -99,11 +101,11 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  const int mode = ring_mode_for(ntv, nu, max_tile_nx, 8, &lds);
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, &lds);
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
                      store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile,           \
-                     mode)
+                     cap)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \
     MLC_PCG(NTV, 0);       \

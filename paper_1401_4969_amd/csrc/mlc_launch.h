@@ -16,12 +16,10 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
                               double omega, int max_tile_nx, hipStream_t s);
-// LDS bytes of `rings` banded smoothing rings for nt threads and the widest tile row,
-// or 0 when they do not fit the device's per-workgroup LDS.
-size_t ring_bytes(int nt, int max_tile_nx, int elem_bytes, int rings);
-// Ring mode of the local solves (0: separate sweeps, 1: banded post-smoothing, 2: banded
-// pre- and post-smoothing) and its LDS bytes in *lds.
-int ring_mode_for(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds);
+// Widest tile row (interior nodes) whose banded smoothing passes fit the device's
+// per-workgroup LDS with nt threads (three rings of nt/64 + 2 rows), capped at the
+// widest tile of the launch; 0 when nu != 2 or nothing fits.  *lds receives the bytes.
+int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds);
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
                            const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
                            hipStream_t s);
