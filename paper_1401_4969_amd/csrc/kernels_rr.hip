@@ -46,18 +46,6 @@ __device__ __forceinline__ double gather(int v, const double* lds, int stride) {
   return s;
 }
 
-__device__ __forceinline__ int bmin_int(int x, int* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-  __syncthreads();
-  int s = red[0];
-#pragma unroll
-  for (int w = 1; w < NWR; ++w) s = min(s, red[w]);
-  return s;
-}
-
 // Number of negative eigenvalues of a symmetric QxQ matrix (LDL^T, Sylvester); an exact
 // zero pivot is nudged.
 template <int Q>
@@ -118,11 +106,9 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
   constexpr int NV = 3 * Q * Q + Q + 1;
   __shared__ double park_lds[NWR * NV];
   __shared__ double vals[NV];
-  __shared__ int redi[NWR];
   __shared__ double sAlpha[Q * Q], sBeta[Q * Q];
   __shared__ double sL[Q * Q], sW[Q * Q];
   __shared__ double sMu[Q], sT[Q], sSol[Q];
-  __shared__ double sLo, sHi;
   extern __shared__ double dyn[];
   const ProbDev& P = probs[blockIdx.x];
   if (m > P.L) return;
@@ -140,10 +126,20 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
     const int64_t nn = (int64_t)(N + 1) * (N + 1);
     const int nblk = (int)((nn + 255) / 256);
     const int nvp = 2 * Q * Q + Q;
-    for (int v = 0; v < 2 * Q * Q; ++v) {
-      double s = 0.0;
-      for (int b = tid; b < nblk; b += NTR) s += P.partials[(int64_t)b * nvp + v];
-      park(s, v, park_lds, NV);
+    // one pass over the block partials per group of 8 values (independent loads)
+    for (int v0 = 0; v0 < 2 * Q * Q; v0 += 8) {
+      double sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sv[u] = 0.0;
+      for (int b = tid; b < nblk; b += NTR) {
+        const double* pb = P.partials + (int64_t)b * nvp + v0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (v0 + u < 2 * Q * Q) sv[u] += pb[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (v0 + u < 2 * Q * Q) park(sv[u], v0 + u, park_lds, NV);
     }
     for (int r = tid; r < nH; r += NTR) Lam[r] = P.Lam[r];
     for (int e = tid; e < 2 * Q * nH; e += NTR) f[e] = P.fg[e];
@@ -261,68 +257,90 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
     }
     __syncthreads();
   }
-  const double hi0 = Lam[Q - 1] + 1e-12 * fabs(Lam[Q - 1]) + 1e-300;
   lo -= 1e-12 * fabs(lo) + 1e-300;
-  // 6. multisection: G points per round, GS threads per point
+  // 6. multisection for all q eigenvalues at once: each round spreads G points over the
+  //    q brackets (G/q per bracket, GS threads per point); every point's inertia count c
+  //    tightens every bracket: mu is an upper bound of eigenvalue k when c >= k + 1 and a
+  //    lower bound when c <= k.  Upper bounds start from interlacing (mu_k <= Lambda_k).
   int GS = 1;
-  while (GS < 64 && GS * 32 < nH) GS <<= 1;
-  const int G = NTR / GS;
+  while (GS < 64 && GS * 32 < nH && NTR / (2 * GS) >= Q) GS <<= 1;
+  const int G = NTR / GS;  // >= Q
+  const int GQ = G / Q;    // points per bracket, >= 1
   const int pnt = tid / GS, gl = tid % GS;
-  for (int k = 0; k < Q; ++k) {
-    if (tid == 0) {
-      sLo = lo;
-      sHi = hi0;
-    }
-    __syncthreads();
-    for (int round = 0; round < 64; ++round) {
-      const double a = sLo, b = sHi;
-      if (b - a <= 4.0 * 2.220446049250313e-16 * fmax(fabs(a), fabs(b))) break;
-      const double mu = a + (b - a) * (double)(pnt + 1) / (double)(G + 1);
-      double S[Q][Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-#pragma unroll
-        for (int j = 0; j < Q; ++j) S[i][j] = 0.0;
-      double nless = 0.0;
-      for (int r = gl; r < nH; r += GS) {
-        double d = Lam[r] - mu;
-        if (d < 0.0) nless += 1.0;
-        if (d == 0.0) d = 1e-300;
-        const double inv = 1.0 / d;
-        double z[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) z[i] = Z[r * Q + i];
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-#pragma unroll
-          for (int j = 0; j <= i; ++j) S[i][j] += z[i] * z[j] * inv;
-      }
-      nless = group_sum(nless, GS);
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j) S[i][j] = group_sum(S[i][j], GS);
-      int flag = G;
-      if (gl == 0) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-#pragma unroll
-          for (int j = 0; j <= i; ++j) {
-            S[i][j] = sW[i * Q + j] - S[i][j] - (i == j ? mu : 0.0);
-            S[j][i] = S[i][j];
-          }
-        const int c = (int)nless + neg_inertia<Q>(S);
-        if (c >= k + 1) flag = pnt;
-      }
-      const int t = bmin_int(flag, redi);
-      if (gl == 0 && pnt == t) sHi = mu;
-      if (gl == 0 && pnt == t - 1) sLo = mu;
-      if (t == G && gl == 0 && pnt == G - 1) sLo = mu;
-      __syncthreads();
-    }
-    if (tid == 0) sMu[k] = 0.5 * (sLo + sHi);
-    __syncthreads();
+  __shared__ double sA[Q], sB[Q], ptMu[NTR];
+  __shared__ int ptCnt[NTR];
+  __shared__ int sDone;
+  if (tid < Q) {
+    sA[tid] = lo;
+    sB[tid] = Lam[tid] + 1e-12 * fabs(Lam[tid]) + 1e-300;
   }
+  __syncthreads();
+  for (int round = 0; round < 200; ++round) {
+    const int kb = pnt / GQ, j = pnt % GQ;  // this point's bracket and position
+    const bool active = kb < Q;
+    const double a = sA[active ? kb : 0], bnd = sB[active ? kb : 0];
+    const double mu = a + (bnd - a) * (double)(j + 1) / (double)(GQ + 1);
+    double S[Q][Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int jj = 0; jj < Q; ++jj) S[i][jj] = 0.0;
+    double nless = 0.0;
+    for (int r = gl; r < nH; r += GS) {
+      double d = Lam[r] - mu;
+      if (d < 0.0) nless += 1.0;
+      if (d == 0.0) d = 1e-300;
+      const double inv = 1.0 / d;
+      double z[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) z[i] = Z[r * Q + i];
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int jj = 0; jj <= i; ++jj) S[i][jj] += z[i] * z[jj] * inv;
+    }
+    nless = group_sum(nless, GS);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int jj = 0; jj <= i; ++jj) S[i][jj] = group_sum(S[i][jj], GS);
+    if (gl == 0) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int jj = 0; jj <= i; ++jj) {
+          S[i][jj] = sW[i * Q + jj] - S[i][jj] - (i == jj ? mu : 0.0);
+          S[jj][i] = S[i][jj];
+        }
+      ptMu[pnt] = mu;
+      ptCnt[pnt] = active ? (int)nless + neg_inertia<Q>(S) : -1;
+    }
+    __syncthreads();
+    if (tid < Q) {
+      const int k = tid;
+      double a2 = sA[k], b2 = sB[k];
+      for (int p2 = 0; p2 < G; ++p2) {
+        const int c = ptCnt[p2];
+        if (c < 0) continue;
+        const double m2 = ptMu[p2];
+        if (c >= k + 1) b2 = fmin(b2, m2);
+        else a2 = fmax(a2, m2);
+      }
+      sA[k] = a2;
+      sB[k] = b2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int done = 1;
+      for (int k = 0; k < Q; ++k)
+        if (sB[k] - sA[k] > 4.0 * 2.220446049250313e-16 * fmax(fabs(sA[k]), fabs(sB[k]))) done = 0;
+      sDone = done;
+    }
+    __syncthreads();
+    if (sDone) break;
+  }
+  if (tid < Q) sMu[tid] = 0.5 * (sA[tid] + sB[tid]);
+  __syncthreads();
   // 7. eigenvectors by inverse iteration on T - sigma I (two steps), classical
   //    Gram-Schmidt against the previous ones
   const int n = nH + Q;
