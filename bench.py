@@ -191,6 +191,59 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Configuration 5 (h = 1/1024, kappa per finest cell): a step is one reverse sweep
+    d lambda_1 / d kappa over all levels (1,048,576 gradient entries) after a forward run
+    with the tape; value = gradient entries per second.  The forward levels are timed
+    once for the ratio; the Euler identity sum kappa g = lambda and the stored oracle
+    central differences along seeded directions check the result."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1401_4969_amd import binding as B
+    prob = W.config5()
+    s = B.Solver(prob, B.default_opts(record_tape=1))
+    s.coarse_setup()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(prob.n_refine):
+        s.level_correct()
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3
+    lam, _ = s.eigenpairs(with_vectors=False)
+    for _ in range(max(args.warmup, 1)):
+        g = s.backward(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = s.backward(1.0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    gn = g.cpu().numpy()
+    euler = abs(float(np.sum(gn * prob.kappa)) - lam[0]) / lam[0]
+    fd_err = None
+    path = os.path.join(ROOT, "tests", "golden", "oracle_c5_fd.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            gold = json.load(f)
+        fd_err = max(abs(float(np.sum(gn * d)) - fd) / abs(fd)
+                     for d, fd in zip(W.kappa_directions(prob.kappa), gold["directional_fd"]))
+    s.close()
+    out = {
+        "metric": "d lambda_1 / d kappa entries per second (reverse sweep, 1 GPU)",
+        "value": gn.size / (ms * 1e-3), "unit": "gradient entries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name + "_adjoint", "kappa_entries": int(gn.size),
+                   "levels": prob.n_refine},
+        "forward_all_levels_ms": fwd_ms, "backward_over_forward": ms / fwd_ms,
+        "lambda": float(lam[0]), "euler_identity_rel": euler,
+        "directional_fd_rel_err_vs_oracle": fd_err,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def workload(name: str):
     import workloads as W
     if name == "c2":
@@ -270,7 +323,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "c3mixed", "c4", "c5adj"],
+                    help="c2: h = 1/512, 8x8 subdomains, q = 3 (default); c3: h = 1/2048, "
+                         "16x16, FP64; c3mixed: the same in FP32 + FP64 refinement; c4: 256 "
+                         "problems batched; c5adj: reverse sweep at h = 1/1024")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -287,6 +344,9 @@ def main():
 
     if args.workload == "c4":
         bench_batch(args)
+        return
+    if args.workload == "c5adj":
+        bench_adjoint(args)
         return
     if args.calibrate_copy:
         src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda:0")

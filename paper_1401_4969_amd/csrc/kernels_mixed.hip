@@ -46,11 +46,13 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   double rr = bb;
   int total = 0, refine = 0;
   float* ring = l0.nx <= ring_cap ? ring_lds_f : nullptr;  // banded passes (per item)
+  // no LDS V-cycle tail here: its registers would crowd out the prefetching passes
+  float* tail = nullptr;
   while (rr > rtol * rtol * bb && refine < max_refine) {
     ++refine;
     double rr_inner;
     total += pcg_solve<NT, KIND, float>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
-                                        max_it, nu, omega, red, ring,
+                                        max_it, nu, omega, red, ring, tail,
                                         rr_inner);
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
@@ -104,7 +106,7 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, &lds);
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, false, &lds);
 #define MLC_MIX(NTV, KV)                                                                     \
   hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
                      store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \

@@ -48,9 +48,12 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   // banded passes when this tile's rows fit the rings (a per-item decision, so the
   // arithmetic of an item does not depend on the other items of the launch)
   double* ring = l0.nx <= ring_cap ? ring_lds : nullptr;
+  // the LDS V-cycle tail, after the rings, with 1024-thread workgroups (one per CU: the
+  // extra LDS costs no concurrency there)
+  double* tail = (ring && NT == 1024) ? ring_lds + 3 * (NT / 64 + 2) * ring_cap : nullptr;
   const int iters = pcg_solve<NT, KIND, double>(P, lev, base, m, inv + it.inv_off, bb,
                                                 rtol * rtol * bb, max_it, nu, omega, red, ring,
-                                                rr);
+                                                tail, rr);
   if (threadIdx.x == 0) {
     ItemStat s;
     s.iters = iters;
@@ -73,7 +76,7 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
   return total * (int64_t)sizeof(double);
 }
 
-int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds) {
+int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds) {
   static int limit = -1;
   if (limit < 0) {
     int dev = 0, v = 0;
@@ -84,13 +87,15 @@ int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds) 
   }
   *lds = 0;
   if (nu != 2) return 0;
-  // three rings of nt/64 + 2 rows; keep room for the reduction buffer and the compiler's
-  // own LDS.  The cap depends on the device only, unless every tile is narrower.
+  // three rings of nt/64 + 2 rows and the LDS V-cycle tail; keep room for the reduction
+  // buffer and the compiler's own LDS.  The cap depends on the device only, unless every
+  // tile is narrower.
   const long per_node = 3L * (nt / 64 + 2) * elem_bytes;
-  const long fit = (limit - 4096L) / per_node;
+  const long tail = with_tail ? (long)TAIL_ELEMS * elem_bytes : 0L;
+  const long fit = (limit - 4096L - tail) / per_node;
   const int cap = (int)(fit < max_tile_nx ? fit : max_tile_nx);
   if (cap < 1) return 0;
-  *lds = (size_t)cap * per_node;
+  *lds = (size_t)cap * per_node + tail;
   return cap;
 }
 
@@ -101,7 +106,7 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, &lds);
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, ntv == 1024, &lds);
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
                      store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile,           \

@@ -17,9 +17,10 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
                               double omega, int max_tile_nx, hipStream_t s);
 // Widest tile row (interior nodes) whose banded smoothing passes fit the device's
-// per-workgroup LDS with nt threads (three rings of nt/64 + 2 rows), capped at the
-// widest tile of the launch; 0 when nu != 2 or nothing fits.  *lds receives the bytes.
-int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds);
+// per-workgroup LDS with nt threads (three rings of nt/64 + 2 rows, plus the LDS tail of
+// the V-cycle when with_tail), capped at the widest tile of the launch; 0 when nu != 2 or
+// nothing fits.  *lds receives the bytes.
+int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds);
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
                            const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
                            hipStream_t s);

@@ -622,6 +622,100 @@ struct Levels {
   }
 };
 
+// The coarse end of the V-cycle runs in LDS: from the first level whose grid is at most
+// TAIL_N x TAIL_N, every sweep, restriction, interpolation and the coarse solve work on
+// LDS copies (three vectors per level, at most TAIL_ELEMS elements in all), so those
+// small levels cost LDS latency instead of an HBM round trip per barrier interval.
+constexpr int TAIL_N = 31;
+constexpr int TAIL_ELEMS = 3 * 1280;  // >= 3 (31^2 + 15^2 + 7^2 + 3^2 + 1^2)
+
+__device__ __forceinline__ bool tail_level(const LevelDesc& lv) {
+  return lv.nx <= TAIL_N && lv.ny <= TAIL_N;
+}
+
+// Levels t0 .. m of one V-cycle in LDS (sm, TAIL_ELEMS elements): b of level t0 is read
+// from the item's global buffer, the correction z of level t0 is written back to it
+// (base + lev[t0].oz).  With t0 = 0 the last post-smoothing sweep also adds this
+// thread's share of b.z to *rz.
+template <int NT, int KIND, typename T>
+__device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
+                            const double* Kinv, int nu, T omega, T* base, T* sm, double* rz) {
+  auto loff = [&](int t) -> int {
+    int o = 0;
+    for (int u = t0; u < t; ++u) o += 3 * (int)lev.size(u);
+    return o;
+  };
+  {
+    const LevelDesc lv = lev[t0];
+    const T* gb = base + lv.ob;
+    FOR_TILE(lv) {
+      const unsigned i = (unsigned)(iy * lv.nx + ix);
+      sm[i] = gb[i];
+    }
+    __syncthreads();
+  }
+  for (int t = t0; t < m; ++t) {
+    const LevelDesc lv = lev[t];
+    const int S = (int)lev.size(t);
+    T* b = sm + loff(t);
+    T* za = b + S;
+    T* zb = za + S;
+    if (nu >= 2)
+      op_first2<NT, KIND, T>(P, lv, b, za, omega);
+    else
+      op_first<NT, KIND, T>(P, lv, b, za, omega);
+    __syncthreads();
+    for (int s = 2; s < nu; ++s) {
+      op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+      __syncthreads();
+      T* tmp = za;
+      za = zb;
+      zb = tmp;
+    }
+    op_residual<NT, KIND, T>(P, lv, b, za, zb);
+    __syncthreads();
+    op_restrict<NT, T>(P, lv, lev[t + 1], zb, sm + loff(t + 1));
+    __syncthreads();
+  }
+  T* zc = sm + loff(m) + (int)lev.size(m);
+  op_coarse_solve<NT, T>(lev[m], Kinv, sm + loff(m), zc);
+  __syncthreads();
+  for (int t = m - 1; t >= t0; --t) {
+    const LevelDesc lv = lev[t];
+    const int S = (int)lev.size(t);
+    T* b = sm + loff(t);
+    T* za = b + S;
+    T* zb = za + S;
+    const int singles = nu >= 2 ? nu - 2 : 0;
+    if (singles & 1) {
+      T* tmp = za;
+      za = zb;
+      zb = tmp;
+    }
+    op_prolong_add<NT, T>(P, lev[t + 1], lv, zc, za);
+    __syncthreads();
+    for (int s = 0; s < nu; ++s) {
+      if (t == 0 && s == nu - 1)
+        op_jacobi<NT, KIND, T, true>(P, lv, b, za, zb, omega, rz);
+      else
+        op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+      __syncthreads();
+      T* tmp = za;
+      za = zb;
+      zb = tmp;
+    }
+    zc = za;
+  }
+  {
+    const LevelDesc lv = lev[t0];
+    T* gz = base + lv.oz;
+    FOR_TILE(lv) {
+      const unsigned i = (unsigned)(iy * lv.nx + ix);
+      gz[i] = zc[i];
+    }
+  }
+}
+
 // One symmetric V-cycle applied to the level-0 right-hand side at lev[0].ob; returns
 // the buffer that holds the result z and adds this thread's share of b.z to *rz.  With
 // nu = 2 and three LDS rings sized for the tile level (non-null `ring`), the pre-
@@ -629,9 +723,17 @@ struct Levels {
 // one banded pass each.
 template <int NT, int KIND, typename T>
 __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
-                     int nu, T omega, double* rz, T* ring) {
+                     int nu, T omega, double* rz, T* ring, T* tail) {
   constexpr bool PREFETCH = sizeof(T) == 4 && KIND == 0;
-  for (int t = 0; t < m; ++t) {
+  int tl = m + 1;  // first level handled in LDS (none when m + 1)
+  if (tail != nullptr) {
+    for (int t = 0; t < m; ++t)
+      if (tail_level(lev[t])) {
+        tl = t;
+        break;
+      }
+  }
+  for (int t = 0; t < m && t < tl; ++t) {
     const LevelDesc lv = lev[t];
     const T* b = base + lv.ob;
     T* za = base + lv.oz;
@@ -661,10 +763,17 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     op_restrict<NT, T>(P, lv, lev[t + 1], zb, base + lev[t + 1].ob);
     __syncthreads();
   }
-  op_coarse_solve<NT, T>(lev[m], Kinv, base + lev[m].ob, base + lev[m].oz);
-  __syncthreads();
-  T* zc = base + lev[m].oz;
-  for (int t = m - 1; t >= 0; --t) {
+  T* zc;
+  if (tl <= m) {
+    vcycle_tail<NT, KIND, T>(P, lev, tl, m, Kinv, nu, omega, base, tail, rz);
+    __syncthreads();
+    zc = base + lev[tl].oz;
+  } else {
+    op_coarse_solve<NT, T>(lev[m], Kinv, base + lev[m].ob, base + lev[m].oz);
+    __syncthreads();
+    zc = base + lev[m].oz;
+  }
+  for (int t = (tl <= m ? tl : m) - 1; t >= 0; --t) {
     const LevelDesc lv = lev[t];
     const T* b = base + lv.ob;
     T* za = base + lv.oz;
@@ -717,7 +826,7 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
 template <int NT, int KIND, typename T>
 __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
                          double bb, double tol2, int max_it, int nu, double omega, double* red,
-                         T* ring, double& rr) {
+                         T* ring, T* tail, double& rr) {
   const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
   T* X = base;
@@ -730,7 +839,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   if (!(bb > 0.0)) return 0;
   double acc[2];
   acc[0] = acc[1] = 0.0;
-  const T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring);
+  const T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, tail);
   block_sum<NT, 2>(acc, red);
   double rho = acc[0];
   T beta = T(0);
@@ -776,7 +885,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
     rr = acc[0];
     if (rr <= tol2) break;
     acc[0] = acc[1] = 0.0;
-    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring);
+    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, tail);
     block_sum<NT, 2>(acc, red);
     beta = T(acc[0] / rho);
     rho = acc[0];
