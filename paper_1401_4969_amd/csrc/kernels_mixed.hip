@@ -9,12 +9,15 @@
 
 namespace {
 
+// One band row per wave: taller bands' registers would crowd out the prefetching passes.
+constexpr int MIXED_MAX_ROWS = 1;
+
 template <int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const TileItem* items,
                                                     char* store, const double* inv, int m,
                                                     ItemStat* stats, double rtol, int max_it,
                                                     int max_refine, double inner_rtol, int nu,
-                                                    double omega, int ring_cap) {
+                                                    double omega, int ring_cap, int ring_cap2) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ float ring_lds_f[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
@@ -45,14 +48,15 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   const double bb = acc[0];
   double rr = bb;
   int total = 0, refine = 0;
-  float* ring = l0.nx <= ring_cap ? ring_lds_f : nullptr;  // banded passes (per item)
+  const int rows = l0.nx <= ring_cap ? 1 : 0;  // banded passes where the rings fit (per item)
+  float* ring = rows ? ring_lds_f : nullptr;
   // no LDS V-cycle tail here: its registers would crowd out the prefetching passes
   float* tail = nullptr;
   while (rr > rtol * rtol * bb && refine < max_refine) {
     ++refine;
     double rr_inner;
-    total += pcg_solve<NT, KIND, float>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
-                                        max_it, nu, omega, red, ring, tail,
+    total += pcg_solve<NT, KIND, float, MIXED_MAX_ROWS>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
+                                        max_it, nu, omega, red, ring, rows, tail,
                                         rr_inner);
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
@@ -106,11 +110,14 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, false, &lds);
+  int cap2 = 0;
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, false, &lds, &cap2);
+  cap2 = 0;  // one band row per wave here
+  lds = cap > 0 ? (size_t)ring_elems(ntv / 64, cap, 0) * 4 : 0;
 #define MLC_MIX(NTV, KV)                                                                     \
   hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
                      store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \
-                     cap)
+                     cap, cap2)
 #define MLC_MIX_NT(NTV) \
   if (kind == 0)        \
     MLC_MIX(NTV, 0);    \

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
                                                      char* store, const double* inv, int m,
                                                      ItemStat* stats, double rtol, int max_it,
                                                      int nu, double omega, int rhs_in_tile,
-                                                     int ring_cap) {
+                                                     int ring_cap, int ring_cap2) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ double ring_lds[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
@@ -47,13 +47,15 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   double rr = bb;
   // banded passes when this tile's rows fit the rings (a per-item decision, so the
   // arithmetic of an item does not depend on the other items of the launch)
-  double* ring = l0.nx <= ring_cap ? ring_lds : nullptr;
+  // band rows per wave: two where this tile's rows fit the taller rings, else one
+  const int rows = l0.nx <= ring_cap2 ? 2 : (l0.nx <= ring_cap ? 1 : 0);
+  double* ring = rows ? ring_lds : nullptr;
   // the LDS V-cycle tail, after the rings, with 1024-thread workgroups (one per CU: the
   // extra LDS costs no concurrency there)
-  double* tail = (ring && NT == 1024) ? ring_lds + 3 * (NT / 64 + 2) * ring_cap : nullptr;
-  const int iters = pcg_solve<NT, KIND, double>(P, lev, base, m, inv + it.inv_off, bb,
+  double* tail = (rows && NT == 1024) ? ring_lds + ring_elems(NT / 64, ring_cap, ring_cap2) : nullptr;
+  const int iters = pcg_solve<NT, KIND, double, 2>(P, lev, base, m, inv + it.inv_off, bb,
                                                 rtol * rtol * bb, max_it, nu, omega, red, ring,
-                                                tail, rr);
+                                                rows, tail, rr);
   if (threadIdx.x == 0) {
     ItemStat s;
     s.iters = iters;
@@ -76,7 +78,8 @@ int64_t item_bytes_fp64(int cw, int ch, int m) {
   return total * (int64_t)sizeof(double);
 }
 
-int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds) {
+int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds,
+                  int* cap2) {
   static int limit = -1;
   if (limit < 0) {
     int dev = 0, v = 0;
@@ -86,17 +89,21 @@ int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tai
     limit = v;
   }
   *lds = 0;
+  *cap2 = 0;
   if (nu != 2) return 0;
-  // three rings of nt/64 + 2 rows and the LDS V-cycle tail; keep room for the reduction
-  // buffer and the compiler's own LDS.  The cap depends on the device only, unless every
-  // tile is narrower.
-  const long per_node = 3L * (nt / 64 + 2) * elem_bytes;
+  // three rings of B + 2 rows (B = nt/64 rows per band step, or twice that) and the LDS
+  // V-cycle tail; keep room for the reduction buffer and the compiler's own LDS.  The
+  // caps depend on the device only, unless every tile is narrower.
+  const int nw = nt / 64;
+  const long row1 = 3L * (nw + 2) * elem_bytes, row2 = 3L * (2 * nw + 2) * elem_bytes;
   const long tail = with_tail ? (long)TAIL_ELEMS * elem_bytes : 0L;
-  const long fit = (limit - 4096L - tail) / per_node;
-  const int cap = (int)(fit < max_tile_nx ? fit : max_tile_nx);
-  if (cap < 1) return 0;
-  *lds = (size_t)cap * per_node + tail;
-  return cap;
+  const long room = limit - 4096L - tail;
+  const long fit1 = room / row1, fit2 = room / row2;
+  const int cap1 = (int)(fit1 < max_tile_nx ? fit1 : max_tile_nx);
+  if (cap1 < 1) return 0;
+  *cap2 = (int)(fit2 < max_tile_nx ? fit2 : max_tile_nx);
+  *lds = (size_t)ring_elems(nw, cap1, *cap2) * elem_bytes + tail;
+  return cap1;
 }
 
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
@@ -106,11 +113,12 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, ntv == 1024, &lds);
+  int cap2 = 0;
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, ntv == 1024, &lds, &cap2);
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
                      store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile,           \
-                     cap)
+                     cap, cap2)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \
     MLC_PCG(NTV, 0);       \

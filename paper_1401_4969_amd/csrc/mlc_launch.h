@@ -19,8 +19,15 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
 // Widest tile row (interior nodes) whose banded smoothing passes fit the device's
 // per-workgroup LDS with nt threads (three rings of nt/64 + 2 rows, plus the LDS tail of
 // the V-cycle when with_tail), capped at the widest tile of the launch; 0 when nu != 2 or
-// nothing fits.  *lds receives the bytes.
-int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds);
+// nothing fits.  *cap2 receives the same for bands of two rows per wave (rings of
+// 2 nt/64 + 2 rows), *lds the bytes to allocate.
+int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds,
+                  int* cap2);
+// Elements of the ring region for nw waves and the two caps above (the tail follows it).
+__host__ __device__ inline long ring_elems(int nw, int cap1, int cap2) {
+  const long a = 3L * (nw + 2) * cap1, b = 3L * (2 * nw + 2) * cap2;
+  return a > b ? a : b;
+}
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
                            const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
                            hipStream_t s);

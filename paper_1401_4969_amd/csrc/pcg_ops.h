@@ -198,76 +198,89 @@ __device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, 
 
 // Pre-smoothing, residual and restriction of a V-cycle level with nu = 2 as one pass:
 //   z = J(J(0)) (two damped-Jacobi sweeps from zero), r = b - A z, bc = P^T r.
-// Same banded walk as the post-smoothing below, with three LDS rings of NW + 2 rows
-// (first sweep, second sweep, residual): at step k wave w forms the first sweep on row
-// k NW + w - 1 (stage A), the second sweep one row below, also written to za (B), the
-// residual two rows below (C), and waves w < NW/2 restrict the three residual rows
-// 2cy .. 2cy+2 into coarse row cy = k NW/2 + w - 2 (D).  b is read three times (twice
-// from cache); z and bc are written once, instead of the 6 passes of separate sweeps.
-template <int NT, int KIND, typename T>
+// The workgroup walks the tile in bands of B = NW R rows (wave w owns rows w + NW r of a
+// band) with three LDS rings of B + 2 rows (first sweep, second sweep, residual): at
+// step k the first sweep is formed on rows k B - 1 .. k B + B - 2 (stage A), the second
+// sweep one row below, also written to za (B), the residual two rows below (C), and the
+// B/2 coarse rows cy = k B/2 - 2 .. are restricted from residual rows 2cy .. 2cy+2 (D).
+// b is read once from HBM (the later stages hit cache); z and bc are written once,
+// instead of the 6 passes of separate sweeps.  A ring row is overwritten only after the
+// barrier that follows its last reader.  Taller bands (R = 2) halve the barrier
+// intervals where the rings fit.
+template <int NT, int KIND, typename T, int R>
 __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
                              const T* b, T* za, T* bc, T omega, T* ring) {
-  constexpr int NW = NT / 64, RING = NW + 2;
+  constexpr int NW = NT / 64, BH = NW * R, RING = BH + 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = lv.nx, ny = lv.ny, ncx = lc.nx, ncy = lc.ny;
   T* r1 = ring;
   T* r2 = ring + RING * nx;
   T* rr = ring + 2 * RING * nx;
   auto row = [&](T* r, int y) -> T* { return r + ((y + 1) % RING) * nx; };
-  for (int k = 0; k * NW - 3 < ny || k * (NW / 2) - 2 < ncy; ++k) {
-    const int ya = k * NW + w - 1;
-    if (ya >= -1 && ya <= ny) {
-      T* dst = row(r1, ya);
-      const bool inside = ya >= 0 && ya < ny;
-      for (int ix = lane; ix < nx; ix += 64) {
-        T v = T(0);
-        if (inside) {
-          const T bi = b[(unsigned)(ya * nx + ix)];
-          const T d = T(diag_at<KIND>(P, lv, ix, ya));
-          v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bi / d : T(0);
-        }
-        dst[ix] = v;
-      }
-    }
-    __syncthreads();
-    const int yb = ya - 1;
-    if (yb >= -1 && yb <= ny) {
-      T* dst = row(r2, yb);
-      if (yb >= 0 && yb < ny) {
-        const T* rs = row(r1, yb - 1);
-        const T* rc = row(r1, yb);
-        const T* rn = row(r1, yb + 1);
+  for (int k = 0; k * BH - 3 < ny || k * (BH / 2) - 2 < ncy; ++k) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int ya = k * BH + w + NW * q - 1;
+      if (ya >= -1 && ya <= ny) {
+        T* dst = row(r1, ya);
+        const bool inside = ya >= 0 && ya < ny;
         for (int ix = lane; ix < nx; ix += 64) {
-          const unsigned i = (unsigned)(yb * nx + ix);
-          T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega);
-          v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+          T v = T(0);
+          if (inside) {
+            const T bi = b[(unsigned)(ya * nx + ix)];
+            const T d = T(diag_at<KIND>(P, lv, ix, ya));
+            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bi / d : T(0);
+          }
           dst[ix] = v;
-          za[i] = v;
         }
-      } else {
-        for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
       }
     }
     __syncthreads();
-    const int yc = ya - 2;
-    if (yc >= -1 && yc <= ny) {
-      T* dst = row(rr, yc);
-      if (yc >= 0 && yc < ny) {
-        const T* rs = row(r2, yc - 1);
-        const T* rc = row(r2, yc);
-        const T* rn = row(r2, yc + 1);
-        for (int ix = lane; ix < nx; ix += 64) {
-          T d;
-          const T v = b[(unsigned)(yc * nx + ix)] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
-          dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int yb = k * BH + w + NW * q - 2;
+      if (yb >= -1 && yb <= ny) {
+        T* dst = row(r2, yb);
+        if (yb >= 0 && yb < ny) {
+          const T* rs = row(r1, yb - 1);
+          const T* rc = row(r1, yb);
+          const T* rn = row(r1, yb + 1);
+          for (int ix = lane; ix < nx; ix += 64) {
+            const unsigned i = (unsigned)(yb * nx + ix);
+            T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega);
+            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+            dst[ix] = v;
+            za[i] = v;
+          }
+        } else {
+          for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
         }
-      } else {
-        for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
       }
     }
     __syncthreads();
-    if (w < NW / 2) {
-      const int y = k * NW - 2 + 2 * w;  // even: the top fine row 2cy + 2 of coarse row cy
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int yc = k * BH + w + NW * q - 3;
+      if (yc >= -1 && yc <= ny) {
+        T* dst = row(rr, yc);
+        if (yc >= 0 && yc < ny) {
+          const T* rs = row(r2, yc - 1);
+          const T* rc = row(r2, yc);
+          const T* rn = row(r2, yc + 1);
+          for (int ix = lane; ix < nx; ix += 64) {
+            T d;
+            const T v =
+                b[(unsigned)(yc * nx + ix)] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
+            dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
+          }
+        } else {
+          for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = w; j < BH / 2; j += NW) {
+      const int y = k * BH - 2 + 2 * j;  // even: the top fine row 2cy + 2 of coarse row cy
       const int cy = (y - 2) / 2;
       if (cy >= 0 && cy < ncy) {
         const T* rs = row(rr, y - 2);
@@ -285,18 +298,15 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
 
 // Post-smoothing of a V-cycle level with nu = 2 as one pass over the tile:
 //   za <- J(J(za + P zc)),   J(z) = z + omega D^-1 (b - A z).
-// The workgroup walks the tile in bands of NW rows, one row per wave.  The prolonged
-// iterate and the first sweep pass through two LDS rings of NW + 2 rows each, so za is
-// read once and written once and b is read twice (the second time from cache), instead
-// of the 8 passes of a separate interpolation and two sweeps.  At step k wave w forms
-// row k NW + w - 1 of za + P zc (stage A), the first sweep on the row below (stage B)
-// and the second sweep two rows below (stage C, written into za in place: no later stage
-// reads za at or below that row).  A row of a ring is overwritten only after the barrier
-// that follows its last reader.
-template <int NT, int KIND, typename T, bool DOT>
+// Same banded walk with two LDS rings of B + 2 rows (the prolonged iterate, the first
+// sweep): at step k rows k B - 1 .. of za + P zc are formed (stage A), the first sweep
+// one row below (B) and the second sweep two rows below (C, written into za in place: no
+// later stage reads za at or below that row).  za is read and written once and b read
+// once from HBM, instead of the 8 passes of a separate interpolation and two sweeps.
+template <int NT, int KIND, typename T, bool DOT, int R>
 __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
                               const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
-  constexpr int NW = NT / 64, RING = NW + 2;
+  constexpr int NW = NT / 64, BH = NW * R, RING = BH + 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = lv.nx, ny = lv.ny;
   T* ringA = ring;
@@ -308,54 +318,63 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
     const T v = zc[in ? (unsigned)(cy * ncx + cx) : 0u];
     return in ? v : T(0);
   };
-  for (int k = 0; k * NW - 3 < ny; ++k) {
-    const int ya = k * NW + w - 1;
-    if (ya >= -1 && ya <= ny) {
-      T* dst = row(ringA, ya);
-      const bool inside = ya >= 0 && ya < ny;
-      for (int ix = lane; ix < nx; ix += 64) {
-        T v = T(0);
-        if (inside) {
-          const unsigned i = (unsigned)(ya * nx + ix);
-          const int cx = ix >> 1, cy = ya >> 1;
-          const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
-          const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
-          const T old = za[i];
-          v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
-        }
-        dst[ix] = v;
-      }
-    }
-    __syncthreads();
-    const int yb = ya - 1;
-    if (yb >= -1 && yb <= ny) {
-      T* dst = row(ringB, yb);
-      if (yb >= 0 && yb < ny) {
-        const T* rs = row(ringA, yb - 1);
-        const T* rc = row(ringA, yb);
-        const T* rn = row(ringA, yb + 1);
+  for (int k = 0; k * BH - 3 < ny; ++k) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int ya = k * BH + w + NW * q - 1;
+      if (ya >= -1 && ya <= ny) {
+        T* dst = row(ringA, ya);
+        const bool inside = ya >= 0 && ya < ny;
         for (int ix = lane; ix < nx; ix += 64) {
-          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[(unsigned)(yb * nx + ix)], ix, yb,
-                                           omega);
-          dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+          T v = T(0);
+          if (inside) {
+            const unsigned i = (unsigned)(ya * nx + ix);
+            const int cx = ix >> 1, cy = ya >> 1;
+            const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
+            const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
+            const T old = za[i];
+            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
+          }
+          dst[ix] = v;
         }
-      } else {
-        for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
       }
     }
     __syncthreads();
-    const int yc = ya - 2;
-    if (yc >= 0 && yc < ny) {
-      const T* rs = row(ringB, yc - 1);
-      const T* rc = row(ringB, yc);
-      const T* rn = row(ringB, yc + 1);
-      for (int ix = lane; ix < nx; ix += 64) {
-        const unsigned i = (unsigned)(yc * nx + ix);
-        const T bi = b[i];
-        const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega);
-        const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
-        za[i] = dof ? v : T(0);
-        if (DOT && dof) *acc += (double)bi * (double)v;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int yb = k * BH + w + NW * q - 2;
+      if (yb >= -1 && yb <= ny) {
+        T* dst = row(ringB, yb);
+        if (yb >= 0 && yb < ny) {
+          const T* rs = row(ringA, yb - 1);
+          const T* rc = row(ringA, yb);
+          const T* rn = row(ringA, yb + 1);
+          for (int ix = lane; ix < nx; ix += 64) {
+            const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[(unsigned)(yb * nx + ix)], ix,
+                                             yb, omega);
+            dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+          }
+        } else {
+          for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int yc = k * BH + w + NW * q - 3;
+      if (yc >= 0 && yc < ny) {
+        const T* rs = row(ringB, yc - 1);
+        const T* rc = row(ringB, yc);
+        const T* rn = row(ringB, yc + 1);
+        for (int ix = lane; ix < nx; ix += 64) {
+          const unsigned i = (unsigned)(yc * nx + ix);
+          const T bi = b[i];
+          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega);
+          const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
+          za[i] = dof ? v : T(0);
+          if (DOT && dof) *acc += (double)bi * (double)v;
+        }
       }
     }
   }
@@ -718,12 +737,12 @@ __device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
 
 // One symmetric V-cycle applied to the level-0 right-hand side at lev[0].ob; returns
 // the buffer that holds the result z and adds this thread's share of b.z to *rz.  With
-// nu = 2 and three LDS rings sized for the tile level (non-null `ring`), the pre-
-// smoothing with residual and restriction and the post-smoothing of every level run as
-// one banded pass each.
-template <int NT, int KIND, typename T>
+// nu = 2 and three LDS rings sized for the tile level (ring_rows = rows per wave per
+// band step, 1 or 2; 0: no rings), the pre-smoothing with residual and restriction and
+// the post-smoothing of every level run as one banded pass each.
+template <int NT, int KIND, typename T, int MAXR>
 __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
-                     int nu, T omega, double* rz, T* ring, T* tail) {
+                     int nu, T omega, double* rz, T* ring, int ring_rows, T* tail) {
   constexpr bool PREFETCH = sizeof(T) == 4 && KIND == 0;
   int tl = m + 1;  // first level handled in LDS (none when m + 1)
   if (tail != nullptr) {
@@ -738,11 +757,14 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     const T* b = base + lv.ob;
     T* za = base + lv.oz;
     T* zb = base + lv.ot;
-    if (ring != nullptr && nu == 2) {
-      if (PREFETCH && lv.nx <= 64 * RING_CHUNKS)
-        op_pre_fused_pf<NT, KIND, T>(P, lv, lev[t + 1], b, za, base + lev[t + 1].ob, omega, ring);
+    if (ring_rows > 0 && nu == 2) {
+      T* bc = base + lev[t + 1].ob;
+      if (MAXR >= 2 && ring_rows == 2)
+        op_pre_fused<NT, KIND, T, MAXR>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+      else if (PREFETCH && lv.nx <= 64 * RING_CHUNKS)
+        op_pre_fused_pf<NT, KIND, T>(P, lv, lev[t + 1], b, za, bc, omega, ring);
       else
-        op_pre_fused<NT, KIND, T>(P, lv, lev[t + 1], b, za, base + lev[t + 1].ob, omega, ring);
+        op_pre_fused<NT, KIND, T, 1>(P, lv, lev[t + 1], b, za, bc, omega, ring);
       __syncthreads();
       continue;
     }
@@ -786,16 +808,25 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
       za = zb;
       zb = tmp;
     }
-    if (ring != nullptr && nu == 2) {
-      const bool pf = PREFETCH && lv.nx <= 64 * RING_CHUNKS;
-      if (t == 0 && pf)
-        op_post_fused_pf<NT, KIND, T, true>(P, lev[t + 1], lv, zc, b, za, omega, ring, rz);
-      else if (t == 0)
-        op_post_fused<NT, KIND, T, true>(P, lev[t + 1], lv, zc, b, za, omega, ring, rz);
-      else if (pf)
-        op_post_fused_pf<NT, KIND, T, false>(P, lev[t + 1], lv, zc, b, za, omega, ring, nullptr);
-      else
-        op_post_fused<NT, KIND, T, false>(P, lev[t + 1], lv, zc, b, za, omega, ring, nullptr);
+    if (ring_rows > 0 && nu == 2) {
+      const LevelDesc lc = lev[t + 1];
+      const bool pf = ring_rows == 1 && PREFETCH && lv.nx <= 64 * RING_CHUNKS;
+      if (MAXR >= 2 && ring_rows == 2) {
+        if (t == 0)
+          op_post_fused<NT, KIND, T, true, MAXR>(P, lc, lv, zc, b, za, omega, ring, rz);
+        else
+          op_post_fused<NT, KIND, T, false, MAXR>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+      } else if (pf) {
+        if (t == 0)
+          op_post_fused_pf<NT, KIND, T, true>(P, lc, lv, zc, b, za, omega, ring, rz);
+        else
+          op_post_fused_pf<NT, KIND, T, false>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+      } else {
+        if (t == 0)
+          op_post_fused<NT, KIND, T, true, 1>(P, lc, lv, zc, b, za, omega, ring, rz);
+        else
+          op_post_fused<NT, KIND, T, false, 1>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+      }
       __syncthreads();
       zc = za;
       continue;
@@ -821,12 +852,13 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
 // the vector type T of the tile buffers (reductions in FP64).  On entry R (level-0
 // right-hand side buffer) holds r and X is zero; bb = ||r||^2.  Iterates until
 // ||r_k||^2 <= tol2 or max_it; returns the iteration count and the final ||r_k||^2 in rr.
+// MAXR: the most band rows per wave the caller's rings may ask for (1 or 2).
 // The search direction alternates between two buffers (the new one is formed from the
 // old one and the preconditioned residual while neighbours still read the old one).
-template <int NT, int KIND, typename T>
+template <int NT, int KIND, typename T, int MAXR>
 __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
                          double bb, double tol2, int max_it, int nu, double omega, double* red,
-                         T* ring, T* tail, double& rr) {
+                         T* ring, int ring_rows, T* tail, double& rr) {
   const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
   T* X = base;
@@ -839,7 +871,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   if (!(bb > 0.0)) return 0;
   double acc[2];
   acc[0] = acc[1] = 0.0;
-  const T* Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, tail);
+  const T* Z = vcycle<NT, KIND, T, MAXR>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_rows, tail);
   block_sum<NT, 2>(acc, red);
   double rho = acc[0];
   T beta = T(0);
@@ -885,7 +917,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
     rr = acc[0];
     if (rr <= tol2) break;
     acc[0] = acc[1] = 0.0;
-    Z = vcycle<NT, KIND, T>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, tail);
+    Z = vcycle<NT, KIND, T, MAXR>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_rows, tail);
     block_sum<NT, 2>(acc, red);
     beta = T(acc[0] / rho);
     rho = acc[0];
