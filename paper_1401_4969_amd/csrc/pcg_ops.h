@@ -848,6 +848,161 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
   return zc;
 }
 
+// x += alpha p, r -= alpha A p and this thread's share of ||r||^2 over the tile, software
+// pipelined: each wave walks its row chunks (rows w, w + NW, ..., 64 nodes per chunk) and
+// issues the loads of the next chunk (p at the five stencil points, x, r) before it
+// computes and stores the current one, so two memory round trips are in flight.
+template <int NT, int KIND, typename T>
+__device__ void pass_xr(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const T* Pn, T alpha,
+                        double* acc) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nxc = (nx + 63) >> 6;
+  struct Ld {
+    T c, e, w, n, s, x, r;
+  };
+  auto load = [&](int iy, int ix, Ld& L) {
+    const int jx = ix < nx ? ix : nx - 1;  // lanes past the row end read a valid node
+    const unsigned i = (unsigned)(iy * nx + jx);
+    const bool he = jx + 1 < nx, hw = jx > 0, hn = iy + 1 < ny, hs = iy > 0;
+    L.c = Pn[i];
+    L.e = Pn[he ? i + 1 : i];
+    L.w = Pn[hw ? i - 1 : i];
+    L.n = Pn[hn ? i + nx : i];
+    L.s = Pn[hs ? i - nx : i];
+    L.x = X[i];
+    L.r = R[i];
+  };
+  int iy = w, cix = 0;
+  Ld cur, nxt;
+  if (iy < ny) load(iy, lane, cur);
+  while (iy < ny) {
+    int niy = iy, ncx = cix + 1;
+    if (ncx == nxc) {
+      ncx = 0;
+      niy += NW;
+    }
+    if (niy < ny) load(niy, lane + 64 * ncx, nxt);
+    const int ix = lane + 64 * cix;
+    if (ix < nx) {
+      const unsigned i = (unsigned)(iy * nx + ix);
+      T q = T(0);
+      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
+        const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+        const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+        const T e = ix + 1 < nx ? cur.e : T(0), wv = ix > 0 ? cur.w : T(0);
+        const T n = iy + 1 < ny ? cur.n : T(0), sv = iy > 0 ? cur.s : T(0);
+        q = (we + ww + wn + ws) * cur.c - we * e - ww * wv - wn * n - ws * sv;
+      }
+      X[i] = cur.x + alpha * cur.c;
+      const T r = cur.r - alpha * q;
+      R[i] = r;
+      *acc += (double)r * (double)r;
+    }
+    cur = nxt;
+    iy = niy;
+    cix = ncx;
+  }
+}
+
+// p_new = z + beta p_old (beta = 0 and p_old unread on the first iteration), stored, and
+// this thread's share of p_new . A p_new with A p_new formed from p_new at the node and
+// its neighbours; software pipelined like pass_xr (z and p_old at the five stencil points
+// of the next chunk are loaded before the current chunk is computed).
+template <int NT, int KIND, typename T>
+__device__ void pass_dir(const ProbDev& P, const LevelDesc& l0, const T* Z, const T* Po, T* Pn,
+                         T beta, bool first, double* acc) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nxc = (nx + 63) >> 6;
+  const T bet = first ? T(0) : beta;
+  const T* Pold = first ? Z : Po;  // any valid vector: its values are multiplied by 0
+  struct Ld {
+    T z[5], p[5];  // centre, e, w, n, s
+  };
+  auto load = [&](int iy, int ix, Ld& L) {
+    const int jx = ix < nx ? ix : nx - 1;
+    const unsigned i = (unsigned)(iy * nx + jx);
+    const bool he = jx + 1 < nx, hw = jx > 0, hn = iy + 1 < ny, hs = iy > 0;
+    const unsigned j[5] = {i, he ? i + 1 : i, hw ? i - 1 : i, hn ? i + nx : i, hs ? i - nx : i};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      L.z[k] = Z[j[k]];
+      L.p[k] = Pold[j[k]];
+    }
+  };
+  int iy = w, cix = 0;
+  Ld cur, nxt;
+  if (iy < ny) load(iy, lane, cur);
+  while (iy < ny) {
+    int niy = iy, ncx = cix + 1;
+    if (ncx == nxc) {
+      ncx = 0;
+      niy += NW;
+    }
+    if (niy < ny) load(niy, lane + 64 * ncx, nxt);
+    const int ix = lane + 64 * cix;
+    if (ix < nx) {
+      const unsigned i = (unsigned)(iy * nx + ix);
+      T v[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] = cur.z[k] + bet * cur.p[k];
+      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
+        const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+        const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+        const T e = ix + 1 < nx ? v[1] : T(0), wv = ix > 0 ? v[2] : T(0);
+        const T n = iy + 1 < ny ? v[3] : T(0), sv = iy > 0 ? v[4] : T(0);
+        const T q = (we + ww + wn + ws) * v[0] - we * e - ww * wv - wn * n - ws * sv;
+        *acc += (double)v[0] * (double)q;
+      }
+      Pn[i] = v[0];
+    }
+    cur = nxt;
+    iy = niy;
+    cix = ncx;
+  }
+}
+
+// The same two passes without pipelining: one chunk at a time.  With a variable
+// coefficient the edge-weight loads need the registers the pipelining would take.
+template <int NT, int KIND, typename T>
+__device__ void pass_dir_plain(const ProbDev& P, const LevelDesc& l0, const T* Z, const T* Po,
+                               T* Pn, T beta, bool first, double* acc) {
+  const T bet = first ? T(0) : beta;
+  const T* Pold = first ? Z : Po;  // any valid vector: its values are multiplied by 0
+  auto pv = [&](unsigned j) -> T { return Z[j] + bet * Pold[j]; };
+  FOR_TILE(l0) {
+    const unsigned i = (unsigned)(iy * l0.nx + ix);
+    const bool he = ix + 1 < l0.nx, hw = ix > 0, hn = iy + 1 < l0.ny, hs = iy > 0;
+    const T pc = pv(i);
+    const T e0 = pv(he ? i + 1 : i), w0 = pv(hw ? i - 1 : i);
+    const T n0 = pv(hn ? i + l0.nx : i), s0 = pv(hs ? i - l0.nx : i);
+    const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = hn ? n0 : T(0), s = hs ? s0 : T(0);
+    const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+    const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+    const T q = (we + ww + wn + ws) * pc - we * e - ww * w - wn * n - ws * s;
+    if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) *acc += (double)pc * (double)q;
+    Pn[i] = pc;
+  }
+}
+
+template <int NT, int KIND, typename T>
+__device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const T* Pn,
+                              T alpha, double* acc) {
+  FOR_TILE(l0) {
+    const unsigned i = (unsigned)(iy * l0.nx + ix);
+    T q = T(0);
+    if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
+      T d;
+      q = stencil<KIND, T>(P, l0, Pn, ix, iy, i, d);
+    }
+    X[i] += alpha * Pn[i];
+    const T r = R[i] - alpha * q;
+    R[i] = r;
+    *acc += (double)r * (double)r;
+  }
+}
+
 // Preconditioned conjugate gradients on K_j x = r with the V-cycle preconditioner, in
 // the vector type T of the tile buffers (reductions in FP64).  On entry R (level-0
 // right-hand side buffer) holds r and X is zero; bb = ||r||^2.  Iterates until
@@ -881,38 +1036,18 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
     // p_new = z + beta p_old and p_new . A p_new, with A p_new formed from p_new at the
     // node and its neighbours
     acc[0] = acc[1] = 0.0;
-    const T bet = first ? T(0) : beta;
-    const T* Pold = first ? Z : Po;  // any valid vector: its value is multiplied by 0
-    auto pv = [&](unsigned j) -> T { return Z[j] + bet * Pold[j]; };
-    FOR_TILE(l0) {
-      const unsigned i = (unsigned)(iy * l0.nx + ix);
-      const bool he = ix + 1 < l0.nx, hw = ix > 0, hn = iy + 1 < l0.ny, hs = iy > 0;
-      const T pc = pv(i);
-      const T e0 = pv(he ? i + 1 : i), w0 = pv(hw ? i - 1 : i);
-      const T n0 = pv(hn ? i + l0.nx : i), s0 = pv(hs ? i - l0.nx : i);
-      const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = hn ? n0 : T(0), s = hs ? s0 : T(0);
-      const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
-      const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
-      const T q = (we + ww + wn + ws) * pc - we * e - ww * w - wn * n - ws * s;
-      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) acc[0] += (double)pc * (double)q;
-      Pn[i] = pc;
-    }
+    if constexpr (KIND == 0)
+      pass_dir<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
+    else
+      pass_dir_plain<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
     block_sum<NT, 2>(acc, red);
     const T alpha = T(rho / acc[0]);
     // x += alpha p, r -= alpha A p, ||r||^2
     acc[0] = acc[1] = 0.0;
-    FOR_TILE(l0) {
-      const unsigned i = (unsigned)(iy * l0.nx + ix);
-      T q = T(0);
-      if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
-        T d;
-        q = stencil<KIND, T>(P, l0, Pn, ix, iy, i, d);
-      }
-      X[i] += alpha * Pn[i];
-      const T r = R[i] - alpha * q;
-      R[i] = r;
-      acc[0] += (double)r * (double)r;
-    }
+    if constexpr (KIND == 0)
+      pass_xr<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
+    else
+      pass_xr_plain<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
     block_sum<NT, 2>(acc, red);
     rr = acc[0];
     if (rr <= tol2) break;
