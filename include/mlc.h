@@ -60,6 +60,11 @@ enum { MLC_COEF_ONE = 0,        /* kappa == 1 */
        MLC_COEF_COARSE = 1,     /* one kappa per coarse cell, [n_coarse*n_coarse] */
        MLC_COEF_FINE = 2 };     /* one kappa per finest square cell, [N_L*N_L] */
 
+/* Gluing of the local corrections, u~ = I u + sum_j chi_j e^j with chi_j = phi_j / sum_l phi_l
+   (a partition of unity in place of the G_j / G_{m+1} construction of Algorithm 4.1 step 2): */
+enum { MLC_POU_RAMP = 0,        /* phi_j = rho(x) rho(y): 1 on D_j, linear to 0 across the overlap */
+       MLC_POU_INDICATOR = 1 }; /* phi_j = indicator of the closed D_j (allows overlap 0) */
+
 enum { MLC_PREC_FP64 = 0,       /* every local solve in FP64 */
        MLC_PREC_MIXED = 1 };    /* FP32 inner PCG with FP64 residual refinement */
 
@@ -70,11 +75,14 @@ typedef struct mlc_problem_desc {
   int32_t n_refine;    /* number of corrections L; finest h = H/2^L; level 0 is the coarse mesh */
   int32_t sub_x;       /* D_j blocks along x: boundaries at floor(b*n_coarse/sub_x) coarse cells */
   int32_t sub_y;       /* D_j blocks along y */
-  int32_t overlap;     /* Omega_j = D_j grown by this many coarse cells per side (>= 1) */
+  int32_t overlap;     /* Omega_j = D_j grown by this many coarse cells per side (>= 1 with
+                          MLC_POU_RAMP, >= 0 with MLC_POU_INDICATOR); every Omega_j must be at
+                          least 2 coarse cells wide and tall */
   int32_t n_eig;       /* q, number of lowest eigenpairs (1..8) */
   int32_t coef_kind;   /* MLC_COEF_*; both triangles of a square cell share its value */
   const double* kappa; /* host pointer, row-major [row along y][col along x]; read during
                           mlc_create only (copied); NULL for MLC_COEF_ONE.  Must be > 0 and finite. */
+  int32_t pou;         /* MLC_POU_* (0 unless set) */
 } mlc_problem_desc;
 
 /* Solver options; mlc_default_opts fills the defaults shown. */

@@ -78,12 +78,17 @@ def ramp(t: np.ndarray, a: float, b: float, delta: float) -> np.ndarray:
 
 
 def pou_weights(prob, subs: List[Subdomain], ti: np.ndarray, tj: np.ndarray) -> np.ndarray:
-    """chi_j at points with coarse-cell coordinates (ti, tj): phi_j / sum_l phi_l,
-    phi_j(x, y) = ramp(x; D_j) ramp(y; D_j) with ramp width delta = overlap coarse cells.
+    """chi_j at points with coarse-cell coordinates (ti, tj): phi_j / sum_l phi_l, with
+    phi_j(x, y) = ramp(x; D_j) ramp(y; D_j), ramp width delta = overlap coarse cells
+    (prob.pou = 0), or phi_j = indicator of the closed D_j (prob.pou = 1).
     Returns an (m, P) array."""
-    delta = float(prob.overlap)
-    phi = np.stack([ramp(ti, s.D[0], s.D[1], delta) * ramp(tj, s.D[2], s.D[3], delta)
-                    for s in subs])
+    if getattr(prob, "pou", 0) == 1:
+        phi = np.stack([((ti >= s.D[0]) & (ti <= s.D[1]) & (tj >= s.D[2]) & (tj <= s.D[3]))
+                        .astype(np.float64) for s in subs])
+    else:
+        delta = float(prob.overlap)
+        phi = np.stack([ramp(ti, s.D[0], s.D[1], delta) * ramp(tj, s.D[2], s.D[3], delta)
+                        for s in subs])
     tot = phi.sum(axis=0)
     chi = np.zeros_like(phi)
     nz = tot > 0

@@ -37,7 +37,7 @@ class ProblemDesc(C.Structure):
     _fields_ = [("domain", C.c_int32), ("n_coarse", C.c_int32), ("n_refine", C.c_int32),
                 ("sub_x", C.c_int32), ("sub_y", C.c_int32), ("overlap", C.c_int32),
                 ("n_eig", C.c_int32), ("coef_kind", C.c_int32),
-                ("kappa", C.POINTER(C.c_double))]
+                ("kappa", C.POINTER(C.c_double)), ("pou", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
@@ -142,7 +142,7 @@ def make_desc(prob) -> Tuple[ProblemDesc, Optional[np.ndarray]]:
     kap = None
     d = ProblemDesc(int(prob.domain), int(prob.n_coarse), int(prob.n_refine), int(prob.sub_x),
                     int(prob.sub_y), int(prob.overlap), int(prob.n_eig), int(prob.coef_kind),
-                    None)
+                    None, int(getattr(prob, "pou", 0)))
     if prob.coef_kind != 0:
         kap = np.ascontiguousarray(prob.kappa, dtype=np.float64)
         d.kappa = kap.ctypes.data_as(C.POINTER(C.c_double))
@@ -301,6 +301,7 @@ def _problem_with_kappa(prob, kappa: np.ndarray):
     from types import SimpleNamespace
     f = {k: getattr(prob, k) for k in ("domain", "n_coarse", "n_refine", "sub_x", "sub_y",
                                        "overlap", "n_eig", "coef_kind")}
+    f["pou"] = getattr(prob, "pou", 0)
     return SimpleNamespace(kappa=kappa, **f)
 
 

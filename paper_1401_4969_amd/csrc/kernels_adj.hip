@@ -279,22 +279,6 @@ __global__ __launch_bounds__(NTA) void k_adj_utbar(const ProbDev* probs, int m, 
   out[idx] = v;
 }
 
-__device__ __forceinline__ int axis_cand(const int32_t* bnd, int nb_, int g, int r, int ov,
-                                         int (&id)[MLC_MAX_CAND], double (&rho)[MLC_MAX_CAND]) {
-  const int d = ov * r;
-  int n = 0;
-  for (int b = 0; b < nb_ && n < MLC_MAX_CAND; ++b) {
-    const int lo = bnd[b] * r, hi = bnd[b + 1] * r;
-    const int v = min(g - lo + d, hi + d - g);
-    if (v > 0) {
-      id[n] = b;
-      rho[n] = (double)min(v, d) / (double)d;
-      ++n;
-    }
-  }
-  return n;
-}
-
 // Right-hand side of the adjoint local solve of each item: chi_j u~_bar on its tile,
 // written into the item's residual buffer (the local solver then starts from it).
 __global__ __launch_bounds__(NTA) void k_adj_tile_rhs(const ProbDev* probs, const TileItem* items,
@@ -315,8 +299,8 @@ __global__ __launch_bounds__(NTA) void k_adj_tile_rhs(const ProbDev* probs, cons
     if (is_dof(P.domain, N, gx, gy)) {
       int cx[MLC_MAX_CAND], cy[MLC_MAX_CAND];
       double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-      const int nxc = axis_cand(P.bx, P.sub_x, gx, r, P.overlap, cx, rx);
-      const int nyc = axis_cand(P.by, P.sub_y, gy, r, P.overlap, cy, ry);
+      const int nxc = pou_axis(P.bx, P.sub_x, gx, r, P.overlap, P.pou, cx, rx);
+      const int nyc = pou_axis(P.by, P.sub_y, gy, r, P.overlap, P.pou, cy, ry);
       double tot = 0.0, mine = 0.0;
       for (int a = 0; a < nyc; ++a)
         for (int b = 0; b < nxc; ++b) {
@@ -325,7 +309,7 @@ __global__ __launch_bounds__(NTA) void k_adj_tile_rhs(const ProbDev* probs, cons
           tot += phi;
           if (cx[b] == sxb && cy[a] == syb) mine = phi;
         }
-      v = mine / tot * utbar[(int64_t)gy * n1 + gx];
+      v = tot > 0.0 ? mine / tot * utbar[(int64_t)gy * n1 + gx] : 0.0;
     }
     R[i] = v;
   }
@@ -345,8 +329,8 @@ __global__ __launch_bounds__(NTA) void k_adj_rbar(const ProbDev* probs, const Ti
     const int r = 1 << m;
     int cx[MLC_MAX_CAND], cy[MLC_MAX_CAND];
     double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-    const int nxc = axis_cand(P.bx, P.sub_x, gx, r, P.overlap, cx, rx);
-    const int nyc = axis_cand(P.by, P.sub_y, gy, r, P.overlap, cy, ry);
+    const int nxc = pou_axis(P.bx, P.sub_x, gx, r, P.overlap, P.pou, cx, rx);
+    const int nyc = pou_axis(P.by, P.sub_y, gy, r, P.overlap, P.pou, cy, ry);
     for (int a = 0; a < nyc; ++a)
       for (int b = 0; b < nxc; ++b) {
         const int item = sub_item[P.sub_item_off + (cy[a] * P.sub_x + cx[b]) * P.q];

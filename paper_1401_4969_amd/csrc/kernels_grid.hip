@@ -59,24 +59,6 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
   }
 }
 
-__device__ __forceinline__ int axis_candidates(const int32_t* bnd, int nb, int g, int r, int ov,
-                                               int (&id)[MLC_MAX_CAND], double (&rho)[MLC_MAX_CAND]) {
-  // ramp(t; a, b) = clamp(min(t - a + d, b + d - t)/d, 0, 1), d = overlap coarse cells,
-  // here in fine-node units (exact dyadic arithmetic).
-  const int d = ov * r;
-  int n = 0;
-  for (int b = 0; b < nb && n < MLC_MAX_CAND; ++b) {
-    const int lo = bnd[b] * r, hi = bnd[b + 1] * r;
-    const int v = min(g - lo + d, hi + d - g);
-    if (v > 0) {
-      id[n] = b;
-      rho[n] = (double)min(v, d) / (double)d;
-      ++n;
-    }
-  }
-  return n;
-}
-
 // a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
 __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const TileItem* items,
                                                    const int32_t* sub_item, const char* store,
@@ -96,8 +78,8 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   const int r = 1 << m;
   int ix[MLC_MAX_CAND], iy[MLC_MAX_CAND];
   double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-  const int nxc = axis_candidates(P.bx, P.sub_x, gx, r, P.overlap, ix, rx);
-  const int nyc = axis_candidates(P.by, P.sub_y, gy, r, P.overlap, iy, ry);
+  const int nxc = pou_axis(P.bx, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
+  const int nyc = pou_axis(P.by, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
   for (int i = 0; i < P.q; ++i) {
     double acc = 0.0, tot = 0.0;
     for (int a = 0; a < nyc; ++a) {
@@ -113,7 +95,8 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
         tot += phi;
       }
     }
-    P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + acc / tot;
+    // tot = 0 only on D_j block boundaries with overlap 0, where every e^j vanishes
+    P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + (tot > 0.0 ? acc / tot : 0.0);
   }
 }
 

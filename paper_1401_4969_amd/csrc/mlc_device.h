@@ -28,7 +28,7 @@ struct ProbDev {
   const int32_t* by;          // sub_y+1
   int32_t sub_item_off;       // offset of this problem's (sub_x*sub_y)*q block in a step's
                               // subdomain -> item table (-1 entries: dropped or inactive)
-  int32_t pad0;
+  int32_t pou;                // gluing weights: 0 ramp, 1 indicator of the closed D_j
   const int32_t* coarse_nodes;  // nH: grid index (on (n_c+1)^2) of coarse dof r
   const int32_t* coarse_index;  // (n_c+1)^2: dof index or -1
   double* u[2];               // eigenvectors, q*(N_L+1)^2 each (ping-pong)
@@ -111,6 +111,27 @@ __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, 
     W.s = 0.5 * (up[c - N] + lo[c - N - 1]);
   }
   return W;
+}
+
+// Blocks along one axis whose Omega range (D_j grown by `ov` coarse cells) holds fine
+// grid index g strictly inside, i.e. whose tiles cover the node, with the factor rho of
+// phi_j along that axis: the ramp (1 on D_j, linear to 0 across the overlap; exact
+// dyadic arithmetic) or the indicator of the closed D_j range.  r = fine cells per
+// coarse cell.  Returns the number of candidates (at most MLC_MAX_CAND).
+__device__ __forceinline__ int pou_axis(const int32_t* bnd, int nb, int g, int r, int ov, int pou,
+                                        int (&id)[MLC_MAX_CAND], double (&rho)[MLC_MAX_CAND]) {
+  const int d = ov * r;
+  int n = 0;
+  for (int b = 0; b < nb && n < MLC_MAX_CAND; ++b) {
+    const int lo = bnd[b] * r, hi = bnd[b + 1] * r;
+    const int v = min(g - lo + d, hi + d - g);
+    if (v > 0) {
+      id[n] = b;
+      rho[n] = pou == 0 ? (double)min(v, d) / (double)d : (g >= lo && g <= hi ? 1.0 : 0.0);
+      ++n;
+    }
+  }
+  return n;
 }
 
 // ---------------------------------------------------------------------------------

@@ -38,7 +38,7 @@ struct SubBox {
 
 // Geometry derived from one problem description (host tables only).
 struct Geometry {
-  int L = 0, q = 0, nc = 0, nH = 0, kind = 0, domain = 0, sub_x = 1, sub_y = 1, overlap = 1;
+  int L = 0, q = 0, nc = 0, nH = 0, kind = 0, domain = 0, sub_x = 1, sub_y = 1, overlap = 1, pou = 0;
   double side = 1.0;
   std::vector<int> bx, by;
   std::vector<SubBox> subs;     // kept subdomains, largest first
@@ -86,7 +86,11 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
     msg = "sub_x and sub_y must be in 1..n_coarse";
     return MLC_EINVAL;
   }
-  if (d->overlap < 1 || d->overlap > d->n_coarse) { msg = "overlap must be in 1..n_coarse"; return MLC_EINVAL; }
+  if (d->pou != MLC_POU_RAMP && d->pou != MLC_POU_INDICATOR) { msg = "pou must be 0 or 1"; return MLC_EINVAL; }
+  if (d->overlap < (d->pou == MLC_POU_RAMP ? 1 : 0) || d->overlap > d->n_coarse) {
+    msg = "overlap must be in 1..n_coarse (0..n_coarse with the indicator partition of unity)";
+    return MLC_EINVAL;
+  }
   if (d->n_eig < 1 || d->n_eig > MLC_MAX_Q) { msg = "n_eig must be in 1..8"; return MLC_EINVAL; }
   g.L = d->n_refine;
   g.q = d->n_eig;
@@ -96,6 +100,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
   g.sub_x = d->sub_x;
   g.sub_y = d->sub_y;
   g.overlap = d->overlap;
+  g.pou = d->pou;
   g.side = d->domain == 0 ? 1.0 : 2.0;
   const int nc = g.nc;
   if (g.kind != 0) {
@@ -130,6 +135,10 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
       s.Om[0] = std::max(0, s.D[0] - ov); s.Om[1] = std::min(nc, s.D[1] + ov);
       s.Om[2] = std::max(0, s.D[2] - ov); s.Om[3] = std::min(nc, s.D[3] + ov);
       const int cw = s.Om[1] - s.Om[0], ch = s.Om[3] - s.Om[2];
+      if (cw < 2 || ch < 2) {
+        msg = "every Omega_j must span at least 2 coarse cells each way (more overlap or fewer subdomains)";
+        return MLC_EINVAL;
+      }
       if ((cw - 1) * (ch - 1) > MLC_MAX_TILE_COARSE) {
         msg = "a subdomain has more than 64 coarse interior nodes (use more subdomains)";
         return MLC_EINVAL;
@@ -493,6 +502,7 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     D.sub_x = g.sub_x;
     D.sub_y = g.sub_y;
     D.overlap = g.overlap;
+    D.pou = g.pou;
     D.nH = g.nH;
     D.side = g.side;
     D.kH = (const double*)(w + L.kH);

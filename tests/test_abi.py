@@ -60,7 +60,7 @@ def test_workspace_size_config3_fits_hbm():
 @pytest.mark.parametrize("bad", [
     dict(domain=3), dict(n_coarse=1), dict(n_refine=0), dict(n_refine=11),
     dict(sub_x=0), dict(sub_x=9), dict(overlap=0), dict(n_eig=0), dict(n_eig=9),
-    dict(coef_kind=5),
+    dict(coef_kind=5), dict(pou=2), dict(pou=-1), dict(pou=1, overlap=-1),
 ])
 def test_invalid_descriptors_rejected(bad):
     p = W.config1().with_(**bad)
@@ -108,3 +108,15 @@ def test_null_context_calls():
     assert lib.mlc_level_correct(None, None) == B.MLC_EINVAL
     assert lib.mlc_destroy(None) == B.MLC_EINVAL
     assert lib.mlc_last_error(None) == b"null context"
+
+
+def test_indicator_partition_allows_overlap_zero():
+    """The indicator partition of unity accepts overlap 0 (Omega_j = D_j); every Omega_j
+    must still span two coarse cells each way."""
+    ok = W.config1().with_(overlap=0, pou=1)              # 2x2-cell blocks
+    assert B.workspace_size(ok) > 0
+    assert B.workspace_size(W.config1().with_(overlap=2, pou=1)) > 0
+    narrow = W.Problem(0, 8, 2, 8, 8, 0, 1, 0, None, pou=1)  # 1-cell blocks, no overlap
+    with pytest.raises(B.MLCError) as e:
+        B.workspace_size(narrow)
+    assert e.value.status == B.MLC_EINVAL

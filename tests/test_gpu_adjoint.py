@@ -74,6 +74,20 @@ def test_fine_cell_gradient_matches_oracle_fd(factory):
     assert abs(np.sum(hf * prob.kappa) - lam) < 1e-10 * lam   # HF also satisfies Euler
 
 
+@pytest.mark.parametrize("overlap", [0, 2])
+def test_indicator_gluing_gradient_matches_oracle_fd(overlap):
+    """Reverse sweep with indicator gluing (overlap 0 included) against central
+    differences of the oracle."""
+    _torch()
+    prob = W.small_field().with_(overlap=overlap, pou=1)
+    lam, g, _ = gpu_grad(prob)
+    rng = np.random.Generator(np.random.PCG64(9))
+    cells = rng.choice(g.size, size=10, replace=False)
+    fd = oracle_fd(prob, cells)
+    assert np.max(np.abs(g.ravel()[cells] - fd)) < 1e-6 * np.max(np.abs(g)), (g.ravel()[cells], fd)
+    assert abs(np.sum(g * prob.kappa) - lam) < 1e-10 * lam
+
+
 def test_coarse_cell_gradient_lshape_matches_oracle_fd():
     _torch()
     prob = W.small_ragged().with_(n_eig=1)

@@ -117,6 +117,26 @@ def test_autotune_choices_and_results():
     bs.close()
 
 
+def test_batch_mixed_gluing():
+    """Problems with different gluing weights and overlaps share a batch; each matches its
+    single-problem run bitwise and the oracle to 1e-10."""
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    probs = [p.with_(overlap=ov, pou=pou) for p, (ov, pou) in
+             zip(_small_batch(1, 1, n=6, seed0=300), [(0, 1), (1, 1), (2, 1), (1, 0), (0, 1), (2, 0)])]
+    probs = [p for p in probs if min(p.n_coarse // p.sub_x, p.n_coarse // p.sub_y) + 2 * p.overlap >= 2]
+    bs = B.BatchSolver(probs)
+    bs.setup()
+    bs.run()
+    for i, p in enumerate(probs):
+        lam, u = bs.get(i)
+        lam1, u1 = _single(p)
+        assert np.array_equal(lam, lam1)
+        assert torch.equal(u, u1)
+        assert np.allclose(lam, oracle_solve(p).lam, rtol=1e-10, atol=0)
+    bs.close()
+
+
 def test_batch_rejects_mixed_q_or_kind():
     _torch()
     from paper_1401_4969_amd import binding as B

@@ -214,3 +214,17 @@ def test_mixed_precision_matches_oracle(factory):
     so eigenvalues agree with the FP64 oracle to the FP64 tolerance."""
     lam, u, levels, stats, ref = compare(factory(), precision=1)
     assert max(s["refine_max"] for s in stats) >= 2   # the refinement loop did its job
+
+
+@pytest.mark.parametrize("overlap", [0, 1, 2])
+@pytest.mark.parametrize("which", ["square", "lshape_q2", "field"])
+def test_indicator_gluing(which, overlap):
+    """Indicator partition of unity (chi_j = normalised indicator of the closed D_j), with
+    overlap 0 (Omega_j = D_j) included: parity with the oracle on every level."""
+    if which == "square":
+        prob = W.Problem(0, 8, 3, 4, 4, overlap, 1, 0, None, "ind_square", pou=1)
+    elif which == "lshape_q2":
+        prob = W.small_ragged().with_(overlap=overlap, pou=1)
+    else:
+        prob = W.small_field().with_(overlap=overlap, pou=1)
+    compare(prob)

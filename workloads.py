@@ -41,6 +41,7 @@ class Problem:
     coef_kind: int = 0
     kappa: Optional[np.ndarray] = field(default=None, repr=False)
     name: str = ""
+    pou: int = 0               # gluing weights: 0 ramp across the overlap, 1 indicator of D_j
 
     # --- geometry helpers (no method arithmetic) ---
     @property
