@@ -332,43 +332,68 @@ __global__ __launch_bounds__(NTG) void k_init_u0(const ProbDev* probs, int dst) 
 }
 
 // Exact inverse of each subdomain's coarsest-grid operator K_H restricted to the coarse
-// interior nodes of Omega_j (Gauss-Jordan in LDS; SPD so no pivoting).  Nodes outside the
-// domain get identity rows.  One workgroup per subdomain (first item of it).
+// interior nodes of Omega_j (Gauss-Jordan, SPD so no pivoting: in LDS up to 64 nodes, in
+// place in HBM up to 1024, O(n^3) at setup).  Nodes outside the domain get identity
+// rows.  One workgroup per subdomain (first item of it).
+template <int KIND>
+__device__ __forceinline__ double tile_coarse_entry(const ProbDev& P, const TileItem& it, int nx,
+                                                    int n, int e) {
+  const int N = P.n_c;
+  const int i = e / n, j = e - i * n;
+  const int ix = i % nx, iy = i / nx;
+  const int gx = it.cx0 + 1 + ix, gy = it.cy0 + 1 + iy;
+  if (!is_dof(P.domain, N, gx, gy)) return (i == j) ? 1.0 : 0.0;
+  const int jx = j % nx, jy = j / nx;
+  const bool dj = is_dof(P.domain, N, it.cx0 + 1 + jx, it.cy0 + 1 + jy);
+  const Weights W = edge_weights<KIND>(P, 0, N, gx, gy);
+  if (i == j) return W.e + W.w + W.n + W.s;
+  if (dj && jy == iy && jx == ix + 1) return -W.e;
+  if (dj && jy == iy && jx == ix - 1) return -W.w;
+  if (dj && jx == ix && jy == iy + 1) return -W.n;
+  if (dj && jx == ix && jy == iy - 1) return -W.s;
+  return 0.0;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(NTG) void k_tile_inverse(const ProbDev* probs, const TileItem* items,
                                                        double* inv) {
   __shared__ double A[MLC_MAX_TILE_COARSE * MLC_MAX_TILE_COARSE];
+  __shared__ double rowk[MLC_MAX_TILE_COARSE_ALL], colk[MLC_MAX_TILE_COARSE_ALL];
   constexpr int PER = MLC_MAX_TILE_COARSE * MLC_MAX_TILE_COARSE / NTG;
   const TileItem it = items[blockIdx.x];
   if (it.rhs != 0) return;
   const ProbDev& P = probs[it.prob];
   const int nx = it.cw - 1, ny = it.ch - 1, n = nx * ny;
-  const int N = P.n_c;
-  for (int e = threadIdx.x; e < n * n; e += NTG) {
-    const int i = e / n, j = e - i * n;
-    const int ix = i % nx, iy = i / nx;
-    const int gx = it.cx0 + 1 + ix, gy = it.cy0 + 1 + iy;
-    const bool di = is_dof(P.domain, N, gx, gy);
-    double v = 0.0;
-    if (!di) {
-      v = (i == j) ? 1.0 : 0.0;
-    } else {
-      const int jx = j % nx, jy = j / nx;
-      const bool dj = is_dof(P.domain, N, it.cx0 + 1 + jx, it.cy0 + 1 + jy);
-      const Weights W = edge_weights<KIND>(P, 0, N, gx, gy);
-      if (i == j)
-        v = W.e + W.w + W.n + W.s;
-      else if (dj && jy == iy && jx == ix + 1)
-        v = -W.e;
-      else if (dj && jy == iy && jx == ix - 1)
-        v = -W.w;
-      else if (dj && jx == ix && jy == iy + 1)
-        v = -W.n;
-      else if (dj && jx == ix && jy == iy - 1)
-        v = -W.s;
+  if (n > MLC_MAX_TILE_COARSE) {
+    // Gauss-Jordan in place in HBM: pivot row and column of each step are first copied
+    // to LDS, so every entry is updated from its own old value and the two copies
+    double* G = inv + it.inv_off;
+    for (int e = threadIdx.x; e < n * n; e += NTG) G[e] = tile_coarse_entry<KIND>(P, it, nx, n, e);
+    for (int k = 0; k < n; ++k) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < n; t += NTG) {
+        rowk[t] = G[(int64_t)k * n + t];
+        colk[t] = G[(int64_t)t * n + k];
+      }
+      __syncthreads();
+      const double pk = 1.0 / rowk[k];
+      for (int e = threadIdx.x; e < n * n; e += NTG) {
+        const int i = e / n, j = e - i * n;
+        double v;
+        if (i == k && j == k)
+          v = pk;
+        else if (i == k)
+          v = rowk[j] * pk;
+        else if (j == k)
+          v = -colk[i] * pk;
+        else
+          v = G[e] - colk[i] * rowk[j] * pk;
+        G[e] = v;
+      }
     }
-    A[e] = v;
+    return;
   }
+  for (int e = threadIdx.x; e < n * n; e += NTG) A[e] = tile_coarse_entry<KIND>(P, it, nx, n, e);
   double tmp[PER];
   for (int k = 0; k < n; ++k) {
     __syncthreads();

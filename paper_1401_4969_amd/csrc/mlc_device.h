@@ -12,7 +12,8 @@
 
 #define MLC_MAX_LEVELS 10
 #define MLC_MAX_Q 8
-#define MLC_MAX_TILE_COARSE 64
+#define MLC_MAX_TILE_COARSE 64      // coarse tile grids up to this size are inverted in LDS
+#define MLC_MAX_TILE_COARSE_ALL 1024  // larger ones (up to this) in HBM
 #define MLC_MAX_CAND 8
 
 // Per-problem device record.  Pointers are into the caller's workspace.

@@ -139,8 +139,8 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
         msg = "every Omega_j must span at least 2 coarse cells each way (more overlap or fewer subdomains)";
         return MLC_EINVAL;
       }
-      if ((cw - 1) * (ch - 1) > MLC_MAX_TILE_COARSE) {
-        msg = "a subdomain has more than 64 coarse interior nodes (use more subdomains)";
+      if ((cw - 1) * (ch - 1) > MLC_MAX_TILE_COARSE_ALL) {
+        msg = "a subdomain has more than 1024 coarse interior nodes (use more subdomains)";
         return MLC_EINVAL;
       }
       g.subs.push_back(s);

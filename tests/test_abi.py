@@ -82,8 +82,10 @@ def test_invalid_kappa_rejected():
 def test_odd_lshape_and_oversized_subdomain_rejected():
     with pytest.raises(B.MLCError):
         B.workspace_size(W.Problem(1, 7, 2, 2, 2, 1, 1, 0, None))
-    with pytest.raises(B.MLCError):   # Omega_j of 12x12 coarse cells: 121 coarse interior nodes
-        B.workspace_size(W.Problem(0, 16, 2, 1, 1, 1, 1, 0, None))
+    with pytest.raises(B.MLCError):   # Omega_j of 40x40 coarse cells: 1521 coarse interior nodes
+        B.workspace_size(W.Problem(0, 40, 2, 1, 1, 1, 1, 0, None))
+    # up to 1024 coarse interior nodes per Omega_j are accepted (inverted in HBM at setup)
+    assert B.workspace_size(W.Problem(0, 16, 2, 1, 1, 1, 1, 0, None)) > 0
 
 
 def test_invalid_options_rejected():

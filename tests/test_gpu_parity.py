@@ -228,3 +228,11 @@ def test_indicator_gluing(which, overlap):
     else:
         prob = W.small_field().with_(overlap=overlap, pou=1)
     compare(prob)
+
+
+def test_large_coarse_tiles():
+    """Omega_j with 100 and 225 coarse interior nodes: the coarse tile inverse is formed in
+    HBM (beyond the 64 nodes inverted in LDS); per-coarse-cell kappa, L-shape too."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    compare(W.Problem(0, 20, 2, 2, 2, 1, 1, 1, W.loguniform_coarse_kappa(20, rng), "big_tiles_sq"))
+    compare(W.Problem(1, 16, 2, 1, 1, 0, 1, 0, None, "big_tiles_L", pou=1))
