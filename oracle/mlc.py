@@ -233,6 +233,38 @@ def rayleigh_ritz(hier: Hierarchy, m: int, Ut: np.ndarray, q: int):
     return mu, U, C
 
 
+def interface_gluing(hier: Hierarchy, m: int, rhs: np.ndarray, sols) -> np.ndarray:
+    """Algorithm 4.1 step 2 as the paper states it (prob.pou = 2): u~ = u~^j on G_j, and on
+    G_{m+1} = Omega minus the closed G_j the solution of a(u~, v) = lambda b(u, v) for
+    v in V_0h(G_{m+1}) with u~ = u~^j on the boundary of each G_j (and 0 on the boundary
+    of Omega).  Reading: G_j = D_j shrunk by half a coarse cell on every side (aligned
+    with every mesh from h_1 = H/2 on).  In correction form (u~ = I u + e): e = e^j on
+    each closed G_j, and on the remaining dofs S the Dirichlet problem
+    K_SS e_S = rhs_S - K_SG e_G (sparse LU).  Returns e at the level-m dofs."""
+    i, j = hier.node_ij(m, hier.meshes[m].dof)
+    r = 1 << m
+    half = r // 2
+    n = hier.n_dof(m)
+    e = np.zeros_like(rhs)
+    in_g = np.zeros(n, dtype=bool)
+    for s, (idx, e_j) in zip(hier.subs, sols):
+        x0, x1, y0, y1 = s.D
+        sel = ((i >= x0 * r + half) & (i <= x1 * r - half) &
+               (j >= y0 * r + half) & (j <= y1 * r - half))
+        full = np.zeros_like(rhs)
+        full[idx] = e_j
+        assert not np.any(in_g & sel)   # the closed G_j are disjoint
+        e[sel] = full[sel]
+        in_g |= sel
+    S = np.nonzero(~in_g)[0]
+    G = np.nonzero(in_g)[0]
+    K = hier.K[m].tocsr()
+    if S.size:
+        b = rhs[S] - K[S][:, G] @ e[G]
+        e[S] = spla.splu(K[S][:, S].tocsc()).solve(np.ascontiguousarray(b))
+    return e
+
+
 def correction(hier: Hierarchy, k: int, lam_k: np.ndarray, u_k: np.ndarray, refine: bool = True):
     """Algorithm 4.1: one correction step from level k to level k+1 (or, with
     refine=False, within level k itself, used only to test the fixed point)."""
@@ -244,11 +276,16 @@ def correction(hier: Hierarchy, k: int, lam_k: np.ndarray, u_k: np.ndarray, refi
     M = hier.M[m]
     # right-hand side of (Aux_Problem): lambda_{h_k} b(u_{h_k}, v) - a(u_{h_k}, v)
     rhs = (M @ ubar) * lam_k[None, :] - K @ ubar
-    # step 1: local solves; step 2: partition-of-unity gluing
-    chi = hier.pou(m)
-    ut = ubar.copy()
-    for (idx, e_j), chi_j in zip(local_solves(hier, m, rhs), chi):
-        ut[idx] += chi_j[idx, None] * e_j
+    # step 1: local solves; step 2: gluing (partition of unity, or the paper's interface
+    # problem on G_{m+1})
+    sols = local_solves(hier, m, rhs)
+    if getattr(hier.prob, "pou", 0) == 2:
+        ut = ubar + interface_gluing(hier, m, rhs, sols)
+    else:
+        chi = hier.pou(m)
+        ut = ubar.copy()
+        for (idx, e_j), chi_j in zip(sols, chi):
+            ut[idx] += chi_j[idx, None] * e_j
     # step 3: Rayleigh-Ritz on V_0H + span{u~}
     mu, U, _ = rayleigh_ritz(hier, m, ut, q)
     return mu, sign_normalise(U), dict(rhs=rhs, ubar=ubar, ut=ut)

@@ -123,10 +123,14 @@ def test_b_orthonormal_output():
         assert np.allclose(lam, res.lam_levels[m], rtol=1e-11)
 
 
-def test_single_subdomain_is_inverse_iteration():
-    """m = 1: Omega_1 = Omega, chi = 1, so u~ = lambda K^-1 M (I u_k); the Ritz values
-    on V_0H + span{u~} from an independent M-orthonormal basis must agree."""
-    p = W.Problem(0, 6, 2, 1, 1, 1, 2, 1, np.exp(np.random.default_rng(4).normal(size=(6, 6))))
+@pytest.mark.parametrize("pou", [0, 1, 2])
+def test_single_subdomain_is_inverse_iteration(pou):
+    """m = 1: Omega_1 = Omega, so u~ = lambda K^-1 M (I u_k) whatever the gluing (with the
+    paper's gluing the interface problem on the boundary strip is solved by the
+    restriction of the global solution); the Ritz values on V_0H + span{u~} from an
+    independent M-orthonormal basis must agree."""
+    p = W.Problem(0, 6, 2, 1, 1, 1, 2, 1, np.exp(np.random.default_rng(4).normal(size=(6, 6))),
+                  pou=pou)
     hier = Hierarchy(p)
     lam0, U0 = mlc.coarse_eigs(hier, 2)
     lam1, U1, aux = correction(hier, 0, lam0, U0)
@@ -140,6 +144,21 @@ def test_single_subdomain_is_inverse_iteration():
     C = Bih @ (S.T @ (K @ S)) @ Bih
     ritz = np.linalg.eigvalsh(0.5 * (C + C.T))[:2]
     assert np.allclose(lam1, ritz, rtol=1e-9)
+
+
+@pytest.mark.parametrize("pou", [0, 1, 2])
+def test_covering_subdomains_give_inverse_iteration(pou):
+    """Every Omega_j = Omega (overlap = n_coarse): each e^j is the global solution K^-1 r,
+    so every gluing returns u~ = I u + K^-1 r whatever the partition (for the paper's
+    gluing the interface problem's Dirichlet data then match the global solution)."""
+    p = W.Problem(1, 8, 2, 3, 2, 8, 1, 1, np.exp(np.random.default_rng(5).normal(size=(8, 8))),
+                  pou=pou)
+    hier = Hierarchy(p)
+    lam0, U0 = mlc.coarse_eigs(hier, 1)
+    _, _, aux = correction(hier, 0, lam0, U0)
+    K = hier.K[1].tocsc()
+    e = spla.spsolve(K, aux["rhs"][:, 0])
+    assert np.allclose(aux["ut"][:, 0], aux["ubar"][:, 0] + e, rtol=1e-10, atol=1e-12)
 
 
 def test_exact_eigenpair_is_fixed_point():
@@ -220,7 +239,7 @@ def test_gluing_overlap_sensitivity():
     two coarse cells of overlap it converges to it (the paper's sensitivity experiments:
     the overlap must not be too small)."""
     final = {}
-    for ov, pou in [(0, 1), (1, 0), (1, 1), (2, 0), (2, 1)]:
+    for ov, pou in [(0, 1), (1, 0), (1, 1), (2, 0), (2, 1), (0, 2), (1, 2)]:
         p = W.Problem(0, 8, 3, 4, 4, ov, 1, 0, None, pou=pou)
         res = solve(p)
         errs = []
@@ -230,7 +249,7 @@ def test_gluing_overlap_sensitivity():
         assert min(errs) >= -1e-13, (ov, pou, errs)
         final[(ov, pou)] = errs[-1]
     assert final[(0, 1)] > 1e-4
-    for key in [(1, 0), (1, 1), (2, 0), (2, 1)]:
+    for key in [(1, 0), (1, 1), (2, 0), (2, 1), (0, 2), (1, 2)]:
         assert final[key] < 1e-6, (key, final[key])
         assert final[(0, 1)] > 100 * final[key]
 
