@@ -252,6 +252,10 @@ def workload(name: str):
         return W.config3(), dict(precision=0)
     if name == "c3mixed":
         return W.config3(), dict(precision=1)
+    if name == "c2iface":
+        return W.config2().with_(pou=2, name="c2_iface"), dict(precision=0)
+    if name == "c3iface":
+        return W.config3().with_(pou=2, name="c3_iface"), dict(precision=0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -324,10 +328,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c3mixed", "c4", "c5adj"],
+                    choices=["c2", "c3", "c3mixed", "c4", "c5adj", "c2iface", "c3iface"],
                     help="c2: h = 1/512, 8x8 subdomains, q = 3 (default); c3: h = 1/2048, "
                          "16x16, FP64; c3mixed: the same in FP32 + FP64 refinement; c4: 256 "
-                         "problems batched; c5adj: reverse sweep at h = 1/1024")
+                         "problems batched; c5adj: reverse sweep at h = 1/1024; c2iface, "
+                         "c3iface: c2 / c3 with the paper's own gluing (interface problem)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -432,7 +437,9 @@ def main():
         "config": {"workload": prob.name, "level": m, "h": prob.h(m), "fine_dofs": n_dofs,
                    "n_eig": prob.n_eig, "subdomains": f"{prob.sub_x}x{prob.sub_y}",
                    "overlap": prob.overlap, "precision": "fp64" if opts.precision == 0 else "mixed",
-                   "local_rtol": opts.rtol},
+                   "local_rtol": opts.rtol,
+                   "gluing": ["partition of unity (ramp)", "partition of unity (indicator)",
+                              "interface problem on G_m+1"][getattr(prob, "pou", 0)]},
         "lambda": lam.tolist(),
         "lambda_rel_err_vs_oracle": lam_err,
         "local_solve": {"ms": pcg_ms, "items": st["n_items"], "tile_dofs": st["n_tile_dofs"],
@@ -443,6 +450,9 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
     }
+    if getattr(prob, "pou", 0) == 2:
+        out["interface_problem"] = {"cg_iterations": st["glue_it"],
+                                    "relres": st["glue_relres"]}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

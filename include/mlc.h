@@ -63,7 +63,12 @@ enum { MLC_COEF_ONE = 0,        /* kappa == 1 */
 /* Gluing of the local corrections, u~ = I u + sum_j chi_j e^j with chi_j = phi_j / sum_l phi_l
    (a partition of unity in place of the G_j / G_{m+1} construction of Algorithm 4.1 step 2): */
 enum { MLC_POU_RAMP = 0,        /* phi_j = rho(x) rho(y): 1 on D_j, linear to 0 across the overlap */
-       MLC_POU_INDICATOR = 1 }; /* phi_j = indicator of the closed D_j (allows overlap 0) */
+       MLC_POU_INDICATOR = 1,   /* phi_j = indicator of the closed D_j (allows overlap 0) */
+       MLC_POU_INTERFACE = 2 }; /* not a partition of unity: Algorithm 4.1 step 2 as stated,
+                                   u~ = u~^j on G_j = D_j shrunk by half a coarse cell, and on
+                                   G_{m+1} (the rest) the Dirichlet problem of equation
+                                   (G_m+1_Problem), solved by a global CG; single-problem
+                                   contexts without a tape only, no hipGraph steps */
 
 enum { MLC_PREC_FP64 = 0,       /* every local solve in FP64 */
        MLC_PREC_MIXED = 1 };    /* FP32 inner PCG with FP64 residual refinement */
@@ -76,8 +81,8 @@ typedef struct mlc_problem_desc {
   int32_t sub_x;       /* D_j blocks along x: boundaries at floor(b*n_coarse/sub_x) coarse cells */
   int32_t sub_y;       /* D_j blocks along y */
   int32_t overlap;     /* Omega_j = D_j grown by this many coarse cells per side (>= 1 with
-                          MLC_POU_RAMP, >= 0 with MLC_POU_INDICATOR); every Omega_j must be at
-                          least 2 coarse cells wide and tall */
+                          MLC_POU_RAMP, >= 0 otherwise); every Omega_j must be at least 2
+                          coarse cells wide and tall */
   int32_t n_eig;       /* q, number of lowest eigenpairs (1..8) */
   int32_t coef_kind;   /* MLC_COEF_*; both triangles of a square cell share its value */
   const double* kappa; /* host pointer, row-major [row along y][col along x]; read during
@@ -115,6 +120,8 @@ typedef struct mlc_level_stats {
   double relres_max;    /* max final ||r||/||b|| over the local solves */
   double lambda[8];     /* the q eigenvalues after the step */
   int64_t refine_dofs;  /* mixed precision: sum over local solves of refinement steps x unknowns */
+  int32_t glue_it;      /* MLC_POU_INTERFACE: CG iterations of the G_{m+1} problem (max over rhs) */
+  double glue_relres;   /* MLC_POU_INTERFACE: its final ||r||/||r_0|| (max over rhs) */
 } mlc_level_stats;
 
 /* Fill opts with the defaults listed above. */

@@ -52,14 +52,15 @@ class LevelStats(C.Structure):
                 ("n_dofs", C.c_int64), ("n_tile_dofs", C.c_int64), ("it_max", C.c_int32),
                 ("refine_max", C.c_int32), ("it_sum", C.c_int64), ("it_dofs", C.c_int64),
                 ("relres_max", C.c_double), ("lambda_", C.c_double * 8),
-                ("refine_dofs", C.c_int64)]
+                ("refine_dofs", C.c_int64), ("glue_it", C.c_int32), ("glue_relres", C.c_double)]
 
     def as_dict(self, q: int) -> dict:
         return dict(level=self.level, n_items=self.n_items, h=self.h, n_dofs=self.n_dofs,
                     n_tile_dofs=self.n_tile_dofs, it_max=self.it_max,
                     refine_max=self.refine_max, it_sum=self.it_sum, it_dofs=self.it_dofs,
                     relres_max=self.relres_max, lam=list(self.lambda_[:q]),
-                    refine_dofs=self.refine_dofs)
+                    refine_dofs=self.refine_dofs, glue_it=self.glue_it,
+                    glue_relres=self.glue_relres)
 
 
 class MLCError(RuntimeError):

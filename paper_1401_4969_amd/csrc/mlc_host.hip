@@ -86,9 +86,9 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
     msg = "sub_x and sub_y must be in 1..n_coarse";
     return MLC_EINVAL;
   }
-  if (d->pou != MLC_POU_RAMP && d->pou != MLC_POU_INDICATOR) { msg = "pou must be 0 or 1"; return MLC_EINVAL; }
+  if (d->pou < MLC_POU_RAMP || d->pou > MLC_POU_INTERFACE) { msg = "pou must be 0, 1 or 2"; return MLC_EINVAL; }
   if (d->overlap < (d->pou == MLC_POU_RAMP ? 1 : 0) || d->overlap > d->n_coarse) {
-    msg = "overlap must be in 1..n_coarse (0..n_coarse with the indicator partition of unity)";
+    msg = "overlap must be in 1..n_coarse (0..n_coarse unless the gluing is the ramp)";
     return MLC_EINVAL;
   }
   if (d->n_eig < 1 || d->n_eig > MLC_MAX_Q) { msg = "n_eig must be in 1..8"; return MLC_EINVAL; }
@@ -174,7 +174,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
 // Byte offsets (from the workspace base) of one problem's buffers.
 struct ProbLayout {
   size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
-      E, info, fg, partials, rr_x, rr_y, rr_t, rr_ab, cH, out_parts;
+      E, info, fg, partials, rr_x, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
   int64_t rchain_off[MLC_MAX_LEVELS + 1];
   int64_t inv_base;      // doubles, into the batch inverse region
@@ -233,6 +233,10 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
   P.kind = P.geo[0].kind;
   for (const Geometry& g : P.geo) {
     if (g.q != P.q || g.kind != P.kind) { msg = "all problems of a batch need the same n_eig and coef_kind"; return MLC_EINVAL; }
+    if (g.pou == MLC_POU_INTERFACE && (n != 1 || o->record_tape)) {
+      msg = "the interface gluing runs on single-problem contexts without a tape";
+      return MLC_EINVAL;
+    }
     P.Lmax = std::max(P.Lmax, g.L);
     P.max_nH = std::max(P.max_nH, g.nH);
     P.max_nc1sq = std::max(P.max_nc1sq, (g.nc + 1) * (g.nc + 1));
@@ -290,6 +294,12 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.rr_ab = take(2 * 8);
     L.cH = take(q * ncs * 8);
     L.out_parts = take(64 * q * 8);
+    L.skel = L.skel_parts = L.skel_scal = 0;
+    if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem on the finest grid
+      L.skel = take(6 * nnL * 8);
+      L.skel_parts = take(((nnL + 255) / 256) * 2 * 8);
+      L.skel_scal = take(8 * 8);
+    }
     L.inv_base = P.inv_total;
     P.inv_total += g.inv_total;
     L.sub_item_off = sub_off;
@@ -419,6 +429,8 @@ struct mlc_batch {
   std::vector<hipEvent_t> ev_free;
   std::vector<std::array<hipEvent_t, 4>> ev_pending;
   std::vector<double> e0;  // unit coefficient vector (host copy kept for the async upload)
+  int glue_it = 0;         // last step's G_{m+1} problem (MLC_POU_INTERFACE)
+  double glue_relres = 0.0;
 };
 
 struct mlc_ctx {
@@ -672,7 +684,15 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
                                   b->o.nu, b->o.omega, T.max_tile_nx, st));
   }
   if (timing) MLC_HIP(b, hipEventRecord(ev[2], st));
-  MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, st));
+  if (P.geo[0].pou == MLC_POU_INTERFACE) {  // single problem (checked at plan time)
+    const ProbLayout& L = P.pl[0];
+    MLC_HIP(b, run_interface_gluing(P.kind, b->dprob, items, sub_item, w + P.store, s, P.q,
+                                    P.geo[0].nodes(s), b->o.rtol, 100000, (double*)(w + L.skel),
+                                    (double*)(w + L.skel_parts), (double*)(w + L.skel_scal), st,
+                                    &b->glue_it, &b->glue_relres));
+  } else {
+    MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, st));
+  }
   MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, st));
   for (int l = s - 1; l >= 0; --l)
     MLC_HIP(b, launch_restrict(b->dprob, P.n, l, s, T.nodes_l[l], st));
@@ -714,6 +734,10 @@ mlc_status batch_step(mlc_batch* b, int use_graph) {
   // every problem stepping here holds level s-1 in buffer (s-1+shift)&1; the shift is
   // zero except after mlc_set_state on a single-problem context
   const int src = (s - 1 + b->shift[0]) & 1, dst = 1 - src;
+  if (use_graph && P.geo[0].pou == MLC_POU_INTERFACE) {
+    b->err = "the interface gluing tests convergence on the host: no hipGraph steps";
+    return MLC_EINVAL;
+  }
   if (use_graph) {
     if (!b->graphs[s]) {
       // capture on a private stream (default priority); the instantiated graph is then
@@ -788,6 +812,14 @@ mlc_status step_stats(mlc_batch* b, mlc_level_stats* stt) {
   if (stt->relres_max > b->o.rtol * 1.0000001) {
     b->err = "a local solve did not converge within max_it";
     return MLC_ENOCONV;
+  }
+  if (P.geo[0].pou == MLC_POU_INTERFACE) {
+    stt->glue_it = b->glue_it;
+    stt->glue_relres = b->glue_relres;
+    if (b->glue_relres > b->o.rtol * 1.0000001) {
+      b->err = "the G_{m+1} problem did not converge";
+      return MLC_ENOCONV;
+    }
   }
   return MLC_OK;
 }

@@ -16,6 +16,16 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
                               double omega, int max_tile_nx, hipStream_t s);
+// Algorithm 4.1 step 2 as stated (MLC_POU_INTERFACE), single problem: u~ from the tile
+// solutions on the closed G_j and a global Jacobi-PCG on the rest (vec: 6 full-grid
+// vectors of `nodes` doubles, parts: 2 per 256 nodes, scal: 8 doubles).  Synchronises
+// the stream to test convergence every 8 iterations.
+hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* items,
+                                const int32_t* sub_item, const char* store, int m, int q,
+                                int64_t nodes, double rtol, int max_it, double* vec,
+                                double* parts, double* scal, hipStream_t s, int* iters_out,
+                                double* relres_out);
+
 // Widest tile row (interior nodes) whose banded smoothing passes fit the device's
 // per-workgroup LDS with nt threads (three rings of nt/64 + 2 rows, plus the LDS tail of
 // the V-cycle when with_tail), capped at the widest tile of the launch; 0 when nu != 2 or

@@ -60,7 +60,7 @@ def test_workspace_size_config3_fits_hbm():
 @pytest.mark.parametrize("bad", [
     dict(domain=3), dict(n_coarse=1), dict(n_refine=0), dict(n_refine=11),
     dict(sub_x=0), dict(sub_x=9), dict(overlap=0), dict(n_eig=0), dict(n_eig=9),
-    dict(coef_kind=5), dict(pou=2), dict(pou=-1), dict(pou=1, overlap=-1),
+    dict(coef_kind=5), dict(pou=3), dict(pou=-1), dict(pou=1, overlap=-1),
 ])
 def test_invalid_descriptors_rejected(bad):
     p = W.config1().with_(**bad)
@@ -121,4 +121,16 @@ def test_indicator_partition_allows_overlap_zero():
     narrow = W.Problem(0, 8, 2, 8, 8, 0, 1, 0, None, pou=1)  # 1-cell blocks, no overlap
     with pytest.raises(B.MLCError) as e:
         B.workspace_size(narrow)
+    assert e.value.status == B.MLC_EINVAL
+
+
+def test_interface_gluing_limits():
+    """The paper's gluing (pou = 2) runs on single-problem contexts without a tape."""
+    p = W.config1().with_(pou=2, overlap=0)
+    assert B.workspace_size(p) > B.workspace_size(p.with_(pou=1))   # + the G_{m+1} vectors
+    with pytest.raises(B.MLCError) as e:
+        B.batch_workspace_size([p, p])
+    assert e.value.status == B.MLC_EINVAL
+    with pytest.raises(B.MLCError) as e:
+        B.workspace_size(W.small_field().with_(pou=2), B.default_opts(record_tape=1))
     assert e.value.status == B.MLC_EINVAL

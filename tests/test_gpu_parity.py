@@ -236,3 +236,25 @@ def test_large_coarse_tiles():
     rng = np.random.Generator(np.random.PCG64(41))
     compare(W.Problem(0, 20, 2, 2, 2, 1, 1, 1, W.loguniform_coarse_kappa(20, rng), "big_tiles_sq"))
     compare(W.Problem(1, 16, 2, 1, 1, 0, 1, 0, None, "big_tiles_L", pou=1))
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+@pytest.mark.parametrize("which", ["square", "lshape_q2", "field"])
+def test_interface_gluing(which, overlap):
+    """The paper's own gluing (Algorithm 4.1 step 2 as stated): u~ = u~^j on G_j and the
+    G_{m+1} Dirichlet problem on the rest, solved on the GPU by a global CG; parity with
+    the oracle (sparse LU on G_{m+1}) on every level."""
+    if which == "square":
+        prob = W.Problem(0, 8, 3, 4, 4, overlap, 1, 0, None, "iface_square", pou=2)
+    elif which == "lshape_q2":
+        prob = W.small_ragged().with_(overlap=overlap, pou=2)
+    else:
+        prob = W.small_field().with_(overlap=overlap, pou=2)
+    lam, u, levels, stats, ref = compare(prob)
+    for st in stats:
+        assert st["glue_it"] > 0 and st["glue_relres"] <= 1e-12 * 1.0000001
+
+
+def test_interface_gluing_mixed_precision():
+    prob = W.Problem(0, 8, 3, 4, 4, 1, 1, 0, None, "iface_mixed", pou=2)
+    compare(prob, precision=1)
