@@ -11,7 +11,9 @@ Everything is computed the plain way:
   * interior (degree-of-freedom) nodes are the nodes not on any boundary edge,
     a boundary edge being an edge that belongs to exactly one triangle;
   * element matrices come from the vertex coordinates of each triangle
-    (gradients of the barycentric functions, area/12 (1 + delta_ab) mass);
+    (gradients of the barycentric functions, area/12 (1 + delta_ab) mass); for the
+    operator of Example 6.2 (a full tensor A and a mass weight phi, both constant on
+    each triangle) the stiffness is area * G A G^T and the mass is scaled by phi;
   * the nodal interpolation from a coarse to a fine mesh evaluates the coarse
     P1 function at every fine node by locating the node in a coarse triangle
     and using its barycentric coordinates.
@@ -91,7 +93,7 @@ def _interior_nodes(tri: np.ndarray, n_nodes: int) -> np.ndarray:
 
 
 def triangle_kappa(mesh: Mesh, coef_kind: int, kappa: np.ndarray, n_coarse: int) -> np.ndarray:
-    """kappa of every triangle from the problem's coefficient layout."""
+    """kappa of every triangle from the problem's coefficient layout (scalar kinds 0-2)."""
     J = mesh.tri_cell // mesh.n
     I = mesh.tri_cell % mesh.n
     if coef_kind == 0:
@@ -106,9 +108,28 @@ def triangle_kappa(mesh: Mesh, coef_kind: int, kappa: np.ndarray, n_coarse: int)
     raise ValueError(coef_kind)
 
 
-def assemble(mesh: Mesh, kappa_tri: np.ndarray):
+def triangle_tensor(mesh: Mesh, coef: np.ndarray):
+    """Coefficient kind 3: the symmetric tensor A (T x 2 x 2) and the mass weight phi (T,)
+    of every triangle, from the layout [component (a11, a12, a22, phi)][triangle (0 below
+    the diagonal, 1 above)][J][I] of the finest cells."""
+    c = np.asarray(coef, dtype=np.float64)
+    assert c.shape == (4, 2, mesh.n, mesh.n)
+    J = mesh.tri_cell // mesh.n
+    I = mesh.tri_cell % mesh.n
+    t = mesh.tri_upper.astype(np.int64)
+    A = np.empty((mesh.tri.shape[0], 2, 2))
+    A[:, 0, 0] = c[0, t, J, I]
+    A[:, 0, 1] = A[:, 1, 0] = c[1, t, J, I]
+    A[:, 1, 1] = c[2, t, J, I]
+    return A, c[3, t, J, I]
+
+
+def assemble(mesh: Mesh, kappa_tri: np.ndarray, A_tri: np.ndarray = None,
+             phi_tri: np.ndarray = None):
     """Global P1 stiffness a(u,v) = (kappa grad u, grad v) and mass b(u,v) = (u,v)
-    over all nodes (Section 2.2 weak form, Section 3 eigenproblem), as CSR matrices."""
+    over all nodes (Section 2.2 weak form, Section 3 eigenproblem), as CSR matrices.
+    With A_tri and phi_tri (Example 6.2): a(u,v) = (A grad u, grad v) and
+    b(u,v) = (phi u, v), A and phi constant on each triangle."""
     p = mesh.xy[mesh.tri]                       # T x 3 x 2
     d1 = p[:, 1] - p[:, 0]
     d2 = p[:, 2] - p[:, 0]
@@ -124,8 +145,12 @@ def assemble(mesh: Mesh, kappa_tri: np.ndarray):
     ref = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])   # l_a in terms of (l1, l2)
     G = np.einsum("am,tmc->tac", ref, Jinv)
     # G[t, a, :] = physical gradient of barycentric function a on triangle t
-    Kloc = np.einsum("tai,tbi->tab", G, G) * (kappa_tri * area)[:, None, None]
-    Mloc = (np.ones((3, 3)) + np.eye(3))[None] * (area / 12.0)[:, None, None]
+    if A_tri is None:
+        Kloc = np.einsum("tai,tbi->tab", G, G) * (kappa_tri * area)[:, None, None]
+        Mloc = (np.ones((3, 3)) + np.eye(3))[None] * (area / 12.0)[:, None, None]
+    else:
+        Kloc = np.einsum("tai,tij,tbj->tab", G, A_tri, G) * area[:, None, None]
+        Mloc = (np.ones((3, 3)) + np.eye(3))[None] * (phi_tri * area / 12.0)[:, None, None]
     rows = np.repeat(mesh.tri, 3, axis=1).ravel()
     cols = np.tile(mesh.tri, (1, 3)).ravel()
     K = sp.coo_matrix((Kloc.ravel(), (rows, cols)), shape=(mesh.n_nodes, mesh.n_nodes)).tocsr()

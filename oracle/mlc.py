@@ -38,7 +38,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import Mesh, assemble, interpolation, make_mesh, triangle_kappa
+from .fem import Mesh, assemble, interpolation, make_mesh, triangle_kappa, triangle_tensor
 
 
 # ---------------------------------------------------------------------------
@@ -113,8 +113,14 @@ class Hierarchy:
         self.meshes: List[Mesh] = [make_mesh(prob.domain, prob.n_cells(m), prob.side, prob.origin)
                                    for m in range(L + 1)]
         fine = self.meshes[L]
-        ktri = triangle_kappa(fine, prob.coef_kind, prob.kappa, prob.n_coarse)
-        Kf, Mf = assemble(fine, ktri)
+        if prob.coef_kind == 3:
+            # reading: A and phi constant on each finest triangle, every level integrating
+            # exactly (the Galerkin products below)
+            A_tri, phi_tri = triangle_tensor(fine, prob.kappa)
+            Kf, Mf = assemble(fine, None, A_tri, phi_tri)
+        else:
+            ktri = triangle_kappa(fine, prob.coef_kind, prob.kappa, prob.n_coarse)
+            Kf, Mf = assemble(fine, ktri)
         d = fine.dof
         self.K = [None] * (L + 1)
         self.M = [None] * (L + 1)

@@ -180,3 +180,105 @@ def test_triangle_kappa_layouts():
     J = mesh.tri_cell // 8
     I = mesh.tri_cell % 8
     assert np.all(kt == kc[J // 2, I // 2])
+
+
+# ---- coefficient kind 3: full tensor A and weighted mass (Example 6.2) ----
+
+def _random_tensor(mesh, seed):
+    rng = np.random.default_rng(seed)
+    T = mesh.tri.shape[0]
+    a11 = np.exp(rng.normal(size=T))
+    a22 = np.exp(rng.normal(size=T))
+    a12 = rng.uniform(-0.9, 0.9, size=T) * np.sqrt(a11 * a22)
+    A = np.empty((T, 2, 2))
+    A[:, 0, 0], A[:, 0, 1], A[:, 1, 0], A[:, 1, 1] = a11, a12, a12, a22
+    return A, np.exp(rng.normal(size=T))
+
+
+@pytest.mark.parametrize("domain,n,side,origin", [(0, 6, 1.0, 0.0), (2, 6, 2.0, -1.0),
+                                                  (1, 8, 2.0, -1.0)])
+def test_tensor_stiffness_energy(domain, n, side, origin):
+    """u^T K u = sum_T |T| g_T . A_T g_T with the gradient g_T of the P1 function taken
+    from differences along the legs, for a random symmetric positive definite A per
+    triangle (the tensor form of Example 6.2)."""
+    rng = np.random.default_rng(3)
+    mesh = make_mesh(domain, n, side, origin)
+    A, phi = _random_tensor(mesh, 4)
+    K, _ = assemble(mesh, None, A, phi)
+    u = rng.normal(size=mesh.n_nodes)
+    g = _tri_gradients_by_legs(mesh, u)
+    energy = np.sum(0.5 * mesh.h ** 2 * np.einsum("ti,tij,tj->t", g, A, g))
+    assert u @ (K @ u) == pytest.approx(energy, rel=1e-12)
+
+
+def test_tensor_hypotenuse_coupling():
+    """With an off-diagonal a12 the SW-NE hypotenuse couples: on a right triangle with
+    legs along x and y the coupling of the two acute vertices is -a12/2, so the cell's
+    SW and NE nodes couple by -(a12(lower) + a12(upper))/2; SE-NW stays uncoupled."""
+    mesh = make_mesh(0, 4, 1.0, 0.0)
+    A, phi = _random_tensor(mesh, 5)
+    K, _ = assemble(mesh, None, A, phi)
+    n1 = 5
+    for t in range(0, mesh.tri.shape[0], 2):     # lower, upper of one cell
+        cell = mesh.tri_cell[t]
+        j, i = divmod(cell, 4)
+        a = j * n1 + i
+        assert K[a, a + n1 + 1] == pytest.approx(-0.5 * (A[t, 0, 1] + A[t + 1, 0, 1]), rel=1e-13)
+        assert K[a + 1, a + n1] == 0.0
+
+
+@pytest.mark.parametrize("domain,n,side,origin", [(0, 5, 1.0, 0.0), (2, 4, 2.0, -1.0)])
+def test_weighted_mass_matches_quadrature(domain, n, side, origin):
+    """u^T M v equals sum_T phi_T times the Gauss-quadrature integral of u_h v_h over T."""
+    rng = np.random.default_rng(6)
+    mesh = make_mesh(domain, n, side, origin)
+    A, phi = _random_tensor(mesh, 7)
+    _, M = assemble(mesh, None, A, phi)
+    u = rng.normal(size=mesh.n_nodes)
+    v = rng.normal(size=mesh.n_nodes)
+    l1, l2, wq = _duffy_rule()
+    p = mesh.xy[mesh.tri]
+    d1 = p[:, 1] - p[:, 0]
+    d2 = p[:, 2] - p[:, 0]
+    det = np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    total = 0.0
+    for a, b, w in zip(l1, l2, wq):
+        bc = barycentric(mesh, np.arange(mesh.tri.shape[0]), p[:, 0] + a * d1 + b * d2)
+        total += w * np.sum(phi * det * (bc * u[mesh.tri]).sum(axis=1) * (bc * v[mesh.tri]).sum(axis=1))
+    assert u @ (M @ v) == pytest.approx(total, rel=1e-12)
+
+
+def test_tensor_identity_reduces_to_scalar():
+    """A = kappa I and phi = 1 give the matrices of the scalar coefficient kappa."""
+    mesh = make_mesh(1, 8, 2.0, -1.0)
+    rng = np.random.default_rng(8)
+    kt = np.exp(rng.normal(size=mesh.tri.shape[0]))
+    A = kt[:, None, None] * np.eye(2)[None]
+    K1, M1 = assemble(mesh, kt)
+    K3, M3 = assemble(mesh, None, A, np.ones(mesh.tri.shape[0]))
+    assert abs(K1 - K3).max() < 1e-13 and abs(M1 - M3).max() < 1e-15
+
+
+def test_example62_extrapolated_eigenvalues():
+    """Example 6.2 (Section 6): A = [[e^(1+x^2), e^(xy)], [e^(xy), e^(1+y^2)]] and
+    phi = (1+x^2)(1+y^2) on (-1,1)^2, sampled at the triangle centroids.  The direct
+    discrete eigenvalues on two meshes (h = 1/40, 1/80), extrapolated in h^2, reproduce
+    the six values the paper prints to its six decimals (relative 2e-7)."""
+    import json, os
+    import scipy.sparse.linalg as spla
+    import workloads as W
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "example62_eigenvalues.json")))["eigenvalues"]
+    lam = []
+    for n in (80, 160):
+        mesh = make_mesh(2, n, 2.0, -1.0)
+        from oracle.fem import triangle_tensor
+        A, phi = triangle_tensor(mesh, W.example62_coefficients(n))
+        K, M = assemble(mesh, None, A, phi)
+        d = mesh.dof
+        ev = spla.eigsh(K[d][:, d].tocsc(), k=6, M=M[d][:, d].tocsc(), sigma=0.0,
+                        which="LM", tol=1e-14)[0]
+        lam.append(np.sort(ev))
+    ext = (4.0 * lam[1] - lam[0]) / 3.0
+    assert np.all(lam[1] > np.array(ref))          # conforming P1 approximates from above
+    assert np.max(np.abs(ext - ref) / np.array(ref)) < 2e-7, ext

@@ -310,3 +310,20 @@ def test_pins_catch_planted_mistakes(monkeypatch, planted):
     rate_ok = np.all(np.log2(err[:-1] / err[1:])[1:] > 1.9)
     close_ok = (res.lam_levels[-1][0] - lam_h[0]) / lam_h[0] < 1e-4
     assert not (rate_ok and close_ok)
+
+
+def test_example62_multilevel():
+    """Example 6.2 with H = 0.1 (20 coarse cells on (-1,1)^2), 2 x 2 subdomains and four
+    level grids (three corrections): the six multilevel eigenvalues lie above the direct
+    discrete ones (min-max) and within 1e-7 of them."""
+    import workloads as W
+    prob = W.example62(n_refine=3, sub=2, n_eig=6)
+    hier = Hierarchy(prob)
+    res = solve(prob, hier)
+    lam_h = direct_eigs(hier, 3, 6)[0]
+    rel = (res.lam - lam_h) / lam_h
+    assert np.all(rel >= -1e-12), rel
+    assert np.all(rel < 1e-7), rel
+    # every level stays above the direct eigenvalues of its own mesh
+    for k, lk in enumerate(res.lam_levels):
+        assert np.all(lk >= direct_eigs(hier, k, 6)[0] * (1 - 1e-12))

@@ -17,6 +17,12 @@ Coefficient layouts (row-major, index = row * ncols + col, row along y):
   coef_kind 1: one value per coarse cell, shape (n_coarse, n_coarse).
   coef_kind 2: one value per finest square cell, shape (N, N), N = n_coarse*2^n_refine.
 Both triangles of a square cell share the cell's value.
+  coef_kind 3 (the operator of Example 6.2: a(u,v) = (A grad u, grad v), b(u,v) =
+  (phi u, v)): shape (4, 2, N, N), [component (a11, a12, a22, phi)][triangle (0 below
+  the SW-NE diagonal, 1 above)][J][I], one symmetric positive definite tensor and one
+  positive weight per finest triangle.
+
+Domains: 0 the unit square (0,1)^2, 1 the L-shape, 2 the square (-1,1)^2 of Example 6.2.
 """
 from __future__ import annotations
 
@@ -27,6 +33,7 @@ import numpy as np
 
 DOMAIN_SQUARE = 0   # (0,1)^2
 DOMAIN_LSHAPE = 1   # (-1,1)^2 \ [0,1)x(-1,0]
+DOMAIN_SQUARE2 = 2  # (-1,1)^2
 
 
 @dataclass
@@ -147,6 +154,55 @@ def config5(seed: int = 5) -> Problem:
     n = 16 << 6
     return Problem(DOMAIN_SQUARE, 16, 6, 8, 8, 1, 1, 2, gaussian_field_kappa(n, seed),
                    "c5_square_H16_h1024_8x8_grf")
+
+
+def triangle_centroids(domain: int, n: int):
+    """Centroids (x, y) of the finest triangles, each of shape (2, n, n) in the kind-3
+    layout [triangle][J][I]."""
+    side = 1.0 if domain == DOMAIN_SQUARE else 2.0
+    origin = 0.0 if domain == DOMAIN_SQUARE else -1.0
+    h = side / n
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    x0 = origin + I * h
+    y0 = origin + J * h
+    # lower triangle (SW, SE, NE): centroid at (x0 + 2h/3, y0 + h/3); upper (SW, NE, NW):
+    # at (x0 + h/3, y0 + 2h/3)
+    x = np.stack([x0 + 2.0 * h / 3.0, x0 + h / 3.0])
+    y = np.stack([y0 + h / 3.0, y0 + 2.0 * h / 3.0])
+    return x, y
+
+
+def example62_coefficients(n: int) -> np.ndarray:
+    """Example 6.2: A = [[exp(1+x^2), exp(xy)], [exp(xy), exp(1+y^2)]] and
+    phi = (1+x^2)(1+y^2) on (-1,1)^2, each evaluated at the centroid of every finest
+    triangle (n cells per side), in the kind-3 layout."""
+    x, y = triangle_centroids(DOMAIN_SQUARE2, n)
+    return np.stack([np.exp(1.0 + x * x), np.exp(x * y), np.exp(1.0 + y * y),
+                     (1.0 + x * x) * (1.0 + y * y)])
+
+
+def random_tensor_coefficients(domain: int, n: int, seed: int) -> np.ndarray:
+    """A seeded kind-3 field: per triangle a11, a22 log-uniform in [0.5, 2], a12 =
+    t sqrt(a11 a22) with t uniform in [-0.4, 0.4] (so A is positive definite), phi
+    log-uniform in [0.5, 2]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shp = (2, n, n)
+    a11 = np.exp(rng.uniform(np.log(0.5), np.log(2.0), size=shp))
+    a22 = np.exp(rng.uniform(np.log(0.5), np.log(2.0), size=shp))
+    a12 = rng.uniform(-0.4, 0.4, size=shp) * np.sqrt(a11 * a22)
+    phi = np.exp(rng.uniform(np.log(0.5), np.log(2.0), size=shp))
+    return np.stack([a11, a12, a22, phi])
+
+
+def example62(n_refine: int = 3, sub: int = 2, n_eig: int = 6, overlap: int = 1,
+              n_coarse: int = 20) -> Problem:
+    """Example 6.2 on (-1,1)^2 with H = 0.1 (20 coarse cells per side), n_refine
+    corrections, sub x sub subdomains, the lowest n_eig eigenpairs."""
+    n = n_coarse << n_refine
+    return Problem(DOMAIN_SQUARE2, n_coarse, n_refine, sub, sub, overlap, n_eig, 3,
+                   example62_coefficients(n),
+                   f"ex62_H{n_coarse}_h{n}_{sub}x{sub}_q{n_eig}")
+
 
 
 def kappa_directions(kappa: np.ndarray, seed: int = 501) -> List[np.ndarray]:
