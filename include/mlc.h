@@ -4,7 +4,9 @@
  *
  * Problem (Section 3, eigenproblem (Weak_Eigenvalue_Problem) with the operator of
  * Section 2.2, A = kappa I): find (lambda, u) with -div(kappa grad u) = lambda u in Omega,
- * u = 0 on the boundary, b(u, u) = 1, discretised by conforming P1 elements on nested
+ * u = 0 on the boundary, b(u, u) = 1 -- or, with MLC_COEF_TENSOR, the operator of
+ * Example 6.2: -div(A grad u) = lambda phi u, A a full symmetric tensor and phi > 0 a
+ * weight, b(u, v) = (phi u, v) -- discretised by conforming P1 elements on nested
  * uniform right-triangle meshes (each square cell cut by its lower-left to upper-right
  * diagonal; regular refinement, beta = 2, Section 6).
  *
@@ -54,11 +56,19 @@ typedef enum mlc_status {
 } mlc_status;
 
 enum { MLC_DOMAIN_SQUARE = 0,   /* (0,1)^2 */
-       MLC_DOMAIN_LSHAPE = 1 }; /* (-1,1)^2 \ [0,1)x(-1,0] */
+       MLC_DOMAIN_LSHAPE = 1,   /* (-1,1)^2 \ [0,1)x(-1,0] */
+       MLC_DOMAIN_SQUARE2 = 2 };/* (-1,1)^2 (Example 6.2) */
 
 enum { MLC_COEF_ONE = 0,        /* kappa == 1 */
        MLC_COEF_COARSE = 1,     /* one kappa per coarse cell, [n_coarse*n_coarse] */
-       MLC_COEF_FINE = 2 };     /* one kappa per finest square cell, [N_L*N_L] */
+       MLC_COEF_FINE = 2,       /* one kappa per finest square cell, [N_L*N_L] */
+       MLC_COEF_TENSOR = 3 };   /* Example 6.2: per finest triangle a symmetric positive definite
+                                   A and a mass weight phi > 0, [4][2][N_L][N_L]: component
+                                   (a11, a12, a22, phi), triangle (0 below the SW-NE diagonal,
+                                   1 above), row J along y, column I along x.  Each value is
+                                   taken constant on its triangle and every level integrates
+                                   the forms exactly (seven-point stencils, Galerkin coarse
+                                   levels).  Not available with record_tape. */
 
 /* Gluing of the local corrections, u~ = I u + sum_j chi_j e^j with chi_j = phi_j / sum_l phi_l
    (a partition of unity in place of the G_j / G_{m+1} construction of Algorithm 4.1 step 2): */
@@ -84,9 +94,11 @@ typedef struct mlc_problem_desc {
                           MLC_POU_RAMP, >= 0 otherwise); every Omega_j must be at least 2
                           coarse cells wide and tall */
   int32_t n_eig;       /* q, number of lowest eigenpairs (1..8) */
-  int32_t coef_kind;   /* MLC_COEF_*; both triangles of a square cell share its value */
-  const double* kappa; /* host pointer, row-major [row along y][col along x]; read during
-                          mlc_create only (copied); NULL for MLC_COEF_ONE.  Must be > 0 and finite. */
+  int32_t coef_kind;   /* MLC_COEF_*; for kinds 1 and 2 both triangles of a square cell
+                          share its value */
+  const double* kappa; /* host pointer, row-major [row along y][col along x] (kind 3: the
+                          layout of MLC_COEF_TENSOR); read during mlc_create only (copied);
+                          NULL for MLC_COEF_ONE.  Must be > 0 and finite. */
   int32_t pou;         /* MLC_POU_* (0 unless set) */
 } mlc_problem_desc;
 
@@ -135,9 +147,11 @@ mlc_status mlc_workspace_size(const mlc_problem_desc* desc, const mlc_solver_opt
  * 256-byte aligned, owned by the caller and kept alive until mlc_destroy.  hip_stream:
  * a hipStream_t (NULL = default stream).  Uploads geometry tables on the stream.
  * MLC_EINVAL for: domain/coef_kind out of range, n_coarse < 2, odd n_coarse on the
- * L-shape, n_refine outside 1..10, sub_x/sub_y outside 1..n_coarse, overlap < 1,
- * n_eig outside 1..8 or above the number of coarse interior nodes, kappa NULL when
- * needed or not > 0 and finite, a subdomain whose coarse interior exceeds 64 nodes. */
+ * L-shape, n_refine outside 1..10, sub_x/sub_y outside 1..n_coarse, overlap below 1
+ * (ramp gluing) or 0 (otherwise), an Omega_j narrower than 2 coarse cells, n_eig outside
+ * 1..8 or above the number of coarse interior nodes, kappa NULL when needed, not > 0
+ * and finite (kind 3: A not positive definite or phi not > 0 on some triangle), a
+ * subdomain whose coarse interior exceeds 1024 nodes. */
 mlc_status mlc_create(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
                       void* dev_workspace, size_t workspace_bytes, void* hip_stream,
                       struct mlc_ctx** out);

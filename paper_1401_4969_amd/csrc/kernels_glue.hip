@@ -34,8 +34,13 @@ template <int KIND>
 __device__ __forceinline__ double apply_masked(const ProbDev& P, int m, int N, int n1, int gx,
                                                int gy, int64_t idx, const double* v, double& d) {
   const Weights W = edge_weights<KIND>(P, m, N, gx, gy);
-  d = W.e + W.w + W.n + W.s;
-  return d * v[idx] - W.e * v[idx + 1] - W.w * v[idx - 1] - W.n * v[idx + n1] - W.s * v[idx - n1];
+  double ne = 0.0, sw = 0.0;
+  if constexpr (KIND == 3) {
+    ne = v[idx + n1 + 1];
+    sw = v[idx - n1 - 1];
+  }
+  return apply_k<KIND, double>(W, v[idx], v[idx + 1], v[idx - 1], v[idx + n1], v[idx - n1], ne,
+                               sw, d);
 }
 
 __device__ __forceinline__ void block_partials(double a, double b, double* parts) {
@@ -132,8 +137,13 @@ __global__ __launch_bounds__(NTS) void k_skel_dir(const ProbDev* probs, int m, c
       auto pv = [&](int64_t j) -> double { return Z[j] + beta * Pold[j]; };
       const Weights W = edge_weights<KIND>(P, m, N, gx, gy);
       pc = pv(idx);
-      q = (W.e + W.w + W.n + W.s) * pc - W.e * pv(idx + 1) - W.w * pv(idx - 1) -
-          W.n * pv(idx + n1) - W.s * pv(idx - n1);
+      double ne = 0.0, sw = 0.0, d;
+      if constexpr (KIND == 3) {
+        ne = pv(idx + n1 + 1);
+        sw = pv(idx - n1 - 1);
+      }
+      q = apply_k<KIND, double>(W, pc, pv(idx + 1), pv(idx - 1), pv(idx + n1), pv(idx - n1), ne,
+                                sw, d);
       pq = pc * q;
     }
     Pn[idx] = pc;
@@ -160,7 +170,7 @@ __global__ __launch_bounds__(NTS) void k_skel_upd(const ProbDev* probs, int m, d
       const Weights W = edge_weights<KIND>(P, m, N, gx, gy);
       E[idx] += alpha * Pv[idx];
       const double w = Wv[idx] - alpha * Q[idx];
-      const double z = w / (W.e + W.w + W.n + W.s);
+      const double z = w / diag_of<KIND>(W);
       Wv[idx] = w;
       Z[idx] = z;
       wz = w * z;
@@ -246,8 +256,10 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
       hipLaunchKernelGGL(k_skel_init<0>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
     else if (kind == 1)
       hipLaunchKernelGGL(k_skel_init<1>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
-    else
+    else if (kind == 2)
       hipLaunchKernelGGL(k_skel_init<2>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
+    else
+      hipLaunchKernelGGL(k_skel_init<3>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
     hipLaunchKernelGGL(k_skel_reduce, dim3(1), dim3(1024), 0, s, parts, (int)nblk, 0, scal);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -269,15 +281,19 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
             hipLaunchKernelGGL(k_skel_dir<0>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
           else if (kind == 1)
             hipLaunchKernelGGL(k_skel_dir<1>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
-          else
+          else if (kind == 2)
             hipLaunchKernelGGL(k_skel_dir<2>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
+          else
+            hipLaunchKernelGGL(k_skel_dir<3>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
           hipLaunchKernelGGL(k_skel_reduce, dim3(1), dim3(1024), 0, s, parts, (int)nblk, 1, scal);
           if (kind == 0)
             hipLaunchKernelGGL(k_skel_upd<0>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
           else if (kind == 1)
             hipLaunchKernelGGL(k_skel_upd<1>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
-          else
+          else if (kind == 2)
             hipLaunchKernelGGL(k_skel_upd<2>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
+          else
+            hipLaunchKernelGGL(k_skel_upd<3>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
           hipLaunchKernelGGL(k_skel_reduce, dim3(1), dim3(1024), 0, s, parts, (int)nblk, 2, scal);
           double* t = Po;
           Po = Pn;

@@ -37,7 +37,11 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
   const double h = P.side / N;
   const double mh = h * h * (1.0 / 12.0);
   Weights W;
-  if (dof) W = edge_weights<KIND>(P, m, N, gx, gy);
+  MassW Mw;
+  if (dof) {
+    W = edge_weights<KIND>(P, m, N, gx, gy);
+    Mw = mass_weights<KIND>(P, m, N, gx, gy, mh);
+  }
   for (int i = 0; i < P.q; ++i) {
     double* ub = P.ubar + (int64_t)i * nn;
     double* r = P.res + (int64_t)i * nn;
@@ -51,8 +55,9 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
     const double e = interp2(uc, nc1, gx + 1, gy), w = interp2(uc, nc1, gx - 1, gy);
     const double n = interp2(uc, nc1, gx, gy + 1), s = interp2(uc, nc1, gx, gy - 1);
     const double ne = interp2(uc, nc1, gx + 1, gy + 1), sw = interp2(uc, nc1, gx - 1, gy - 1);
-    const double Ku = (W.e + W.w + W.n + W.s) * c - W.e * e - W.w * w - W.n * n - W.s * s;
-    const double Mu = mh * (6.0 * c + e + w + n + s + ne + sw);
+    double d;
+    const double Ku = apply_k<KIND, double>(W, c, e, w, n, s, ne, sw, d);
+    const double Mu = apply_mass<KIND>(Mw, mh, c, e, w, n, s, ne, sw);
     const double lam = P.lam[src * MLC_MAX_Q + i];
     ub[idx] = c;
     r[idx] = lam * Mu - Ku;
@@ -126,7 +131,11 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
   const double h = P.side / N;
   const double mh = h * h * (1.0 / 12.0);
   Weights W;
-  if (dof) W = edge_weights<KIND>(P, m, N, gx, gy);
+  MassW Mw;
+  if (dof) {
+    W = edge_weights<KIND>(P, m, N, gx, gy);
+    Mw = mass_weights<KIND>(P, m, N, gx, gy, mh);
+  }
   double uv[MLC_MAX_Q], yk[MLC_MAX_Q], ym[MLC_MAX_Q];
 #pragma unroll
   for (int i = 0; i < MLC_MAX_Q; ++i) {
@@ -136,8 +145,9 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
       const double c = u[idx], e = u[idx + 1], w = u[idx - 1], n = u[idx + n1], s = u[idx - n1];
       const double ne = u[idx + n1 + 1], sw = u[idx - n1 - 1];
       uv[i] = c;
-      yk[i] = (W.e + W.w + W.n + W.s) * c - W.e * e - W.w * w - W.n * n - W.s * s;
-      ym[i] = mh * (6.0 * c + e + w + n + s + ne + sw);
+      double d;
+      yk[i] = apply_k<KIND, double>(W, c, e, w, n, s, ne, sw, d);
+      ym[i] = apply_mass<KIND>(Mw, mh, c, e, w, n, s, ne, sw);
     }
     if (i < q && inr) {
       P.res[(int64_t)i * nn + idx] = yk[i];
@@ -295,6 +305,104 @@ __global__ __launch_bounds__(NTG) void k_coarsen_kappa(const double* lo_f, const
   up_c[idx] = 0.25 * (up_f[a] + up_f[a + Nf] + lo_f[a + Nf] + up_f[a + Nf + 1]);
 }
 
+// Coefficient kind 3 on the finest level: the seven-point stiffness and mass of every
+// node from the element matrices of the (up to) six triangles around it.  On a triangle
+// with legs h along x and y, A and phi constant, a(phi_a, phi_b) = g_a . A g_b / 2 with
+// g the gradients scaled by h, and b(phi_a, phi_b) = phi h^2 (1 + delta_ab) / 24.  Input:
+// coef[c][t][J][I] (c: a11, a12, a22, phi; t: 0 below the SW-NE diagonal, 1 above).
+// Output: the 8 planes described in ProbDev::st7.  h2 = h^2 on this level.
+__global__ __launch_bounds__(NTG) void k_tensor_fine(const double* coef, double* st, int N,
+                                                     double h2) {
+  const int n1 = N + 1;
+  const int64_t pl = (int64_t)n1 * n1, cells = (int64_t)N * N;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= pl) return;
+  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  // vertices (lattice offsets from the cell's SW corner) and scaled gradients
+  const int vx[2][3] = {{0, 1, 1}, {0, 1, 0}}, vy[2][3] = {{0, 0, 1}, {0, 1, 1}};
+  const double gxv[2][3] = {{-1.0, 1.0, 0.0}, {0.0, 1.0, -1.0}};
+  const double gyv[2][3] = {{0.0, -1.0, 1.0}, {-1.0, 0.0, 1.0}};
+  const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
+  double kv[4] = {0.0, 0.0, 0.0, 0.0}, mv[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int J = gy - 1; J <= gy; ++J) {
+    for (int I = gx - 1; I <= gx; ++I) {
+      if (I < 0 || J < 0 || I >= N || J >= N) continue;
+      for (int t = 0; t < 2; ++t) {
+        int a = -1;
+        for (int k = 0; k < 3; ++k)
+          if (I + vx[t][k] == gx && J + vy[t][k] == gy) a = k;
+        if (a < 0) continue;
+        const int64_t c = (int64_t)J * N + I;
+        const double a11 = coef[(0 * 2 + t) * cells + c], a12 = coef[(1 * 2 + t) * cells + c];
+        const double a22 = coef[(2 * 2 + t) * cells + c], phi = coef[(3 * 2 + t) * cells + c];
+        for (int o = 0; o < 4; ++o) {
+          int b = -1;
+          for (int k = 0; k < 3; ++k)
+            if (I + vx[t][k] == gx + dx[o] && J + vy[t][k] == gy + dy[o]) b = k;
+          if (b < 0) continue;
+          const double ag_x = a11 * gxv[t][b] + a12 * gyv[t][b];
+          const double ag_y = a12 * gxv[t][b] + a22 * gyv[t][b];
+          kv[o] += 0.5 * (gxv[t][a] * ag_x + gyv[t][a] * ag_y);
+          mv[o] += phi * (a == b ? 2.0 : 1.0) / 24.0;
+        }
+      }
+    }
+  }
+  st[idx] = kv[0];
+  for (int o = 1; o < 4; ++o) st[o * pl + idx] = -kv[o];  // stored as weights -K(i, j)
+  for (int o = 0; o < 4; ++o) st[(4 + o) * pl + idx] = mv[o] * h2;
+}
+
+// Coefficient kind 3 on a coarser level: the Galerkin product P^T A P of the seven-point
+// stiffness and mass one level finer (exact integration on the nested spaces).  The
+// coarse basis function of node I is 1 at fine node 2I and 1/2 at its six neighbours
+// 2I +- (1,0), +-(0,1), +-(1,1); A_c(I, J) = sum over those fine nodes f of I and g of J
+// of P(f,I) A_f(f,g) P(g,J).  Fine nodes off the grid are skipped: they occur only for
+// coarse nodes on the boundary of the box, whose entries multiply zero values.
+__global__ __launch_bounds__(NTG) void k_galerkin7(const double* fine, double* coarse, int Nc) {
+  const int nc1 = Nc + 1, Nf = 2 * Nc, nf1 = Nf + 1;
+  const int64_t plc = (int64_t)nc1 * nc1, plf = (int64_t)nf1 * nf1;
+  const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
+  if (idx >= plc) return;
+  const int Y = (int)(idx / nc1), X = (int)(idx - (int64_t)Y * nc1);
+  const int ox[7] = {0, 1, -1, 0, 0, 1, -1}, oy[7] = {0, 0, 0, 1, -1, 1, -1};
+  const double ow[7] = {1.0, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
+  const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
+  // matrix entry A_f(f, f + (ex, ey)) of operator `op` (0 stiffness, 1 mass) on the fine grid
+  auto entry = [&](int op, int fx, int fy, int ex, int ey) -> double {
+    const double* pln = fine + (int64_t)(4 * op) * plf;
+    const double sg = op == 0 ? -1.0 : 1.0;  // stiffness planes hold -K off the diagonal
+    if (ex == 0 && ey == 0) return pln[(int64_t)fy * nf1 + fx];
+    int k = 0;
+    if (ex == 1 && ey == 0) k = 1;
+    else if (ex == 0 && ey == 1) k = 2;
+    else if (ex == 1 && ey == 1) k = 3;
+    else if (ex == -1 && ey == 0) { k = 1; fx -= 1; }
+    else if (ex == 0 && ey == -1) { k = 2; fy -= 1; }
+    else if (ex == -1 && ey == -1) { k = 3; fx -= 1; fy -= 1; }
+    else return 0.0;
+    return sg * pln[k * plf + (int64_t)fy * nf1 + fx];
+  };
+  for (int op = 0; op < 2; ++op) {
+    for (int o = 0; o < 4; ++o) {
+      double acc = 0.0;
+      for (int a = 0; a < 7; ++a) {
+        const int fx = 2 * X + ox[a], fy = 2 * Y + oy[a];
+        if (fx < 0 || fy < 0 || fx > Nf || fy > Nf) continue;
+        for (int b = 0; b < 7; ++b) {
+          const int gx = 2 * (X + dx[o]) + ox[b], gy = 2 * (Y + dy[o]) + oy[b];
+          if (gx < 0 || gy < 0 || gx > Nf || gy > Nf) continue;
+          const int ex = gx - fx, ey = gy - fy;
+          if (ex < -1 || ex > 1 || ey < -1 || ey > 1 || ex * ey < 0) continue;
+          acc += ow[a] * ow[b] * entry(op, fx, fy, ex, ey);
+        }
+      }
+      const double v = (op == 0 && o > 0) ? -acc : acc;
+      coarse[(int64_t)(4 * op + o) * plc + idx] = v;
+    }
+  }
+}
+
 // Coarse stiffness K_H and consistent mass M_H (dense, column-major) on V_0H.
 template <int KIND>
 __global__ __launch_bounds__(NTG) void k_coarse_matrices(const ProbDev* probs) {
@@ -307,15 +415,17 @@ __global__ __launch_bounds__(NTG) void k_coarse_matrices(const ProbDev* probs) {
   const Weights W = edge_weights<KIND>(P, 0, N, gx, gy);
   const double H = P.side / N;
   const double mh = H * H / 12.0;
-  P.Kc[(int64_t)r * nH + r] = W.e + W.w + W.n + W.s;
-  P.Mc[(int64_t)r * nH + r] = 6.0 * mh;
+  const MassW Mw = mass_weights<KIND>(P, 0, N, gx, gy, mh);
+  P.Kc[(int64_t)r * nH + r] = diag_of<KIND>(W);
+  P.Mc[(int64_t)r * nH + r] = Mw.d;
   const int dx[6] = {1, -1, 0, 0, 1, -1}, dy[6] = {0, 0, 1, -1, 1, -1};
-  const double kw[6] = {W.e, W.w, W.n, W.s, 0.0, 0.0};
+  const double kw[6] = {W.e, W.w, W.n, W.s, KIND == 3 ? W.ne : 0.0, KIND == 3 ? W.sw : 0.0};
+  const double mw[6] = {Mw.e, Mw.w, Mw.n, Mw.s, Mw.ne, Mw.sw};
   for (int t = 0; t < 6; ++t) {
     const int c = P.coarse_index[(gy + dy[t]) * n1 + gx + dx[t]];
     if (c < 0) continue;
     P.Kc[(int64_t)c * nH + r] = -kw[t];
-    P.Mc[(int64_t)c * nH + r] = mh;
+    P.Mc[(int64_t)c * nH + r] = mw[t];
   }
 }
 
@@ -346,11 +456,15 @@ __device__ __forceinline__ double tile_coarse_entry(const ProbDev& P, const Tile
   const int jx = j % nx, jy = j / nx;
   const bool dj = is_dof(P.domain, N, it.cx0 + 1 + jx, it.cy0 + 1 + jy);
   const Weights W = edge_weights<KIND>(P, 0, N, gx, gy);
-  if (i == j) return W.e + W.w + W.n + W.s;
+  if (i == j) return diag_of<KIND>(W);
   if (dj && jy == iy && jx == ix + 1) return -W.e;
   if (dj && jy == iy && jx == ix - 1) return -W.w;
   if (dj && jx == ix && jy == iy + 1) return -W.n;
   if (dj && jx == ix && jy == iy - 1) return -W.s;
+  if constexpr (KIND == 3) {
+    if (dj && jx == ix + 1 && jy == iy + 1) return -W.ne;
+    if (dj && jx == ix - 1 && jy == iy - 1) return -W.sw;
+  }
   return 0.0;
 }
 
@@ -477,8 +591,10 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
     hipLaunchKernelGGL(k_prolong_residual<0>, g, dim3(NTG), 0, s, probs, m, src);
   else if (kind == 1)
     hipLaunchKernelGGL(k_prolong_residual<1>, g, dim3(NTG), 0, s, probs, m, src);
-  else
+  else if (kind == 2)
     hipLaunchKernelGGL(k_prolong_residual<2>, g, dim3(NTG), 0, s, probs, m, src);
+  else
+    hipLaunchKernelGGL(k_prolong_residual<3>, g, dim3(NTG), 0, s, probs, m, src);
   return hipGetLastError();
 }
 
@@ -497,8 +613,10 @@ hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int
     hipLaunchKernelGGL(k_rr_apply<0>, g, dim3(NTG), 0, s, probs, m);
   else if (kind == 1)
     hipLaunchKernelGGL(k_rr_apply<1>, g, dim3(NTG), 0, s, probs, m);
-  else
+  else if (kind == 2)
     hipLaunchKernelGGL(k_rr_apply<2>, g, dim3(NTG), 0, s, probs, m);
+  else
+    hipLaunchKernelGGL(k_rr_apply<3>, g, dim3(NTG), 0, s, probs, m);
   return hipGetLastError();
 }
 
@@ -533,6 +651,18 @@ hipError_t launch_coarsen_kappa(const double* lo_f, const double* up_f, double* 
   return hipGetLastError();
 }
 
+hipError_t launch_tensor_fine(const double* coef, double* st, int N, double h2, hipStream_t s) {
+  hipLaunchKernelGGL(k_tensor_fine, dim3(nblocks((int64_t)(N + 1) * (N + 1))), dim3(NTG), 0, s,
+                     coef, st, N, h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_galerkin7(const double* fine, double* coarse, int Nc, hipStream_t s) {
+  hipLaunchKernelGGL(k_galerkin7, dim3(nblocks((int64_t)(Nc + 1) * (Nc + 1))), dim3(NTG), 0, s,
+                     fine, coarse, Nc);
+  return hipGetLastError();
+}
+
 hipError_t launch_coarse_matrices(int kind, const ProbDev* probs, int nprob, int max_nH,
                                   hipStream_t s) {
   dim3 g(nblocks(max_nH), nprob);
@@ -540,8 +670,10 @@ hipError_t launch_coarse_matrices(int kind, const ProbDev* probs, int nprob, int
     hipLaunchKernelGGL(k_coarse_matrices<0>, g, dim3(NTG), 0, s, probs);
   else if (kind == 1)
     hipLaunchKernelGGL(k_coarse_matrices<1>, g, dim3(NTG), 0, s, probs);
-  else
+  else if (kind == 2)
     hipLaunchKernelGGL(k_coarse_matrices<2>, g, dim3(NTG), 0, s, probs);
+  else
+    hipLaunchKernelGGL(k_coarse_matrices<3>, g, dim3(NTG), 0, s, probs);
   return hipGetLastError();
 }
 
@@ -556,8 +688,10 @@ hipError_t launch_tile_inverse(int kind, const ProbDev* probs, const TileItem* i
     hipLaunchKernelGGL(k_tile_inverse<0>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
   else if (kind == 1)
     hipLaunchKernelGGL(k_tile_inverse<1>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
-  else
+  else if (kind == 2)
     hipLaunchKernelGGL(k_tile_inverse<2>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
+  else
+    hipLaunchKernelGGL(k_tile_inverse<3>, dim3(nitems), dim3(NTG), 0, s, probs, items, inv);
   return hipGetLastError();
 }
 

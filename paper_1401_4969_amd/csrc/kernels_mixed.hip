@@ -123,8 +123,10 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
     MLC_MIX(NTV, 0);    \
   else if (kind == 1)   \
     MLC_MIX(NTV, 1);    \
+  else if (kind == 2)   \
+    MLC_MIX(NTV, 2);    \
   else                  \
-    MLC_MIX(NTV, 2);
+    MLC_MIX(NTV, 3);
   if (nt == 256) {
     MLC_MIX_NT(256)
   } else if (nt == 512) {

@@ -124,8 +124,10 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
     MLC_PCG(NTV, 0);       \
   else if (kind == 1)      \
     MLC_PCG(NTV, 1);       \
+  else if (kind == 2)      \
+    MLC_PCG(NTV, 2);       \
   else                     \
-    MLC_PCG(NTV, 2);
+    MLC_PCG(NTV, 3);
   if (nt == 256) {
     MLC_PCG_NT(256)
   } else if (nt == 512) {

@@ -3,9 +3,11 @@
 // Geometry: a level-l grid of the bounding box has N_l = n_c * 2^l cells per side and
 // (N_l+1)^2 nodes, node (gx, gy) at index gy*(N_l+1)+gx.  Square cell (I, J) is cut by
 // its SW-NE diagonal into a lower triangle (SW, SE, NE) and an upper one (SW, NE, NW).
-// With P1 elements only the two legs of each triangle couple, so the stiffness is a
-// five-point stencil whose edge weights average the kappa of the two triangles on each
-// side of the edge; the mass is (h^2/12)[6; E, W, N, S, NE, SW].
+// With P1 elements and a scalar coefficient only the two legs of each triangle couple,
+// so the stiffness is a five-point stencil whose edge weights average the kappa of the
+// two triangles on each side of the edge; the mass is (h^2/12)[6; E, W, N, S, NE, SW].
+// With a full tensor A (Example 6.2) the hypotenuse couples too and the mass carries the
+// weight phi: both are seven-point stencils, stored per level (coefficient kind 3).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,6 +27,10 @@ struct ProbDev {
   const double* kH;           // coef kinds 0/1: n_c*n_c per coarse cell
   const double* kLR[MLC_MAX_LEVELS + 1];  // coef kind 2: per level, N_l*N_l lower-triangle kappa
   const double* kUL[MLC_MAX_LEVELS + 1];  //                            upper-triangle kappa
+  // coef kind 3: per level, 8 planes of (N_l+1)^2 values: the stiffness diagonal and the
+  // weights -K(i, i+E), -K(i, i+N), -K(i, i+NE), then the mass M(i,i), M(i,i+E),
+  // M(i,i+N), M(i,i+NE)
+  const double* st7[MLC_MAX_LEVELS + 1];
   const int32_t* bx;          // sub_x+1 block boundaries in coarse cells
   const int32_t* by;          // sub_y+1
   int32_t sub_item_off;       // offset of this problem's (sub_x*sub_y)*q block in a step's
@@ -73,9 +79,12 @@ __device__ __forceinline__ bool is_dof(int domain, int N, int gx, int gy) {
   return true;
 }
 
-// Edge weights around node (gx, gy) on a level with N cells, level index l (coarse = 0).
+// Edge weights around node (gx, gy) on a level with N cells, level index l (coarse = 0):
+// minus the stiffness couplings to the four leg neighbours, and with coefficient kind 3
+// also to the NE and SW neighbours plus the diagonal d (for kinds 0-2 the diagonal is
+// e + w + n + s and ne, sw, d are not set).
 struct Weights {
-  double e, w, n, s;
+  double e, w, n, s, ne, sw, d;
 };
 
 // Coefficient arrays are reached through pointers held in ProbDev; the cast to the
@@ -85,7 +94,19 @@ typedef __attribute__((address_space(1))) const double gconst_double;
 template <int KIND>
 __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, int gx, int gy) {
   Weights W;
-  if (KIND == 0) {
+  if constexpr (KIND == 3) {
+    const gconst_double* st = (const gconst_double*)P.st7[l];
+    const int n1 = N + 1;
+    const int64_t pl = (int64_t)n1 * n1;
+    const int64_t c = (int64_t)gy * n1 + gx;
+    W.d = st[c];
+    W.e = st[pl + c];
+    W.w = st[pl + c - 1];
+    W.n = st[2 * pl + c];
+    W.s = st[2 * pl + c - n1];
+    W.ne = st[3 * pl + c];
+    W.sw = st[3 * pl + c - n1 - 1];
+  } else if (KIND == 0) {
     W.e = W.w = W.n = W.s = 1.0;
   } else if (KIND == 1) {
     const int nc = P.n_c;
@@ -112,6 +133,69 @@ __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, 
     W.s = 0.5 * (up[c - N] + lo[c - N - 1]);
   }
   return W;
+}
+
+// Stiffness diagonal from the weights.
+template <int KIND>
+__device__ __forceinline__ double diag_of(const Weights& W) {
+  if constexpr (KIND == 3)
+    return W.d;
+  else
+    return W.e + W.w + W.n + W.s;
+}
+
+// K u at a node from u at the node and its six neighbours (five-point for kinds 0-2,
+// where ne and sw are not used); d receives the diagonal.
+template <int KIND, typename T>
+__device__ __forceinline__ T apply_k(const Weights& W, T c, T e, T w, T n, T s, T ne, T sw, T& d) {
+  const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
+  if constexpr (KIND == 3) {
+    d = T(W.d);
+    return d * c - we * e - ww * w - wn * n - ws * s - T(W.ne) * ne - T(W.sw) * sw;
+  } else {
+    d = we + ww + wn + ws;
+    return d * c - we * e - ww * w - wn * n - ws * s;
+  }
+}
+
+// Mass couplings of node (gx, gy) on level l: the diagonal and the six neighbours
+// (kind 3 reads the stored weighted mass; kinds 0-2 have the constant h^2/12 pattern).
+struct MassW {
+  double d, e, w, n, s, ne, sw;
+};
+
+template <int KIND>
+__device__ __forceinline__ MassW mass_weights(const ProbDev& P, int l, int N, int gx, int gy,
+                                              double mh) {
+  MassW M;
+  if constexpr (KIND == 3) {
+    const int n1 = N + 1;
+    const int64_t pl = (int64_t)n1 * n1;
+    const gconst_double* m = (const gconst_double*)P.st7[l] + 4 * pl;
+    const int64_t i = (int64_t)gy * n1 + gx;
+    M.d = m[i];
+    M.e = m[pl + i];
+    M.w = m[pl + i - 1];
+    M.n = m[2 * pl + i];
+    M.s = m[2 * pl + i - n1];
+    M.ne = m[3 * pl + i];
+    M.sw = m[3 * pl + i - n1 - 1];
+  } else {
+    M.d = 6.0 * mh;
+    M.e = M.w = M.n = M.s = M.ne = M.sw = mh;
+  }
+  return M;
+}
+
+// M u at a node: the consistent mass (h^2/12)[6; E, W, N, S, NE, SW] for kinds 0-2
+// (mh = h^2/12), the stored weighted mass for kind 3.
+template <int KIND>
+__device__ __forceinline__ double apply_mass(const MassW& M, double mh, double c, double e,
+                                             double w, double n, double s, double ne, double sw) {
+  if constexpr (KIND == 3)
+    return M.d * c + M.e * e + M.w * w + M.n * n + M.s * s + M.ne * ne + M.sw * sw;
+  else
+    return mh * (6.0 * c + e + w + n + s + ne + sw);
 }
 
 // Blocks along one axis whose Omega range (D_j grown by `ov` coarse cells) holds fine

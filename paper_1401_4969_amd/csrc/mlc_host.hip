@@ -76,8 +76,8 @@ mlc_status check_opts(const mlc_solver_opts* o, std::string& msg) {
 
 mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& msg) {
   if (!d) { msg = "null descriptor"; return MLC_EINVAL; }
-  if (d->domain != 0 && d->domain != 1) { msg = "domain must be 0 or 1"; return MLC_EINVAL; }
-  if (d->coef_kind < 0 || d->coef_kind > 2) { msg = "coef_kind must be 0, 1 or 2"; return MLC_EINVAL; }
+  if (d->domain < 0 || d->domain > 2) { msg = "domain must be 0, 1 or 2"; return MLC_EINVAL; }
+  if (d->coef_kind < 0 || d->coef_kind > 3) { msg = "coef_kind must be 0, 1, 2 or 3"; return MLC_EINVAL; }
   if (d->n_coarse < 2 || d->n_coarse > 4096) { msg = "n_coarse must be in 2..4096"; return MLC_EINVAL; }
   if (d->domain == 1 && (d->n_coarse & 1)) { msg = "the L-shape needs an even n_coarse"; return MLC_EINVAL; }
   if (d->n_refine < 1 || d->n_refine > MLC_MAX_LEVELS) { msg = "n_refine must be in 1..10"; return MLC_EINVAL; }
@@ -103,12 +103,26 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
   g.pou = d->pou;
   g.side = d->domain == 0 ? 1.0 : 2.0;
   const int nc = g.nc;
-  if (g.kind != 0) {
+  if (g.kind == 1 || g.kind == 2) {
     if (!d->kappa) { msg = "kappa is NULL"; return MLC_EINVAL; }
     const int64_t n = g.kind == 1 ? (int64_t)nc * nc : g.N(g.L) * g.N(g.L);
     for (int64_t i = 0; i < n; ++i) {
       const double k = d->kappa[i];
       if (!(k > 0.0) || !std::isfinite(k)) { msg = "kappa must be positive and finite"; return MLC_EINVAL; }
+    }
+  }
+  if (g.kind == 3) {  // per finest triangle: A symmetric positive definite, phi > 0
+    if (!d->kappa) { msg = "kappa is NULL"; return MLC_EINVAL; }
+    const int64_t n = 2 * g.N(g.L) * g.N(g.L);
+    const double* a11 = d->kappa;
+    const double* a12 = d->kappa + n;
+    const double* a22 = d->kappa + 2 * n;
+    const double* phi = d->kappa + 3 * n;
+    for (int64_t i = 0; i < n; ++i) {
+      const bool ok = std::isfinite(a11[i]) && std::isfinite(a12[i]) && std::isfinite(a22[i]) &&
+                      std::isfinite(phi[i]) && a11[i] > 0.0 && a22[i] > 0.0 &&
+                      a11[i] * a22[i] - a12[i] * a12[i] > 0.0 && phi[i] > 0.0;
+      if (!ok) { msg = "coef_kind 3 needs finite values, A positive definite and phi > 0 on every triangle"; return MLC_EINVAL; }
     }
   }
   g.coarse_index.assign((size_t)(nc + 1) * (nc + 1), -1);
@@ -176,6 +190,7 @@ struct ProbLayout {
   size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
       E, info, fg, partials, rr_x, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
+  size_t st7[MLC_MAX_LEVELS + 1], coef3;  // coef kind 3: stencil planes, per-triangle input
   int64_t rchain_off[MLC_MAX_LEVELS + 1];
   int64_t inv_base;      // doubles, into the batch inverse region
   int32_t sub_item_off;  // into every step's subdomain -> item table
@@ -261,13 +276,18 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.coarse_nodes = take((size_t)g.nH * 4);
     L.coarse_index = take(ncs * 4);
     L.kH = take((size_t)g.nc * g.nc * 8);
-    for (int l = 0; l <= MLC_MAX_LEVELS; ++l) L.kLR[l] = L.kUL[l] = 0;
+    for (int l = 0; l <= MLC_MAX_LEVELS; ++l) L.kLR[l] = L.kUL[l] = L.st7[l] = 0;
+    L.coef3 = 0;
     if (g.kind == 2)
       for (int l = 0; l <= g.L; ++l) {
         const size_t c = (size_t)(g.N(l) * g.N(l)) * 8;
         L.kLR[l] = take(c);
         L.kUL[l] = (l == g.L) ? L.kLR[l] : take(c);
       }
+    if (g.kind == 3) {
+      L.coef3 = take((size_t)(8 * g.N(g.L) * g.N(g.L)) * 8);
+      for (int l = 0; l <= g.L; ++l) L.st7[l] = take((size_t)(8 * g.nodes(l)) * 8);
+    }
     L.u[0] = take(q * nnL * 8);
     L.u[1] = take(q * nnL * 8);
     L.lam = take(2 * MLC_MAX_Q * 8);
@@ -504,6 +524,8 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     if (g.kind == 1) b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)g.nc * g.nc);
     if (g.kind == 0) b->kappa[i].assign((size_t)g.nc * g.nc, 1.0);
     if (g.kind == 2) b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(g.N(g.L) * g.N(g.L)));
+    if (g.kind == 3)
+      b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(8 * g.N(g.L) * g.N(g.L)));
     ProbDev& D = b->hp[i];
     std::memset(&D, 0, sizeof(D));
     D.domain = g.domain;
@@ -521,6 +543,7 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     for (int l = 0; l <= g.L; ++l) {
       D.kLR[l] = g.kind == 2 ? (const double*)(w + L.kLR[l]) : nullptr;
       D.kUL[l] = g.kind == 2 ? (const double*)(w + L.kUL[l]) : nullptr;
+      D.st7[l] = g.kind == 3 ? (const double*)(w + L.st7[l]) : nullptr;
     }
     D.bx = (const int32_t*)(w + L.bx);
     D.by = (const int32_t*)(w + L.by);
@@ -566,6 +589,8 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     ok = ok && up(L.coarse_index, g.coarse_index.data(), g.coarse_index.size() * 4);
     if (g.kind == 2)
       ok = ok && up(L.kLR[g.L], b->kappa[i].data(), b->kappa[i].size() * 8);
+    else if (g.kind == 3)
+      ok = ok && up(L.coef3, b->kappa[i].data(), b->kappa[i].size() * 8);
     else
       ok = ok && up(L.kH, b->kappa[i].data(), b->kappa[i].size() * 8);
   }
@@ -605,6 +630,14 @@ mlc_status batch_setup(mlc_batch* b) {
         MLC_HIP(b, launch_coarsen_kappa(b->hp[i].kLR[l + 1], b->hp[i].kUL[l + 1],
                                         (double*)(w + L.kLR[l]), (double*)(w + L.kUL[l]),
                                         (int)g.N(l), st));
+    if (g.kind == 3) {  // seven-point stiffness and mass on every level (Galerkin products)
+      const double h = g.side / (double)g.N(g.L);
+      MLC_HIP(b, launch_tensor_fine((const double*)(w + L.coef3), (double*)(w + L.st7[g.L]),
+                                    (int)g.N(g.L), h * h, st));
+      for (int l = g.L - 1; l >= 0; --l)
+        MLC_HIP(b, launch_galerkin7((const double*)(w + L.st7[l + 1]), (double*)(w + L.st7[l]),
+                                    (int)g.N(l), st));
+    }
     const size_t nH = (size_t)g.nH;
     MLC_HIP(b, hipMemsetAsync(w + L.Kc, 0, nH * nH * 8, st));
     MLC_HIP(b, hipMemsetAsync(w + L.Mc, 0, nH * nH * 8, st));

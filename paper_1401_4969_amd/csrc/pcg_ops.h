@@ -46,9 +46,15 @@ __device__ __forceinline__ T stencil(const ProbDev& P, const LevelDesc& lv, cons
   const T n0 = u[hn ? i + lv.nx : i];
   const T s0 = u[hs ? i - lv.nx : i];
   const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = hn ? n0 : T(0), s = hs ? s0 : T(0);
-  const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
-  diag = we + ww + wn + ws;
-  return diag * c - we * e - ww * w - wn * n - ws * s;
+  T ne = T(0), sw = T(0);
+  if constexpr (KIND == 3) {  // the hypotenuse neighbours
+    const bool hne = he && hn, hsw = hw && hs;
+    const T ne0 = u[hne ? i + lv.nx + 1 : i];
+    const T sw0 = u[hsw ? i - lv.nx - 1 : i];
+    ne = hne ? ne0 : T(0);
+    sw = hsw ? sw0 : T(0);
+  }
+  return apply_k<KIND, T>(W, c, e, w, n, s, ne, sw, diag);
 }
 
 // z = omega D^-1 b (first sweep from a zero iterate)
@@ -59,7 +65,7 @@ __device__ void op_first(const ProbDev& P, const LevelDesc& lv, const T* b, T* z
     T v = T(0);
     if (is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy)) {
       const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
-      v = omega * b[i] / T(W.e + W.w + W.n + W.s);
+      v = omega * b[i] / T(diag_of<KIND>(W));
     }
     z[i] = v;
   }
@@ -72,7 +78,7 @@ __device__ void op_first(const ProbDev& P, const LevelDesc& lv, const T* b, T* z
 template <int KIND>
 __device__ __forceinline__ double diag_at(const ProbDev& P, const LevelDesc& lv, int ix, int iy) {
   const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
-  return W.e + W.w + W.n + W.s;
+  return diag_of<KIND>(W);
 }
 
 template <int NT, int KIND, typename T>
@@ -88,14 +94,24 @@ __device__ void op_first2(const ProbDev& P, const LevelDesc& lv, const T* b, T* 
     };
     const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
     const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
-    const T d = we + ww + wn + ws;
+    T d;
+    if constexpr (KIND == 3)
+      d = T(W.d);
+    else
+      d = we + ww + wn + ws;
     const T bc = b[i];
     const T zc = omega * bc / d;
     const T ze = z1(ix + 1 < lv.nx, ix + 1, iy, i + 1);
     const T zw = z1(ix > 0, ix - 1, iy, i - 1);
     const T zn = z1(iy + 1 < lv.ny, ix, iy + 1, i + lv.nx);
     const T zs = z1(iy > 0, ix, iy - 1, i - lv.nx);
-    const T az = d * zc - we * ze - ww * zw - wn * zn - ws * zs;
+    T zne = T(0), zsw = T(0);
+    if constexpr (KIND == 3) {
+      zne = z1(ix + 1 < lv.nx && iy + 1 < lv.ny, ix + 1, iy + 1, i + lv.nx + 1);
+      zsw = z1(ix > 0 && iy > 0, ix - 1, iy - 1, i - lv.nx - 1);
+    }
+    T dd;
+    const T az = apply_k<KIND, T>(W, zc, ze, zw, zn, zs, zne, zsw, dd);
     const T v = zc + omega * (bc - az) / d;
     z[i] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy) ? v : T(0);
   }
@@ -183,9 +199,13 @@ __device__ __forceinline__ T apply_rows(const ProbDev& P, const LevelDesc& lv, c
   const T c = rc[ix];
   const T e0 = rc[he ? ix + 1 : ix], w0 = rc[hw ? ix - 1 : ix];
   const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = rn[ix], s = rs[ix];
-  const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
-  d = we + ww + wn + ws;
-  return d * c - we * e - ww * w - wn * n - ws * s;
+  T ne = T(0), sw = T(0);
+  if constexpr (KIND == 3) {  // hypotenuse neighbours: the rows above and below hold zeros
+    const T ne0 = rn[he ? ix + 1 : ix], sw0 = rs[hw ? ix - 1 : ix];  // off the tile
+    ne = he ? ne0 : T(0);
+    sw = hw ? sw0 : T(0);
+  }
+  return apply_k<KIND, T>(W, c, e, w, n, s, ne, sw, d);
 }
 
 template <int KIND, typename T>
@@ -978,9 +998,16 @@ __device__ void pass_dir_plain(const ProbDev& P, const LevelDesc& l0, const T* Z
     const T e0 = pv(he ? i + 1 : i), w0 = pv(hw ? i - 1 : i);
     const T n0 = pv(hn ? i + l0.nx : i), s0 = pv(hs ? i - l0.nx : i);
     const T e = he ? e0 : T(0), w = hw ? w0 : T(0), n = hn ? n0 : T(0), s = hs ? s0 : T(0);
+    T ne = T(0), sw = T(0);
+    if constexpr (KIND == 3) {
+      const bool hne = he && hn, hsw = hw && hs;
+      const T ne0 = pv(hne ? i + l0.nx + 1 : i), sw0 = pv(hsw ? i - l0.nx - 1 : i);
+      ne = hne ? ne0 : T(0);
+      sw = hsw ? sw0 : T(0);
+    }
     const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
-    const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
-    const T q = (we + ww + wn + ws) * pc - we * e - ww * w - wn * n - ws * s;
+    T d;
+    const T q = apply_k<KIND, T>(W, pc, e, w, n, s, ne, sw, d);
     if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) *acc += (double)pc * (double)q;
     Pn[i] = pc;
   }

@@ -58,9 +58,9 @@ def test_workspace_size_config3_fits_hbm():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(domain=3), dict(n_coarse=1), dict(n_refine=0), dict(n_refine=11),
+    dict(domain=3), dict(domain=-1), dict(n_coarse=1), dict(n_refine=0), dict(n_refine=11),
     dict(sub_x=0), dict(sub_x=9), dict(overlap=0), dict(n_eig=0), dict(n_eig=9),
-    dict(coef_kind=5), dict(pou=3), dict(pou=-1), dict(pou=1, overlap=-1),
+    dict(coef_kind=4), dict(coef_kind=-1), dict(pou=3), dict(pou=-1), dict(pou=1, overlap=-1),
 ])
 def test_invalid_descriptors_rejected(bad):
     p = W.config1().with_(**bad)
@@ -134,3 +134,26 @@ def test_interface_gluing_limits():
     with pytest.raises(B.MLCError) as e:
         B.workspace_size(W.small_field().with_(pou=2), B.default_opts(record_tape=1))
     assert e.value.status == B.MLC_EINVAL
+
+
+def test_tensor_coefficients_validated():
+    """Coefficient kind 3 (Example 6.2): every triangle needs a finite, positive definite A
+    and phi > 0; the tensor kind has no reverse sweep; the seven-point planes enlarge the
+    workspace."""
+    p = W.example62(n_refine=2, sub=2, n_eig=6)
+    n = B.workspace_size(p)
+    assert n > B.workspace_size(p.with_(coef_kind=0, kappa=None))
+    for comp, tri, val in ((0, 0, 0.0), (2, 1, -1.0), (3, 0, 0.0), (1, 1, np.nan),
+                           (0, 1, np.inf), (1, 0, 10.0)):   # the last: a12^2 > a11 a22
+        k = p.kappa.copy()
+        k[comp, tri, 7, 11] = val
+        with pytest.raises(B.MLCError) as e:
+            B.workspace_size(p.with_(kappa=k))
+        assert e.value.status == B.MLC_EINVAL
+    with pytest.raises(B.MLCError) as e:
+        B.workspace_size(p.with_(n_eig=1), B.default_opts(record_tape=1))
+    assert e.value.status == B.MLC_EINVAL
+    # the tensor kind on the other domains
+    for dom in (0, 1):
+        q = W.Problem(dom, 8, 2, 2, 2, 1, 2, 3, W.random_tensor_coefficients(dom, 32, 3))
+        assert B.workspace_size(q) > 0

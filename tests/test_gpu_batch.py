@@ -37,6 +37,8 @@ def _small_batch(kind=1, q=1, n=7, seed0=100):
             kap = W.loguniform_coarse_kappa(nc, rng)
         elif kind == 2:
             kap = np.exp(rng.uniform(-1, 1, size=(nc << L, nc << L)))
+        elif kind == 3:
+            kap = W.random_tensor_coefficients(dom, nc << L, seed0 + i)
         out.append(W.Problem(dom, nc, L, s, s, 1, q, kind, kap, f"b{i}"))
     return out
 
@@ -51,7 +53,8 @@ def _single(prob, **kw):
     return lam, u
 
 
-@pytest.mark.parametrize("kind,q,precision", [(1, 1, 0), (2, 1, 0), (0, 2, 0), (1, 1, 1)])
+@pytest.mark.parametrize("kind,q,precision", [(1, 1, 0), (2, 1, 0), (0, 2, 0), (1, 1, 1),
+                                              (3, 2, 0), (3, 1, 1)])
 def test_batch_matches_single_and_oracle(kind, q, precision):
     torch = _torch()
     from paper_1401_4969_amd import binding as B
@@ -71,12 +74,13 @@ def test_batch_matches_single_and_oracle(kind, q, precision):
     bs.close()
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("kind", [1, 3])
+def test_graph_replays_match_eager(kind):
     """Every graph replay, with eager work and synchronisations in between, reproduces
     the eager step bitwise."""
     torch = _torch()
     from paper_1401_4969_amd import binding as B
-    probs = _small_batch(1, 1)
+    probs = _small_batch(kind, 1)
     eager = B.BatchSolver(probs)
     eager.setup()
     eager.run(use_graph=False)
