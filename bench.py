@@ -42,7 +42,7 @@ def ring_mode(nt: int, tile_nx: int, nu: int, elem: int = 8, lds_limit: int = 16
 
 
 def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
-                            mode: int = 2) -> float:
+                            mode: int = 2, coef: int = 0) -> float:
     """Bytes the local-solve kernel must move per PCG iteration for one tile: every
     vector a pass reads or writes counted once per pass (a vector read at several
     stages of one banded pass counts once; the later reads are served from cache):
@@ -56,26 +56,35 @@ def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
         interpolation add 2 and nu sweeps 3 each;
         plus on level t+1 the restriction write 1 and the correction read 1;
       r.z rides on the last sweep of level 0;
-      coarsest: read b, write z, and the dense inverse (n^2 values)."""
+      coarsest: read b, write z, and the dense inverse (n^2 values).
+    coef: bytes per node of a stored operator (the tensor kind's four FP64 stiffness planes,
+    32), read once by every pass that applies the stiffness: on level 0 the direction and
+    x/r passes, on every V-cycle level the banded pre- and post-smoothing passes (mode 2)
+    or each sweep and the residual apart."""
     S = tile_levels(cw, ch, m)
     v = 0.0
     pre = 2 if (mode >= 2 and nu == 2) else 2 + 3 * max(nu - 2, 0) + 3 + 1
     post = 3 if (mode >= 2 and nu == 2) else 2 + 3 * nu
+    k_passes = 2 if (mode >= 2 and nu == 2) else 1 + max(nu - 2, 0) + 1 + nu
+    c = 0.0
     for t in range(m):
         v += S[t] * (pre + post) + S[t + 1] * 2
+        c += S[t] * k_passes
     v += 2 * S[m] + S[m] ** 2
-    return elem * (8 * S[0] + v)
+    c += 2 * S[0]
+    return elem * (8 * S[0] + v) + coef * c
 
 
 def mixed_bytes(cw: int, ch: int, m: int, nu: int, it_dofs: int, refine_dofs: int,
-                tile_dofs: int, mode: int = 2) -> float:
+                tile_dofs: int, mode: int = 2, coef: int = 0) -> float:
     """Bytes of one mixed-precision local-solve launch: the FP32 inner iterations (the FP64
     schedule above with 4-byte elements, plus one pass per inner solve), and per
     refinement step the FP64 passes e += d (read e 8, d 4, write e 8) and r = b - K e
-    (read b 8, e 8, write r 4, clear d 4); plus the first pass (read b, write e, r, d)."""
+    (read b 8, e 8, write r 4, clear d 4, and the stored operator's planes, coef); plus
+    the first pass (read b, write e, r, d)."""
     S0 = tile_levels(cw, ch, m)[0]
-    per_it = pcg_bytes_per_iteration(cw, ch, m, nu, elem=4, mode=mode) / S0
-    return per_it * it_dofs + (44.0 + 4.0) * refine_dofs + 24.0 * tile_dofs
+    per_it = pcg_bytes_per_iteration(cw, ch, m, nu, elem=4, mode=mode, coef=coef) / S0
+    return per_it * it_dofs + (44.0 + 4.0 + coef) * refine_dofs + 24.0 * tile_dofs
 
 
 def source_sha(kernel: str) -> str:
@@ -123,7 +132,7 @@ def subdomain_shapes(prob):
 
 def interior_nodes(prob, level: int) -> int:
     n = prob.n_coarse << level
-    if prob.domain == 0:
+    if prob.domain != 1:
         return (n - 1) ** 2
     h = n // 2
     return (n - 1) ** 2 - h * h   # removed quadrant: nodes with i >= N/2 and j <= N/2
@@ -256,6 +265,10 @@ def workload(name: str):
         return W.config2().with_(pou=2, name="c2_iface"), dict(precision=0)
     if name == "c3iface":
         return W.config3().with_(pou=2, name="c3_iface"), dict(precision=0)
+    if name == "ex62":
+        return W.example62(n_refine=5, sub=5, n_eig=6), dict(precision=0)
+    if name == "ex62mixed":
+        return W.example62(n_refine=5, sub=5, n_eig=6), dict(precision=1)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -328,11 +341,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c3mixed", "c4", "c5adj", "c2iface", "c3iface"],
+                    choices=["c2", "c3", "c3mixed", "c4", "c5adj", "c2iface", "c3iface",
+                             "ex62", "ex62mixed"],
                     help="c2: h = 1/512, 8x8 subdomains, q = 3 (default); c3: h = 1/2048, "
                          "16x16, FP64; c3mixed: the same in FP32 + FP64 refinement; c4: 256 "
                          "problems batched; c5adj: reverse sweep at h = 1/1024; c2iface, "
-                         "c3iface: c2 / c3 with the paper's own gluing (interface problem)")
+                         "c3iface: c2 / c3 with the paper's own gluing (interface problem); "
+                         "ex62, ex62mixed: the operator of Example 6.2 (tensor A, weight "
+                         "phi) on (-1,1)^2, H = 0.1, h = 1/320, 5x5 subdomains, q = 6")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -404,19 +420,21 @@ def main():
     tile_nx = max(c for c, _ in shapes) * (1 << m) - 1
     elem = 8 if opts.precision == 0 else 4
     rmode = ring_mode(nt, tile_nx, opts.nu, elem, lds_limit)
+    coef = 32 if prob.coef_kind == 3 else 0
     if opts.precision == 0:
         kernel = "k_local_pcg64"
-        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode) / S0
+        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode, coef=coef) / S0
         bytes_launch = per_dof_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
     else:
         kernel = "k_local_mixed"
-        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode) / S0
+        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode,
+                                              coef=coef) / S0
         bytes_launch = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
-                                   st["n_tile_dofs"], mode=rmode)
+                                   st["n_tile_dofs"], mode=rmode, coef=coef)
     achieved = bytes_launch / (pcg_ms * 1e-3) / 1e9
     traffic = measured_traffic(kernel, prob.name)
 
-    gold = golden_lambda(args.workload.replace("mixed", ""))
+    gold = golden_lambda(args.workload.replace("mixed", ""))  # ex62mixed -> ex62
     lam_err = None
     if gold is not None:
         lam_err = float(np.max(np.abs(lam - np.array(gold)) / np.abs(np.array(gold))))
@@ -438,6 +456,8 @@ def main():
                    "n_eig": prob.n_eig, "subdomains": f"{prob.sub_x}x{prob.sub_y}",
                    "overlap": prob.overlap, "precision": "fp64" if opts.precision == 0 else "mixed",
                    "local_rtol": opts.rtol,
+                   "operator": ("Example 6.2: tensor A, mass weight phi, (-1,1)^2"
+                                if prob.coef_kind == 3 else "kappa"),
                    "gluing": ["partition of unity (ramp)", "partition of unity (indicator)",
                               "interface problem on G_m+1"][getattr(prob, "pou", 0)]},
         "lambda": lam.tolist(),
