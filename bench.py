@@ -57,8 +57,8 @@ def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
         plus on level t+1 the restriction write 1 and the correction read 1;
       r.z rides on the last sweep of level 0;
       coarsest: read b, write z, and the dense inverse (n^2 values).
-    coef: bytes per node of a stored operator (the tensor kind's four FP64 stiffness planes,
-    32), read once by every pass that applies the stiffness: on level 0 the direction and
+    coef: bytes per node of a stored operator (the tensor kind's three stiffness planes: 24
+    in FP64, 12 in FP32), read once by every pass that applies the stiffness: on level 0 the direction and
     x/r passes, on every V-cycle level the banded pre- and post-smoothing passes (mode 2)
     or each sweep and the residual apart."""
     S = tile_levels(cw, ch, m)
@@ -76,15 +76,15 @@ def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
 
 
 def mixed_bytes(cw: int, ch: int, m: int, nu: int, it_dofs: int, refine_dofs: int,
-                tile_dofs: int, mode: int = 2, coef: int = 0) -> float:
+                tile_dofs: int, mode: int = 2, coef: int = 0, coef64: int = 0) -> float:
     """Bytes of one mixed-precision local-solve launch: the FP32 inner iterations (the FP64
     schedule above with 4-byte elements, plus one pass per inner solve), and per
     refinement step the FP64 passes e += d (read e 8, d 4, write e 8) and r = b - K e
-    (read b 8, e 8, write r 4, clear d 4, and the stored operator's planes, coef); plus
-    the first pass (read b, write e, r, d)."""
+    (read b 8, e 8, write r 4, clear d 4, and the stored operator's FP64 planes, coef64);
+    plus the first pass (read b, write e, r, d).  coef: the FP32 planes of the inner solves."""
     S0 = tile_levels(cw, ch, m)[0]
     per_it = pcg_bytes_per_iteration(cw, ch, m, nu, elem=4, mode=mode, coef=coef) / S0
-    return per_it * it_dofs + (44.0 + 4.0 + coef) * refine_dofs + 24.0 * tile_dofs
+    return per_it * it_dofs + (44.0 + 4.0 + coef64) * refine_dofs + 24.0 * tile_dofs
 
 
 def source_sha(kernel: str) -> str:
@@ -420,7 +420,8 @@ def main():
     tile_nx = max(c for c, _ in shapes) * (1 << m) - 1
     elem = 8 if opts.precision == 0 else 4
     rmode = ring_mode(nt, tile_nx, opts.nu, elem, lds_limit)
-    coef = 32 if prob.coef_kind == 3 else 0
+    # the tensor kind streams its three stiffness planes (FP64, or FP32 in inner solves)
+    coef = (24 if opts.precision == 0 else 12) if prob.coef_kind == 3 else 0
     if opts.precision == 0:
         kernel = "k_local_pcg64"
         per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode, coef=coef) / S0
@@ -430,7 +431,8 @@ def main():
         per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode,
                                               coef=coef) / S0
         bytes_launch = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
-                                   st["n_tile_dofs"], mode=rmode, coef=coef)
+                                   st["n_tile_dofs"], mode=rmode, coef=coef,
+                                   coef64=24 if prob.coef_kind == 3 else 0)
     achieved = bytes_launch / (pcg_ms * 1e-3) / 1e9
     traffic = measured_traffic(kernel, prob.name)
 

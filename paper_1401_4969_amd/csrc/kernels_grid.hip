@@ -310,9 +310,10 @@ __global__ __launch_bounds__(NTG) void k_coarsen_kappa(const double* lo_f, const
 // with legs h along x and y, A and phi constant, a(phi_a, phi_b) = g_a . A g_b / 2 with
 // g the gradients scaled by h, and b(phi_a, phi_b) = phi h^2 (1 + delta_ab) / 24.  Input:
 // coef[c][t][J][I] (c: a11, a12, a22, phi; t: 0 below the SW-NE diagonal, 1 above).
-// Output: the 8 planes described in ProbDev::st7.  h2 = h^2 on this level.
-__global__ __launch_bounds__(NTG) void k_tensor_fine(const double* coef, double* st, int N,
-                                                     double h2) {
+// Output: the 7 planes described in ProbDev::st7 and the FP32 copy of the stiffness
+// planes (stf).  h2 = h^2 on this level.
+__global__ __launch_bounds__(NTG) void k_tensor_fine(const double* coef, double* st, float* stf,
+                                                     int N, double h2) {
   const int n1 = N + 1;
   const int64_t pl = (int64_t)n1 * n1, cells = (int64_t)N * N;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
@@ -348,18 +349,25 @@ __global__ __launch_bounds__(NTG) void k_tensor_fine(const double* coef, double*
       }
     }
   }
-  st[idx] = kv[0];
-  for (int o = 1; o < 4; ++o) st[o * pl + idx] = -kv[o];  // stored as weights -K(i, j)
-  for (int o = 0; o < 4; ++o) st[(4 + o) * pl + idx] = mv[o] * h2;
+  // the diagonal kv[0] equals the sum of the weights (zero row sums) and is not stored
+  for (int o = 1; o < 4; ++o) {
+    st[(o - 1) * pl + idx] = -kv[o];  // stored as weights -K(i, j)
+    stf[(o - 1) * pl + idx] = (float)(-kv[o]);
+  }
+  for (int o = 0; o < 4; ++o) st[(3 + o) * pl + idx] = mv[o] * h2;
 }
 
 // Coefficient kind 3 on a coarser level: the Galerkin product P^T A P of the seven-point
 // stiffness and mass one level finer (exact integration on the nested spaces).  The
 // coarse basis function of node I is 1 at fine node 2I and 1/2 at its six neighbours
 // 2I +- (1,0), +-(0,1), +-(1,1); A_c(I, J) = sum over those fine nodes f of I and g of J
-// of P(f,I) A_f(f,g) P(g,J).  Fine nodes off the grid are skipped: they occur only for
-// coarse nodes on the boundary of the box, whose entries multiply zero values.
-__global__ __launch_bounds__(NTG) void k_galerkin7(const double* fine, double* coarse, int Nc) {
+// of P(f,I) A_f(f,g) P(g,J).  Fine nodes off the grid are skipped: the hat functions of
+// boundary nodes are cut at the boundary of the box, where no fine node lies beyond it
+// (weights towards nodes off the grid are zero on every level).  The stiffness diagonal of
+// a fine node is the sum of its weights to the neighbours on the grid (zero row sums
+// hold for the cut hats of boundary nodes too).
+__global__ __launch_bounds__(NTG) void k_galerkin7(const double* fine, double* coarse,
+                                                   float* coarsef, int Nc) {
   const int nc1 = Nc + 1, Nf = 2 * Nc, nf1 = Nf + 1;
   const int64_t plc = (int64_t)nc1 * nc1, plf = (int64_t)nf1 * nf1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
@@ -368,20 +376,33 @@ __global__ __launch_bounds__(NTG) void k_galerkin7(const double* fine, double* c
   const int ox[7] = {0, 1, -1, 0, 0, 1, -1}, oy[7] = {0, 0, 0, 1, -1, 1, -1};
   const double ow[7] = {1.0, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
   const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
-  // matrix entry A_f(f, f + (ex, ey)) of operator `op` (0 stiffness, 1 mass) on the fine grid
+  // matrix entry A_f(f, f + (ex, ey)) of operator `op` (0 stiffness, 1 mass) on the fine
+  // grid; both nodes on the grid.  Stiffness planes: weights -K(i, i+E), -K(i, i+N),
+  // -K(i, i+NE); mass planes: M(i,i), M(i,i+E), M(i,i+N), M(i,i+NE).
   auto entry = [&](int op, int fx, int fy, int ex, int ey) -> double {
-    const double* pln = fine + (int64_t)(4 * op) * plf;
-    const double sg = op == 0 ? -1.0 : 1.0;  // stiffness planes hold -K off the diagonal
-    if (ex == 0 && ey == 0) return pln[(int64_t)fy * nf1 + fx];
+    const int64_t f = (int64_t)fy * nf1 + fx;
+    if (op == 0 && ex == 0 && ey == 0) {
+      const double* K = fine;
+      double d = K[f] + K[plf + f] + K[2 * plf + f];
+      if (fx > 0) d += K[f - 1];
+      if (fy > 0) d += K[plf + f - nf1];
+      if (fx > 0 && fy > 0) d += K[2 * plf + f - nf1 - 1];
+      return d;
+    }
+    const double sg = op == 0 ? -1.0 : 1.0;
     int k = 0;
-    if (ex == 1 && ey == 0) k = 1;
+    int64_t at = f;
+    if (ex == 0 && ey == 0) k = 0;
+    else if (ex == 1 && ey == 0) k = 1;
     else if (ex == 0 && ey == 1) k = 2;
     else if (ex == 1 && ey == 1) k = 3;
-    else if (ex == -1 && ey == 0) { k = 1; fx -= 1; }
-    else if (ex == 0 && ey == -1) { k = 2; fy -= 1; }
-    else if (ex == -1 && ey == -1) { k = 3; fx -= 1; fy -= 1; }
+    else if (ex == -1 && ey == 0) { k = 1; at = f - 1; }
+    else if (ex == 0 && ey == -1) { k = 2; at = f - nf1; }
+    else if (ex == -1 && ey == -1) { k = 3; at = f - nf1 - 1; }
     else return 0.0;
-    return sg * pln[k * plf + (int64_t)fy * nf1 + fx];
+    // stiffness: plane k-1 (k >= 1 here); mass: plane 3+k
+    const int64_t plane = op == 0 ? k - 1 : 3 + k;
+    return sg * fine[plane * plf + at];
   };
   for (int op = 0; op < 2; ++op) {
     for (int o = 0; o < 4; ++o) {
@@ -397,8 +418,13 @@ __global__ __launch_bounds__(NTG) void k_galerkin7(const double* fine, double* c
           acc += ow[a] * ow[b] * entry(op, fx, fy, ex, ey);
         }
       }
-      const double v = (op == 0 && o > 0) ? -acc : acc;
-      coarse[(int64_t)(4 * op + o) * plc + idx] = v;
+      if (op == 0) {
+        if (o == 0) continue;  // the diagonal is not stored
+        coarse[(int64_t)(o - 1) * plc + idx] = -acc;
+        coarsef[(int64_t)(o - 1) * plc + idx] = (float)(-acc);
+      } else {
+        coarse[(int64_t)(3 + o) * plc + idx] = acc;
+      }
     }
   }
 }
@@ -651,15 +677,17 @@ hipError_t launch_coarsen_kappa(const double* lo_f, const double* up_f, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_tensor_fine(const double* coef, double* st, int N, double h2, hipStream_t s) {
+hipError_t launch_tensor_fine(const double* coef, double* st, float* stf, int N, double h2,
+                              hipStream_t s) {
   hipLaunchKernelGGL(k_tensor_fine, dim3(nblocks((int64_t)(N + 1) * (N + 1))), dim3(NTG), 0, s,
-                     coef, st, N, h2);
+                     coef, st, stf, N, h2);
   return hipGetLastError();
 }
 
-hipError_t launch_galerkin7(const double* fine, double* coarse, int Nc, hipStream_t s) {
+hipError_t launch_galerkin7(const double* fine, double* coarse, float* coarsef, int Nc,
+                            hipStream_t s) {
   hipLaunchKernelGGL(k_galerkin7, dim3(nblocks((int64_t)(Nc + 1) * (Nc + 1))), dim3(NTG), 0, s,
-                     fine, coarse, Nc);
+                     fine, coarse, coarsef, Nc);
   return hipGetLastError();
 }
 

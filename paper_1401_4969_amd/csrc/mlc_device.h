@@ -27,10 +27,12 @@ struct ProbDev {
   const double* kH;           // coef kinds 0/1: n_c*n_c per coarse cell
   const double* kLR[MLC_MAX_LEVELS + 1];  // coef kind 2: per level, N_l*N_l lower-triangle kappa
   const double* kUL[MLC_MAX_LEVELS + 1];  //                            upper-triangle kappa
-  // coef kind 3: per level, 8 planes of (N_l+1)^2 values: the stiffness diagonal and the
-  // weights -K(i, i+E), -K(i, i+N), -K(i, i+NE), then the mass M(i,i), M(i,i+E),
-  // M(i,i+N), M(i,i+NE)
+  // coef kind 3: per level, 7 planes of (N_l+1)^2 values: the stiffness weights
+  // -K(i, i+E), -K(i, i+N), -K(i, i+NE), then the mass M(i,i), M(i,i+E), M(i,i+N),
+  // M(i,i+NE).  The stiffness diagonal is the sum of the six weights of a node (every row
+  // of the Galerkin stiffness sums to zero: a(phi_i, 1) = 0), so it is not stored.
   const double* st7[MLC_MAX_LEVELS + 1];
+  const float* st7f[MLC_MAX_LEVELS + 1];  // the three stiffness planes in FP32 (mixed solver)
   const int32_t* bx;          // sub_x+1 block boundaries in coarse cells
   const int32_t* by;          // sub_y+1
   int32_t sub_item_off;       // offset of this problem's (sub_x*sub_y)*q block in a step's
@@ -81,31 +83,43 @@ __device__ __forceinline__ bool is_dof(int domain, int N, int gx, int gy) {
 
 // Edge weights around node (gx, gy) on a level with N cells, level index l (coarse = 0):
 // minus the stiffness couplings to the four leg neighbours, and with coefficient kind 3
-// also to the NE and SW neighbours plus the diagonal d (for kinds 0-2 the diagonal is
-// e + w + n + s and ne, sw, d are not set).
+// also to the NE and SW neighbours (for kinds 0-2 ne and sw are not set).  The diagonal
+// is the sum of the weights.
 struct Weights {
-  double e, w, n, s, ne, sw, d;
+  double e, w, n, s, ne, sw;
 };
 
 // Coefficient arrays are reached through pointers held in ProbDev; the cast to the
 // global address space lets the compiler emit global (not flat) loads for them.
 typedef __attribute__((address_space(1))) const double gconst_double;
 
-template <int KIND>
+typedef __attribute__((address_space(1))) const float gconst_float;
+
+// T selects the stored precision of the kind-3 stiffness (FP32 planes for float solves).
+template <int KIND, typename T = double>
 __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, int gx, int gy) {
   Weights W;
   if constexpr (KIND == 3) {
-    const gconst_double* st = (const gconst_double*)P.st7[l];
     const int n1 = N + 1;
     const int64_t pl = (int64_t)n1 * n1;
     const int64_t c = (int64_t)gy * n1 + gx;
-    W.d = st[c];
-    W.e = st[pl + c];
-    W.w = st[pl + c - 1];
-    W.n = st[2 * pl + c];
-    W.s = st[2 * pl + c - n1];
-    W.ne = st[3 * pl + c];
-    W.sw = st[3 * pl + c - n1 - 1];
+    if constexpr (sizeof(T) == 4) {
+      const gconst_float* st = (const gconst_float*)P.st7f[l];
+      W.e = st[c];
+      W.w = st[c - 1];
+      W.n = st[pl + c];
+      W.s = st[pl + c - n1];
+      W.ne = st[2 * pl + c];
+      W.sw = st[2 * pl + c - n1 - 1];
+    } else {
+      const gconst_double* st = (const gconst_double*)P.st7[l];
+      W.e = st[c];
+      W.w = st[c - 1];
+      W.n = st[pl + c];
+      W.s = st[pl + c - n1];
+      W.ne = st[2 * pl + c];
+      W.sw = st[2 * pl + c - n1 - 1];
+    }
   } else if (KIND == 0) {
     W.e = W.w = W.n = W.s = 1.0;
   } else if (KIND == 1) {
@@ -139,7 +153,7 @@ __device__ __forceinline__ Weights edge_weights(const ProbDev& P, int l, int N, 
 template <int KIND>
 __device__ __forceinline__ double diag_of(const Weights& W) {
   if constexpr (KIND == 3)
-    return W.d;
+    return W.e + W.w + W.n + W.s + W.ne + W.sw;
   else
     return W.e + W.w + W.n + W.s;
 }
@@ -150,8 +164,9 @@ template <int KIND, typename T>
 __device__ __forceinline__ T apply_k(const Weights& W, T c, T e, T w, T n, T s, T ne, T sw, T& d) {
   const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
   if constexpr (KIND == 3) {
-    d = T(W.d);
-    return d * c - we * e - ww * w - wn * n - ws * s - T(W.ne) * ne - T(W.sw) * sw;
+    const T wne = T(W.ne), wsw = T(W.sw);
+    d = we + ww + wn + ws + wne + wsw;
+    return d * c - we * e - ww * w - wn * n - ws * s - wne * ne - wsw * sw;
   } else {
     d = we + ww + wn + ws;
     return d * c - we * e - ww * w - wn * n - ws * s;
@@ -171,7 +186,7 @@ __device__ __forceinline__ MassW mass_weights(const ProbDev& P, int l, int N, in
   if constexpr (KIND == 3) {
     const int n1 = N + 1;
     const int64_t pl = (int64_t)n1 * n1;
-    const gconst_double* m = (const gconst_double*)P.st7[l] + 4 * pl;
+    const gconst_double* m = (const gconst_double*)P.st7[l] + 3 * pl;
     const int64_t i = (int64_t)gy * n1 + gx;
     M.d = m[i];
     M.e = m[pl + i];

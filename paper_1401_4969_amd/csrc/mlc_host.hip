@@ -190,7 +190,8 @@ struct ProbLayout {
   size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
       E, info, fg, partials, rr_x, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
-  size_t st7[MLC_MAX_LEVELS + 1], coef3;  // coef kind 3: stencil planes, per-triangle input
+  size_t st7[MLC_MAX_LEVELS + 1], st7f[MLC_MAX_LEVELS + 1], coef3;  // coef kind 3: stencil
+                                                                     // planes, input
   int64_t rchain_off[MLC_MAX_LEVELS + 1];
   int64_t inv_base;      // doubles, into the batch inverse region
   int32_t sub_item_off;  // into every step's subdomain -> item table
@@ -276,7 +277,7 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.coarse_nodes = take((size_t)g.nH * 4);
     L.coarse_index = take(ncs * 4);
     L.kH = take((size_t)g.nc * g.nc * 8);
-    for (int l = 0; l <= MLC_MAX_LEVELS; ++l) L.kLR[l] = L.kUL[l] = L.st7[l] = 0;
+    for (int l = 0; l <= MLC_MAX_LEVELS; ++l) L.kLR[l] = L.kUL[l] = L.st7[l] = L.st7f[l] = 0;
     L.coef3 = 0;
     if (g.kind == 2)
       for (int l = 0; l <= g.L; ++l) {
@@ -286,7 +287,10 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
       }
     if (g.kind == 3) {
       L.coef3 = take((size_t)(8 * g.N(g.L) * g.N(g.L)) * 8);
-      for (int l = 0; l <= g.L; ++l) L.st7[l] = take((size_t)(8 * g.nodes(l)) * 8);
+      for (int l = 0; l <= g.L; ++l) {
+        L.st7[l] = take((size_t)(7 * g.nodes(l)) * 8);
+        L.st7f[l] = take((size_t)(3 * g.nodes(l)) * 4);
+      }
     }
     L.u[0] = take(q * nnL * 8);
     L.u[1] = take(q * nnL * 8);
@@ -544,6 +548,7 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
       D.kLR[l] = g.kind == 2 ? (const double*)(w + L.kLR[l]) : nullptr;
       D.kUL[l] = g.kind == 2 ? (const double*)(w + L.kUL[l]) : nullptr;
       D.st7[l] = g.kind == 3 ? (const double*)(w + L.st7[l]) : nullptr;
+      D.st7f[l] = g.kind == 3 ? (const float*)(w + L.st7f[l]) : nullptr;
     }
     D.bx = (const int32_t*)(w + L.bx);
     D.by = (const int32_t*)(w + L.by);
@@ -633,10 +638,10 @@ mlc_status batch_setup(mlc_batch* b) {
     if (g.kind == 3) {  // seven-point stiffness and mass on every level (Galerkin products)
       const double h = g.side / (double)g.N(g.L);
       MLC_HIP(b, launch_tensor_fine((const double*)(w + L.coef3), (double*)(w + L.st7[g.L]),
-                                    (int)g.N(g.L), h * h, st));
+                                    (float*)(w + L.st7f[g.L]), (int)g.N(g.L), h * h, st));
       for (int l = g.L - 1; l >= 0; --l)
         MLC_HIP(b, launch_galerkin7((const double*)(w + L.st7[l + 1]), (double*)(w + L.st7[l]),
-                                    (int)g.N(l), st));
+                                    (float*)(w + L.st7f[l]), (int)g.N(l), st));
     }
     const size_t nH = (size_t)g.nH;
     MLC_HIP(b, hipMemsetAsync(w + L.Kc, 0, nH * nH * 8, st));

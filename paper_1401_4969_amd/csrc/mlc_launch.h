@@ -58,8 +58,10 @@ hipError_t launch_coarsen_kappa(const double* lo_f, const double* up_f, double* 
                                 double* up_c, int Nc, hipStream_t s);
 // Coefficient kind 3: seven-point stiffness and mass planes of the finest level from the
 // per-triangle tensor and weight, and of a coarser level by the Galerkin product.
-hipError_t launch_tensor_fine(const double* coef, double* st, int N, double h2, hipStream_t s);
-hipError_t launch_galerkin7(const double* fine, double* coarse, int Nc, hipStream_t s);
+hipError_t launch_tensor_fine(const double* coef, double* st, float* stf, int N, double h2,
+                              hipStream_t s);
+hipError_t launch_galerkin7(const double* fine, double* coarse, float* coarsef, int Nc,
+                            hipStream_t s);
 hipError_t launch_coarse_matrices(int kind, const ProbDev* probs, int nprob, int max_nH,
                                   hipStream_t s);
 hipError_t launch_init_u0(const ProbDev* probs, int nprob, int dst, int max_nc1sq, hipStream_t s);

@@ -38,7 +38,7 @@ struct LevelDesc {
 template <int KIND, typename T>
 __device__ __forceinline__ T stencil(const ProbDev& P, const LevelDesc& lv, const T* u, int ix,
                                      int iy, unsigned i, T& diag) {
-  const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+  const Weights W = edge_weights<KIND, T>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
   const bool he = ix + 1 < lv.nx, hw = ix > 0, hn = iy + 1 < lv.ny, hs = iy > 0;
   const T c = u[i];
   const T e0 = u[he ? i + 1 : i];
@@ -64,7 +64,7 @@ __device__ void op_first(const ProbDev& P, const LevelDesc& lv, const T* b, T* z
     const unsigned i = (unsigned)(iy * lv.nx + ix);
     T v = T(0);
     if (is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy)) {
-      const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+      const Weights W = edge_weights<KIND, T>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
       v = omega * b[i] / T(diag_of<KIND>(W));
     }
     z[i] = v;
@@ -75,9 +75,9 @@ __device__ void op_first(const ProbDev& P, const LevelDesc& lv, const T* b, T* z
 //   z1 = omega D^-1 b,  z = z1 + omega D^-1 (b - A z1),
 // with z1 formed on the fly at the node and its four neighbours (zero off the tile and
 // on nodes outside the domain, where b is zero and the diagonal need not exist).
-template <int KIND>
+template <int KIND, typename T>
 __device__ __forceinline__ double diag_at(const ProbDev& P, const LevelDesc& lv, int ix, int iy) {
-  const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+  const Weights W = edge_weights<KIND, T>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
   return diag_of<KIND>(W);
 }
 
@@ -88,15 +88,15 @@ __device__ void op_first2(const ProbDev& P, const LevelDesc& lv, const T* b, T* 
     // first-sweep value at tile node (jx, jy) = index j, zero when `in` is false
     auto z1 = [&](bool in, int jx, int jy, unsigned j) -> T {
       const T bj = b[in ? j : i];
-      const T dj = T(diag_at<KIND>(P, lv, in ? jx : ix, in ? jy : iy));
+      const T dj = T(diag_at<KIND, T>(P, lv, in ? jx : ix, in ? jy : iy));
       const bool ok = in && is_dof(P.domain, lv.N, lv.gx0 + jx, lv.gy0 + jy);
       return ok ? omega * bj / dj : T(0);
     };
-    const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
+    const Weights W = edge_weights<KIND, T>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + iy);
     const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
     T d;
     if constexpr (KIND == 3)
-      d = T(W.d);
+      d = we + ww + wn + ws + T(W.ne) + T(W.sw);
     else
       d = we + ww + wn + ws;
     const T bc = b[i];
@@ -194,7 +194,7 @@ __device__ void op_prolong_add(const ProbDev& P, const LevelDesc& lc, const Leve
 template <int KIND, typename T>
 __device__ __forceinline__ T apply_rows(const ProbDev& P, const LevelDesc& lv, const T* rs,
                                         const T* rc, const T* rn, int ix, int y, T& d) {
-  const Weights W = edge_weights<KIND>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + y);
+  const Weights W = edge_weights<KIND, T>(P, lv.l, lv.N, lv.gx0 + ix, lv.gy0 + y);
   const bool he = ix + 1 < lv.nx, hw = ix > 0;
   const T c = rc[ix];
   const T e0 = rc[he ? ix + 1 : ix], w0 = rc[hw ? ix - 1 : ix];
@@ -248,7 +248,7 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
           T v = T(0);
           if (inside) {
             const T bi = b[(unsigned)(ya * nx + ix)];
-            const T d = T(diag_at<KIND>(P, lv, ix, ya));
+            const T d = T(diag_at<KIND, T>(P, lv, ix, ya));
             v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bi / d : T(0);
           }
           dst[ix] = v;
@@ -451,7 +451,7 @@ __device__ void op_pre_fused_pf(const ProbDev& P, const LevelDesc& lv, const Lev
         if (c < nch && ix < nx) {
           T v = T(0);
           if (inA) {
-            const T d = T(diag_at<KIND>(P, lv, ix, ya));
+            const T d = T(diag_at<KIND, T>(P, lv, ix, ya));
             v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bA[c] / d : T(0);
           }
           dst[ix] = v;
@@ -908,7 +908,7 @@ __device__ void pass_xr(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const
       const unsigned i = (unsigned)(iy * nx + ix);
       T q = T(0);
       if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
-        const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+        const Weights W = edge_weights<KIND, T>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
         const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
         const T e = ix + 1 < nx ? cur.e : T(0), wv = ix > 0 ? cur.w : T(0);
         const T n = iy + 1 < ny ? cur.n : T(0), sv = iy > 0 ? cur.s : T(0);
@@ -968,7 +968,7 @@ __device__ void pass_dir(const ProbDev& P, const LevelDesc& l0, const T* Z, cons
 #pragma unroll
       for (int k = 0; k < 5; ++k) v[k] = cur.z[k] + bet * cur.p[k];
       if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
-        const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+        const Weights W = edge_weights<KIND, T>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
         const T we = T(W.e), ww = T(W.w), wn = T(W.n), ws = T(W.s);
         const T e = ix + 1 < nx ? v[1] : T(0), wv = ix > 0 ? v[2] : T(0);
         const T n = iy + 1 < ny ? v[3] : T(0), sv = iy > 0 ? v[4] : T(0);
@@ -1005,7 +1005,7 @@ __device__ void pass_dir_plain(const ProbDev& P, const LevelDesc& l0, const T* Z
       ne = hne ? ne0 : T(0);
       sw = hsw ? sw0 : T(0);
     }
-    const Weights W = edge_weights<KIND>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
+    const Weights W = edge_weights<KIND, T>(P, l0.l, l0.N, l0.gx0 + ix, l0.gy0 + iy);
     T d;
     const T q = apply_k<KIND, T>(W, pc, e, w, n, s, ne, sw, d);
     if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) *acc += (double)pc * (double)q;
