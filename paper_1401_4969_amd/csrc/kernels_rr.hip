@@ -17,21 +17,20 @@
 // the q x q Schur complement.  Cost O(nH q^2) per evaluation instead of the
 // O((nH+q)^3) of a dense eigensolver.
 //
-// Reductions are batched: each wave reduces its partial sums with shuffles and writes
-// them to LDS, and one barrier later every value is summed over the waves in a fixed
-// order (deterministic).  Multisection evaluates G points per round, GS threads per
-// point (GS consecutive lanes reduce with shuffles inside the wave).
+// One workgroup of 1024 (q <= 2) or 512 threads per problem (many waves hide the latency
+// of the short loops).  Reductions are batched: each wave reduces its partial sums across lanes (DPP
+// moves) and writes them to LDS, and one barrier later every value is summed over the
+// waves in a fixed order (deterministic).  Multisection evaluates G points per round, GS
+// consecutive lanes per point (about 32 terms each), reduced by DPP inside the wave; wave k
+// then updates bracket k from all points.  The inverse-iteration vectors live in LDS.
 #include "mlc_launch.h"
 
 namespace {
 
-constexpr int NTR = 256;
-constexpr int NWR = NTR / 64;
-
-__device__ __forceinline__ double group_sum(double x, int gs) {
-  for (int o = gs >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
+// Workgroup size: 1024 threads for q <= 2; 512 above, where the q(q+1)/2 accumulators of
+// a point need more than the 128 registers a 1024-thread workgroup allows.
+template <int Q>
+constexpr int rr_threads() { return Q <= 2 ? 1024 : 512; }
 
 // Wave-reduce x and park it in lds[wave * stride + v]; the caller barriers, then sums.
 __device__ __forceinline__ void park(double x, int v, double* lds, int stride) {
@@ -39,76 +38,89 @@ __device__ __forceinline__ void park(double x, int v, double* lds, int stride) {
   if ((threadIdx.x & 63) == 0) lds[(threadIdx.x >> 6) * stride + v] = x;
 }
 
+template <int NW>
 __device__ __forceinline__ double gather(int v, const double* lds, int stride) {
   double s = 0.0;
 #pragma unroll
-  for (int w = 0; w < NWR; ++w) s += lds[w * stride + v];
+  for (int w = 0; w < NW; ++w) s += lds[w * stride + v];
   return s;
 }
 
-// Number of negative eigenvalues of a symmetric QxQ matrix (LDL^T, Sylvester); an exact
-// zero pivot is nudged.
+// Packed lower triangle of a symmetric QxQ matrix: entry (i, j), j <= i, at tri(i, j).
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Number of negative eigenvalues of a symmetric QxQ matrix given by its packed lower
+// triangle (LDL^T, Sylvester); an exact zero pivot is nudged.  Indices are compile-time
+// constants, so the matrix stays in registers.
 template <int Q>
-__device__ int neg_inertia(double (&S)[Q][Q]) {
+__device__ int neg_inertia(double (&S)[Q * (Q + 1) / 2]) {
   int n = 0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    double d = S[k][k];
+    double d = S[tri(k, k)];
     if (d == 0.0) d = -1e-300;
     if (d < 0.0) ++n;
 #pragma unroll
     for (int i = k + 1; i < Q; ++i) {
-      const double f = S[i][k] / d;
+      const double f = S[tri(i, k)] / d;
 #pragma unroll
-      for (int j = k + 1; j < Q; ++j) S[i][j] -= f * S[k][j];
+      for (int j = k + 1; j <= i; ++j) S[tri(i, j)] -= f * S[tri(j, k)];
     }
   }
   return n;
 }
 
-// Solve A x = b (Gaussian elimination, partial pivoting), x returned in b.
+// Solve A x = b (Gaussian elimination, partial pivoting; A row-major QxQ and b in LDS, one
+// thread), x returned in b.
 template <int Q>
-__device__ void small_solve(double (&A)[Q][Q], double (&b)[Q]) {
-#pragma unroll
+__device__ void small_solve(double* A, double* b) {
   for (int k = 0; k < Q; ++k) {
     int p = k;
     for (int i = k + 1; i < Q; ++i)
-      if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
+      if (fabs(A[i * Q + k]) > fabs(A[p * Q + k])) p = i;
     if (p != k) {
       for (int j = 0; j < Q; ++j) {
-        const double t = A[k][j];
-        A[k][j] = A[p][j];
-        A[p][j] = t;
+        const double t = A[k * Q + j];
+        A[k * Q + j] = A[p * Q + j];
+        A[p * Q + j] = t;
       }
       const double t = b[k];
       b[k] = b[p];
       b[p] = t;
     }
-    double d = A[k][k];
+    double d = A[k * Q + k];
     if (d == 0.0) d = 1e-300;
     for (int i = k + 1; i < Q; ++i) {
-      const double f = A[i][k] / d;
-      for (int j = k; j < Q; ++j) A[i][j] -= f * A[k][j];
+      const double f = A[i * Q + k] / d;
+      for (int j = k; j < Q; ++j) A[i * Q + j] -= f * A[k * Q + j];
       b[i] -= f * b[k];
     }
   }
   for (int k = Q - 1; k >= 0; --k) {
     double s = b[k];
-    for (int j = k + 1; j < Q; ++j) s -= A[k][j] * b[j];
-    double d = A[k][k];
+    for (int j = k + 1; j < Q; ++j) s -= A[k * Q + j] * b[j];
+    double d = A[k * Q + k];
     if (d == 0.0) d = 1e-300;
     b[k] = s / d;
   }
 }
 
+// Dynamic LDS of k_rr_solve in doubles: Lambda, Z, f, g and the q eigenvectors.
+__host__ __device__ inline size_t rr_dyn_doubles(int nH, int q) {
+  return (size_t)nH * (1 + 3 * q) + (size_t)q * (nH + q);
+}
+
 template <int Q>
-__global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, int dst) {
+__global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* probs, int m, int dst) {
+  constexpr int NTR = rr_threads<Q>();
+  constexpr int NWR = NTR / 64;
   constexpr int NV = 3 * Q * Q + Q + 1;
   __shared__ double park_lds[NWR * NV];
   __shared__ double vals[NV];
   __shared__ double sAlpha[Q * Q], sBeta[Q * Q];
   __shared__ double sL[Q * Q], sW[Q * Q];
   __shared__ double sMu[Q], sT[Q], sSol[Q];
+  __shared__ double sBw[Q * Q], sAw[Q * Q], sX[Q * Q], sWm[Q * Q];  // one-thread work arrays
   extern __shared__ double dyn[];
   const ProbDev& P = probs[blockIdx.x];
   if (m > P.L) return;
@@ -118,6 +130,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
   double* Z = dyn + nH;              // nH * Q
   double* f = dyn + nH * (1 + Q);    // Q * nH
   double* g = f + Q * nH;            // Q * nH
+  double* X = g + Q * nH;            // Q * (nH + Q): eigenvectors of the reduced problem
 
   // 1. finish the fine-grid reductions (alpha, beta) in a fixed order; stage the
   //    coarse quantities in LDS
@@ -145,7 +158,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
     for (int e = tid; e < 2 * Q * nH; e += NTR) f[e] = P.fg[e];
     __syncthreads();
     for (int v = tid; v < 2 * Q * Q; v += NTR) {
-      const double s = gather(v, park_lds, NV);
+      const double s = gather<NWR>(v, park_lds, NV);
       if (v < Q * Q)
         sAlpha[v] = s;
       else
@@ -169,51 +182,50 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
       park(c, 2 * Q * Q + i * Q + j, park_lds, NV);
     }
   __syncthreads();
-  for (int v = tid; v < 3 * Q * Q; v += NTR) vals[v] = gather(v, park_lds, NV);
+  for (int v = tid; v < 3 * Q * Q; v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
   __syncthreads();
   // 3. Bw = L L^T, W = L^-1 Aw L^-T (one thread; Q <= 8)
-  if (tid == 0) {
+  if (tid == 0) {  // LDS work arrays: Bw, Aw, L (sL), X = L^-1 Aw, Wm = X L^-T
     const double* GG = vals;
     const double* GF = vals + Q * Q;
     const double* GLG = vals + 2 * Q * Q;
-    double Bw[Q][Q], Aw[Q][Q], L[Q][Q];
+    double* Bw = sBw;
+    double* Aw = sAw;
+    double* L = sL;
     for (int i = 0; i < Q; ++i)
       for (int j = 0; j < Q; ++j) {
-        Bw[i][j] = 0.5 * (sBeta[i * Q + j] + sBeta[j * Q + i]) - 0.5 * (GG[i * Q + j] + GG[j * Q + i]);
-        Aw[i][j] = 0.5 * (sAlpha[i * Q + j] + sAlpha[j * Q + i]) - GF[i * Q + j] - GF[j * Q + i] +
-                   0.5 * (GLG[i * Q + j] + GLG[j * Q + i]);
-        L[i][j] = 0.0;
+        Bw[i * Q + j] = 0.5 * (sBeta[i * Q + j] + sBeta[j * Q + i]) - 0.5 * (GG[i * Q + j] + GG[j * Q + i]);
+        Aw[i * Q + j] = 0.5 * (sAlpha[i * Q + j] + sAlpha[j * Q + i]) - GF[i * Q + j] - GF[j * Q + i] +
+                        0.5 * (GLG[i * Q + j] + GLG[j * Q + i]);
+        L[i * Q + j] = 0.0;
       }
     for (int j = 0; j < Q; ++j) {
-      double d = Bw[j][j];
-      for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+      double d = Bw[j * Q + j];
+      for (int k = 0; k < j; ++k) d -= L[j * Q + k] * L[j * Q + k];
       d = d > 1e-300 ? sqrt(d) : 1e-150;
-      L[j][j] = d;
+      L[j * Q + j] = d;
       for (int i = j + 1; i < Q; ++i) {
-        double s = Bw[i][j];
-        for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-        L[i][j] = s / d;
+        double s = Bw[i * Q + j];
+        for (int k = 0; k < j; ++k) s -= L[i * Q + k] * L[j * Q + k];
+        L[i * Q + j] = s / d;
       }
     }
-    double X[Q][Q];  // X = L^-1 Aw
+    double* X = sX;
     for (int c = 0; c < Q; ++c)
       for (int i = 0; i < Q; ++i) {
-        double s = Aw[i][c];
-        for (int k = 0; k < i; ++k) s -= L[i][k] * X[k][c];
-        X[i][c] = s / L[i][i];
+        double s = Aw[i * Q + c];
+        for (int k = 0; k < i; ++k) s -= L[i * Q + k] * X[k * Q + c];
+        X[i * Q + c] = s / L[i * Q + i];
       }
-    double Wm[Q][Q];  // Wm = X L^-T
+    double* Wm = sWm;
     for (int rI = 0; rI < Q; ++rI)
       for (int i = 0; i < Q; ++i) {
-        double s = X[rI][i];
-        for (int k = 0; k < i; ++k) s -= L[i][k] * Wm[rI][k];
-        Wm[rI][i] = s / L[i][i];
+        double s = X[rI * Q + i];
+        for (int k = 0; k < i; ++k) s -= L[i * Q + k] * Wm[rI * Q + k];
+        Wm[rI * Q + i] = s / L[i * Q + i];
       }
     for (int i = 0; i < Q; ++i)
-      for (int j = 0; j < Q; ++j) {
-        sW[i * Q + j] = 0.5 * (Wm[i][j] + Wm[j][i]);
-        sL[i * Q + j] = L[i][j];
-      }
+      for (int j = 0; j < Q; ++j) sW[i * Q + j] = 0.5 * (Wm[i * Q + j] + Wm[j * Q + i]);
   }
   __syncthreads();
   // 4. z_r = L^-1 (f_r - Lambda_r g_r)
@@ -250,7 +262,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
     lo = park_lds[Q];
     for (int w = 1; w < NWR; ++w) lo = fmin(lo, park_lds[w * NV + Q]);
     for (int i = 0; i < Q; ++i) {
-      double w = sW[i * Q + i] - gather(i, park_lds, NV);
+      double w = sW[i * Q + i] - gather<NWR>(i, park_lds, NV);
       for (int j = 0; j < Q; ++j)
         if (j != i) w -= fabs(sW[i * Q + j]);
       lo = fmin(lo, w);
@@ -259,32 +271,34 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
   }
   lo -= 1e-12 * fabs(lo) + 1e-300;
   // 6. multisection for all q eigenvalues at once: each round spreads G points over the
-  //    q brackets (G/q per bracket, GS threads per point); every point's inertia count c
-  //    tightens every bracket: mu is an upper bound of eigenvalue k when c >= k + 1 and a
-  //    lower bound when c <= k.  Upper bounds start from interlacing (mu_k <= Lambda_k).
-  int GS = 1;
-  while (GS < 64 && GS * 32 < nH && NTR / (2 * GS) >= Q) GS <<= 1;
-  const int G = NTR / GS;  // >= Q
-  const int GQ = G / Q;    // points per bracket, >= 1
+  //    q brackets (G/q per bracket, GS lanes per point; the work of a round grows with G
+  //    while the rounds fall only with log G, so G is kept small: 16 points,
+  //    at least 2 per bracket); every
+  //    point's inertia count c tightens every bracket: mu is an upper bound of eigenvalue k
+  //    when c >= k + 1 and a lower bound when c <= k.  Upper bounds start from interlacing
+  //    (mu_k <= Lambda_k).
+  int GS = 64;
+  while (GS > 1 && NTR / GS < 16) GS >>= 1;
+  const int G = NTR / GS;  // 16 >= 2 Q
+  const int GQ = G / Q;    // points per bracket, >= 2
   const int pnt = tid / GS, gl = tid % GS;
+  const int wv = tid >> 6, lane = tid & 63;
   __shared__ double sA[Q], sB[Q], ptMu[NTR];
   __shared__ int ptCnt[NTR];
-  __shared__ int sDone;
   if (tid < Q) {
     sA[tid] = lo;
     sB[tid] = Lam[tid] + 1e-12 * fabs(Lam[tid]) + 1e-300;
   }
   __syncthreads();
+  const double inf = __builtin_inf();
   for (int round = 0; round < 200; ++round) {
     const int kb = pnt / GQ, j = pnt % GQ;  // this point's bracket and position
     const bool active = kb < Q;
     const double a = sA[active ? kb : 0], bnd = sB[active ? kb : 0];
     const double mu = a + (bnd - a) * (double)(j + 1) / (double)(GQ + 1);
-    double S[Q][Q];
+    double S[Q * (Q + 1) / 2];  // packed lower triangle
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-#pragma unroll
-      for (int jj = 0; jj < Q; ++jj) S[i][jj] = 0.0;
+    for (int e = 0; e < Q * (Q + 1) / 2; ++e) S[e] = 0.0;
     double nless = 0.0;
     for (int r = gl; r < nH; r += GS) {
       double d = Lam[r] - mu;
@@ -297,47 +311,44 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
 #pragma unroll
       for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int jj = 0; jj <= i; ++jj) S[i][jj] += z[i] * z[jj] * inv;
+        for (int jj = 0; jj <= i; ++jj) S[tri(i, jj)] += z[i] * z[jj] * inv;
     }
-    nless = group_sum(nless, GS);
+    nless = group_sum_last(nless, GS);
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-#pragma unroll
-      for (int jj = 0; jj <= i; ++jj) S[i][jj] = group_sum(S[i][jj], GS);
-    if (gl == 0) {
+    for (int e = 0; e < Q * (Q + 1) / 2; ++e) S[e] = group_sum_last(S[e], GS);
+    if (gl == GS - 1) {  // the group's sums are complete in its last lane
 #pragma unroll
       for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int jj = 0; jj <= i; ++jj) {
-          S[i][jj] = sW[i * Q + jj] - S[i][jj] - (i == jj ? mu : 0.0);
-          S[jj][i] = S[i][jj];
-        }
+        for (int jj = 0; jj <= i; ++jj)
+          S[tri(i, jj)] = sW[i * Q + jj] - S[tri(i, jj)] - (i == jj ? mu : 0.0);
       ptMu[pnt] = mu;
       ptCnt[pnt] = active ? (int)nless + neg_inertia<Q>(S) : -1;
     }
     __syncthreads();
-    if (tid < Q) {
-      const int k = tid;
-      double a2 = sA[k], b2 = sB[k];
-      for (int p2 = 0; p2 < G; ++p2) {
+    if (wv < Q) {  // wave k tightens bracket k from every point
+      double lo2 = -inf, hi2 = inf;
+      for (int p2 = lane; p2 < G; p2 += 64) {
         const int c = ptCnt[p2];
-        if (c < 0) continue;
         const double m2 = ptMu[p2];
-        if (c >= k + 1) b2 = fmin(b2, m2);
-        else a2 = fmax(a2, m2);
+        if (c >= wv + 1)
+          hi2 = fmin(hi2, m2);
+        else if (c >= 0)
+          lo2 = fmax(lo2, m2);
       }
-      sA[k] = a2;
-      sB[k] = b2;
+      lo2 = group_reduce_last(lo2, 64, -inf, [](double x, double y) { return fmax(x, y); });
+      hi2 = group_reduce_last(hi2, 64, inf, [](double x, double y) { return fmin(x, y); });
+      if (lane == 63) {
+        sA[wv] = fmax(sA[wv], lo2);
+        sB[wv] = fmin(sB[wv], hi2);
+      }
     }
     __syncthreads();
-    if (tid == 0) {
-      int done = 1;
-      for (int k = 0; k < Q; ++k)
-        if (sB[k] - sA[k] > 4.0 * 2.220446049250313e-16 * fmax(fabs(sA[k]), fabs(sB[k]))) done = 0;
-      sDone = done;
-    }
-    __syncthreads();
-    if (sDone) break;
+    bool done = true;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (sB[k] - sA[k] > 4.0 * 2.220446049250313e-16 * fmax(fabs(sA[k]), fabs(sB[k]))) done = false;
+    if (done) break;
   }
   if (tid < Q) sMu[tid] = 0.5 * (sA[tid] + sB[tid]);
   __syncthreads();
@@ -345,43 +356,48 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
   //    Gram-Schmidt against the previous ones
   const int n = nH + Q;
   for (int k = 0; k < Q; ++k) {
-    double* x = P.rr_x + (int64_t)k * n;
+    double* x = X + k * n;
     const double mu = sMu[k];
     const double sigma = mu - fmax(8.0 * 2.220446049250313e-16 * fabs(mu), 1e-300);
     for (int r = tid; r < n; r += NTR) x[r] = 1.0 + 0.01 * (double)((r * 7 + k * 13) % 17);
     __syncthreads();
     for (int iter = 0; iter < 2; ++iter) {
-      double Sp[Q][Q], rp[Q];
-      for (int i = 0; i < Q; ++i) {
-        rp[i] = 0.0;
-        for (int j = 0; j < Q; ++j) Sp[i][j] = 0.0;
-      }
+      double Sp[Q * (Q + 1) / 2], rp[Q];  // packed lower triangle
+#pragma unroll
+      for (int i = 0; i < Q; ++i) rp[i] = 0.0;
+#pragma unroll
+      for (int e = 0; e < Q * (Q + 1) / 2; ++e) Sp[e] = 0.0;
       for (int r = tid; r < nH; r += NTR) {
         double d = Lam[r] - sigma;
         if (d == 0.0) d = 1e-300;
         const double inv = 1.0 / d;
         const double xr = x[r];
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
           rp[i] += Z[r * Q + i] * xr * inv;
-          for (int j = 0; j <= i; ++j) Sp[i][j] += Z[r * Q + i] * Z[r * Q + j] * inv;
+#pragma unroll
+          for (int j = 0; j <= i; ++j) Sp[tri(i, j)] += Z[r * Q + i] * Z[r * Q + j] * inv;
         }
       }
+#pragma unroll
       for (int i = 0; i < Q; ++i) {
         park(rp[i], i, park_lds, NV);
-        for (int j = 0; j <= i; ++j) park(Sp[i][j], Q + i * Q + j, park_lds, NV);
+#pragma unroll
+        for (int j = 0; j <= i; ++j) park(Sp[tri(i, j)], Q + i * Q + j, park_lds, NV);
       }
       __syncthreads();
-      if (tid == 0) {
-        double A[Q][Q], bb[Q];
+      for (int v = tid; v < Q + Q * Q; v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
+      __syncthreads();
+      if (tid == 0) {  // the Schur system in LDS (sAw as its matrix, sSol as b then x)
+        double* A = sAw;
         for (int i = 0; i < Q; ++i) {
-          bb[i] = x[nH + i] - gather(i, park_lds, NV);
+          sSol[i] = x[nH + i] - vals[i];
           for (int j = 0; j <= i; ++j) {
-            A[i][j] = sW[i * Q + j] - (i == j ? sigma : 0.0) - gather(Q + i * Q + j, park_lds, NV);
-            A[j][i] = A[i][j];
+            A[i * Q + j] = sW[i * Q + j] - (i == j ? sigma : 0.0) - vals[Q + i * Q + j];
+            A[j * Q + i] = A[i * Q + j];
           }
         }
-        small_solve<Q>(A, bb);
-        for (int i = 0; i < Q; ++i) sSol[i] = bb[i];
+        small_solve<Q>(A, sSol);
       }
       __syncthreads();
       for (int r = tid; r < nH; r += NTR) {
@@ -395,15 +411,17 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
       __syncthreads();
       if (k > 0) {
         for (int kp = 0; kp < k; ++kp) {
-          const double* xp = P.rr_x + (int64_t)kp * n;
+          const double* xp = X + kp * n;
           double d = 0.0;
           for (int r = tid; r < n; r += NTR) d += x[r] * xp[r];
           park(d, kp, park_lds, NV);
         }
         __syncthreads();
+        for (int v = tid; v < k; v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
+        __syncthreads();
         for (int r = tid; r < n; r += NTR) {
           double s = x[r];
-          for (int kp = 0; kp < k; ++kp) s -= gather(kp, park_lds, NV) * P.rr_x[(int64_t)kp * n + r];
+          for (int kp = 0; kp < k; ++kp) s -= vals[kp] * X[kp * n + r];
           x[r] = s;
         }
         __syncthreads();
@@ -412,7 +430,7 @@ __global__ __launch_bounds__(NTR) void k_rr_solve(const ProbDev* probs, int m, i
       for (int r = tid; r < n; r += NTR) nr += x[r] * x[r];
       park(nr, 0, park_lds, NV);
       __syncthreads();
-      const double inv = 1.0 / sqrt(gather(0, park_lds, NV));
+      const double inv = 1.0 / sqrt(gather<NWR>(0, park_lds, NV));
       for (int r = tid; r < n; r += NTR) x[r] *= inv;
       __syncthreads();
     }
@@ -454,11 +472,11 @@ __global__ __launch_bounds__(256) void k_transpose(const ProbDev* probs) {
 
 hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, int max_nH, int dst,
                            hipStream_t s) {
-  const size_t shm = (size_t)max_nH * (1 + 3 * max_q) * sizeof(double);
+  const size_t shm = rr_dyn_doubles(max_nH, max_q) * sizeof(double);
   switch (max_q) {
 #define MLC_RR_CASE(QQ)                                                                       \
   case QQ:                                                                                    \
-    hipLaunchKernelGGL(k_rr_solve<QQ>, dim3(nprob), dim3(NTR), shm, s, probs, m, dst); \
+    hipLaunchKernelGGL(k_rr_solve<QQ>, dim3(nprob), dim3(rr_threads<QQ>()), shm, s, probs, m, dst); \
     break;
     MLC_RR_CASE(1)
     MLC_RR_CASE(2)

@@ -54,7 +54,6 @@ struct ProbDev {
   double* VT;                 // nH*nH row-major V^T (aliases Mc after setup)
   double* fg;                 // 2*q*nH: f = V^T a, g = V^T b
   double* partials;           // nparts*(2q^2+q)
-  double* rr_x;               // q*(nH+q) eigenvectors of the reduced problem
   double* rr_y;               // q*nH coarse eigen-coordinates of the new eigenvectors
   double* rr_t;               // q*q coefficients of u~
   double* rr_ab;              // alpha = u~^T K u~, beta = u~^T M u~ (q = 1: 2 values)
@@ -245,11 +244,51 @@ __device__ __forceinline__ double uniform_f64(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// One cross-lane move of a double by DPP (a register read from another lane of the same
+// row of 16 lanes, or a row broadcast), applied to both 32-bit halves; lanes without a
+// source lane, or in rows not selected by ROW_MASK, receive `old`.  Needs every lane of
+// the wave active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v, double old) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long o = (unsigned long long)__double_as_longlong(old);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b,
+                                                            CTRL, ROW_MASK, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(
+      (int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Reduction over aligned groups of gs lanes (gs a power of two, 1..64) with the operation
+// op and its identity id; the result is complete in the last lane of each group.  Steps:
+// neighbour pairs and quads (quad permutations), shifts by 4 and 8 inside rows of 16, then
+// row 0 into row 1 and row 2 into row 3 (broadcast of lane 15), rows 0-1 into rows 2-3
+// (broadcast of lane 31).
+template <typename Op>
+__device__ __forceinline__ double group_reduce_last(double v, int gs, double id, Op op) {
+  if (gs > 1) v = op(v, dpp_f64<0xb1, 0xf>(v, id));   // quad_perm [1,0,3,2]
+  if (gs > 2) v = op(v, dpp_f64<0x4e, 0xf>(v, id));   // quad_perm [2,3,0,1]
+  if (gs > 4) v = op(v, dpp_f64<0x114, 0xf>(v, id));  // row_shr 4
+  if (gs > 8) v = op(v, dpp_f64<0x118, 0xf>(v, id));  // row_shr 8
+  if (gs > 16) v = op(v, dpp_f64<0x142, 0xa>(v, id)); // row_bcast 15 into rows 1 and 3
+  if (gs > 32) v = op(v, dpp_f64<0x143, 0xc>(v, id)); // row_bcast 31 into rows 2 and 3
   return v;
+}
+
+__device__ __forceinline__ double group_sum_last(double v, int gs) {
+  return group_reduce_last(v, gs, 0.0, [](double a, double b) { return a + b; });
+}
+
+__device__ __forceinline__ double read_lane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (every lane active), the same value in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  return read_lane_f64(group_sum_last(v, 64), 63);
 }
 
 template <int NT, int K>

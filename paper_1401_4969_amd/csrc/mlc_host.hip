@@ -188,7 +188,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
 // Byte offsets (from the workspace base) of one problem's buffers.
 struct ProbLayout {
   size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
-      E, info, fg, partials, rr_x, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal;
+      E, info, fg, partials, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
   size_t st7[MLC_MAX_LEVELS + 1], st7f[MLC_MAX_LEVELS + 1], coef3;  // coef kind 3: stencil
                                                                      // planes, input
@@ -312,7 +312,6 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.info = take(4);
     L.fg = take(2 * q * nH * 8);
     L.partials = take(((nnL + 255) / 256) * (2 * q * q + q) * 8);
-    L.rr_x = take(q * (nH + q) * 8);
     L.rr_y = take(q * nH * 8);
     L.rr_t = take(q * q * 8);
     L.rr_ab = take(2 * 8);
@@ -571,7 +570,6 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     D.fg = (double*)(w + L.fg);
     D.partials = (double*)(w + L.partials);
     D.nparts = (int)((g.nodes(g.L) + 255) / 256);
-    D.rr_x = (double*)(w + L.rr_x);
     D.rr_y = (double*)(w + L.rr_y);
     D.rr_t = (double*)(w + L.rr_t);
     D.rr_ab = (double*)(w + L.rr_ab);
