@@ -299,8 +299,8 @@ __global__ __launch_bounds__(NTA) void k_adj_tile_rhs(const ProbDev* probs, cons
     if (is_dof(P.domain, N, gx, gy)) {
       int cx[MLC_MAX_CAND], cy[MLC_MAX_CAND];
       double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-      const int nxc = pou_axis(P.bx, P.sub_x, gx, r, P.overlap, P.pou, cx, rx);
-      const int nyc = pou_axis(P.by, P.sub_y, gy, r, P.overlap, P.pou, cy, ry);
+      const int nxc = pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, cx, rx);
+      const int nyc = pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, cy, ry);
       double tot = 0.0, mine = 0.0;
       for (int a = 0; a < nyc; ++a)
         for (int b = 0; b < nxc; ++b) {
@@ -329,8 +329,8 @@ __global__ __launch_bounds__(NTA) void k_adj_rbar(const ProbDev* probs, const Ti
     const int r = 1 << m;
     int cx[MLC_MAX_CAND], cy[MLC_MAX_CAND];
     double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-    const int nxc = pou_axis(P.bx, P.sub_x, gx, r, P.overlap, P.pou, cx, rx);
-    const int nyc = pou_axis(P.by, P.sub_y, gy, r, P.overlap, P.pou, cy, ry);
+    const int nxc = pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, cx, rx);
+    const int nyc = pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, cy, ry);
     for (int a = 0; a < nyc; ++a)
       for (int b = 0; b < nxc; ++b) {
         const int item = sub_item[P.sub_item_off + (cy[a] * P.sub_x + cx[b]) * P.q];

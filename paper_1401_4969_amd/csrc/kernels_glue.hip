@@ -16,18 +16,18 @@ namespace {
 
 constexpr int NTS = 256;
 
-// Closed G_b along one axis holding fine index g (r fine cells per coarse cell), or -1.
-__device__ __forceinline__ int g_block(const int32_t* bnd, int nb, int g, int r) {
+// Closed G_b along one axis holding fine index g (r fine cells per coarse cell, r >= 2),
+// or -1.  G_b lies inside D_b, so only the block of g's coarse cell can hold it.
+__device__ __forceinline__ int g_block(int nc, int nb, int g, int r) {
   const int half = r >> 1;
-  for (int b = 0; b < nb; ++b)
-    if (g >= bnd[b] * r + half && g <= bnd[b + 1] * r - half) return b;
-  return -1;
+  const int b = block_of_cell(min(g / r, nc - 1), nc, nb);
+  return (g >= block_bound(b, nc, nb) * r + half && g <= block_bound(b + 1, nc, nb) * r - half) ? b : -1;
 }
 
 // Skeleton dof: a dof of the domain outside every closed G_j.
 __device__ __forceinline__ bool skel_dof(const ProbDev& P, int N, int r, int gx, int gy) {
   if (!is_dof(P.domain, N, gx, gy)) return false;
-  return g_block(P.bx, P.sub_x, gx, r) < 0 || g_block(P.by, P.sub_y, gy, r) < 0;
+  return g_block(P.n_c, P.sub_x, gx, r) < 0 || g_block(P.n_c, P.sub_y, gy, r) < 0;
 }
 
 template <int KIND>
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(NTS) void k_skel_fill(const ProbDev* probs, const T
   const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, gx, gy)) {
-    const int bx = g_block(P.bx, P.sub_x, gx, r), by = g_block(P.by, P.sub_y, gy, r);
+    const int bx = g_block(P.n_c, P.sub_x, gx, r), by = g_block(P.n_c, P.sub_y, gy, r);
     if (bx >= 0 && by >= 0) {
       const int item = sub_item[P.sub_item_off + (by * P.sub_x + bx) * P.q + i_rhs];
       if (item >= 0) {

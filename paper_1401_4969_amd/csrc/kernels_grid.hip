@@ -83,8 +83,8 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   const int r = 1 << m;
   int ix[MLC_MAX_CAND], iy[MLC_MAX_CAND];
   double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-  const int nxc = pou_axis(P.bx, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
-  const int nyc = pou_axis(P.by, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
+  const int nxc = pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
+  const int nyc = pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
   for (int i = 0; i < P.q; ++i) {
     double acc = 0.0, tot = 0.0;
     for (int a = 0; a < nyc; ++a) {

@@ -212,17 +212,28 @@ __device__ __forceinline__ double apply_mass(const MassW& M, double mh, double c
     return mh * (6.0 * c + e + w + n + s + ne + sw);
 }
 
+// D_j block boundaries along one axis: floor(b * nc / nb) coarse cells (nb blocks over nc
+// cells, each block at least one cell wide), and the block holding coarse cell c.
+__device__ __forceinline__ int block_bound(int b, int nc, int nb) { return (b * nc) / nb; }
+__device__ __forceinline__ int block_of_cell(int c, int nc, int nb) {
+  return ((c + 1) * nb - 1) / nc;
+}
+
 // Blocks along one axis whose Omega range (D_j grown by `ov` coarse cells) holds fine
 // grid index g strictly inside, i.e. whose tiles cover the node, with the factor rho of
 // phi_j along that axis: the ramp (1 on D_j, linear to 0 across the overlap; exact
 // dyadic arithmetic) or the indicator of the closed D_j range.  r = fine cells per
-// coarse cell.  Returns the number of candidates (at most MLC_MAX_CAND).
-__device__ __forceinline__ int pou_axis(const int32_t* bnd, int nb, int g, int r, int ov, int pou,
+// coarse cell, nc coarse cells, nb blocks.  Blocks are at least one coarse cell wide, so
+// only the block of g's coarse cell and ov + 1 blocks on each side can qualify; they are
+// visited in ascending order.  Returns the number of candidates (at most MLC_MAX_CAND).
+__device__ __forceinline__ int pou_axis(int nc, int nb, int g, int r, int ov, int pou,
                                         int (&id)[MLC_MAX_CAND], double (&rho)[MLC_MAX_CAND]) {
   const int d = ov * r;
+  const int b0 = block_of_cell(min(g / r, nc - 1), nc, nb);
+  const int blo = max(0, b0 - ov - 1), bhi = min(nb - 1, b0 + ov + 1);
   int n = 0;
-  for (int b = 0; b < nb && n < MLC_MAX_CAND; ++b) {
-    const int lo = bnd[b] * r, hi = bnd[b + 1] * r;
+  for (int b = blo; b <= bhi && n < MLC_MAX_CAND; ++b) {
+    const int lo = block_bound(b, nc, nb) * r, hi = block_bound(b + 1, nc, nb) * r;
     const int v = min(g - lo + d, hi + d - g);
     if (v > 0) {
       id[n] = b;
