@@ -8,13 +8,20 @@
 //
 // The skeleton is one connected region of the whole grid, so it is solved by a global
 // preconditioned CG (Jacobi) over full-grid vectors that vanish off S: one thread per
-// node, a few launches per iteration, scalars kept in device memory (no host round trip
-// per iteration), block partial sums reduced in a fixed order (deterministic).
+// node, a few launches per iteration for all q right-hand sides at once (blockIdx.y),
+// scalars kept in device memory (no host round trip per iteration), block partial sums
+// reduced in a fixed order (deterministic).  A right-hand side that has converged is
+// frozen by a flag its reduction sets; the host polls the flags every 16 iterations.
+//
+// Per right-hand side i: vectors E, W, Z, P (two, used alternately), Q at vec + i*6*nodes;
+// block partials at parts + i*2*nblk; scalars at scal + i*SKEL_NS: rho, alpha, beta,
+// ||w||^2, ||w_0||^2, done, tol^2, iterations.
 #include "mlc_launch.h"
 
 namespace {
 
 constexpr int NTS = 256;
+constexpr int SKEL_NS = 8;  // scalars per right-hand side
 
 // Closed G_b along one axis holding fine index g (r fine cells per coarse cell, r >= 2),
 // or -1.  G_b lies inside D_b, so only the block of g's coarse cell can hold it.
@@ -67,11 +74,14 @@ __device__ __forceinline__ void block_partials(double a, double b, double* parts
 // e = e^j on the closed G_j (item of subdomain j and right-hand side i), 0 elsewhere.
 __global__ __launch_bounds__(NTS) void k_skel_fill(const ProbDev* probs, const TileItem* items,
                                                    const int32_t* sub_item, const char* store,
-                                                   int m, int i_rhs, double* E) {
+                                                   int m, double* vec) {
   const ProbDev& P = probs[0];
   const int N = P.n_c << m, n1 = N + 1, r = 1 << m;
+  const int64_t nn = (int64_t)n1 * n1;
+  const int i_rhs = blockIdx.y;
+  double* E = vec + (int64_t)i_rhs * 6 * nn;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
-  if (idx >= (int64_t)n1 * n1) return;
+  if (idx >= nn) return;
   const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, gx, gy)) {
@@ -91,12 +101,17 @@ __global__ __launch_bounds__(NTS) void k_skel_fill(const ProbDev* probs, const T
 
 // w = r - K e on S (0 elsewhere), z = D^-1 w, p = z; partial sums (w.z, w.w).
 template <int KIND>
-__global__ __launch_bounds__(NTS) void k_skel_init(const ProbDev* probs, int m, int i_rhs,
-                                                   const double* E, double* Wv, double* Z,
-                                                   double* Pv, double* parts) {
+__global__ __launch_bounds__(NTS) void k_skel_init(const ProbDev* probs, int m, double* vec,
+                                                   double* parts_all) {
   const ProbDev& P = probs[0];
   const int N = P.n_c << m, n1 = N + 1, r = 1 << m;
   const int64_t nn = (int64_t)n1 * n1;
+  const int i_rhs = blockIdx.y;
+  const double* E = vec + (int64_t)i_rhs * 6 * nn;
+  double* Wv = vec + ((int64_t)i_rhs * 6 + 1) * nn;
+  double* Z = vec + ((int64_t)i_rhs * 6 + 2) * nn;
+  double* Pv = vec + ((int64_t)i_rhs * 6 + 3) * nn;
+  double* parts = parts_all + (int64_t)i_rhs * 2 * gridDim.x;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   double wz = 0.0, ww = 0.0;
   if (idx < nn) {
@@ -119,13 +134,21 @@ __global__ __launch_bounds__(NTS) void k_skel_init(const ProbDev* probs, int m, 
 // p_new = z + beta p_old on S (formed on the fly at the stencil points; 0 off S), stored
 // in Pn; q = A p_new on S; partial sums (p.q, 0).  first: beta = 0, p_old unread.
 template <int KIND>
-__global__ __launch_bounds__(NTS) void k_skel_dir(const ProbDev* probs, int m, const double* Z,
-                                                  const double* Po, double* Pn, double* Q,
-                                                  const double* scal, int first,
-                                                  double* parts) {
+__global__ __launch_bounds__(NTS) void k_skel_dir(const ProbDev* probs, int m, double* vec,
+                                                  int po, const double* scal_all, int first,
+                                                  double* parts_all) {
   const ProbDev& P = probs[0];
   const int N = P.n_c << m, n1 = N + 1, r = 1 << m;
   const int64_t nn = (int64_t)n1 * n1;
+  const int i_rhs = blockIdx.y;
+  const double* scal = scal_all + i_rhs * SKEL_NS;
+  if (scal[5] != 0.0) return;  // converged: frozen (uniform over the workgroup)
+  double* base = vec + (int64_t)i_rhs * 6 * nn;
+  const double* Z = base + 2 * nn;
+  const double* Po = base + (3 + po) * nn;
+  double* Pn = base + (4 - po) * nn;
+  double* Q = base + 5 * nn;
+  double* parts = parts_all + (int64_t)i_rhs * 2 * gridDim.x;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   const double beta = first ? 0.0 : scal[2];
   const double* Pold = first ? Z : Po;  // any valid vector: multiplied by 0
@@ -154,13 +177,22 @@ __global__ __launch_bounds__(NTS) void k_skel_dir(const ProbDev* probs, int m, c
 
 // e += alpha p, w -= alpha q, z = D^-1 w on S; partial sums (w.z, w.w).
 template <int KIND>
-__global__ __launch_bounds__(NTS) void k_skel_upd(const ProbDev* probs, int m, double* E,
-                                                  double* Wv, double* Z, const double* Pv,
-                                                  const double* Q, const double* scal,
-                                                  double* parts) {
+__global__ __launch_bounds__(NTS) void k_skel_upd(const ProbDev* probs, int m, double* vec,
+                                                  int pn, const double* scal_all,
+                                                  double* parts_all) {
   const ProbDev& P = probs[0];
   const int N = P.n_c << m, n1 = N + 1, r = 1 << m;
   const int64_t nn = (int64_t)n1 * n1;
+  const int i_rhs = blockIdx.y;
+  const double* scal = scal_all + i_rhs * SKEL_NS;
+  if (scal[5] != 0.0) return;  // converged: frozen
+  double* base = vec + (int64_t)i_rhs * 6 * nn;
+  double* E = base;
+  double* Wv = base + nn;
+  double* Z = base + 2 * nn;
+  const double* Pv = base + (3 + pn) * nn;
+  const double* Q = base + 5 * nn;
+  double* parts = parts_all + (int64_t)i_rhs * 2 * gridDim.x;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   const double alpha = scal[1];
   double wz = 0.0, ww = 0.0;
@@ -180,13 +212,20 @@ __global__ __launch_bounds__(NTS) void k_skel_upd(const ProbDev* probs, int m, d
   block_partials(wz, ww, parts);
 }
 
-// Fixed-order sum of the block partials, then the CG scalars in scal:
-//   stage 0 (after init):  scal[0] = rho = w.z, scal[3] = ||w||^2, scal[4] = ||w_0||^2
-//   stage 1 (after dir):   scal[1] = alpha = rho / p.q
-//   stage 2 (after upd):   scal[2] = beta = (w.z) / rho, scal[0] = w.z, scal[3] = ||w||^2
-__global__ __launch_bounds__(1024) void k_skel_reduce(const double* parts, int nblk, int stage,
-                                                      double* scal) {
+// Fixed-order sum of the block partials of right-hand side blockIdx.x, then its CG scalars:
+//   stage 0 (after init):  rho = w.z, ||w||^2 = ||w_0||^2 = w.w, tol^2 = rtol^2 ||w_0||^2,
+//                          iterations 0, done when w_0 = 0
+//   stage 1 (after dir):   alpha = rho / p.q
+//   stage 2 (after upd):   beta = (w.z) / rho, rho = w.z, ||w||^2 = w.w, iterations + 1,
+//                          done when ||w||^2 <= tol^2
+// Stages 1 and 2 leave a converged right-hand side untouched.
+__global__ __launch_bounds__(1024) void k_skel_reduce(const double* parts_all, int nblk, int stage,
+                                                      double rtol, double* scal_all) {
   __shared__ double red[2 * 16];
+  const int i_rhs = blockIdx.x;
+  double* scal = scal_all + i_rhs * SKEL_NS;
+  if (stage != 0 && scal[5] != 0.0) return;
+  const double* parts = parts_all + (int64_t)i_rhs * 2 * nblk;
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < nblk; k += 1024) {
     a += parts[2 * k];
@@ -210,22 +249,29 @@ __global__ __launch_bounds__(1024) void k_skel_reduce(const double* parts, int n
       scal[0] = sa;
       scal[3] = sb;
       scal[4] = sb;
+      scal[6] = rtol * rtol * sb;
+      scal[7] = 0.0;
+      scal[5] = sb > 0.0 ? 0.0 : 1.0;
     } else if (stage == 1) {
       scal[1] = sa != 0.0 ? scal[0] / sa : 0.0;
     } else {
       scal[2] = scal[0] != 0.0 ? sa / scal[0] : 0.0;
       scal[0] = sa;
       scal[3] = sb;
+      scal[7] += 1.0;
+      if (sb <= scal[6]) scal[5] = 1.0;
     }
   }
 }
 
 // u~ = I u + e for right-hand side i (0 off the domain).
-__global__ __launch_bounds__(NTS) void k_skel_finish(const ProbDev* probs, int m, int i_rhs,
-                                                     const double* E) {
+__global__ __launch_bounds__(NTS) void k_skel_finish(const ProbDev* probs, int m,
+                                                     const double* vec) {
   const ProbDev& P = probs[0];
   const int N = P.n_c << m, n1 = N + 1;
   const int64_t nn = (int64_t)n1 * n1;
+  const int i_rhs = blockIdx.y;
+  const double* E = vec + (int64_t)i_rhs * 6 * nn;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   if (idx >= nn) return;
   const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
@@ -241,76 +287,56 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
                                 double* parts, double* scal, hipStream_t s, int* iters_out,
                                 double* relres_out) {
   const unsigned nblk = (unsigned)((nodes + NTS - 1) / NTS);
-  double* E = vec;
-  double* Wv = vec + nodes;
-  double* Z = vec + 2 * nodes;
-  double* Pa = vec + 3 * nodes;
-  double* Pb = vec + 4 * nodes;
-  double* Q = vec + 5 * nodes;
+  const dim3 g(nblk, (unsigned)q);
+  hipLaunchKernelGGL(k_skel_fill, g, dim3(NTS), 0, s, dprob, items, sub_item, store, m, vec);
+#define MLC_SKEL(K, ...)                                                                  \
+  do {                                                                                    \
+    if (kind == 0)                                                                        \
+      hipLaunchKernelGGL(K<0>, g, dim3(NTS), 0, s, __VA_ARGS__);                          \
+    else if (kind == 1)                                                                   \
+      hipLaunchKernelGGL(K<1>, g, dim3(NTS), 0, s, __VA_ARGS__);                          \
+    else if (kind == 2)                                                                   \
+      hipLaunchKernelGGL(K<2>, g, dim3(NTS), 0, s, __VA_ARGS__);                          \
+    else                                                                                  \
+      hipLaunchKernelGGL(K<3>, g, dim3(NTS), 0, s, __VA_ARGS__);                          \
+  } while (0)
+  MLC_SKEL(k_skel_init, dprob, m, vec, parts);
+  hipLaunchKernelGGL(k_skel_reduce, dim3(q), dim3(1024), 0, s, parts, (int)nblk, 0, rtol, scal);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double h[SKEL_NS * MLC_MAX_Q];
+  int it = 0;
+  while (it < max_it) {
+    // sixteen iterations between polls of the convergence flags
+    for (int k = 0; k < 16 && it < max_it; ++k, ++it) {
+      const int po = it & 1;  // the two direction buffers alternate
+      MLC_SKEL(k_skel_dir, dprob, m, vec, po, scal, it == 0 ? 1 : 0, parts);
+      hipLaunchKernelGGL(k_skel_reduce, dim3(q), dim3(1024), 0, s, parts, (int)nblk, 1, rtol, scal);
+      MLC_SKEL(k_skel_upd, dprob, m, vec, 1 - po, scal, parts);
+      hipLaunchKernelGGL(k_skel_reduce, dim3(q), dim3(1024), 0, s, parts, (int)nblk, 2, rtol, scal);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h, scal, sizeof(double) * SKEL_NS * q, hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    bool all = true;
+    for (int i = 0; i < q; ++i) all = all && h[i * SKEL_NS + 5] != 0.0;
+    if (all) break;
+  }
+#undef MLC_SKEL
+  hipLaunchKernelGGL(k_skel_finish, g, dim3(NTS), 0, s, dprob, m, vec);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(h, scal, sizeof(double) * SKEL_NS * q, hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   int it_max = 0;
   double rel_max = 0.0;
   for (int i = 0; i < q; ++i) {
-    hipLaunchKernelGGL(k_skel_fill, dim3(nblk), dim3(NTS), 0, s, dprob, items, sub_item, store,
-                       m, i, E);
-    if (kind == 0)
-      hipLaunchKernelGGL(k_skel_init<0>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
-    else if (kind == 1)
-      hipLaunchKernelGGL(k_skel_init<1>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
-    else if (kind == 2)
-      hipLaunchKernelGGL(k_skel_init<2>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
-    else
-      hipLaunchKernelGGL(k_skel_init<3>, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E, Wv, Z, Pa, parts);
-    hipLaunchKernelGGL(k_skel_reduce, dim3(1), dim3(1024), 0, s, parts, (int)nblk, 0, scal);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    double h[5];
-    if ((e = hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const double rr0 = h[4];
-    double rr = rr0;
-    int it = 0;
-    double* Po = Pa;
-    double* Pn = Pb;
-    if (rr0 > 0.0) {
-      const double tol2 = rtol * rtol * rr0;
-      while (it < max_it) {
-        // eight iterations between convergence checks
-        for (int k = 0; k < 8 && it < max_it; ++k, ++it) {
-          const int first = it == 0 ? 1 : 0;
-          if (kind == 0)
-            hipLaunchKernelGGL(k_skel_dir<0>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
-          else if (kind == 1)
-            hipLaunchKernelGGL(k_skel_dir<1>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
-          else if (kind == 2)
-            hipLaunchKernelGGL(k_skel_dir<2>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
-          else
-            hipLaunchKernelGGL(k_skel_dir<3>, dim3(nblk), dim3(NTS), 0, s, dprob, m, Z, Po, Pn, Q, scal, first, parts);
-          hipLaunchKernelGGL(k_skel_reduce, dim3(1), dim3(1024), 0, s, parts, (int)nblk, 1, scal);
-          if (kind == 0)
-            hipLaunchKernelGGL(k_skel_upd<0>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
-          else if (kind == 1)
-            hipLaunchKernelGGL(k_skel_upd<1>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
-          else if (kind == 2)
-            hipLaunchKernelGGL(k_skel_upd<2>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
-          else
-            hipLaunchKernelGGL(k_skel_upd<3>, dim3(nblk), dim3(NTS), 0, s, dprob, m, E, Wv, Z, Pn, Q, scal, parts);
-          hipLaunchKernelGGL(k_skel_reduce, dim3(1), dim3(1024), 0, s, parts, (int)nblk, 2, scal);
-          double* t = Po;
-          Po = Pn;
-          Pn = t;
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess)
-          return e;
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-        rr = h[3];
-        if (rr <= tol2) break;
-      }
-    }
-    hipLaunchKernelGGL(k_skel_finish, dim3(nblk), dim3(NTS), 0, s, dprob, m, i, E);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    it_max = it > it_max ? it : it_max;
-    const double rel = rr0 > 0.0 ? sqrt(rr / rr0) : 0.0;
+    const double* c = h + i * SKEL_NS;
+    it_max = (int)c[7] > it_max ? (int)c[7] : it_max;
+    const double rel = c[4] > 0.0 ? sqrt(c[3] / c[4]) : 0.0;
     rel_max = rel > rel_max ? rel : rel_max;
   }
   *iters_out = it_max;

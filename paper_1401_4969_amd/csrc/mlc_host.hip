@@ -319,9 +319,9 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.out_parts = take(64 * q * 8);
     L.skel = L.skel_parts = L.skel_scal = 0;
     if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem on the finest grid
-      L.skel = take(6 * nnL * 8);
-      L.skel_parts = take(((nnL + 255) / 256) * 2 * 8);
-      L.skel_scal = take(8 * 8);
+      L.skel = take(6 * q * nnL * 8);  // six vectors per right-hand side
+      L.skel_parts = take(((nnL + 255) / 256) * 2 * q * 8);
+      L.skel_scal = take(8 * q * 8);
     }
     L.inv_base = P.inv_total;
     P.inv_total += g.inv_total;
