@@ -100,6 +100,16 @@ def test_config1_variants(kw):
     compare(W.config1().with_(**kw))
 
 
+@pytest.mark.parametrize("q", [5, 7, 8])
+def test_many_eigenpairs(q):
+    """q = 5, 7 and 8 (the largest supported): the Rayleigh-Ritz solve on V_0H + span{u~_1..u~_q}
+    (its 512-thread instantiations); a seeded per-coarse-cell kappa keeps the lowest eight
+    eigenvalues apart (relative gaps above 4%), so every eigenvector is compared alone."""
+    rng = np.random.Generator(np.random.PCG64(58))
+    kap = W.loguniform_coarse_kappa(8, rng)
+    compare(W.Problem(0, 8, 2, 3, 3, 1, q, 1, kap, f"many_q{q}"))
+
+
 @pytest.mark.parametrize("kw", [dict(nu=1), dict(nu=3, omega=0.6), dict(block=256),
                                 dict(block=512)])
 def test_solver_options_do_not_change_results(kw):
