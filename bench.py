@@ -7,7 +7,12 @@ previous level's eigenpairs already resident in HBM: prolongation and residual o
 V_0H + span{u~} and the new eigenvectors.  The library rewinds its ping-pong state
 between steps, so every step repeats exactly the same correction.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3mixed] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3mixed|c4|c5adj|c2iface|
+                     c3iface|ex62|ex62mixed] [--no-cpu-baseline]
+
+(c4: a step is the whole multilevel run of 256 batched problems; c5adj: one reverse sweep;
+*iface: the paper's own gluing in place of the partition of unity; ex62*: the operator of
+Example 6.2.)
 
 Prints one JSON line.  ``value`` is fine interior DOFs corrected per second at the finest
 level (work of every eigenpair included).  ``roofline`` is for the local-solve kernel,
@@ -87,15 +92,24 @@ def mixed_bytes(cw: int, ch: int, m: int, nu: int, it_dofs: int, refine_dofs: in
     return per_it * it_dofs + (44.0 + 4.0 + coef64) * refine_dofs + 24.0 * tile_dofs
 
 
+def code_text(src: str) -> str:
+    """Source text without comments and blank space (a comment edit is no kernel change)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(" ".join(line.split()) for line in src.splitlines() if line.strip())
+
+
 def source_sha(kernel: str) -> str:
+    """Hash of the code the kernel is built from (comments ignored)."""
     import hashlib
     c = os.path.join(ROOT, "paper_1401_4969_amd", "csrc")
     files = {"k_local_pcg64": ["kernels_pcg.hip", "pcg_ops.h", "mlc_device.h"],
              "k_local_mixed": ["kernels_mixed.hip", "pcg_ops.h", "mlc_device.h"]}[kernel]
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(c, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(c, f)) as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
       P.ubar[(int64_t)i * nn + idx] = ym[i];
     }
   }
-  // partial sums: every wave reduces each value with shuffles, one barrier, then the
+  // partial sums: every wave reduces each value across its lanes, one barrier, then the
   // waves' values are added in a fixed order
   const int nv = 2 * q * q + q;
   double* out = P.partials + (int64_t)blockIdx.x * nv;

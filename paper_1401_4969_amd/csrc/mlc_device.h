@@ -245,7 +245,8 @@ __device__ __forceinline__ int pou_axis(int nc, int nb, int g, int r, int ov, in
 }
 
 // ---------------------------------------------------------------------------------
-// Workgroup reductions (fixed order: wave butterfly, then waves in index order)
+// Workgroup reductions (fixed order: across a wave's lanes by DPP moves, then the waves in
+// index order)
 // ---------------------------------------------------------------------------------
 // A value every lane holds equally, moved to a scalar register.
 __device__ __forceinline__ double uniform_f64(double v) {
