@@ -227,7 +227,10 @@ __device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, 
 // instead of the 6 passes of separate sweeps.  A ring row is overwritten only after the
 // barrier that follows its last reader.  Taller bands (R = 2) halve the barrier
 // intervals where the rings fit.
-template <int NT, int KIND, typename T, int R>
+// CMP > 0 (rows of at most 64 CMP nodes): the right-hand side rows of the next band
+// step's first stage are loaded into registers at the end of this step's first stage, so
+// their memory latency overlaps the three later stages instead of opening the next step.
+template <int NT, int KIND, typename T, int R, int CMP = 0>
 __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
                              const T* b, T* za, T* bc, T omega, T* ring) {
   constexpr int NW = NT / 64, BH = NW * R, RING = BH + 2;
@@ -237,21 +240,60 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
   T* r2 = ring + RING * nx;
   T* rr = ring + 2 * RING * nx;
   auto row = [&](T* r, int y) -> T* { return r + ((y + 1) % RING) * nx; };
-  for (int k = 0; k * BH - 3 < ny || k * (BH / 2) - 2 < ncy; ++k) {
+  constexpr int CP = CMP > 0 ? CMP : 1;
+  T nb[R][CP];  // first-stage right-hand side of the coming band step (CMP > 0)
+  auto load_a = [&](int kk) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int ya = k * BH + w + NW * q - 1;
-      if (ya >= -1 && ya <= ny) {
-        T* dst = row(r1, ya);
-        const bool inside = ya >= 0 && ya < ny;
-        for (int ix = lane; ix < nx; ix += 64) {
-          T v = T(0);
-          if (inside) {
-            const T bi = b[(unsigned)(ya * nx + ix)];
-            const T d = T(diag_at<KIND, T>(P, lv, ix, ya));
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bi / d : T(0);
+      const int ya = kk * BH + w + NW * q - 1;
+      const bool inside = ya >= 0 && ya < ny;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        const int ix = lane + 64 * c;
+        nb[q][c] = b[(inside && ix < nx) ? (unsigned)(ya * nx + ix) : 0u];
+      }
+    }
+  };
+  if constexpr (CMP > 0) load_a(0);
+  for (int k = 0; k * BH - 3 < ny || k * (BH / 2) - 2 < ncy; ++k) {
+    if constexpr (CMP > 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int ya = k * BH + w + NW * q - 1;
+        if (ya >= -1 && ya <= ny) {
+          T* dst = row(r1, ya);
+          const bool inside = ya >= 0 && ya < ny;
+#pragma unroll
+          for (int c = 0; c < CP; ++c) {
+            const int ix = lane + 64 * c;
+            if (ix < nx) {
+              T v = T(0);
+              if (inside) {
+                const T d = T(diag_at<KIND, T>(P, lv, ix, ya));
+                v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * nb[q][c] / d : T(0);
+              }
+              dst[ix] = v;
+            }
           }
-          dst[ix] = v;
+        }
+      }
+      load_a(k + 1);
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int ya = k * BH + w + NW * q - 1;
+        if (ya >= -1 && ya <= ny) {
+          T* dst = row(r1, ya);
+          const bool inside = ya >= 0 && ya < ny;
+          for (int ix = lane; ix < nx; ix += 64) {
+            T v = T(0);
+            if (inside) {
+              const T bi = b[(unsigned)(ya * nx + ix)];
+              const T d = T(diag_at<KIND, T>(P, lv, ix, ya));
+              v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bi / d : T(0);
+            }
+            dst[ix] = v;
+          }
         }
       }
     }
@@ -779,8 +821,18 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     T* zb = base + lv.ot;
     if (ring_rows > 0 && nu == 2) {
       T* bc = base + lev[t + 1].ob;
-      if (MAXR >= 2 && ring_rows == 2)
-        op_pre_fused<NT, KIND, T, MAXR>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+      // FP64 with a constant coefficient: the next band's first-stage rows are prefetched
+      // (the variable coefficients' weight loads leave no registers for it)
+      constexpr bool PF64 = KIND == 0 && sizeof(T) == 8;
+      if (MAXR >= 2 && ring_rows == 2) {
+        if (PF64 && lv.nx <= 128)
+          op_pre_fused<NT, KIND, T, MAXR, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+        else
+          op_pre_fused<NT, KIND, T, MAXR>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+      } else if (PF64 && lv.nx <= 128)
+        op_pre_fused<NT, KIND, T, 1, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+      else if (PF64 && lv.nx <= 256)
+        op_pre_fused<NT, KIND, T, 1, PF64 ? 4 : 0>(P, lv, lev[t + 1], b, za, bc, omega, ring);
       else if (PREFETCH && lv.nx <= 64 * RING_CHUNKS)
         op_pre_fused_pf<NT, KIND, T>(P, lv, lev[t + 1], b, za, bc, omega, ring);
       else
@@ -1052,35 +1104,43 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   rr = bb;
   if (!(bb > 0.0)) return 0;
   double acc[2];
-  acc[0] = acc[1] = 0.0;
-  const T* Z = vcycle<NT, KIND, T, MAXR>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_rows, tail);
-  block_sum<NT, 2>(acc, red);
-  double rho = acc[0];
+  // One call site for the V-cycle (it is inlined, and a second copy would cost
+  // registers): the first pass through the loop only preconditions r_0.
+  const T* Z = nullptr;
+  double rho = 0.0;
   T beta = T(0);
   bool first = true;
-  while (iters < max_it) {
-    ++iters;
-    // p_new = z + beta p_old and p_new . A p_new, with A p_new formed from p_new at the
-    // node and its neighbours
+  for (;;) {
+    if (Z != nullptr) {
+      if (iters >= max_it) break;
+      ++iters;
+      // p_new = z + beta p_old and p_new . A p_new, with A p_new formed from p_new at the
+      // node and its neighbours
+      acc[0] = acc[1] = 0.0;
+      if constexpr (KIND == 0)
+        pass_dir<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
+      else
+        pass_dir_plain<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
+      block_sum<NT, 2>(acc, red);
+      const T alpha = T(rho / acc[0]);
+      // x += alpha p, r -= alpha A p, ||r||^2
+      acc[0] = acc[1] = 0.0;
+      if constexpr (KIND == 0)
+        pass_xr<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
+      else
+        pass_xr_plain<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
+      block_sum<NT, 2>(acc, red);
+      rr = acc[0];
+      if (rr <= tol2) break;
+    }
     acc[0] = acc[1] = 0.0;
-    if constexpr (KIND == 0)
-      pass_dir<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
-    else
-      pass_dir_plain<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
-    block_sum<NT, 2>(acc, red);
-    const T alpha = T(rho / acc[0]);
-    // x += alpha p, r -= alpha A p, ||r||^2
-    acc[0] = acc[1] = 0.0;
-    if constexpr (KIND == 0)
-      pass_xr<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
-    else
-      pass_xr_plain<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
-    block_sum<NT, 2>(acc, red);
-    rr = acc[0];
-    if (rr <= tol2) break;
-    acc[0] = acc[1] = 0.0;
+    const bool init = Z == nullptr;
     Z = vcycle<NT, KIND, T, MAXR>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_rows, tail);
     block_sum<NT, 2>(acc, red);
+    if (init) {
+      rho = acc[0];
+      continue;
+    }
     beta = T(acc[0] / rho);
     rho = acc[0];
     first = false;
