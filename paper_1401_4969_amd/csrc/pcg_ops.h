@@ -365,10 +365,14 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
 // one row below (B) and the second sweep two rows below (C, written into za in place: no
 // later stage reads za at or below that row).  za is read and written once and b read
 // once from HBM, instead of the 8 passes of a separate interpolation and two sweeps.
-template <int NT, int KIND, typename T, bool DOT, int R>
+// CMP > 0 (rows of at most 64 CMP nodes): the right-hand side rows of the second stage are
+// loaded into registers before the first stage, so the two stages' memory latencies
+// overlap.
+template <int NT, int KIND, typename T, bool DOT, int R, int CMP = 0>
 __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
                               const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
   constexpr int NW = NT / 64, BH = NW * R, RING = BH + 2;
+  constexpr int CP = CMP > 0 ? CMP : 1;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = lv.nx, ny = lv.ny;
   T* ringA = ring;
@@ -381,6 +385,19 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
     return in ? v : T(0);
   };
   for (int k = 0; k * BH - 3 < ny; ++k) {
+    T bb[R][CP];  // second-stage right-hand side (CMP > 0)
+    if constexpr (CMP > 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int yb = k * BH + w + NW * q - 2;
+        const bool inside = yb >= 0 && yb < ny;
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+          const int ix = lane + 64 * c;
+          bb[q][c] = b[(inside && ix < nx) ? (unsigned)(yb * nx + ix) : 0u];
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int ya = k * BH + w + NW * q - 1;
@@ -411,10 +428,21 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
           const T* rs = row(ringA, yb - 1);
           const T* rc = row(ringA, yb);
           const T* rn = row(ringA, yb + 1);
-          for (int ix = lane; ix < nx; ix += 64) {
-            const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[(unsigned)(yb * nx + ix)], ix,
-                                             yb, omega);
-            dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+          if constexpr (CMP > 0) {
+#pragma unroll
+            for (int c = 0; c < CP; ++c) {
+              const int ix = lane + 64 * c;
+              if (ix < nx) {
+                const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bb[q][c], ix, yb, omega);
+                dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+              }
+            }
+          } else {
+            for (int ix = lane; ix < nx; ix += 64) {
+              const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[(unsigned)(yb * nx + ix)],
+                                               ix, yb, omega);
+              dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+            }
           }
         } else {
           for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
@@ -883,11 +911,24 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     if (ring_rows > 0 && nu == 2) {
       const LevelDesc lc = lev[t + 1];
       const bool pf = ring_rows == 1 && PREFETCH && lv.nx <= 64 * RING_CHUNKS;
+      constexpr bool PF64 = KIND == 0 && sizeof(T) == 8;
+      constexpr int C2 = PF64 ? 2 : 0, C4 = PF64 ? 4 : 0;
       if (MAXR >= 2 && ring_rows == 2) {
-        if (t == 0)
+        if (PF64 && lv.nx <= 128) {
+          if (t == 0)
+            op_post_fused<NT, KIND, T, true, MAXR, C2>(P, lc, lv, zc, b, za, omega, ring, rz);
+          else
+            op_post_fused<NT, KIND, T, false, MAXR, C2>(P, lc, lv, zc, b, za, omega, ring,
+                                                        nullptr);
+        } else if (t == 0)
           op_post_fused<NT, KIND, T, true, MAXR>(P, lc, lv, zc, b, za, omega, ring, rz);
         else
           op_post_fused<NT, KIND, T, false, MAXR>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+      } else if (PF64 && lv.nx <= 256) {
+        if (t == 0)
+          op_post_fused<NT, KIND, T, true, 1, C4>(P, lc, lv, zc, b, za, omega, ring, rz);
+        else
+          op_post_fused<NT, KIND, T, false, 1, C4>(P, lc, lv, zc, b, za, omega, ring, nullptr);
       } else if (pf) {
         if (t == 0)
           op_post_fused_pf<NT, KIND, T, true>(P, lc, lv, zc, b, za, omega, ring, rz);
