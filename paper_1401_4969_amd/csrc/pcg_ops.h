@@ -367,7 +367,8 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
 // once from HBM, instead of the 8 passes of a separate interpolation and two sweeps.
 // CMP > 0 (rows of at most 64 CMP nodes): the right-hand side rows of the second stage are
 // loaded into registers before the first stage, so the two stages' memory latencies
-// overlap.
+// overlap, and the iterate rows of the next step's first stage are loaded at the end of
+// this step.
 template <int NT, int KIND, typename T, bool DOT, int R, int CMP = 0>
 __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
                               const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
@@ -384,6 +385,20 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
     const T v = zc[in ? (unsigned)(cy * ncx + cx) : 0u];
     return in ? v : T(0);
   };
+  T nz[R][CP];  // first-stage iterate rows of the coming step (CMP > 0)
+  auto load_z = [&](int kk) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int ya = kk * BH + w + NW * q - 1;
+      const bool inside = ya >= 0 && ya < ny;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        const int ix = lane + 64 * c;
+        nz[q][c] = za[(inside && ix < nx) ? (unsigned)(ya * nx + ix) : 0u];
+      }
+    }
+  };
+  if constexpr (CMP > 0) load_z(0);
   for (int k = 0; k * BH - 3 < ny; ++k) {
     T bb[R][CP];  // second-stage right-hand side (CMP > 0)
     if constexpr (CMP > 0) {
@@ -404,17 +419,35 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
       if (ya >= -1 && ya <= ny) {
         T* dst = row(ringA, ya);
         const bool inside = ya >= 0 && ya < ny;
-        for (int ix = lane; ix < nx; ix += 64) {
-          T v = T(0);
-          if (inside) {
-            const unsigned i = (unsigned)(ya * nx + ix);
-            const int cx = ix >> 1, cy = ya >> 1;
-            const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
-            const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
-            const T old = za[i];
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
+        if constexpr (CMP > 0) {
+#pragma unroll
+          for (int c = 0; c < CP; ++c) {
+            const int ix = lane + 64 * c;
+            if (ix < nx) {
+              T v = T(0);
+              if (inside) {
+                const int cx = ix >> 1, cy = ya >> 1;
+                const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
+                const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
+                const T old = nz[q][c];
+                v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
+              }
+              dst[ix] = v;
+            }
           }
-          dst[ix] = v;
+        } else {
+          for (int ix = lane; ix < nx; ix += 64) {
+            T v = T(0);
+            if (inside) {
+              const unsigned i = (unsigned)(ya * nx + ix);
+              const int cx = ix >> 1, cy = ya >> 1;
+              const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
+              const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
+              const T old = za[i];
+              v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
+            }
+            dst[ix] = v;
+          }
         }
       }
     }
@@ -467,6 +500,8 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
         }
       }
     }
+    // the next step's first-stage rows lie above every row this step writes
+    if constexpr (CMP > 0) load_z(k + 1);
   }
 }
 
