@@ -265,6 +265,12 @@ def test_interface_gluing(which, overlap):
         assert st["glue_it"] > 0 and st["glue_relres"] <= 1e-12 * 1.0000001
 
 
+def test_interface_gluing_four_eigenpairs():
+    """The G_{m+1} solves of four right-hand sides share their launches (each frozen once it
+    has converged): parity with the oracle on every level."""
+    compare(W.Problem(0, 8, 3, 4, 4, 1, 4, 0, None, "iface_q4", pou=2))
+
+
 def test_interface_gluing_mixed_precision():
     prob = W.Problem(0, 8, 3, 4, 4, 1, 1, 0, None, "iface_mixed", pou=2)
     compare(prob, precision=1)
