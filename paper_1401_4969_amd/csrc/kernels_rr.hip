@@ -21,8 +21,9 @@
 // of the short loops).  Reductions are batched: each wave reduces its partial sums across lanes (DPP
 // moves) and writes them to LDS, and one barrier later every value is summed over the
 // waves in a fixed order (deterministic).  Multisection evaluates G points per round, GS
-// consecutive lanes per point (about 32 terms each), reduced by DPP inside the wave; wave k
-// then updates bracket k from all points.  The inverse-iteration vectors live in LDS.
+// consecutive lanes per point (about 32 terms each), reduced by DPP inside the wave; thread
+// k then updates bracket k from all points and places its next points.  The
+// inverse-iteration vectors live in LDS.
 #include "mlc_launch.h"
 
 namespace {
@@ -50,16 +51,19 @@ __device__ __forceinline__ double gather(int v, const double* lds, int stride) {
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // Number of negative eigenvalues of a symmetric QxQ matrix given by its packed lower
-// triangle (LDL^T, Sylvester); an exact zero pivot is nudged.  Indices are compile-time
-// constants, so the matrix stays in registers.
+// triangle (LDL^T, Sylvester); an exact zero pivot is nudged.  det receives the product
+// of the pivots (the determinant).  Indices are compile-time constants, so the matrix
+// stays in registers.
 template <int Q>
-__device__ int neg_inertia(double (&S)[Q * (Q + 1) / 2]) {
+__device__ int neg_inertia(double (&S)[Q * (Q + 1) / 2], double& det) {
   int n = 0;
+  det = 1.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     double d = S[tri(k, k)];
     if (d == 0.0) d = -1e-300;
     if (d < 0.0) ++n;
+    det *= d;
 #pragma unroll
     for (int i = k + 1; i < Q; ++i) {
       const double f = S[tri(i, k)] / d;
@@ -103,6 +107,25 @@ __device__ void small_solve(double* A, double* b) {
     if (d == 0.0) d = 1e-300;
     b[k] = s / d;
   }
+}
+
+// Lanes per multisection point: the largest power of two up to 64 that leaves at least
+// 16 points per round.
+constexpr int rr_group_lanes(int ntr) {
+  int gs = 64;
+  while (gs > 1 && ntr / gs < 16) gs >>= 1;
+  return gs;
+}
+
+// Offsets of a guided round's points from the regula falsi estimate, as fractions of the
+// bracket width: the centre (for an odd count) and pairs +-s on a geometric ladder from
+// 3e-2 down to 1e-6.
+__device__ inline double guided_offset(int j, int per_bracket) {
+  const int odd = per_bracket & 1, pairs = per_bracket / 2;
+  if (j < odd) return 0.0;
+  const int i = (j - odd) >> 1;
+  const double s = pairs == 1 ? sqrt(3e-2 * 1e-6) : 3e-2 * pow(1e-6 / 3e-2, (double)i / (double)(pairs - 1));
+  return ((j - odd) & 1) ? s : -s;
 }
 
 // Dynamic LDS of k_rr_solve in doubles: Lambda, Z, f, g and the q eigenvectors.
@@ -270,32 +293,46 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
     __syncthreads();
   }
   lo -= 1e-12 * fabs(lo) + 1e-300;
-  // 6. multisection for all q eigenvalues at once: each round spreads G points over the
+  // 6. multisection for all q eigenvalues at once: each round evaluates G points over the
   //    q brackets (G/q per bracket, GS lanes per point; the work of a round grows with G
-  //    while the rounds fall only with log G, so G is kept small: 16 points,
-  //    at least 2 per bracket); every
-  //    point's inertia count c tightens every bracket: mu is an upper bound of eigenvalue k
-  //    when c >= k + 1 and a lower bound when c <= k.  Upper bounds start from interlacing
-  //    (mu_k <= Lambda_k).
-  int GS = 64;
-  while (GS > 1 && NTR / GS < 16) GS >>= 1;
-  const int G = NTR / GS;  // 16 >= 2 Q
-  const int GQ = G / Q;    // points per bracket, >= 2
+  //    while the rounds fall only with log G, so G is kept small: 16 points, at least 2
+  //    per bracket); every point's inertia count c tightens every bracket: mu is an upper
+  //    bound of eigenvalue k when c >= k + 1 and a lower bound when c <= k.  Upper bounds
+  //    start from interlacing (mu_k <= Lambda_k).
+  //    A bracket's points are spread uniformly until it holds exactly one eigenvalue and no
+  //    pole (the inertia counts at its ends differ by one and the numbers of Lambda_r below
+  //    them agree): det S(mu) is then smooth on the bracket and changes sign once, at the
+  //    eigenvalue, and the next round centres the bracket's points on the regula falsi
+  //    estimate from det S at the two ends (offsets: guided_offset).  A guided round that
+  //    shrinks its bracket by less than 4x is followed by a uniform one.  Where the points
+  //    go changes only how fast the brackets shrink, never what they contain.
+  constexpr int GS = rr_group_lanes(NTR);
+  constexpr int G = NTR / GS;  // 16 >= 2 Q
+  constexpr int GQ = G / Q;    // points per bracket, >= 2
   const int pnt = tid / GS, gl = tid % GS;
-  const int wv = tid >> 6, lane = tid & 63;
-  __shared__ double sA[Q], sB[Q], ptMu[NTR];
-  __shared__ int ptCnt[NTR];
+  const int kb = pnt / GQ, j = pnt % GQ;  // this point's bracket and position
+  const bool active = kb < Q;
+  const int kk = active ? kb : 0;
+  const double off = guided_offset(j, GQ);
+  const double frac = (double)(j + 1) / (double)(GQ + 1);  // uniform position
+  __shared__ double sA[Q], sB[Q], sFA[Q], sFB[Q], sEst[Q], ptMu[G], ptDet[G];
+  __shared__ int sCA[Q], sCB[Q], sNA[Q], sNB[Q], sGuide[Q], ptCnt[G], ptLess[G];
   if (tid < Q) {
     sA[tid] = lo;
     sB[tid] = Lam[tid] + 1e-12 * fabs(Lam[tid]) + 1e-300;
+    sFA[tid] = sFB[tid] = sEst[tid] = 0.0;
+    sCA[tid] = sCB[tid] = -1;  // ends not evaluated yet
+    sNA[tid] = sNB[tid] = 0;
+    sGuide[tid] = 0;
   }
   __syncthreads();
-  const double inf = __builtin_inf();
   for (int round = 0; round < 200; ++round) {
-    const int kb = pnt / GQ, j = pnt % GQ;  // this point's bracket and position
-    const bool active = kb < Q;
-    const double a = sA[active ? kb : 0], bnd = sB[active ? kb : 0];
-    const double mu = a + (bnd - a) * (double)(j + 1) / (double)(GQ + 1);
+    const double a = sA[kk], bnd = sB[kk];
+    double mu = a + (bnd - a) * frac;
+    if (sGuide[kk]) {
+      const double gm = sEst[kk] + off * (bnd - a);
+      mu = (gm > a && gm < bnd) ? gm : a + 0.5 * (bnd - a);
+    }
     double S[Q * (Q + 1) / 2];  // packed lower triangle
 #pragma unroll
     for (int e = 0; e < Q * (Q + 1) / 2; ++e) S[e] = 0.0;
@@ -322,26 +359,58 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
 #pragma unroll
         for (int jj = 0; jj <= i; ++jj)
           S[tri(i, jj)] = sW[i * Q + jj] - S[tri(i, jj)] - (i == jj ? mu : 0.0);
+      double det;
+      const int neg = neg_inertia<Q>(S, det);
       ptMu[pnt] = mu;
-      ptCnt[pnt] = active ? (int)nless + neg_inertia<Q>(S) : -1;
+      ptDet[pnt] = det;
+      ptLess[pnt] = (int)nless;
+      ptCnt[pnt] = active ? (int)nless + neg : -1;
     }
     __syncthreads();
-    if (wv < Q) {  // wave k tightens bracket k from every point
-      double lo2 = -inf, hi2 = inf;
-      for (int p2 = lane; p2 < G; p2 += 64) {
+    if (tid < Q) {  // thread k tightens bracket k from every point and places its next round
+      const int k = tid;
+      const double a0 = sA[k], b0 = sB[k];
+      double ak = a0, bk = b0;
+      int ia = -1, ib = -1;  // the points that become the ends (all loads issued at once)
+#pragma unroll
+      for (int p2 = 0; p2 < G; ++p2) {
         const int c = ptCnt[p2];
         const double m2 = ptMu[p2];
-        if (c >= wv + 1)
-          hi2 = fmin(hi2, m2);
-        else if (c >= 0)
-          lo2 = fmax(lo2, m2);
+        const bool up = c >= k + 1, down = c >= 0 && c <= k;
+        if (up && m2 < bk) {
+          bk = m2;
+          ib = p2;
+        }
+        if (down && m2 > ak) {
+          ak = m2;
+          ia = p2;
+        }
       }
-      lo2 = group_reduce_last(lo2, 64, -inf, [](double x, double y) { return fmax(x, y); });
-      hi2 = group_reduce_last(hi2, 64, inf, [](double x, double y) { return fmin(x, y); });
-      if (lane == 63) {
-        sA[wv] = fmax(sA[wv], lo2);
-        sB[wv] = fmin(sB[wv], hi2);
+      double fa = sFA[k], fb = sFB[k];
+      int ca = sCA[k], cb = sCB[k], na = sNA[k], nb = sNB[k];
+      if (ia >= 0) {
+        fa = ptDet[ia];
+        ca = ptCnt[ia];
+        na = ptLess[ia];
       }
+      if (ib >= 0) {
+        fb = ptDet[ib];
+        cb = ptCnt[ib];
+        nb = ptLess[ib];
+      }
+      const bool isolated = cb - ca == 1 && na == nb && fa != 0.0 && fb != 0.0 &&
+                            (fa < 0.0) != (fb < 0.0) && isfinite(fa) && isfinite(fb);
+      const bool slow = sGuide[k] && bk - ak > 0.25 * (b0 - a0);
+      sA[k] = ak;
+      sB[k] = bk;
+      sFA[k] = fa;
+      sFB[k] = fb;
+      sCA[k] = ca;
+      sCB[k] = cb;
+      sNA[k] = na;
+      sNB[k] = nb;
+      sGuide[k] = isolated && !slow;
+      sEst[k] = isolated ? ak + (bk - ak) * (fa / (fa - fb)) : ak;
     }
     __syncthreads();
     bool done = true;
