@@ -304,8 +304,11 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   //    them agree): det S(mu) is then smooth on the bracket and changes sign once, at the
   //    eigenvalue, and the next round centres the bracket's points on the regula falsi
   //    estimate from det S at the two ends (offsets: guided_offset).  A guided round that
-  //    shrinks its bracket by less than 4x is followed by a uniform one.  Where the points
-  //    go changes only how fast the brackets shrink, never what they contain.
+  //    shrinks its bracket by less than 4x is followed by a uniform one.  The first round
+  //    puts a bracket's points below the eigenvalue this level step started from (the
+  //    previous level's, or the coarse one), at 1e-1 down to 1e-6 of it: eigenvalues move
+  //    little from level to level.  Where the points go changes only how fast the
+  //    brackets shrink, never what they contain.
   constexpr int GS = rr_group_lanes(NTR);
   constexpr int G = NTR / GS;  // 16 >= 2 Q
   constexpr int GQ = G / Q;    // points per bracket, >= 2
@@ -315,6 +318,8 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   const int kk = active ? kb : 0;
   const double off = guided_offset(j, GQ);
   const double frac = (double)(j + 1) / (double)(GQ + 1);  // uniform position
+  const double warm = P.lam[(1 - dst) * MLC_MAX_Q + kk] *
+                      (1.0 - 1e-1 * pow(1e-5, (double)j / (double)(GQ - 1)));
   __shared__ double sA[Q], sB[Q], sFA[Q], sFB[Q], sEst[Q], ptMu[G], ptDet[G];
   __shared__ int sCA[Q], sCB[Q], sNA[Q], sNB[Q], sGuide[Q], ptCnt[G], ptLess[G];
   if (tid < Q) {
@@ -329,7 +334,9 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   for (int round = 0; round < 200; ++round) {
     const double a = sA[kk], bnd = sB[kk];
     double mu = a + (bnd - a) * frac;
-    if (sGuide[kk]) {
+    if (round == 0) {
+      if (warm > a && warm < bnd) mu = warm;
+    } else if (sGuide[kk]) {
       const double gm = sEst[kk] + off * (bnd - a);
       mu = (gm > a && gm < bnd) ? gm : a + 0.5 * (bnd - a);
     }
