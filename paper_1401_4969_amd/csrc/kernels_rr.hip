@@ -74,38 +74,69 @@ __device__ int neg_inertia(double (&S)[Q * (Q + 1) / 2], double& det) {
   return n;
 }
 
-// Solve A x = b (Gaussian elimination, partial pivoting; A row-major QxQ and b in LDS, one
-// thread), x returned in b.
+// LU factorisation with partial pivoting of a QxQ matrix held in registers (indices are
+// compile-time constants and row exchanges are selects, so nothing leaves registers):
+// piv[k] is the row exchanged with row k at step k, the multipliers of step k are left in
+// column k below the diagonal, U above; an exact zero pivot is nudged.
 template <int Q>
-__device__ void small_solve(double* A, double* b) {
+__device__ __forceinline__ void lu_factor(double (&A)[Q][Q], int (&piv)[Q]) {
+#pragma unroll
   for (int k = 0; k < Q; ++k) {
     int p = k;
+    double best = fabs(A[k][k]);
+#pragma unroll
     for (int i = k + 1; i < Q; ++i)
-      if (fabs(A[i * Q + k]) > fabs(A[p * Q + k])) p = i;
-    if (p != k) {
-      for (int j = 0; j < Q; ++j) {
-        const double t = A[k * Q + j];
-        A[k * Q + j] = A[p * Q + j];
-        A[p * Q + j] = t;
+      if (fabs(A[i][k]) > best) {
+        best = fabs(A[i][k]);
+        p = i;
       }
-      const double t = b[k];
-      b[k] = b[p];
-      b[p] = t;
-    }
-    double d = A[k * Q + k];
-    if (d == 0.0) d = 1e-300;
+    piv[k] = p;
+#pragma unroll
     for (int i = k + 1; i < Q; ++i) {
-      const double f = A[i * Q + k] / d;
-      for (int j = k; j < Q; ++j) A[i * Q + j] -= f * A[k * Q + j];
-      b[i] -= f * b[k];
+      const bool sw = i == p;
+#pragma unroll
+      for (int j = k; j < Q; ++j) {
+        const double t = A[k][j];
+        A[k][j] = sw ? A[i][j] : t;
+        A[i][j] = sw ? t : A[i][j];
+      }
+    }
+    double d = A[k][k];
+    if (d == 0.0) d = 1e-300;
+    A[k][k] = d;
+#pragma unroll
+    for (int i = k + 1; i < Q; ++i) {
+      const double f = A[i][k] / d;
+      A[i][k] = f;
+#pragma unroll
+      for (int j = k + 1; j < Q; ++j) A[i][j] -= f * A[k][j];
     }
   }
+}
+
+// Solve with the factors of lu_factor: the exchanges and eliminations replayed on b in
+// the order of the factorisation, then back substitution; x returned in b.
+template <int Q>
+__device__ __forceinline__ void lu_solve(const double (&A)[Q][Q], const int (&piv)[Q],
+                                         double (&b)[Q]) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+#pragma unroll
+    for (int i = k + 1; i < Q; ++i) {
+      const bool sw = i == piv[k];
+      const double t = b[k];
+      b[k] = sw ? b[i] : t;
+      b[i] = sw ? t : b[i];
+    }
+#pragma unroll
+    for (int i = k + 1; i < Q; ++i) b[i] -= A[i][k] * b[k];
+  }
+#pragma unroll
   for (int k = Q - 1; k >= 0; --k) {
     double s = b[k];
-    for (int j = k + 1; j < Q; ++j) s -= A[k * Q + j] * b[j];
-    double d = A[k * Q + k];
-    if (d == 0.0) d = 1e-300;
-    b[k] = s / d;
+#pragma unroll
+    for (int j = k + 1; j < Q; ++j) s -= A[k][j] * b[j];
+    b[k] = s / A[k][k];
   }
 }
 
@@ -142,7 +173,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   __shared__ double vals[NV];
   __shared__ double sAlpha[Q * Q], sBeta[Q * Q];
   __shared__ double sL[Q * Q], sW[Q * Q];
-  __shared__ double sMu[Q], sT[Q], sSol[Q];
+  __shared__ double sMu[Q], sT[Q];
   __shared__ double sBw[Q * Q], sAw[Q * Q], sX[Q * Q], sWm[Q * Q];  // one-thread work arrays
   extern __shared__ double dyn[];
   const ProbDev& P = probs[blockIdx.x];
@@ -429,20 +460,32 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   if (tid < Q) sMu[tid] = 0.5 * (sA[tid] + sB[tid]);
   __syncthreads();
   // 7. eigenvectors by inverse iteration on T - sigma I (two steps), classical
-  //    Gram-Schmidt against the previous ones
+  //    Gram-Schmidt against the previous ones.  Every entry of a vector is read and
+  //    written by one thread only (entries tid, tid + NTR, ...), so only the reductions
+  //    of a step need barriers, and every thread solves the q x q Schur system itself, in
+  //    registers.  The Schur matrix W - sigma I - sum_r z_r z_r^T / (Lambda_r - sigma)
+  //    depends on sigma only: it is summed and factored in the first step and the factors
+  //    are reused in the second.  Reduction slots: Schur sums at 0 .. Q + Q^2 - 1,
+  //    Gram-Schmidt products after them, the norm last, so no slot is rewritten while
+  //    another wave may still read it.
   const int n = nH + Q;
+  const int lane = tid & 63, wv = tid >> 6;
+  constexpr int GS_SLOT = Q + Q * Q, NORM_SLOT = GS_SLOT + Q;
   for (int k = 0; k < Q; ++k) {
     double* x = X + k * n;
     const double mu = sMu[k];
     const double sigma = mu - fmax(8.0 * 2.220446049250313e-16 * fabs(mu), 1e-300);
     for (int r = tid; r < n; r += NTR) x[r] = 1.0 + 0.01 * (double)((r * 7 + k * 13) % 17);
-    __syncthreads();
+    double A[Q][Q];  // LU factors of the Schur matrix (multipliers below the diagonal)
+    int piv[Q];
+#pragma unroll
     for (int iter = 0; iter < 2; ++iter) {
-      double Sp[Q * (Q + 1) / 2], rp[Q];  // packed lower triangle
+      constexpr int NS = Q * (Q + 1) / 2;
+      double rp[Q], Sp[NS];  // packed lower triangle
 #pragma unroll
       for (int i = 0; i < Q; ++i) rp[i] = 0.0;
 #pragma unroll
-      for (int e = 0; e < Q * (Q + 1) / 2; ++e) Sp[e] = 0.0;
+      for (int e = 0; e < NS; ++e) Sp[e] = 0.0;
       for (int r = tid; r < nH; r += NTR) {
         double d = Lam[r] - sigma;
         if (d == 0.0) d = 1e-300;
@@ -451,65 +494,87 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           rp[i] += Z[r * Q + i] * xr * inv;
+          if (iter == 0) {
 #pragma unroll
-          for (int j = 0; j <= i; ++j) Sp[tri(i, j)] += Z[r * Q + i] * Z[r * Q + j] * inv;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        park(rp[i], i, park_lds, NV);
-#pragma unroll
-        for (int j = 0; j <= i; ++j) park(Sp[tri(i, j)], Q + i * Q + j, park_lds, NV);
-      }
-      __syncthreads();
-      for (int v = tid; v < Q + Q * Q; v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
-      __syncthreads();
-      if (tid == 0) {  // the Schur system in LDS (sAw as its matrix, sSol as b then x)
-        double* A = sAw;
-        for (int i = 0; i < Q; ++i) {
-          sSol[i] = x[nH + i] - vals[i];
-          for (int j = 0; j <= i; ++j) {
-            A[i * Q + j] = sW[i * Q + j] - (i == j ? sigma : 0.0) - vals[Q + i * Q + j];
-            A[j * Q + i] = A[i * Q + j];
+            for (int j = 0; j <= i; ++j) Sp[tri(i, j)] += Z[r * Q + i] * Z[r * Q + j] * inv;
           }
         }
-        small_solve<Q>(A, sSol);
+      }
+      // every wave sum first, then one store per wave (a store after each sum would
+      // serialise the reductions)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) rp[i] = wave_sum(rp[i]);
+      if (iter == 0) {
+#pragma unroll
+        for (int e = 0; e < NS; ++e) Sp[e] = wave_sum(Sp[e]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          park_lds[wv * NV + i] = rp[i];
+          if (iter == 0) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j) park_lds[wv * NV + Q + i * Q + j] = Sp[tri(i, j)];
+          }
+        }
       }
       __syncthreads();
-      for (int r = tid; r < nH; r += NTR) {
-        double d = Lam[r] - sigma;
-        if (d == 0.0) d = 1e-300;
-        double s = x[r];
-        for (int i = 0; i < Q; ++i) s -= Z[r * Q + i] * sSol[i];
-        x[r] = s / d;
-      }
-      if (tid < Q) x[nH + tid] = sSol[tid];
+      for (int v = tid; v < (iter == 0 ? Q + Q * Q : Q); v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
       __syncthreads();
+      double sol[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) sol[i] = x[nH + i] - vals[i];
+      if (iter == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j) {
+            A[i][j] = sW[i * Q + j] - (i == j ? sigma : 0.0) - vals[Q + i * Q + j];
+            A[j][i] = A[i][j];
+          }
+        lu_factor<Q>(A, piv);
+      }
+      lu_solve<Q>(A, piv, sol);
+      for (int r = tid; r < n; r += NTR) {
+        if (r < nH) {
+          double d = Lam[r] - sigma;
+          if (d == 0.0) d = 1e-300;
+          double s = x[r];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) s -= Z[r * Q + i] * sol[i];
+          x[r] = s / d;
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            if (r == nH + i) x[r] = sol[i];
+        }
+      }
       if (k > 0) {
+        double c[Q];
         for (int kp = 0; kp < k; ++kp) {
           const double* xp = X + kp * n;
           double d = 0.0;
           for (int r = tid; r < n; r += NTR) d += x[r] * xp[r];
-          park(d, kp, park_lds, NV);
+          c[kp] = wave_sum(d);
         }
+        if (lane == 0)
+          for (int kp = 0; kp < k; ++kp) park_lds[wv * NV + GS_SLOT + kp] = c[kp];
         __syncthreads();
-        for (int v = tid; v < k; v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
-        __syncthreads();
+        for (int kp = 0; kp < k; ++kp) c[kp] = gather<NWR>(GS_SLOT + kp, park_lds, NV);
         for (int r = tid; r < n; r += NTR) {
           double s = x[r];
-          for (int kp = 0; kp < k; ++kp) s -= vals[kp] * X[kp * n + r];
+          for (int kp = 0; kp < k; ++kp) s -= c[kp] * X[kp * n + r];
           x[r] = s;
         }
-        __syncthreads();
       }
       double nr = 0.0;
       for (int r = tid; r < n; r += NTR) nr += x[r] * x[r];
-      park(nr, 0, park_lds, NV);
+      park(nr, NORM_SLOT, park_lds, NV);
       __syncthreads();
-      const double inv = 1.0 / sqrt(gather<NWR>(0, park_lds, NV));
+      const double inv = 1.0 / sqrt(gather<NWR>(NORM_SLOT, park_lds, NV));
       for (int r = tid; r < n; r += NTR) x[r] *= inv;
-      __syncthreads();
     }
+    __syncthreads();  // the q trailing entries, written by their own threads, are read below
     // 8. back to the original basis: u_k = P V (y - g t) + u~ t, t = L^-T s
     if (tid == 0) {
       double t[Q];
