@@ -229,7 +229,11 @@ __device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, 
 // intervals where the rings fit.
 // CMP > 0 (rows of at most 64 CMP nodes): the right-hand side rows of the next band
 // step's first stage are loaded into registers at the end of this step's first stage, so
-// their memory latency overlaps the three later stages instead of opening the next step.
+// their memory latency overlaps the three later stages instead of opening the next step;
+// the second and third stages' rows (cache hits) are loaded one stage ahead, at the start
+// of the step and of the second stage, so each waits behind the stage before it and its
+// barrier rather than after it.  (Used with a constant coefficient in FP64: with variable
+// coefficients, or in FP32, the extra registers measured slower.)
 template <int NT, int KIND, typename T, int R, int CMP = 0>
 __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
                              const T* b, T* za, T* bc, T omega, T* ring) {
@@ -254,8 +258,23 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
       }
     }
   };
+  // rows y = kk BH + w + NW q - off of b into regs (zero outside the tile)
+  auto load_rows = [&](T (&regs)[R][CP], int kk, int off) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int y = kk * BH + w + NW * q - off;
+      const bool inside = y >= 0 && y < ny;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        const int ix = lane + 64 * c;
+        regs[q][c] = b[(inside && ix < nx) ? (unsigned)(y * nx + ix) : 0u];
+      }
+    }
+  };
+  T bb2[R][CP], bc3[R][CP];  // stage B and C right-hand sides (CMP > 0)
   if constexpr (CMP > 0) load_a(0);
   for (int k = 0; k * BH - 3 < ny || k * (BH / 2) - 2 < ncy; ++k) {
+    if constexpr (CMP > 0) load_rows(bb2, k, 2);  // stage B's right-hand side, a stage ahead
     if constexpr (CMP > 0) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -298,6 +317,7 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
       }
     }
     __syncthreads();
+    if constexpr (CMP > 0) load_rows(bc3, k, 3);  // stage C's right-hand side, one stage ahead
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int yb = k * BH + w + NW * q - 2;
@@ -307,12 +327,26 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
           const T* rs = row(r1, yb - 1);
           const T* rc = row(r1, yb);
           const T* rn = row(r1, yb + 1);
-          for (int ix = lane; ix < nx; ix += 64) {
-            const unsigned i = (unsigned)(yb * nx + ix);
-            T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega);
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
-            dst[ix] = v;
-            za[i] = v;
+          if constexpr (CMP > 0) {
+#pragma unroll
+            for (int c = 0; c < CP; ++c) {
+              const int ix = lane + 64 * c;
+              if (ix < nx) {
+                const unsigned i = (unsigned)(yb * nx + ix);
+                T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bb2[q][c], ix, yb, omega);
+                v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+                dst[ix] = v;
+                za[i] = v;
+              }
+            }
+          } else {
+            for (int ix = lane; ix < nx; ix += 64) {
+              const unsigned i = (unsigned)(yb * nx + ix);
+              T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega);
+              v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
+              dst[ix] = v;
+              za[i] = v;
+            }
           }
         } else {
           for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
@@ -329,11 +363,23 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
           const T* rs = row(r2, yc - 1);
           const T* rc = row(r2, yc);
           const T* rn = row(r2, yc + 1);
-          for (int ix = lane; ix < nx; ix += 64) {
-            T d;
-            const T v =
-                b[(unsigned)(yc * nx + ix)] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
-            dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
+          if constexpr (CMP > 0) {
+#pragma unroll
+            for (int c = 0; c < CP; ++c) {
+              const int ix = lane + 64 * c;
+              if (ix < nx) {
+                T d;
+                const T v = bc3[q][c] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
+                dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
+              }
+            }
+          } else {
+            for (int ix = lane; ix < nx; ix += 64) {
+              T d;
+              const T v =
+                  b[(unsigned)(yc * nx + ix)] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
+              dst[ix] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
+            }
           }
         } else {
           for (int ix = lane; ix < nx; ix += 64) dst[ix] = T(0);
@@ -366,9 +412,9 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
 // later stage reads za at or below that row).  za is read and written once and b read
 // once from HBM, instead of the 8 passes of a separate interpolation and two sweeps.
 // CMP > 0 (rows of at most 64 CMP nodes): the right-hand side rows of the second stage are
-// loaded into registers before the first stage, so the two stages' memory latencies
-// overlap, and the iterate rows of the next step's first stage are loaded at the end of
-// this step.
+// loaded into registers before the first stage and those of the third at the start of the
+// second, so their memory latencies overlap the stage before, and the iterate rows of the
+// next step's first stage are loaded at the end of this step.
 template <int NT, int KIND, typename T, bool DOT, int R, int CMP = 0>
 __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
                               const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
@@ -452,6 +498,19 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
       }
     }
     __syncthreads();
+    T bb3[R][CP];  // stage C's right-hand side, loaded a stage ahead (CMP > 0)
+    if constexpr (CMP > 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int yc = k * BH + w + NW * q - 3;
+        const bool inside = yc >= 0 && yc < ny;
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+          const int ix = lane + 64 * c;
+          bb3[q][c] = b[(inside && ix < nx) ? (unsigned)(yc * nx + ix) : 0u];
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int yb = k * BH + w + NW * q - 2;
@@ -490,6 +549,21 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
         const T* rs = row(ringB, yc - 1);
         const T* rc = row(ringB, yc);
         const T* rn = row(ringB, yc + 1);
+        if constexpr (CMP > 0) {
+#pragma unroll
+          for (int c = 0; c < CP; ++c) {
+            const int ix = lane + 64 * c;
+            if (ix < nx) {
+              const unsigned i = (unsigned)(yc * nx + ix);
+              const T bi = bb3[q][c];
+              const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega);
+              const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
+              za[i] = dof ? v : T(0);
+              if (DOT && dof) *acc += (double)bi * (double)v;
+            }
+          }
+          continue;
+        }
         for (int ix = lane; ix < nx; ix += 64) {
           const unsigned i = (unsigned)(yc * nx + ix);
           const T bi = b[i];
