@@ -413,8 +413,9 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
 // once from HBM, instead of the 8 passes of a separate interpolation and two sweeps.
 // CMP > 0 (rows of at most 64 CMP nodes): the right-hand side rows of the second stage are
 // loaded into registers before the first stage and those of the third at the start of the
-// second, so their memory latencies overlap the stage before, and the iterate rows of the
-// next step's first stage are loaded at the end of this step.
+// second, so their memory latencies overlap the stage before; the iterate rows of the
+// next step's first stage are loaded at the end of this step, and the coarse rows it
+// interpolates from are staged in LDS during this step.
 template <int NT, int KIND, typename T, bool DOT, int R, int CMP = 0>
 __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
                               const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
@@ -444,8 +445,44 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
       }
     }
   };
-  if constexpr (CMP > 0) load_z(0);
+  // (CMP > 0) the coarse rows of a step's first stage, staged in LDS one step ahead in the
+  // third ring's space (unused by this pass), two buffers: the loads of step kk + 1 are
+  // issued at the start of step kk and written at the end of its second stage, before a
+  // barrier, so the first stage reads them from LDS instead of waiting on memory
+  constexpr int CBN = (NT / 64) * R / 2 + 3;  // coarse rows a step's first stage touches (max)
+  constexpr int CBV = (CBN * 128 + NT - 1) / NT;  // staged values per thread, rows <= 128
+  T* cbuf = ring + 2 * RING * nx;
+  const int cbs = CBN * ncx;  // one buffer
+  auto cb_row0 = [&](int kk) { return ((kk * BH - 1) >> 1) - 1; };
+  T cv[CBV];
+  auto cb_load = [&](int kk) {
+    const int c0 = cb_row0(kk);
+#pragma unroll
+    for (int u = 0; u < CBV; ++u) {
+      const int e = threadIdx.x + NT * u;
+      const int j = e / ncx, cx = e - j * ncx;
+      const int cy = c0 + j;
+      const bool in = e < cbs && cy >= 0 && cy < ncy;
+      const T v = zc[in ? (unsigned)(cy * ncx + cx) : 0u];
+      cv[u] = in ? v : T(0);
+    }
+  };
+  auto cb_store = [&](int kk) {
+    T* dst = cbuf + (kk & 1) * cbs;
+#pragma unroll
+    for (int u = 0; u < CBV; ++u) {
+      const int e = threadIdx.x + NT * u;
+      if (e < cbs) dst[e] = cv[u];
+    }
+  };
+  if constexpr (CMP > 0) {
+    load_z(0);
+    cb_load(0);
+    cb_store(0);
+    __syncthreads();
+  }
   for (int k = 0; k * BH - 3 < ny; ++k) {
+    if constexpr (CMP > 0) cb_load(k + 1);
     T bb[R][CP];  // second-stage right-hand side (CMP > 0)
     if constexpr (CMP > 0) {
 #pragma unroll
@@ -474,7 +511,11 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
               if (inside) {
                 const int cx = ix >> 1, cy = ya >> 1;
                 const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
-                const T pz = T(0.5) * (at(ax, ay) + at(cx, cy));
+                const T* cb = cbuf + (k & 1) * cbs;
+                const int c0 = cb_row0(k);
+                const T za_ = (ax >= 0 && ax < ncx) ? cb[(ay - c0) * ncx + ax] : T(0);
+                const T zc_ = (cx >= 0 && cx < ncx) ? cb[(cy - c0) * ncx + cx] : T(0);
+                const T pz = T(0.5) * (za_ + zc_);
                 const T old = nz[q][c];
                 v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? old + pz : old;
               }
@@ -541,6 +582,7 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
         }
       }
     }
+    if constexpr (CMP > 0) cb_store(k + 1);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
