@@ -85,24 +85,31 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
   const int nxc = pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
   const int nyc = pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
-  for (int i = 0; i < P.q; ++i) {
-    double acc = 0.0, tot = 0.0;
-    for (int a = 0; a < nyc; ++a) {
-      for (int b = 0; b < nxc; ++b) {
-        const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q + i];
-        if (item < 0) continue;
-        const TileItem& it = items[item];
-        const int nx = it.cw * r - 1;
-        const int lx = gx - (it.cx0 * r + 1), ly = gy - (it.cy0 * r + 1);
-        const double* e = reinterpret_cast<const double*>(store + it.off);
-        const double phi = rx[b] * ry[a];
-        acc += phi * e[(int64_t)ly * nx + lx];
-        tot += phi;
-      }
+  // one item lookup per covering subdomain: its q right-hand sides follow at rhs_stride
+  double acc[MLC_MAX_Q], tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < MLC_MAX_Q; ++i) acc[i] = 0.0;
+  for (int a = 0; a < nyc; ++a) {
+    for (int b = 0; b < nxc; ++b) {
+      const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q];
+      if (item < 0) continue;
+      const TileItem it = items[item];
+      const int nx = it.cw * r - 1;
+      const int lx = gx - (it.cx0 * r + 1), ly = gy - (it.cy0 * r + 1);
+      const char* e0 = store + it.off + ((int64_t)ly * nx + lx) * (int64_t)sizeof(double);
+      const double phi = rx[b] * ry[a];
+#pragma unroll
+      for (int i = 0; i < MLC_MAX_Q; ++i)
+        if (i < P.q)
+          acc[i] += phi * *reinterpret_cast<const double*>(e0 + (int64_t)i * it.rhs_stride);
+      tot += phi;
     }
-    // tot = 0 only on D_j block boundaries with overlap 0, where every e^j vanishes
-    P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + (tot > 0.0 ? acc / tot : 0.0);
   }
+  // tot = 0 only on D_j block boundaries with overlap 0, where every e^j vanishes
+#pragma unroll
+  for (int i = 0; i < MLC_MAX_Q; ++i)
+    if (i < P.q)
+      P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + (tot > 0.0 ? acc[i] / tot : 0.0);
 }
 
 // a5: y_K = K u~ (into res), y_M = M u~ (into ubar), and per-block partial sums of

@@ -63,7 +63,9 @@ struct ProbDev {
 
 // One local solve: subdomain Omega_j of problem prob, right-hand side rhs.
 struct TileItem {
-  int32_t prob, sub, rhs, pad;
+  // rhs_stride: bytes from this item's storage to that of the next right-hand side of the
+  // same subdomain (the q items of a subdomain are consecutive and equally sized)
+  int32_t prob, sub, rhs, rhs_stride;
   int32_t cx0, cy0, cw, ch;   // Omega_j in coarse cells
   int64_t off;                // byte offset of the item's storage
   int64_t inv_off;            // double offset of the subdomain's coarsest-grid inverse

@@ -372,7 +372,20 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
       const int64_t b = fp64_items ? item_bytes_fp64(it.cw, it.ch, s)
                                    : item_bytes_mixed(it.cw, it.ch, s);
       o = align_up(o + (size_t)b);
+      it.rhs_stride = (int32_t)(align_up((size_t)b));
       T.sub_item[(size_t)P.pl[it.prob].sub_item_off + (size_t)it.sub * P.q + it.rhs] = (int32_t)k;
+    }
+    // the gluing reaches right-hand side r of a subdomain at rhs_stride * r bytes from its
+    // first item: the stable sort keeps a subdomain's q equally sized items adjacent
+    for (size_t k = 0; k < all.size(); ++k) {
+      const TileItem& it = all[k];
+      const int32_t first =
+          T.sub_item[(size_t)P.pl[it.prob].sub_item_off + (size_t)it.sub * P.q];
+      if (first < 0 || (size_t)first + (size_t)it.rhs != k ||
+          all[first].off + (int64_t)it.rhs * it.rhs_stride != it.off) {
+        msg = "internal: tile items of a subdomain are not adjacent";
+        return MLC_EINVAL;
+      }
     }
     store_bytes = std::max(store_bytes, o);
     T.items = all;
