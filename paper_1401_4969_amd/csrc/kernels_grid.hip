@@ -21,11 +21,14 @@ __device__ __forceinline__ double interp2(const double* uc, int nc1, int x, int 
 }
 
 // a1 + a2: u_bar = I u_k on level m and the right-hand side of (Aux_Problem),
-// r = lambda_k M u_bar - K u_bar, for each of the q eigenpairs.
+// r = lambda_k M u_bar - K u_bar, for eigenpair i = blockIdx.z (one grid slice per
+// eigenpair, so the loads of all of them are in flight together).
 template <int KIND>
 __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, int m, int src) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
+  const int i = blockIdx.z;
+  if (i >= P.q) return;
   const int N = P.n_c << m;
   const int n1 = N + 1;
   const int64_t nn = (int64_t)n1 * n1;
@@ -42,26 +45,24 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
     W = edge_weights<KIND>(P, m, N, gx, gy);
     Mw = mass_weights<KIND>(P, m, N, gx, gy, mh);
   }
-  for (int i = 0; i < P.q; ++i) {
-    double* ub = P.ubar + (int64_t)i * nn;
-    double* r = P.res + (int64_t)i * nn;
-    if (!dof) {
-      ub[idx] = 0.0;
-      r[idx] = 0.0;
-      continue;
-    }
-    const double* uc = P.u[src] + (int64_t)i * nc1 * nc1;
-    const double c = interp2(uc, nc1, gx, gy);
-    const double e = interp2(uc, nc1, gx + 1, gy), w = interp2(uc, nc1, gx - 1, gy);
-    const double n = interp2(uc, nc1, gx, gy + 1), s = interp2(uc, nc1, gx, gy - 1);
-    const double ne = interp2(uc, nc1, gx + 1, gy + 1), sw = interp2(uc, nc1, gx - 1, gy - 1);
-    double d;
-    const double Ku = apply_k<KIND, double>(W, c, e, w, n, s, ne, sw, d);
-    const double Mu = apply_mass<KIND>(Mw, mh, c, e, w, n, s, ne, sw);
-    const double lam = P.lam[src * MLC_MAX_Q + i];
-    ub[idx] = c;
-    r[idx] = lam * Mu - Ku;
+  double* ub = P.ubar + (int64_t)i * nn;
+  double* r = P.res + (int64_t)i * nn;
+  if (!dof) {
+    ub[idx] = 0.0;
+    r[idx] = 0.0;
+    return;
   }
+  const double* uc = P.u[src] + (int64_t)i * nc1 * nc1;
+  const double c = interp2(uc, nc1, gx, gy);
+  const double e = interp2(uc, nc1, gx + 1, gy), w = interp2(uc, nc1, gx - 1, gy);
+  const double n = interp2(uc, nc1, gx, gy + 1), s = interp2(uc, nc1, gx, gy - 1);
+  const double ne = interp2(uc, nc1, gx + 1, gy + 1), sw = interp2(uc, nc1, gx - 1, gy - 1);
+  double d;
+  const double Ku = apply_k<KIND, double>(W, c, e, w, n, s, ne, sw, d);
+  const double Mu = apply_mass<KIND>(Mw, mh, c, e, w, n, s, ne, sw);
+  const double lam = P.lam[src * MLC_MAX_Q + i];
+  ub[idx] = c;
+  r[idx] = lam * Mu - Ku;
 }
 
 // a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
@@ -144,13 +145,27 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
     Mw = mass_weights<KIND>(P, m, N, gx, gy, mh);
   }
   double uv[MLC_MAX_Q], yk[MLC_MAX_Q], ym[MLC_MAX_Q];
+  // every eigenpair's stencil values are loaded before the first store (a store between
+  // them would keep the next loads from being issued early)
+  double st[MLC_MAX_Q][7];
+#pragma unroll
+  for (int i = 0; i < MLC_MAX_Q; ++i)
+    if (i < q && dof) {
+      const double* u = P.ut + (int64_t)i * nn;
+      st[i][0] = u[idx];
+      st[i][1] = u[idx + 1];
+      st[i][2] = u[idx - 1];
+      st[i][3] = u[idx + n1];
+      st[i][4] = u[idx - n1];
+      st[i][5] = u[idx + n1 + 1];
+      st[i][6] = u[idx - n1 - 1];
+    }
 #pragma unroll
   for (int i = 0; i < MLC_MAX_Q; ++i) {
     uv[i] = yk[i] = ym[i] = 0.0;
     if (i < q && dof) {
-      const double* u = P.ut + (int64_t)i * nn;
-      const double c = u[idx], e = u[idx + 1], w = u[idx - 1], n = u[idx + n1], s = u[idx - n1];
-      const double ne = u[idx + n1 + 1], sw = u[idx - n1 - 1];
+      const double c = st[i][0], e = st[i][1], w = st[i][2], n = st[i][3], s = st[i][4];
+      const double ne = st[i][5], sw = st[i][6];
       uv[i] = c;
       double d;
       yk[i] = apply_k<KIND, double>(W, c, e, w, n, s, ne, sw, d);
@@ -192,10 +207,14 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
 }
 
 // a5 (continued): one level of the transposed interpolation P^T (full weighting on the
-// SW-NE mesh: centre 1, E/W/N/S/NE/SW 1/2) for the 2q border vectors, level l+1 -> l.
+// SW-NE mesh: centre 1, E/W/N/S/NE/SW 1/2) for the 2q border vectors, level l+1 -> l;
+// blockIdx.z selects the vector, so the loads of all vectors are in flight together.
 __global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, int m) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
+  const int q = P.q;
+  const int v = blockIdx.z;
+  if (v >= 2 * q) return;
   const int Nc = P.n_c << l;
   const int nc1 = Nc + 1;
   const int64_t nnc = (int64_t)nc1 * nc1;
@@ -205,23 +224,20 @@ __global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, i
   const int nf1 = 2 * Nc + 1;
   const int64_t nnf = (int64_t)nf1 * nf1;
   const bool dof = is_dof(P.domain, Nc, Ix, Iy);
-  const int q = P.q;
   double* outb = P.rchain + P.rchain_off[l];
-  for (int v = 0; v < 2 * q; ++v) {
-    const double* f;
-    if (l + 1 == m) {
-      f = (v < q ? P.res + (int64_t)v * nnf : P.ubar + (int64_t)(v - q) * nnf);
-    } else {
-      f = P.rchain + P.rchain_off[l + 1] + (int64_t)v * nnf;
-    }
-    double val = 0.0;
-    if (dof) {
-      const int64_t c = (int64_t)(2 * Iy) * nf1 + 2 * Ix;
-      val = f[c] + 0.5 * (f[c + 1] + f[c - 1] + f[c + nf1] + f[c - nf1] + f[c + nf1 + 1] +
-                          f[c - nf1 - 1]);
-    }
-    outb[(int64_t)v * nnc + idx] = val;
+  const double* f;
+  if (l + 1 == m) {
+    f = (v < q ? P.res + (int64_t)v * nnf : P.ubar + (int64_t)(v - q) * nnf);
+  } else {
+    f = P.rchain + P.rchain_off[l + 1] + (int64_t)v * nnf;
   }
+  double val = 0.0;
+  if (dof) {
+    const int64_t c = (int64_t)(2 * Iy) * nf1 + 2 * Ix;
+    val = f[c] + 0.5 * (f[c + 1] + f[c - 1] + f[c + nf1] + f[c - nf1] + f[c + nf1 + 1] +
+                        f[c - nf1 - 1]);
+  }
+  outb[(int64_t)v * nnc + idx] = val;
 }
 
 // a6 (first half): f = V^T a, g = V^T b for the coarse eigenbasis V, one wave per column.
@@ -269,6 +285,8 @@ __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
 __global__ __launch_bounds__(NTG) void k_assemble(const ProbDev* probs, int m, int dst) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
+  const int k = blockIdx.z;  // eigenpair (one grid slice each)
+  if (k >= P.q) return;
   const int N = P.n_c << m;
   const int n1 = N + 1;
   const int64_t nn = (int64_t)n1 * n1;
@@ -281,20 +299,18 @@ __global__ __launch_bounds__(NTG) void k_assemble(const ProbDev* probs, int m, i
   const int I = min(gx >> m, nc - 1), J = min(gy >> m, nc - 1);
   const int a = gx - (I << m), b = gy - (J << m);
   const double inv_r = 1.0 / (double)(1 << m);
-  for (int k = 0; k < q; ++k) {
-    double val = 0.0;
-    if (dof) {
-      const double* c = P.cH_grid + (int64_t)k * nc1 * nc1;
-      const double c00 = c[J * nc1 + I], c10 = c[J * nc1 + I + 1];
-      const double c01 = c[(J + 1) * nc1 + I], c11 = c[(J + 1) * nc1 + I + 1];
-      if (a >= b)
-        val = c00 + (a * (c10 - c00) + b * (c11 - c10)) * inv_r;
-      else
-        val = c00 + (b * (c01 - c00) + a * (c11 - c01)) * inv_r;
-      for (int i = 0; i < q; ++i) val += P.rr_t[k * q + i] * P.ut[(int64_t)i * nn + idx];
-    }
-    P.u[dst][(int64_t)k * nn + idx] = val;
+  double val = 0.0;
+  if (dof) {
+    const double* c = P.cH_grid + (int64_t)k * nc1 * nc1;
+    const double c00 = c[J * nc1 + I], c10 = c[J * nc1 + I + 1];
+    const double c01 = c[(J + 1) * nc1 + I], c11 = c[(J + 1) * nc1 + I + 1];
+    if (a >= b)
+      val = c00 + (a * (c10 - c00) + b * (c11 - c10)) * inv_r;
+    else
+      val = c00 + (b * (c01 - c00) + a * (c11 - c01)) * inv_r;
+    for (int i = 0; i < q; ++i) val += P.rr_t[k * q + i] * P.ut[(int64_t)i * nn + idx];
   }
+  P.u[dst][(int64_t)k * nn + idx] = val;
 }
 
 // ---- setup kernels ----
@@ -618,8 +634,8 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + NTG - 1) / NTG); }
 }  // namespace
 
 hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, int m, int src,
-                                   int64_t max_nodes, hipStream_t s) {
-  dim3 g(nblocks(max_nodes), nprob);
+                                   int64_t max_nodes, int max_q, hipStream_t s) {
+  dim3 g(nblocks(max_nodes), nprob, max_q);
   if (kind == 0)
     hipLaunchKernelGGL(k_prolong_residual<0>, g, dim3(NTG), 0, s, probs, m, src);
   else if (kind == 1)
@@ -654,8 +670,9 @@ hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int
 }
 
 hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(nblocks(max_nodes_l), nprob), dim3(NTG), 0, s, probs, l, m);
+                           int max_q, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3(nblocks(max_nodes_l), nprob, 2 * max_q), dim3(NTG), 0, s,
+                     probs, l, m);
   return hipGetLastError();
 }
 
@@ -671,9 +688,9 @@ hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hip
 }
 
 hipError_t launch_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_assemble, dim3(nblocks(max_nodes), nprob), dim3(NTG), 0, s, probs, m,
-                     dst);
+                           int max_q, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble, dim3(nblocks(max_nodes), nprob, max_q), dim3(NTG), 0, s, probs,
+                     m, dst);
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 
 // ---- one correction step (Algorithm 4.1) at level m, ping-pong src -> dst ----
 hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, int m, int src,
-                                   int64_t max_nodes, hipStream_t s);
+                                   int64_t max_nodes, int max_q, hipStream_t s);
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
                             double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
@@ -44,14 +44,14 @@ hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* item
 hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
                            hipStream_t s);
 hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
-                           hipStream_t s);
+                           int max_q, hipStream_t s);
 hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
 hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, int max_nH, int dst,
                            hipStream_t s);
 hipError_t launch_transpose_v(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
 hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s);
 hipError_t launch_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
-                           hipStream_t s);
+                           int max_q, hipStream_t s);
 
 // ---- setup ----
 hipError_t launch_coarsen_kappa(const double* lo_f, const double* up_f, double* lo_c,
