@@ -240,7 +240,8 @@ __global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, i
   outb[(int64_t)v * nnc + idx] = val;
 }
 
-// a6 (first half): f = V^T a, g = V^T b for the coarse eigenbasis V, one wave per column.
+// a6 (first half): f = V^T a, g = V^T b for the coarse eigenbasis V, one wave per column
+// and border vector.
 __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
   const ProbDev& P = probs[blockIdx.y];
   const int c = blockIdx.x * (NTG / 64) + (threadIdx.x >> 6);
@@ -250,17 +251,17 @@ __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
   const int nc1 = P.n_c + 1;
   const double* a = P.rchain + P.rchain_off[0];
   const double* col = P.V + (int64_t)c * nH;
-  for (int v = 0; v < 2 * q; ++v) {
-    const double* src = a + (int64_t)v * nc1 * nc1;
-    double s = 0.0;
-    for (int r = lane; r < nH; r += 64) s += col[r] * src[P.coarse_nodes[r]];
-    s = wave_sum(s);
-    if (lane == 0) P.fg[(int64_t)v * nH + c] = s;
-  }
+  const int v = blockIdx.z;  // border vector (one grid slice each)
+  if (v >= 2 * q) return;
+  const double* src = a + (int64_t)v * nc1 * nc1;
+  double s = 0.0;
+  for (int r = lane; r < nH; r += 64) s += col[r] * src[P.coarse_nodes[r]];
+  s = wave_sum(s);
+  if (lane == 0) P.fg[(int64_t)v * nH + c] = s;
 }
 
 // a7 (first half): coarse nodal coefficients c_H = V y_hat on the coarse grid, one wave
-// per coarse node sweeping a row of V^T.
+// per coarse node and eigenpair sweeping a row of V^T.
 __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
   const ProbDev& P = probs[blockIdx.y];
   const int nc1 = P.n_c + 1;
@@ -269,16 +270,16 @@ __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
   if (node >= nc1 * nc1) return;
   const int r = P.coarse_index[node];
   const int nH = P.nH;
-  for (int k = 0; k < P.q; ++k) {
-    double s = 0.0;
-    if (r >= 0) {
-      const double* y = P.rr_y + (int64_t)k * nH;
-      const double* row = P.VT + (int64_t)r * nH;
-      for (int c = lane; c < nH; c += 64) s += row[c] * y[c];
-      s = wave_sum(s);
-    }
-    if (lane == 0) P.cH_grid[(int64_t)k * nc1 * nc1 + node] = s;
+  const int k = blockIdx.z;  // eigenpair (one grid slice each)
+  if (k >= P.q) return;
+  double s = 0.0;
+  if (r >= 0) {
+    const double* y = P.rr_y + (int64_t)k * nH;
+    const double* row = P.VT + (int64_t)r * nH;
+    for (int c = lane; c < nH; c += 64) s += row[c] * y[c];
+    s = wave_sum(s);
   }
+  if (lane == 0) P.cH_grid[(int64_t)k * nc1 * nc1 + node] = s;
 }
 
 // a7: u_{k+1} = P_{0->m} c_H + sum_i t_i u~_i on level m.
@@ -676,14 +677,17 @@ hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStream_t s) {
-  hipLaunchKernelGGL(k_rr_project, dim3((max_nH + 3) / 4, nprob), dim3(NTG), 0, s, probs);
+hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, int max_q,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rr_project, dim3((max_nH + 3) / 4, nprob, 2 * max_q), dim3(NTG), 0, s,
+                     probs);
   return hipGetLastError();
 }
 
-hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s) {
-  hipLaunchKernelGGL(k_rr_combine, dim3((max_nc1sq + NTG / 64 - 1) / (NTG / 64), nprob), dim3(NTG),
-                     0, s, probs);
+hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, int max_q,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rr_combine, dim3((max_nc1sq + NTG / 64 - 1) / (NTG / 64), nprob, max_q),
+                     dim3(NTG), 0, s, probs);
   return hipGetLastError();
 }
 

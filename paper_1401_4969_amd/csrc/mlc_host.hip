@@ -745,9 +745,9 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
   MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, st));
   for (int l = s - 1; l >= 0; --l)
     MLC_HIP(b, launch_restrict(b->dprob, P.n, l, s, T.nodes_l[l], P.q, st));
-  MLC_HIP(b, launch_rr_project(b->dprob, P.n, P.max_nH, st));
+  MLC_HIP(b, launch_rr_project(b->dprob, P.n, P.max_nH, P.q, st));
   MLC_HIP(b, launch_rr_solve(P.q, b->dprob, P.n, s, P.max_nH, dst, st));
-  MLC_HIP(b, launch_rr_combine(b->dprob, P.n, P.max_nc1sq, st));
+  MLC_HIP(b, launch_rr_combine(b->dprob, P.n, P.max_nc1sq, P.q, st));
   MLC_HIP(b, launch_assemble(b->dprob, P.n, s, dst, T.max_nodes, P.q, st));
   if (P.tape.on) {  // keep this level's forward state for the reverse sweep
     const TapeLayout& TL = P.tape;

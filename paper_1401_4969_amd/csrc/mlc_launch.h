@@ -45,11 +45,13 @@ hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int
                            hipStream_t s);
 hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
                            int max_q, hipStream_t s);
-hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
+hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, int max_q,
+                             hipStream_t s);
 hipError_t launch_rr_solve(int max_q, const ProbDev* probs, int nprob, int m, int max_nH, int dst,
                            hipStream_t s);
 hipError_t launch_transpose_v(const ProbDev* probs, int nprob, int max_nH, hipStream_t s);
-hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, hipStream_t s);
+hipError_t launch_rr_combine(const ProbDev* probs, int nprob, int max_nc1sq, int max_q,
+                             hipStream_t s);
 hipError_t launch_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
                            int max_q, hipStream_t s);
 
