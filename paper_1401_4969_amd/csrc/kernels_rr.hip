@@ -21,9 +21,10 @@
 // of the short loops).  Reductions are batched: each wave reduces its partial sums across lanes (DPP
 // moves) and writes them to LDS, and one barrier later every value is summed over the
 // waves in a fixed order (deterministic).  Multisection evaluates G points per round, GS
-// consecutive lanes per point (about 32 terms each), reduced by DPP inside the wave; thread
-// k then updates bracket k from all points and places its next points.  The
-// inverse-iteration vectors live in LDS.
+// consecutive lanes per point (about 32 terms each), reduced by DPP inside the wave; wave
+// k then updates bracket k from all points (one per lane: DPP extremes, a ballot for the
+// first point attaining each) and places its next points.  The inverse-iteration vectors
+// live in LDS.
 #include "mlc_launch.h"
 
 namespace {
@@ -405,50 +406,58 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
       ptCnt[pnt] = active ? (int)nless + neg : -1;
     }
     __syncthreads();
-    if (tid < Q) {  // thread k tightens bracket k from every point and places its next round
-      const int k = tid;
-      const double a0 = sA[k], b0 = sB[k];
-      double ak = a0, bk = b0;
-      int ia = -1, ib = -1;  // the points that become the ends (all loads issued at once)
-#pragma unroll
-      for (int p2 = 0; p2 < G; ++p2) {
-        const int c = ptCnt[p2];
-        const double m2 = ptMu[p2];
-        const bool up = c >= k + 1, down = c >= 0 && c <= k;
-        if (up && m2 < bk) {
-          bk = m2;
-          ib = p2;
+    if ((tid >> 6) < Q) {  // wave k tightens bracket k from every point (lane p: point p)
+      const int k = tid >> 6, ln = tid & 63;
+      const double inf = __builtin_inf();
+      const int cp = ln < G ? ptCnt[ln] : -1;
+      const double mp = ln < G ? ptMu[ln] : 0.0;
+      const bool up = cp >= k + 1, down = cp >= 0 && cp <= k;
+      // the highest lower and the lowest upper point, each the first such point in order
+      const auto mx = [](double x, double y) { return fmax(x, y); };
+      const auto mn = [](double x, double y) { return fmin(x, y); };
+      double lo2 = group_reduce_last(down ? mp : -inf, 64, -inf, mx);
+      double hi2 = group_reduce_last(up ? mp : inf, 64, inf, mn);
+      lo2 = read_lane_f64(lo2, 63);
+      hi2 = read_lane_f64(hi2, 63);
+      const unsigned long long bl = __ballot(down && mp == lo2), bh = __ballot(up && mp == hi2);
+      if (ln == 0) {
+        const double a0 = sA[k], b0 = sB[k];
+        double ak = a0, bk = b0;
+        int ia = -1, ib = -1;  // the points that become the ends
+        if (bl != 0ull && lo2 > a0) {
+          ak = lo2;
+          ia = __ffsll(bl) - 1;
         }
-        if (down && m2 > ak) {
-          ak = m2;
-          ia = p2;
+        if (bh != 0ull && hi2 < b0) {
+          bk = hi2;
+          ib = __ffsll(bh) - 1;
         }
+        double fa = sFA[k], fb = sFB[k];
+        int ca = sCA[k], cb = sCB[k], na = sNA[k], nb = sNB[k];
+        if (ia >= 0) {
+          fa = ptDet[ia];
+          ca = ptCnt[ia];
+          na = ptLess[ia];
+        }
+        if (ib >= 0) {
+          fb = ptDet[ib];
+          cb = ptCnt[ib];
+          nb = ptLess[ib];
+        }
+        const bool isolated = cb - ca == 1 && na == nb && fa != 0.0 && fb != 0.0 &&
+                              (fa < 0.0) != (fb < 0.0) && isfinite(fa) && isfinite(fb);
+        const bool slow = sGuide[k] && bk - ak > 0.25 * (b0 - a0);
+        sA[k] = ak;
+        sB[k] = bk;
+        sFA[k] = fa;
+        sFB[k] = fb;
+        sCA[k] = ca;
+        sCB[k] = cb;
+        sNA[k] = na;
+        sNB[k] = nb;
+        sGuide[k] = isolated && !slow;
+        sEst[k] = isolated ? ak + (bk - ak) * (fa / (fa - fb)) : ak;
       }
-      double fa = sFA[k], fb = sFB[k];
-      int ca = sCA[k], cb = sCB[k], na = sNA[k], nb = sNB[k];
-      if (ia >= 0) {
-        fa = ptDet[ia];
-        ca = ptCnt[ia];
-        na = ptLess[ia];
-      }
-      if (ib >= 0) {
-        fb = ptDet[ib];
-        cb = ptCnt[ib];
-        nb = ptLess[ib];
-      }
-      const bool isolated = cb - ca == 1 && na == nb && fa != 0.0 && fb != 0.0 &&
-                            (fa < 0.0) != (fb < 0.0) && isfinite(fa) && isfinite(fb);
-      const bool slow = sGuide[k] && bk - ak > 0.25 * (b0 - a0);
-      sA[k] = ak;
-      sB[k] = bk;
-      sFA[k] = fa;
-      sFB[k] = fb;
-      sCA[k] = ca;
-      sCB[k] = cb;
-      sNA[k] = na;
-      sNB[k] = nb;
-      sGuide[k] = isolated && !slow;
-      sEst[k] = isolated ? ak + (bk - ak) * (fa / (fa - fb)) : ak;
     }
     __syncthreads();
     bool done = true;
