@@ -66,6 +66,8 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
 }
 
 // a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
+// QM: a bound on q (1, 2, 4 or 8) that sizes the per-eigenpair registers.
+template <int QM>
 __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const TileItem* items,
                                                    const int32_t* sub_item, const char* store,
                                                    int m) {
@@ -87,9 +89,9 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   const int nxc = pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
   const int nyc = pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
   // one item lookup per covering subdomain: its q right-hand sides follow at rhs_stride
-  double acc[MLC_MAX_Q], tot = 0.0;
+  double acc[QM], tot = 0.0;
 #pragma unroll
-  for (int i = 0; i < MLC_MAX_Q; ++i) acc[i] = 0.0;
+  for (int i = 0; i < QM; ++i) acc[i] = 0.0;
   for (int a = 0; a < nyc; ++a) {
     for (int b = 0; b < nxc; ++b) {
       const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q];
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
       const char* e0 = store + it.off + ((int64_t)ly * nx + lx) * (int64_t)sizeof(double);
       const double phi = rx[b] * ry[a];
 #pragma unroll
-      for (int i = 0; i < MLC_MAX_Q; ++i)
+      for (int i = 0; i < QM; ++i)
         if (i < P.q)
           acc[i] += phi * *reinterpret_cast<const double*>(e0 + (int64_t)i * it.rhs_stride);
       tot += phi;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   }
   // tot = 0 only on D_j block boundaries with overlap 0, where every e^j vanishes
 #pragma unroll
-  for (int i = 0; i < MLC_MAX_Q; ++i)
+  for (int i = 0; i < QM; ++i)
     if (i < P.q)
       P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + (tot > 0.0 ? acc[i] / tot : 0.0);
 }
@@ -117,7 +119,8 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
 // alpha_ij = u~_i . y_K,j, beta_ij = u~_i . y_M,j and s_i = sum u~_i.
 constexpr int RNV = 2 * MLC_MAX_Q * MLC_MAX_Q + MLC_MAX_Q;
 
-template <int KIND>
+// QM: a bound on q (1, 2, 4 or 8) that sizes the per-eigenpair registers.
+template <int KIND, int QM>
 __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
   __shared__ double red[(NTG / 64) * RNV];
   const ProbDev& P = probs[blockIdx.y];
@@ -144,12 +147,12 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
     W = edge_weights<KIND>(P, m, N, gx, gy);
     Mw = mass_weights<KIND>(P, m, N, gx, gy, mh);
   }
-  double uv[MLC_MAX_Q], yk[MLC_MAX_Q], ym[MLC_MAX_Q];
+  double uv[QM], yk[QM], ym[QM];
   // every eigenpair's stencil values are loaded before the first store (a store between
   // them would keep the next loads from being issued early)
-  double st[MLC_MAX_Q][7];
+  double st[QM][7];
 #pragma unroll
-  for (int i = 0; i < MLC_MAX_Q; ++i)
+  for (int i = 0; i < QM; ++i)
     if (i < q && dof) {
       const double* u = P.ut + (int64_t)i * nn;
       st[i][0] = u[idx];
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
       st[i][6] = u[idx - n1 - 1];
     }
 #pragma unroll
-  for (int i = 0; i < MLC_MAX_Q; ++i) {
+  for (int i = 0; i < QM; ++i) {
     uv[i] = yk[i] = ym[i] = 0.0;
     if (i < q && dof) {
       const double c = st[i][0], e = st[i][1], w = st[i][2], n = st[i][3], s = st[i][4];
@@ -182,10 +185,10 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
   double* out = P.partials + (int64_t)blockIdx.x * nv;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < MLC_MAX_Q; ++i) {
+  for (int i = 0; i < QM; ++i) {
     if (i >= q) break;
 #pragma unroll
-    for (int j = 0; j < MLC_MAX_Q; ++j) {
+    for (int j = 0; j < QM; ++j) {
       if (j >= q) break;
       const double a = wave_sum(uv[i] * yk[j]);
       const double c = wave_sum(uv[i] * ym[j]);
@@ -650,23 +653,46 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
 
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
                            const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_pou_glue, dim3(nblocks(max_nodes), nprob), dim3(NTG), 0, s, probs, items,
-                     sub_item, store, m);
+                           int max_q, hipStream_t s) {
+  const dim3 g(nblocks(max_nodes), nprob);
+#define MLC_GLUE(QM) \
+  hipLaunchKernelGGL(k_pou_glue<QM>, g, dim3(NTG), 0, s, probs, items, sub_item, store, m)
+  if (max_q <= 1)
+    MLC_GLUE(1);
+  else if (max_q <= 2)
+    MLC_GLUE(2);
+  else if (max_q <= 4)
+    MLC_GLUE(4);
+  else
+    MLC_GLUE(8);
+#undef MLC_GLUE
   return hipGetLastError();
 }
 
 hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
-                           hipStream_t s) {
-  dim3 g(nblocks(max_nodes), nprob);
-  if (kind == 0)
-    hipLaunchKernelGGL(k_rr_apply<0>, g, dim3(NTG), 0, s, probs, m);
-  else if (kind == 1)
-    hipLaunchKernelGGL(k_rr_apply<1>, g, dim3(NTG), 0, s, probs, m);
-  else if (kind == 2)
-    hipLaunchKernelGGL(k_rr_apply<2>, g, dim3(NTG), 0, s, probs, m);
-  else
-    hipLaunchKernelGGL(k_rr_apply<3>, g, dim3(NTG), 0, s, probs, m);
+                           int max_q, hipStream_t s) {
+  const dim3 g(nblocks(max_nodes), nprob);
+#define MLC_APPLY(K, QM) hipLaunchKernelGGL((k_rr_apply<K, QM>), g, dim3(NTG), 0, s, probs, m)
+#define MLC_APPLY_Q(K)   \
+  if (max_q <= 1)        \
+    MLC_APPLY(K, 1);     \
+  else if (max_q <= 2)   \
+    MLC_APPLY(K, 2);     \
+  else if (max_q <= 4)   \
+    MLC_APPLY(K, 4);     \
+  else                   \
+    MLC_APPLY(K, 8)
+  if (kind == 0) {
+    MLC_APPLY_Q(0);
+  } else if (kind == 1) {
+    MLC_APPLY_Q(1);
+  } else if (kind == 2) {
+    MLC_APPLY_Q(2);
+  } else {
+    MLC_APPLY_Q(3);
+  }
+#undef MLC_APPLY_Q
+#undef MLC_APPLY
   return hipGetLastError();
 }
 

@@ -740,9 +740,9 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
                                     (double*)(w + L.skel_parts), (double*)(w + L.skel_scal), st,
                                     &b->glue_it, &b->glue_relres));
   } else {
-    MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, st));
+    MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, P.q, st));
   }
-  MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, st));
+  MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, P.q, st));
   for (int l = s - 1; l >= 0; --l)
     MLC_HIP(b, launch_restrict(b->dprob, P.n, l, s, T.nodes_l[l], P.q, st));
   MLC_HIP(b, launch_rr_project(b->dprob, P.n, P.max_nH, P.q, st));

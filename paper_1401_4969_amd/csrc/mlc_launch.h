@@ -40,9 +40,9 @@ __host__ __device__ inline long ring_elems(int nw, int cap1, int cap2) {
 }
 hipError_t launch_pou_glue(const ProbDev* probs, int nprob, const TileItem* items,
                            const int32_t* sub_item, const char* store, int m, int64_t max_nodes,
-                           hipStream_t s);
+                           int max_q, hipStream_t s);
 hipError_t launch_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
-                           hipStream_t s);
+                           int max_q, hipStream_t s);
 hipError_t launch_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
                            int max_q, hipStream_t s);
 hipError_t launch_rr_project(const ProbDev* probs, int nprob, int max_nH, int max_q,
