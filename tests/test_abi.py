@@ -157,3 +157,15 @@ def test_tensor_coefficients_validated():
     for dom in (0, 1):
         q = W.Problem(dom, 8, 2, 2, 2, 1, 2, 3, W.random_tensor_coefficients(dom, 32, 3))
         assert B.workspace_size(q) > 0
+
+
+def test_plans_keep_tile_items_of_a_subdomain_adjacent():
+    """The gluing reaches the q tile items of a subdomain from the first one by a byte
+    stride; planning checks that layout for every level step and reports MLC_EINVAL if
+    it does not hold.  Plan the uneven 256-problem batch (square and L-shaped domains,
+    4x4 to 8x8 subdomains, three mesh sizes) and single problems with q = 1 .. 8."""
+    assert B.batch_workspace_size(W.config4()) > 0
+    for q in range(1, 9):
+        assert B.workspace_size(W.config1().with_(n_eig=q, n_refine=3)) > 0
+    assert B.workspace_size(W.small_ragged()) > 0
+    assert B.workspace_size(W.config2()) > 0
