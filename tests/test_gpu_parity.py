@@ -94,6 +94,14 @@ def test_random_problems(seed):
     compare(W.random_problem(seed))
 
 
+@pytest.mark.parametrize("seed", list(range(24)))
+def test_random_problems_wide(seed):
+    """Seeded problems over the whole input space: the three domains, coefficient kinds 0-3,
+    q up to 5, overlap 0-2, the three gluings, FP64 and mixed precision."""
+    prob, precision = W.random_problem_wide(seed)
+    compare(prob, precision=precision)
+
+
 @pytest.mark.parametrize("kw", [dict(sub_x=1, sub_y=1), dict(overlap=2), dict(n_refine=1),
                                 dict(sub_x=3, sub_y=5), dict(n_eig=4)])
 def test_config1_variants(kw):

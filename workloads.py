@@ -27,7 +27,7 @@ Domains: 0 the unit square (0,1)^2, 1 the L-shape, 2 the square (-1,1)^2 of Exam
 from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -234,6 +234,41 @@ def small_field(seed: int = 12, n_coarse: int = 8, n_refine: int = 2) -> Problem
     n = n_coarse << n_refine
     return Problem(DOMAIN_SQUARE, n_coarse, n_refine, 3, 2, 1, 1, 2,
                    gaussian_field_kappa(n, seed), f"field_nc{n_coarse}_L{n_refine}_3x2")
+
+
+def random_problem_wide(seed: int, max_fine: int = 64) -> Tuple[Problem, int]:
+    """A small random problem over the whole input space, and a precision (0: FP64, 1:
+    FP32 inner solves): any of the three domains, coefficient kinds 0-3 (kind 3 from
+    random_tensor_coefficients), q in 1..5 (1..3 on the coarsest grids), overlap 0..2,
+    any of the three gluings (the ramp needs an overlap), uneven subdomain splits."""
+    rng = np.random.Generator(np.random.PCG64(10_000 + seed))
+    dom = int(rng.integers(0, 3))
+    n_c = int(rng.choice([4, 6, 8]))
+    L = 1
+    while (n_c << (L + 1)) <= max_fine and rng.uniform() < 0.6:
+        L += 1
+    s = int(rng.integers(1, min(n_c, 4) + 1))
+    t = int(rng.integers(1, min(n_c, 4) + 1))
+    q = int(rng.integers(1, (4 if n_c == 4 else 6)))
+    kind = int(rng.integers(0, 4))
+    pou = int(rng.integers(0, 3))
+    overlap = int(rng.integers(1 if pou == 0 else 0, 3))
+    # every Omega_j must span at least two coarse cells each way
+    while s > 1 and n_c // s + overlap < 2:
+        s -= 1
+    while t > 1 and n_c // t + overlap < 2:
+        t -= 1
+    precision = int(rng.integers(0, 2))
+    n = n_c << L
+    kap = None
+    if kind == 1:
+        kap = loguniform_coarse_kappa(n_c, rng)
+    elif kind == 2:
+        kap = np.exp(rng.uniform(np.log(0.2), np.log(5.0), size=(n, n)))
+    elif kind == 3:
+        kap = random_tensor_coefficients(dom, n, 20_000 + seed)
+    prob = Problem(dom, n_c, L, s, t, overlap, q, kind, kap, f"wide{seed}", pou=pou)
+    return prob, precision
 
 
 def random_problem(seed: int, max_fine: int = 64) -> Problem:
