@@ -74,6 +74,69 @@ def test_batch_matches_single_and_oracle(kind, q, precision):
     bs.close()
 
 
+def _wide_batch(kind, q, n=6, seed0=300):
+    """Problems of one coefficient kind and q over the three domains, uneven splits, overlap
+    0-2 and both partition-of-unity gluings (every Omega_j at least two coarse cells)."""
+    rng = np.random.Generator(np.random.PCG64(seed0 + 10 * kind + q))
+    out = []
+    for i in range(n):
+        dom = int(rng.integers(0, 3))
+        nc = int(rng.choice([4, 6, 8]))
+        L = int(rng.integers(1, 4))
+        pou = int(rng.integers(0, 2))
+        ov = int(rng.integers(1 if pou == 0 else 0, 3))
+        sx = int(rng.integers(1, min(nc, 4) + 1))
+        sy = int(rng.integers(1, min(nc, 4) + 1))
+        while sx > 1 and nc // sx + ov < 2:
+            sx -= 1
+        while sy > 1 and nc // sy + ov < 2:
+            sy -= 1
+        kap = None
+        if kind == 1:
+            kap = W.loguniform_coarse_kappa(nc, rng)
+        elif kind == 2:
+            kap = np.exp(rng.uniform(-1, 1, size=(nc << L, nc << L)))
+        elif kind == 3:
+            kap = W.random_tensor_coefficients(dom, nc << L, seed0 + 100 + i)
+        out.append(W.Problem(dom, nc, L, sx, sy, ov, min(q, 3 if nc == 4 else q), kind, kap,
+                             f"w{i}", pou=pou))
+    # one q per batch
+    qb = min(p.n_eig for p in out)
+    return [p.with_(n_eig=qb) for p in out]
+
+
+@pytest.mark.parametrize("kind,q,precision", [(0, 3, 0), (1, 2, 1), (2, 1, 0), (3, 4, 0),
+                                              (3, 1, 1)])
+def test_wide_batch_matches_single_and_oracle(kind, q, precision):
+    """Batches mixing the three domains, splits, overlaps and both partition-of-unity
+    gluings: each problem bitwise as a single run, and the oracle's eigenvalues to 1e-10;
+    a graph-replayed run reproduces the eager one bitwise."""
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    probs = _wide_batch(kind, q)
+    bs = B.BatchSolver(probs, B.default_opts(precision=precision))
+    bs.setup()
+    bs.run()
+    assert bs.stats()["relres_max"] <= 1e-12 * 1.0000001
+    res = [bs.get(i) for i in range(len(probs))]
+    bs.close()
+    for i, p in enumerate(probs):
+        lam, u = res[i]
+        lam1, u1 = _single(p, precision=precision)
+        assert np.array_equal(lam, lam1), (i, lam, lam1)
+        assert torch.equal(u, u1)
+        ref = oracle_solve(p)
+        assert np.allclose(lam, ref.lam, rtol=1e-10, atol=0), (i, lam, ref.lam)
+    gs = B.BatchSolver(probs, B.default_opts(precision=precision))
+    gs.setup()
+    gs.run(use_graph=True)
+    for i in range(len(probs)):
+        lam, u = gs.get(i)
+        assert np.array_equal(lam, res[i][0])
+        assert torch.equal(u, res[i][1])
+    gs.close()
+
+
 @pytest.mark.parametrize("kind", [1, 3])
 def test_graph_replays_match_eager(kind):
     """Every graph replay, with eager work and synchronisations in between, reproduces
