@@ -88,6 +88,27 @@ def test_indicator_gluing_gradient_matches_oracle_fd(overlap):
     assert abs(np.sum(g * prob.kappa) - lam) < 1e-10 * lam
 
 
+@pytest.mark.parametrize("kind,dom,sub,ov,pou", [(2, 2, (3, 2), 1, 0), (1, 2, (2, 3), 2, 1),
+                                                 (2, 1, (3, 3), 0, 1), (1, 0, (4, 1), 1, 0)])
+def test_gradient_domains_and_splits_match_oracle_fd(kind, dom, sub, ov, pou):
+    """The reverse sweep on (-1,1)^2, the L-shape and the unit square with uneven splits,
+    overlap 0-2 and both partition-of-unity gluings, per fine cell (kind 2) or coarse cell
+    (kind 1), against central differences of the oracle; and the Euler identity."""
+    _torch()
+    rng = np.random.Generator(np.random.PCG64(400 + 10 * kind + dom))
+    nc, L = 6, 2
+    if kind == 2:
+        kap = np.exp(rng.uniform(-0.7, 0.7, size=(nc << L, nc << L)))
+    else:
+        kap = W.loguniform_coarse_kappa(nc, rng)
+    prob = W.Problem(dom, nc, L, sub[0], sub[1], ov, 1, kind, kap, f"adj_d{dom}_k{kind}", pou=pou)
+    lam, g, _ = gpu_grad(prob)
+    cells = rng.choice(g.size, size=10, replace=False)
+    fd = oracle_fd(prob, cells)
+    assert np.max(np.abs(g.ravel()[cells] - fd)) < 1e-6 * np.max(np.abs(g)), (g.ravel()[cells], fd)
+    assert abs(np.sum(g * prob.kappa) - lam) < 1e-10 * lam
+
+
 def test_coarse_cell_gradient_lshape_matches_oracle_fd():
     _torch()
     prob = W.small_ragged().with_(n_eig=1)
