@@ -194,20 +194,40 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
     const int64_t nn = (int64_t)(N + 1) * (N + 1);
     const int nblk = (int)((nn + 255) / 256);
     const int nvp = 2 * Q * Q + Q;
-    // one pass over the block partials per group of 8 values (independent loads)
-    for (int v0 = 0; v0 < 2 * Q * Q; v0 += 8) {
-      double sv[8];
+    constexpr int NAB = 2 * Q * Q;
+    if constexpr (NAB <= 32) {
+      // one pass over the block partials for every value, then every wave sum before one
+      // store per wave (a store after each sum would serialise them)
+      double sv[NAB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) sv[u] = 0.0;
+      for (int u = 0; u < NAB; ++u) sv[u] = 0.0;
       for (int b = tid; b < nblk; b += NTR) {
-        const double* pb = P.partials + (int64_t)b * nvp + v0;
+        const double* pb = P.partials + (int64_t)b * nvp;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (v0 + u < 2 * Q * Q) sv[u] += pb[u];
+        for (int u = 0; u < NAB; ++u) sv[u] += pb[u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (v0 + u < 2 * Q * Q) park(sv[u], v0 + u, park_lds, NV);
+      for (int u = 0; u < NAB; ++u) sv[u] = wave_sum(sv[u]);
+      if ((tid & 63) == 0) {
+#pragma unroll
+        for (int u = 0; u < NAB; ++u) park_lds[(tid >> 6) * NV + u] = sv[u];
+      }
+    } else {
+      // one pass over the block partials per group of 8 values (independent loads)
+      for (int v0 = 0; v0 < NAB; v0 += 8) {
+        double sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sv[u] = 0.0;
+        for (int b = tid; b < nblk; b += NTR) {
+          const double* pb = P.partials + (int64_t)b * nvp + v0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (v0 + u < NAB) sv[u] += pb[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (v0 + u < NAB) park(sv[u], v0 + u, park_lds, NV);
+      }
     }
     for (int r = tid; r < nH; r += NTR) Lam[r] = P.Lam[r];
     for (int e = tid; e < 2 * Q * nH; e += NTR) f[e] = P.fg[e];
@@ -223,19 +243,43 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
     __syncthreads();
   }
   // 2. g^T g, g^T f, g^T Lambda g (one batched reduction)
-  for (int i = 0; i < Q; ++i)
-    for (int j = 0; j < Q; ++j) {
-      double a = 0.0, b = 0.0, c = 0.0;
-      for (int r = tid; r < nH; r += NTR) {
+  if constexpr (3 * Q * Q <= 32) {  // every product in one pass, the wave sums before one store
+    double acc[3 * Q * Q];
+#pragma unroll
+    for (int e = 0; e < 3 * Q * Q; ++e) acc[e] = 0.0;
+    for (int r = tid; r < nH; r += NTR) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
         const double gi = g[i * nH + r];
-        a += gi * g[j * nH + r];
-        b += gi * f[j * nH + r];
-        c += gi * Lam[r] * g[j * nH + r];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          acc[i * Q + j] += gi * g[j * nH + r];
+          acc[Q * Q + i * Q + j] += gi * f[j * nH + r];
+          acc[2 * Q * Q + i * Q + j] += gi * Lam[r] * g[j * nH + r];
+        }
       }
-      park(a, i * Q + j, park_lds, NV);
-      park(b, Q * Q + i * Q + j, park_lds, NV);
-      park(c, 2 * Q * Q + i * Q + j, park_lds, NV);
     }
+#pragma unroll
+    for (int e = 0; e < 3 * Q * Q; ++e) acc[e] = wave_sum(acc[e]);
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int e = 0; e < 3 * Q * Q; ++e) park_lds[(tid >> 6) * NV + e] = acc[e];
+    }
+  } else {
+    for (int i = 0; i < Q; ++i)
+      for (int j = 0; j < Q; ++j) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int r = tid; r < nH; r += NTR) {
+          const double gi = g[i * nH + r];
+          a += gi * g[j * nH + r];
+          b += gi * f[j * nH + r];
+          c += gi * Lam[r] * g[j * nH + r];
+        }
+        park(a, i * Q + j, park_lds, NV);
+        park(b, Q * Q + i * Q + j, park_lds, NV);
+        park(c, 2 * Q * Q + i * Q + j, park_lds, NV);
+      }
+  }
   __syncthreads();
   for (int v = tid; v < 3 * Q * Q; v += NTR) vals[v] = gather<NWR>(v, park_lds, NV);
   __syncthreads();
