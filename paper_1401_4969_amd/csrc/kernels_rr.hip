@@ -149,14 +149,15 @@ constexpr int rr_group_lanes(int ntr) {
   return gs;
 }
 
-// Offsets of a guided round's points from the regula falsi estimate, as fractions of the
-// bracket width: the centre (for an odd count) and pairs +-s on a geometric ladder from
-// 3e-2 down to 1e-6.
-__device__ inline double guided_offset(int j, int per_bracket) {
+// Offsets of a round's points from a centre, as fractions of a scale: the centre itself
+// (for an odd count) and pairs +-s on a geometric ladder from hi down to lo.  Guided rounds
+// use the bracket width and 3e-2 ... 1e-6; the first round uses the predicted level change
+// and 0.2 ... 0.02.
+__device__ inline double ladder_offset(int j, int per_bracket, double hi, double lo) {
   const int odd = per_bracket & 1, pairs = per_bracket / 2;
   if (j < odd) return 0.0;
   const int i = (j - odd) >> 1;
-  const double s = pairs == 1 ? sqrt(3e-2 * 1e-6) : 3e-2 * pow(1e-6 / 3e-2, (double)i / (double)(pairs - 1));
+  const double s = pairs == 1 ? sqrt(hi * lo) : hi * pow(lo / hi, (double)i / (double)(pairs - 1));
   return ((j - odd) & 1) ? s : -s;
 }
 
@@ -379,12 +380,17 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   //    pole (the inertia counts at its ends differ by one and the numbers of Lambda_r below
   //    them agree): det S(mu) is then smooth on the bracket and changes sign once, at the
   //    eigenvalue, and the next round centres the bracket's points on the regula falsi
-  //    estimate from det S at the two ends (offsets: guided_offset).  A guided round that
-  //    shrinks its bracket by less than 4x is followed by a uniform one.  The first round
-  //    puts a bracket's points below the eigenvalue this level step started from (the
-  //    previous level's, or the coarse one), at 1e-1 down to 1e-6 of it: eigenvalues move
-  //    little from level to level.  Where the points go changes only how fast the
-  //    brackets shrink, never what they contain.
+  //    estimate from det S at the two ends, or from an inverse quadratic through the two
+  //    ends and the nearest point of the round outside the bracket (same pole count), when
+  //    that estimate falls inside.  A guided round that shrinks its bracket by less than 4x
+  //    is followed by a uniform one.  The first round places a bracket's points around a
+  //    prediction of the eigenvalue: the discrete eigenvalues approach their limit as h^2
+  //    (Section 3), so with Lambda_k the coarse one (level 0) and lambda_k the previous
+  //    level's, the model lambda_l = lambda* + C 4^-l gives the change of level m as
+  //    3 C 4^-m with C = (Lambda_k - lambda_k) / (1 - 4^(1-m)), and the points sit at the
+  //    predicted value +-(0.2 ... 0.02) of that change (level 1 has no such model: there
+  //    they sit below lambda_k at 1e-1 down to 1e-6 of it).  Where the points go changes
+  //    only how fast the brackets shrink, never what they contain.
   constexpr int GS = rr_group_lanes(NTR);
   constexpr int G = NTR / GS;  // 16 >= 2 Q
   constexpr int GQ = G / Q;    // points per bracket, >= 2
@@ -392,12 +398,20 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   const int kb = pnt / GQ, j = pnt % GQ;  // this point's bracket and position
   const bool active = kb < Q;
   const int kk = active ? kb : 0;
-  const double off = guided_offset(j, GQ);
+  const double off = ladder_offset(j, GQ, 3e-2, 1e-6);
   const double frac = (double)(j + 1) / (double)(GQ + 1);  // uniform position
-  const double warm = P.lam[(1 - dst) * MLC_MAX_Q + kk] *
-                      (1.0 - 1e-1 * pow(1e-5, (double)j / (double)(GQ - 1)));
   __shared__ double sA[Q], sB[Q], sFA[Q], sFB[Q], sEst[Q], ptMu[G], ptDet[G];
   __shared__ int sCA[Q], sCB[Q], sNA[Q], sNB[Q], sGuide[Q], ptCnt[G], ptLess[G];
+  __shared__ double ptWarm[G];  // first-round points (in LDS: kept out of the loop's registers)
+  if (gl == 0) {
+    const double prevk = P.lam[(1 - dst) * MLC_MAX_Q + kk];
+    double warm = prevk * (1.0 - 1e-1 * pow(1e-5, (double)j / (double)(GQ - 1)));
+    if (m >= 2 && Lam[kk] > prevk) {
+      const double dl = (Lam[kk] - prevk) * (3.0 * ldexp(1.0, -2 * m) / (1.0 - ldexp(1.0, 2 - 2 * m)));
+      warm = prevk - dl + dl * ladder_offset(j, GQ, 0.2, 0.02);
+    }
+    ptWarm[pnt] = warm;
+  }
   if (tid < Q) {
     sA[tid] = lo;
     sB[tid] = Lam[tid] + 1e-12 * fabs(Lam[tid]) + 1e-300;
@@ -411,6 +425,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
     const double a = sA[kk], bnd = sB[kk];
     double mu = a + (bnd - a) * frac;
     if (round == 0) {
+      const double warm = ptWarm[pnt];
       if (warm > a && warm < bnd) mu = warm;
     } else if (sGuide[kk]) {
       const double gm = sEst[kk] + off * (bnd - a);
@@ -455,6 +470,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
       const double inf = __builtin_inf();
       const int cp = ln < G ? ptCnt[ln] : -1;
       const double mp = ln < G ? ptMu[ln] : 0.0;
+      const int lp = ln < G ? ptLess[ln] : -1;
       const bool up = cp >= k + 1, down = cp >= 0 && cp <= k;
       // the highest lower and the lowest upper point, each the first such point in order
       const auto mx = [](double x, double y) { return fmax(x, y); };
@@ -464,33 +480,47 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
       lo2 = read_lane_f64(lo2, 63);
       hi2 = read_lane_f64(hi2, 63);
       const unsigned long long bl = __ballot(down && mp == lo2), bh = __ballot(up && mp == hi2);
+      // the new ends (every lane: the third point below needs them)
+      const double a0 = sA[k], b0 = sB[k];
+      const int ia = (bl != 0ull && lo2 > a0) ? __ffsll(bl) - 1 : -1;  // the points that
+      const int ib = (bh != 0ull && hi2 < b0) ? __ffsll(bh) - 1 : -1;  // become the ends
+      const double ak = ia >= 0 ? lo2 : a0, bk = ib >= 0 ? hi2 : b0;
+      const int na = ia >= 0 ? ptLess[ia] : sNA[k], nb = ib >= 0 ? ptLess[ib] : sNB[k];
+      // the point of this round nearest the new bracket from outside, with its pole count
+      const bool outside = cp >= 0 && lp == na && (mp < ak || mp > bk);
+      double dn = group_reduce_last(outside ? (mp < ak ? ak - mp : mp - bk) : inf, 64, inf, mn);
+      dn = read_lane_f64(dn, 63);
+      const unsigned long long bn = __ballot(outside && (mp < ak ? ak - mp : mp - bk) == dn);
       if (ln == 0) {
-        const double a0 = sA[k], b0 = sB[k];
-        double ak = a0, bk = b0;
-        int ia = -1, ib = -1;  // the points that become the ends
-        if (bl != 0ull && lo2 > a0) {
-          ak = lo2;
-          ia = __ffsll(bl) - 1;
-        }
-        if (bh != 0ull && hi2 < b0) {
-          bk = hi2;
-          ib = __ffsll(bh) - 1;
-        }
         double fa = sFA[k], fb = sFB[k];
-        int ca = sCA[k], cb = sCB[k], na = sNA[k], nb = sNB[k];
+        int ca = sCA[k], cb = sCB[k];
         if (ia >= 0) {
           fa = ptDet[ia];
           ca = ptCnt[ia];
-          na = ptLess[ia];
         }
         if (ib >= 0) {
           fb = ptDet[ib];
           cb = ptCnt[ib];
-          nb = ptLess[ib];
         }
         const bool isolated = cb - ca == 1 && na == nb && fa != 0.0 && fb != 0.0 &&
                               (fa < 0.0) != (fb < 0.0) && isfinite(fa) && isfinite(fb);
         const bool slow = sGuide[k] && bk - ak > 0.25 * (b0 - a0);
+        double est = ak;
+        if (isolated) {
+          est = ak + (bk - ak) * (fa / (fa - fb));  // regula falsi
+          if (bn != 0ull) {  // inverse quadratic through (ak, fa), (bk, fb), (x2, f2)
+            const int i2 = __ffsll(bn) - 1;
+            const double x2 = ptMu[i2];
+            // scaled by a power of two (exact) so that the cubic products stay in range
+            const int ex = ilogb(fmax(fabs(fa), fmax(fabs(fb), fabs(ptDet[i2]))));
+            const double f0 = ldexp(fa, -ex), f1 = ldexp(fb, -ex), f2 = ldexp(ptDet[i2], -ex);
+            if (f2 != f0 && f2 != f1 && isfinite(f2)) {  // Lagrange weights over one denominator
+              const double e = ak + ((bk - ak) * (f0 * f2 * (f2 - f0)) - (x2 - ak) * (f0 * f1 * (f1 - f0))) /
+                                        ((f1 - f0) * (f1 - f2) * (f2 - f0));
+              if (e > ak && e < bk) est = e;
+            }
+          }
+        }
         sA[k] = ak;
         sB[k] = bk;
         sFA[k] = fa;
@@ -500,7 +530,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
         sNA[k] = na;
         sNB[k] = nb;
         sGuide[k] = isolated && !slow;
-        sEst[k] = isolated ? ak + (bk - ak) * (fa / (fa - fb)) : ak;
+        sEst[k] = est;
       }
     }
     __syncthreads();
