@@ -207,8 +207,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
 #pragma unroll
         for (int u = 0; u < NAB; ++u) sv[u] += pb[u];
       }
-#pragma unroll
-      for (int u = 0; u < NAB; ++u) sv[u] = wave_sum(sv[u]);
+      wave_sum_n(sv);
       if ((tid & 63) == 0) {
 #pragma unroll
         for (int u = 0; u < NAB; ++u) park_lds[(tid >> 6) * NV + u] = sv[u];
@@ -260,8 +259,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
         }
       }
     }
-#pragma unroll
-    for (int e = 0; e < 3 * Q * Q; ++e) acc[e] = wave_sum(acc[e]);
+    wave_sum_n(acc);
     if ((tid & 63) == 0) {
 #pragma unroll
       for (int e = 0; e < 3 * Q * Q; ++e) park_lds[(tid >> 6) * NV + e] = acc[e];
