@@ -305,26 +305,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return read_lane_f64(group_sum_last(v, 64), 63);
 }
 
-// wave_sum of K values, step by step over all of them (the K dependent chains of cross-lane
-// moves interleave instead of running one after another); bitwise equal to K wave_sums.
-template <int K>
-__device__ __forceinline__ void wave_sum_n(double (&v)[K]) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_f64<0xb1, 0xf>(v[k], 0.0);
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_f64<0x4e, 0xf>(v[k], 0.0);
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_f64<0x114, 0xf>(v[k], 0.0);
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_f64<0x118, 0xf>(v[k], 0.0);
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_f64<0x142, 0xa>(v[k], 0.0);
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = v[k] + dpp_f64<0x143, 0xc>(v[k], 0.0);
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = read_lane_f64(v[k], 63);
-}
-
 template <int NT, int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* lds) {
   constexpr int NW = NT / 64;
