@@ -195,6 +195,27 @@ def test_set_state_resume():
     s.close()
 
 
+@pytest.mark.parametrize("scale", [0.9, 1.2])
+def test_set_state_far_eigenvalue(scale):
+    """A resumed eigenvalue far from the truth (10% low; 20% high, above the coarse one)
+    leaves the first multisection round's points far from the next eigenvalue: the
+    inertia counts still give the oracle's Rayleigh-Ritz eigenvalue for that state."""
+    torch = _torch()
+    from oracle import mlc as omlc
+    from paper_1401_4969_amd import binding as B
+    p = W.config1()
+    ref = oracle_solve(p)
+    lam1 = ref.lam_levels[1] * scale
+    mu, _, _ = omlc.correction(ref.hier, 1, lam1, ref.U_levels[1])
+    s = B.Solver(p)
+    s.coarse_setup()
+    u1 = torch.tensor(ref.hier.to_grid(1, ref.U_levels[1]).T.copy(), device="cuda:0")
+    s.set_state(1, lam1, u1)
+    d = s.level_correct(stats=True)
+    assert abs(d["lam"][0] - mu[0]) / mu[0] < LAM_RTOL
+    s.close()
+
+
 def _golden(name):
     import json
     import os
