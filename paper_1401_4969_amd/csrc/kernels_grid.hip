@@ -92,6 +92,53 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   double acc[QM], tot = 0.0;
 #pragma unroll
   for (int i = 0; i < QM; ++i) acc[i] = 0.0;
+  if (nxc <= 2 && nyc <= 2) {
+    // at most 2 x 2 covering subdomains (overlap 1 on blocks of two or more coarse cells):
+    // every index load first, then every item, then every tile value, so the three
+    // dependent loads of the subdomains overlap instead of following one another.  Slots
+    // past the candidates, or without an item, load from the first subdomain that has one
+    // (in bounds, as it covers the node) and add nothing; the sums keep the loop's order.
+    int itm[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int a = c >> 1, b = c & 1;
+      const int sub = (a < nyc && b < nxc) ? iy[a] * P.sub_x + ix[b] : -1;
+      const int raw = sub_item[P.sub_item_off + (sub >= 0 ? sub : 0) * P.q];  // sub 0: in bounds
+      itm[c] = sub >= 0 ? raw : -1;
+    }
+    int first = -1;
+#pragma unroll
+    for (int c = 3; c >= 0; --c)
+      if (itm[c] >= 0) first = c;
+    if (first >= 0) {
+      const int safe = itm[first];
+      const char* e0[4];
+      int rs[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const TileItem it = items[itm[c] >= 0 ? itm[c] : safe];
+        const int nx = it.cw * r - 1;
+        const int lx = gx - (it.cx0 * r + 1), ly = gy - (it.cy0 * r + 1);
+        e0[c] = store + it.off + ((int64_t)ly * nx + lx) * (int64_t)sizeof(double);
+        rs[c] = it.rhs_stride;
+      }
+      double v[4][QM];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < QM; ++i)
+          v[c][i] = i < P.q ? *reinterpret_cast<const double*>(e0[c] + (int64_t)i * rs[c]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (itm[c] < 0) continue;
+        const double phi = rx[c & 1] * ry[c >> 1];
+#pragma unroll
+        for (int i = 0; i < QM; ++i)
+          if (i < P.q) acc[i] += phi * v[c][i];
+        tot += phi;
+      }
+    }
+  } else {
   for (int a = 0; a < nyc; ++a) {
     for (int b = 0; b < nxc; ++b) {
       const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q];
@@ -107,6 +154,7 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
           acc[i] += phi * *reinterpret_cast<const double*>(e0 + (int64_t)i * it.rhs_stride);
       tot += phi;
     }
+  }
   }
   // tot = 0 only on D_j block boundaries with overlap 0, where every e^j vanishes
 #pragma unroll
