@@ -9,15 +9,13 @@ constexpr int NTG = 256;
 
 __device__ __forceinline__ double interp2(const double* uc, int nc1, int x, int y) {
   // P1 nodal interpolation from the grid one level coarser (SW-NE diagonals):
-  // coinciding nodes copy, edge midpoints average the two ends of their edge.
+  // coinciding nodes copy, edge midpoints average the two ends of their edge (E, N or NE
+  // of the first).  Branch-free: a coinciding node averages its value with itself, which
+  // is exact, so neighbouring lanes of either parity issue their loads together.
   const int ix = x >> 1, iy = y >> 1;
   const double a = uc[iy * nc1 + ix];
-  if (x & 1) {
-    if (y & 1) return 0.5 * (a + uc[(iy + 1) * nc1 + ix + 1]);
-    return 0.5 * (a + uc[iy * nc1 + ix + 1]);
-  }
-  if (y & 1) return 0.5 * (a + uc[(iy + 1) * nc1 + ix]);
-  return a;
+  const double b = uc[(iy + (y & 1)) * nc1 + ix + (x & 1)];
+  return 0.5 * (a + b);
 }
 
 // a1 + a2: u_bar = I u_k on level m and the right-hand side of (Aux_Problem),
