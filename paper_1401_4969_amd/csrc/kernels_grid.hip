@@ -63,6 +63,39 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
   r[idx] = lam * Mu - Ku;
 }
 
+// floor(a / b) for 0 <= a < 2^22 and b >= 1 from a float reciprocal of b: the estimate is
+// within one of the quotient (relative error below 2^-22), and one step each way makes it
+// exact.  Integer division costs tens of instructions on the vector unit.
+__device__ __forceinline__ int div_small(int a, int b, float rb) {
+  int q = (int)((float)a * rb);
+  q -= (q * b > a) ? 1 : 0;
+  q += ((q + 1) * b <= a) ? 1 : 0;
+  return q;
+}
+
+// pou_axis with r = 2^m and the block divisions by reciprocals (nc * nb < 2^22, checked by
+// the caller): the same candidates, factors and order.
+__device__ __forceinline__ int pou_axis_fast(int nc, int nb, int g, int m, int ov, int pou,
+                                             int (&id)[MLC_MAX_CAND], double (&rho)[MLC_MAX_CAND]) {
+  const int r = 1 << m, d = ov * r;
+  const float rnb = 1.0f / (float)nb, rnc = 1.0f / (float)nc;
+  const int b0 = div_small((min(g >> m, nc - 1) + 1) * nb - 1, nc, rnc);
+  const int blo = max(0, b0 - ov - 1), bhi = min(nb - 1, b0 + ov + 1);
+  int n = 0;
+  int lo = div_small(blo * nc, nb, rnb) * r;
+  for (int b = blo; b <= bhi && n < MLC_MAX_CAND; ++b) {
+    const int hi = div_small((b + 1) * nc, nb, rnb) * r;
+    const int v = min(g - lo + d, hi + d - g);
+    if (v > 0) {
+      id[n] = b;
+      rho[n] = pou == 0 ? (double)min(v, d) / (double)d : (g >= lo && g <= hi ? 1.0 : 0.0);
+      ++n;
+    }
+    lo = hi;
+  }
+  return n;
+}
+
 // a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
 // QM: a bound on q (1, 2, 4 or 8) that sizes the per-eigenpair registers.
 template <int QM>
@@ -84,8 +117,11 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   const int r = 1 << m;
   int ix[MLC_MAX_CAND], iy[MLC_MAX_CAND];
   double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
-  const int nxc = pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
-  const int nyc = pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
+  const bool fast = P.n_c * max(P.sub_x, P.sub_y) < (1 << 22);
+  const int nxc = fast ? pou_axis_fast(P.n_c, P.sub_x, gx, m, P.overlap, P.pou, ix, rx)
+                       : pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
+  const int nyc = fast ? pou_axis_fast(P.n_c, P.sub_y, gy, m, P.overlap, P.pou, iy, ry)
+                       : pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
   // one item lookup per covering subdomain: its q right-hand sides follow at rhs_stride
   double acc[QM], tot = 0.0;
 #pragma unroll
