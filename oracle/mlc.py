@@ -174,12 +174,29 @@ class Hierarchy:
 # The algorithm
 # ---------------------------------------------------------------------------
 
+SIGN_SUM_RTOL = 1e-8    # a nodal sum below this fraction of sum |u| does not fix the sign
+SIGN_MAX_RTOL = 1e-6    # entries within this relative distance of max |u| tie for the largest
+
+
 def sign_normalise(U: np.ndarray) -> np.ndarray:
-    """Reading of the free sign: each eigenvector has a non-negative nodal sum."""
+    """Reading of the free sign (b(u, u) = 1 fixes u only up to sign): each eigenvector
+    gets a positive nodal sum when |sum u| > 1e-8 sum |u|; otherwise (an eigenvector odd
+    under a symmetry of the problem, whose sum is rounding noise) the first entry in node
+    order whose magnitude is within a relative 1e-6 of the largest is made positive.  The
+    relative band makes the choice stable under rounding: the largest magnitudes of an odd
+    eigenvector come in pairs of opposite sign that tie in exact arithmetic."""
     U = U.copy()
     for c in range(U.shape[1]):
-        if U[:, c].sum() < 0:
-            U[:, c] = -U[:, c]
+        u = U[:, c]
+        s = u.sum()
+        a = np.abs(u)
+        if abs(s) > SIGN_SUM_RTOL * a.sum():
+            flip = s < 0
+        else:
+            first = np.nonzero(a >= (1.0 - SIGN_MAX_RTOL) * a.max())[0][0]
+            flip = u[first] < 0
+        if flip:
+            U[:, c] = -u
     return U
 
 
