@@ -7,16 +7,22 @@ previous level's eigenpairs already resident in HBM: prolongation and residual o
 V_0H + span{u~} and the new eigenvectors.  The library rewinds its ping-pong state
 between steps, so every step repeats exactly the same correction.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3mixed|c4|c5adj|c2iface|
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c3mixed|c4|c5adj|c2iface|
                      c3iface|ex62|ex62mixed] [--no-cpu-baseline]
 
-(c4: a step is the whole multilevel run of 256 batched problems; c5adj: one reverse sweep;
-*iface: the paper's own gluing in place of the partition of unity; ex62*: the operator of
-Example 6.2.)
+The default workload is the unit square at h = 1/2048 (4,190,209 fine DOFs, H = 1/32,
+16 x 16 subdomains, q = 1) in FP64; the same workload in FP32 + FP64 refinement is
+measured beside it and reported under ``mixed``.  (c4: a step is the whole multilevel run
+of 256 batched problems; c5adj: one reverse sweep; *iface: the paper's own gluing in
+place of the partition of unity; ex62*: the operator of Example 6.2.)
 
 Prints one JSON line.  ``value`` is fine interior DOFs corrected per second at the finest
 level (work of every eigenpair included).  ``roofline`` is for the local-solve kernel,
-timed with HIP events the library records on its stream around that kernel.
+timed with HIP events the library records on its stream around that kernel; its
+``achieved`` counts 18 vector passes of 8 bytes per tile unknown and PCG iteration (the
+reference count of the method's work: SpMV with its dot 2, x/r update 6, V-cycle 7.3,
+direction 3), and ``schedule_count`` gives the same figure under this kernel's own fused
+schedule.
 """
 from __future__ import annotations
 
@@ -78,6 +84,27 @@ def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
     v += 2 * S[m] + S[m] ** 2
     c += 2 * S[0]
     return elem * (8 * S[0] + v) + coef * c
+
+
+SURVEY_PASSES = 18     # vector passes per PCG iteration in the reference count of the work
+
+
+def survey_bytes_per_iteration(elem: int = 8, coef_kind: int = 0) -> float:
+    """Reference count of the bytes per tile unknown and PCG iteration: 18 vector passes
+    (SpMV + fused dot 2, x/r update 6, V-cycle about 7.3 fine-level passes, direction
+    update 3) of elem bytes, and for a variable coefficient 2 more passes for each of the
+    4 operator applications of an iteration."""
+    return elem * (SURVEY_PASSES + (8 if coef_kind != 0 else 0))
+
+
+def survey_mixed_bytes(it_dofs: int, refine_dofs: int, tile_dofs: int,
+                       coef_kind: int = 0) -> float:
+    """The reference count for FP32 inner iterations with FP64 residual refinement: 18
+    FP32 passes per inner iteration, per refinement step the FP64 residual r = b - K e
+    (read b, e, write r: 24 bytes) and e += d (read e, d, write e: 20), and the first pass
+    (read b, write e, r, d: 24)."""
+    return (survey_bytes_per_iteration(4, coef_kind) * it_dofs + 44.0 * refine_dofs
+            + 24.0 * tile_dofs)
 
 
 def mixed_bytes(cw: int, ch: int, m: int, nu: int, it_dofs: int, refine_dofs: int,
@@ -294,59 +321,210 @@ def golden_lambda(name: str):
         return json.load(f)["lam_levels"][-1]
 
 
-def cpu_baseline(prob, budget_s: float = 30.0):
-    """Time the oracle's finest-level correction (one thread) on a bounded sample."""
-    import numpy as np
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
+_POOL_STATE = None   # (hierarchy, level, right-hand sides), inherited by forked workers
+
+
+def _oracle_tile_solve(j: int):
+    hier, m, rhs = _POOL_STATE
     from oracle import mlc as O
-    ctx = threadpool_limits(1) if threadpool_limits else None
+    return O.local_solve(hier, m, hier.subs[j], rhs)
+
+
+def cpu_workers() -> int:
+    """Host cores for the oracle's process pool: the CPUs this process may run on, at
+    most 16 (one GPU's share of the host)."""
     try:
-        hier = O.Hierarchy(prob)
-        lam, U = O.coarse_eigs(hier, prob.n_eig)
-        for k in range(prob.n_refine - 1):
-            lam, U, _ = O.correction(hier, k, lam, U)
-        k = prob.n_refine - 1
-        # bounded sample: the local solves of as many subdomains as fit the budget, scaled
-        # to the whole level by tile unknowns; residual, gluing and Rayleigh-Ritz timed whole
-        m = k + 1
-        import scipy.sparse.linalg as spla
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(prob, serial_budget_s: float = 8.0, glue_sample: int = 16):
+    """The oracle's finest-level correction (Algorithm 4.1 at the last level) timed on the
+    host: the local solves of every subdomain by a pool of P worker processes (the oracle's
+    own per-subdomain sparse-LU solve), the right-hand side, partition-of-unity gluing and
+    Rayleigh-Ritz in this process with P BLAS threads; and the same on one core (the
+    local solves of as many subdomains as fit serial_budget_s, scaled by tile unknowns).
+    The gluing weights (a dense subdomains x nodes array in the oracle) are evaluated for
+    glue_sample subdomains and scaled by the subdomain count.  The correction starts from
+    the prolonged coarse eigenpair instead of the previous level's (its cost does not
+    depend on the values), so the earlier levels are not run."""
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import mlc as O
+    global _POOL_STATE
+    P = cpu_workers()
+    t_setup = time.perf_counter()
+    hier = O.Hierarchy(prob)
+    lam, U0 = O.coarse_eigs(hier, prob.n_eig)
+    k = prob.n_refine - 1
+    m = k + 1
+    u_k = hier.P0[k] @ U0
+    t_setup = time.perf_counter() - t_setup
+
+    def rhs_part():
+        ubar = hier.P[k] @ u_k
+        return ubar, (hier.M[m] @ ubar) * lam[None, :] - hier.K[m] @ ubar
+
+    def glue_rr_part(ubar, sols):
+        """Gluing and Rayleigh-Ritz: the weights of glue_sample subdomains timed and scaled,
+        the accumulation over every subdomain (with a sampled weight row each: the same
+        arithmetic), then Rayleigh-Ritz on V_0H + span{u~}."""
+        ns = len(hier.subs)
+        pick = list(range(0, ns, max(1, ns // glue_sample)))[:glue_sample]
+        i, j = hier.node_ij(m, hier.meshes[m].dof)
+        r = float(1 << m)
         t0 = time.perf_counter()
-        ubar = hier.P[k] @ U
-        rhs = (hier.M[m] @ ubar) * lam[None, :] - hier.K[m] @ ubar
-        t_rhs = time.perf_counter() - t0
-        total_dofs = sum(hier.tile_dofs(m, s).size for s in hier.subs)
+        chi = O.pou_weights(prob, [hier.subs[p] for p in pick], i / r, j / r)
+        t_chi = (time.perf_counter() - t0) * ns / len(pick)
         t0 = time.perf_counter()
-        sols = []
-        done_dofs = 0
-        for s in hier.subs:
-            idx = hier.tile_dofs(m, s)
-            lu = spla.splu(hier.K[m][idx][:, idx].tocsc())
-            sols.append((idx, lu.solve(np.ascontiguousarray(rhs[idx]))))
-            done_dofs += idx.size
-            if time.perf_counter() - t0 > budget_s:
-                break
-        t_solve = (time.perf_counter() - t0) * total_dofs / done_dofs
-        t1 = time.perf_counter()
-        chi = hier.pou(m)
         ut = ubar.copy()
-        for (idx, e), c in zip(sols, chi):
-            ut[idx] += c[idx, None] * e
+        for p, (idx, e) in enumerate(sols):
+            ut[idx] += chi[p % len(pick)][idx, None] * e
         O.rayleigh_ritz(hier, m, ut, prob.n_eig)
-        t_rest = time.perf_counter() - t1 + t_rhs
-        done = len(sols)
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    secs = t_solve + t_rest
+        return t_chi + time.perf_counter() - t0
+
+    out = {}
+    sols = None
+    for cores in (P, 1):
+        if cores == 1 and P == 1 and 1 in out:
+            break
+        with threadpool_limits(cores):
+            t0 = time.perf_counter()
+            ubar, rhs = rhs_part()
+            t_rhs = time.perf_counter() - t0
+            if sols is None:   # every subdomain, P worker processes
+                _POOL_STATE = (hier, m, rhs)
+                with mp.get_context("fork").Pool(P) as pool:
+                    pool.map(abs, range(P))   # workers started before the clock
+                    t0 = time.perf_counter()
+                    sols = pool.map(_oracle_tile_solve, range(len(hier.subs)), chunksize=1)
+                    t_solve = time.perf_counter() - t0
+                _POOL_STATE = None
+                done = len(sols)
+            else:              # one core: as many subdomains as fit the budget, scaled
+                total = sum(hier.tile_dofs(m, s).size for s in hier.subs)
+                t0 = time.perf_counter()
+                done, done_dofs = 0, 0
+                for s in hier.subs:
+                    done_dofs += O.local_solve(hier, m, s, rhs)[0].size
+                    done += 1
+                    if time.perf_counter() - t0 > serial_budget_s:
+                        break
+                t_solve = (time.perf_counter() - t0) * total / done_dofs
+            t_rest = glue_rr_part(ubar, sols) + t_rhs
+        out[cores] = (t_solve + t_rest, t_solve, t_rest, done)
     n_dofs = hier.meshes[m].dof.size
-    return dict(value=n_dofs / secs, unit="fine DOFs/s", cores=1, kind="oracle",
-                sample=(f"oracle finest-level correction of {prob.name}: sparse-LU local solves of "
-                        f"{done} of {len(hier.subs)} subdomains timed and scaled by tile unknowns, "
-                        f"gluing + Rayleigh-Ritz timed whole; 1 thread"),
-                seconds_per_step=secs)
+    secs, t_solve, t_rest, _ = out[P]
+    secs1, t_solve1, t_rest1, done1 = out[1]
+    return dict(value=n_dofs / secs, unit="fine DOFs/s", cores=P, kind="oracle",
+                sample=(f"oracle finest-level correction of {prob.name} (h = {prob.h(m):g}, "
+                        f"{len(hier.subs)} subdomains): sparse-LU local solves of every subdomain "
+                        f"in a pool of {P} processes; residual, gluing and Rayleigh-Ritz in one "
+                        f"process with {P} BLAS threads (gluing weights sampled on "
+                        f"{min(glue_sample, len(hier.subs))} subdomains and scaled); started "
+                        f"from the prolonged coarse eigenpair"),
+                seconds_per_step=secs, local_solve_seconds=t_solve, rest_seconds=t_rest,
+                setup_seconds=t_setup,
+                single_core=dict(value=n_dofs / secs1, cores=1, seconds_per_step=secs1,
+                                 local_solve_seconds=t_solve1, rest_seconds=t_rest1,
+                                 sample=(f"local solves of {done1} of {len(hier.subs)} subdomains "
+                                         f"timed on one thread and scaled by tile unknowns")))
+
+
+LLC_BYTES = 256 * 2 ** 20   # MI355X last-level (Infinity) cache
+
+
+def run_steps(prob, opts, args):
+    """Bring a solver to the finest level, then time args.steps repetitions of the last
+    correction (HIP events on the library's stream; the library's own events around the
+    local-solve kernel), and the statistics of one more."""
+    import numpy as np
+    import torch
+    from paper_1401_4969_amd import binding as B
+    s = B.Solver(prob, opts)
+    s.coarse_setup()
+    for _ in range(prob.n_refine):
+        s.level_correct()
+    print(f"[bench] {prob.name} ({'fp64' if opts.precision == 0 else 'mixed'}): reached level "
+          f"{s.level}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        s.rewind()
+        s.level_correct()
+    torch.cuda.synchronize()
+    s.phase_times()  # reset the event accumulators
+    stream = s.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        s.rewind()
+        s.level_correct()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    ph = s.phase_times()
+    pcg_ms = ph[0] / args.steps
+    s.rewind()
+    st = s.level_correct(stats=True)   # statistics of the same step (untimed)
+    s.close()
+    return ms_step, pcg_ms, st, np.array(st["lam"])
+
+
+def roofline(prob, opts, st, pcg_ms, lds_limit):
+    """The local-solve kernel against the HBM peak: algorithmic bytes of one launch by the
+    reference count (18 passes per tile unknown and iteration) over its event-timed
+    duration, and the same under the kernel's own fused schedule."""
+    m = prob.n_refine
+    shapes = subdomain_shapes(prob)
+    cw, ch = max(shapes, key=lambda x: x[0] * x[1])
+    S0 = tile_levels(cw, ch, m)[0]
+    nt = opts.block or 1024
+    tile_nx = max(c for c, _ in shapes) * (1 << m) - 1
+    elem = 8 if opts.precision == 0 else 4
+    rmode = ring_mode(nt, tile_nx, opts.nu, elem, lds_limit)
+    # the tensor kind streams its three stiffness planes (FP64, or FP32 in inner solves)
+    coef = (24 if opts.precision == 0 else 12) if prob.coef_kind == 3 else 0
+    if opts.precision == 0:
+        kernel = "k_local_pcg64"
+        sched_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode, coef=coef) / S0
+        sched = sched_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
+        surv_it = survey_bytes_per_iteration(8, prob.coef_kind)
+        surv = surv_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
+    else:
+        kernel = "k_local_mixed"
+        sched_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode,
+                                           coef=coef) / S0
+        sched = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
+                            st["n_tile_dofs"], mode=rmode, coef=coef,
+                            coef64=24 if prob.coef_kind == 3 else 0)
+        surv_it = survey_bytes_per_iteration(4, prob.coef_kind)
+        surv = survey_mixed_bytes(st["it_dofs"], st["refine_dofs"], st["n_tile_dofs"],
+                                  prob.coef_kind)
+    # tile storage the launch works in (every item's vectors on every level of its V-cycle)
+    ws = sum(8 * (6 * S[0] + 3 * sum(S[1:])) if opts.precision == 0 else
+             8 * S[0] + 4 * (6 * S[0] + 3 * sum(S[1:]))
+             for S in (tile_levels(a, b, m) for a, b in shapes)) * prob.n_eig
+    achieved = surv / (pcg_ms * 1e-3) / 1e9
+    a_sched = sched / (pcg_ms * 1e-3) / 1e9
+    rl = {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+          "traffic": measured_traffic(kernel, prob.name),
+          "count": (f"{surv_it:g} B per tile unknown per PCG iteration (18 vector passes of "
+                    f"{elem} B{', +8 passes for the variable coefficient' if prob.coef_kind else ''}"
+                    f"{'; FP64 refinement passes 44 B per unknown and step' if opts.precision else ''})"
+                    f" + {8 if opts.precision == 0 else 24} B per tile unknown"),
+          "bytes_per_launch": surv,
+          "schedule_count": {"achieved": a_sched, "frac": a_sched / HBM_PEAK_GBS,
+                             "bytes_per_launch": sched, "bytes_per_tile_dof_iter": sched_it},
+          "tile_working_set_bytes": ws}
+    if ws <= LLC_BYTES:
+        rl["cache_resident"] = (f"the launch's tile storage ({ws / 2 ** 20:.0f} MiB) fits the "
+                                f"{LLC_BYTES // 2 ** 20} MiB last-level cache: not a DRAM figure")
+    return rl
 
 
 def main():
@@ -354,17 +532,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c3mixed", "c4", "c5adj", "c2iface", "c3iface",
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c2", "c3mixed", "c4", "c5adj", "c2iface", "c3iface",
                              "ex62", "ex62mixed"],
-                    help="c2: h = 1/512, 8x8 subdomains, q = 3 (default); c3: h = 1/2048, "
-                         "16x16, FP64; c3mixed: the same in FP32 + FP64 refinement; c4: 256 "
-                         "problems batched; c5adj: reverse sweep at h = 1/1024; c2iface, "
-                         "c3iface: c2 / c3 with the paper's own gluing (interface problem); "
-                         "ex62, ex62mixed: the operator of Example 6.2 (tensor A, weight "
-                         "phi) on (-1,1)^2, H = 0.1, h = 1/320, 5x5 subdomains, q = 6")
+                    help="c3 (default): unit square, h = 1/2048, 16x16 subdomains, q = 1, FP64, "
+                         "with the same in FP32 + FP64 refinement beside it; c2: h = 1/512, "
+                         "8x8 subdomains, q = 3; c3mixed: c3 in FP32 + FP64 refinement only; "
+                         "c4: 256 problems batched; c5adj: reverse sweep at h = 1/1024; "
+                         "c2iface, c3iface: c2 / c3 with the paper's own gluing (interface "
+                         "problem); ex62, ex62mixed: the operator of Example 6.2 (tensor A, "
+                         "weight phi) on (-1,1)^2, H = 0.1, h = 1/320, 5x5 subdomains, q = 6")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="c3: skip the mixed-precision run beside the FP64 one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run 4 plain device copies of 256 MiB (counter calibration)")
     args = ap.parse_args()
@@ -392,63 +573,12 @@ def main():
         print(f"[bench] calibration: 4 copies of {src.numel() * 8} bytes", file=sys.stderr,
               flush=True)
         del src, dst
+    lds_limit = getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", 65536)
     prob, okw = workload(args.workload)
     opts = B.default_opts(timing=1, block=args.block, **okw)
-    s = B.Solver(prob, opts)
-    s.coarse_setup()
-    for _ in range(prob.n_refine):
-        s.level_correct()
-    print(f"[bench] {prob.name}: reached level {s.level}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        s.rewind()
-        s.level_correct()
-    torch.cuda.synchronize()
-    s.phase_times()  # reset the event accumulators
-    stream = s.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        s.rewind()
-        s.level_correct()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
-    ph = s.phase_times()
-    pcg_ms = ph[0] / args.steps
-    # statistics of the same step (untimed)
-    s.rewind()
-    st = s.level_correct(stats=True)
-    lam = np.array(st["lam"])
+    ms_step, pcg_ms, st, lam = run_steps(prob, opts, args)
     n_dofs = st["n_dofs"]
-    s.close()
-
-    # algorithmic bytes of one local-solve launch
-    m = prob.n_refine
-    shapes = subdomain_shapes(prob)
-    cw, ch = max(shapes, key=lambda x: x[0] * x[1])
-    S0 = tile_levels(cw, ch, m)[0]
-    nt = opts.block or 1024
-    lds_limit = getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", 65536)
-    tile_nx = max(c for c, _ in shapes) * (1 << m) - 1
-    elem = 8 if opts.precision == 0 else 4
-    rmode = ring_mode(nt, tile_nx, opts.nu, elem, lds_limit)
-    # the tensor kind streams its three stiffness planes (FP64, or FP32 in inner solves)
-    coef = (24 if opts.precision == 0 else 12) if prob.coef_kind == 3 else 0
-    if opts.precision == 0:
-        kernel = "k_local_pcg64"
-        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode, coef=coef) / S0
-        bytes_launch = per_dof_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
-    else:
-        kernel = "k_local_mixed"
-        per_dof_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode,
-                                              coef=coef) / S0
-        bytes_launch = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
-                                   st["n_tile_dofs"], mode=rmode, coef=coef,
-                                   coef64=24 if prob.coef_kind == 3 else 0)
-    achieved = bytes_launch / (pcg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(kernel, prob.name)
+    rl = roofline(prob, opts, st, pcg_ms, lds_limit)
 
     gold = golden_lambda(args.workload.replace("mixed", ""))  # ex62mixed -> ex62
     lam_err = None
@@ -468,9 +598,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if opts.precision == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": prob.name, "level": m, "h": prob.h(m), "fine_dofs": n_dofs,
-                   "n_eig": prob.n_eig, "subdomains": f"{prob.sub_x}x{prob.sub_y}",
-                   "overlap": prob.overlap, "precision": "fp64" if opts.precision == 0 else "mixed",
+        "config": {"workload": prob.name, "level": prob.n_refine, "h": prob.h(prob.n_refine),
+                   "fine_dofs": n_dofs, "n_eig": prob.n_eig,
+                   "subdomains": f"{prob.sub_x}x{prob.sub_y}", "overlap": prob.overlap,
+                   "precision": "fp64" if opts.precision == 0 else "mixed",
                    "local_rtol": opts.rtol,
                    "operator": ("Example 6.2: tensor A, mass weight phi, (-1,1)^2"
                                 if prob.coef_kind == 3 else "kappa"),
@@ -479,16 +610,31 @@ def main():
         "lambda": lam.tolist(),
         "lambda_rel_err_vs_oracle": lam_err,
         "local_solve": {"ms": pcg_ms, "items": st["n_items"], "tile_dofs": st["n_tile_dofs"],
-                        "it_max": st["it_max"], "it_sum": st["it_sum"],
-                        "refine_max": st["refine_max"], "relres_max": st["relres_max"],
-                        "bytes_per_tile_dof_iter": per_dof_it, "bytes_per_launch": bytes_launch},
-        "roofline": {"kernel": kernel, "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+                        "it_max": st["it_max"], "it_sum": st["it_sum"], "it_dofs": st["it_dofs"],
+                        "refine_max": st["refine_max"], "refine_dofs": st["refine_dofs"],
+                        "relres_max": st["relres_max"]},
+        "roofline": rl,
     }
     if getattr(prob, "pou", 0) == 2:
         out["interface_problem"] = {"cg_iterations": st["glue_it"],
                                     "relres": st["glue_relres"]}
+    if args.workload == "c3" and not args.no_mixed:
+        # the same workload with FP32 inner solves and FP64 residual refinement
+        mopts = B.default_opts(timing=1, block=args.block, precision=1)
+        mms, mpcg, mst, mlam = run_steps(prob, mopts, args)
+        mrl = roofline(prob, mopts, mst, mpcg, lds_limit)
+        out["mixed"] = {
+            "value": mst["n_dofs"] / (mms * 1e-3), "unit": "fine DOFs/s", "ms_per_step": mms,
+            "dtype": "f32+f64", "lambda": mlam.tolist(),
+            "lambda_rel_err_vs_oracle": (None if gold is None else float(
+                np.max(np.abs(mlam - np.array(gold)) / np.abs(np.array(gold))))),
+            "lambda_rel_diff_vs_fp64_path": float(np.max(np.abs(mlam - lam) / np.abs(lam))),
+            "speedup_vs_fp64": ms_step / mms,
+            "local_solve": {"ms": mpcg, "it_max": mst["it_max"], "it_dofs": mst["it_dofs"],
+                            "refine_max": mst["refine_max"], "refine_dofs": mst["refine_dofs"],
+                            "relres_max": mst["relres_max"]},
+            "roofline": mrl,
+        }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

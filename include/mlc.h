@@ -50,8 +50,10 @@ typedef enum mlc_status {
   MLC_EINVAL = 1,   /* invalid argument or unsupported problem */
   MLC_ENOMEM = 2,   /* workspace too small */
   MLC_EHIP = 3,     /* a HIP runtime or library call failed; see mlc_last_error */
-  MLC_ENOCONV = 4,  /* a local solve did not reach its tolerance within max_it;
-                       results are still written and the stats say which level */
+  MLC_ENOCONV = 4,  /* a local solve (or, with MLC_POU_INTERFACE, the G_{m+1} problem) did
+                       not reach its tolerance within max_it; results are still written.
+                       Reported by mlc_level_correct with statistics, mlc_run,
+                       mlc_batch_step_stats and mlc_batch_run */
   MLC_ESTATE = 5    /* call out of order (e.g. level_correct before coarse_setup) */
 } mlc_status;
 
@@ -146,12 +148,23 @@ mlc_status mlc_workspace_size(const mlc_problem_desc* desc, const mlc_solver_opt
 /* Create a context.  dev_workspace: device buffer of at least mlc_workspace_size bytes,
  * 256-byte aligned, owned by the caller and kept alive until mlc_destroy.  hip_stream:
  * a hipStream_t (NULL = default stream).  Uploads geometry tables on the stream.
- * MLC_EINVAL for: domain/coef_kind out of range, n_coarse < 2, odd n_coarse on the
- * L-shape, n_refine outside 1..10, sub_x/sub_y outside 1..n_coarse, overlap below 1
- * (ramp gluing) or 0 (otherwise), an Omega_j narrower than 2 coarse cells, n_eig outside
- * 1..8 or above the number of coarse interior nodes, kappa NULL when needed, not > 0
- * and finite (kind 3: A not positive definite or phi not > 0 on some triangle), a
- * subdomain whose coarse interior exceeds 1024 nodes. */
+ * MLC_EINVAL (mlc_workspace_size and the batch calls reject the same) for:
+ *   descriptor: NULL; domain outside 0..2; coef_kind outside 0..3; n_coarse outside
+ *   2..4096, or odd on the L-shape; n_refine outside 1..10; a finest grid of more than
+ *   32768 cells per side (n_coarse * 2^n_refine); sub_x or sub_y outside 1..n_coarse; pou
+ *   outside 0..2; overlap above n_coarse, or below 1 with MLC_POU_RAMP (below 0
+ *   otherwise); an Omega_j narrower than 2 coarse cells either way; more than 8 blocks
+ *   D_j whose Omega_j reach one node along an axis (overlap too wide for the blocks);
+ *   a subdomain whose coarse interior exceeds 1024 nodes; n_eig outside 1..8 or above the
+ *   number of coarse interior nodes n_H; n_H (1 + 3 n_eig) above 8192 (the device
+ *   Rayleigh-Ritz solve); kappa NULL when the kind needs it, or a value not > 0 and
+ *   finite (kind 3: A not positive definite or phi not > 0 on some triangle);
+ *   MLC_POU_INTERFACE with a tape or in a batch of more than one problem; record_tape
+ *   with n_eig != 1 or coef_kind other than 1 and 2;
+ *   options: NULL; precision not 0 or 1; rtol outside (0, 1); max_it < 1; nu outside
+ *   1..8; omega outside (0, 1); mixed precision with max_refine < 1 or inner_rtol outside
+ *   (0, 1); block not 0, 256, 512 or 1024;
+ *   workspace: NULL or not 256-byte aligned (MLC_ENOMEM when smaller than needed). */
 mlc_status mlc_create(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
                       void* dev_workspace, size_t workspace_bytes, void* hip_stream,
                       struct mlc_ctx** out);
@@ -166,7 +179,9 @@ mlc_status mlc_coarse_setup(struct mlc_ctx* ctx);
  * and asynchronous when st == NULL.  MLC_ESTATE before setup or at the finest level. */
 mlc_status mlc_level_correct(struct mlc_ctx* ctx, mlc_level_stats* st);
 
-/* Run every remaining correction (no statistics). */
+/* Run every remaining correction (no statistics); then synchronise and return
+ * MLC_ENOCONV if a local solve of any of these steps ended above rtol (mlc_level_correct
+ * without statistics is asynchronous and reports nothing). */
 mlc_status mlc_run(struct mlc_ctx* ctx);
 
 /* Step back to the previous level (its eigenpair is still held), so the last
@@ -177,12 +192,18 @@ mlc_status mlc_rewind(struct mlc_ctx* ctx);
 mlc_status mlc_current_level(const struct mlc_ctx* ctx, int32_t* level);
 
 /* The current eigenpairs: lambda_host[q] (host, may be NULL) and u_dev (device,
- * q*(N_k+1)^2 doubles, may be NULL).  Each eigenvector is signed so that its nodal sum
- * is >= 0.  Synchronises the stream when lambda_host != NULL. */
+ * q*(N_k+1)^2 doubles, may be NULL).  b(u, u) = 1 leaves the sign free; each eigenvector
+ * is signed so that its nodal sum is positive when |sum u| > 1e-8 sum |u|, and otherwise
+ * (a vector odd under a symmetry of the problem) so that the first node in grid order
+ * whose magnitude is within a relative 1e-6 of the largest is positive.  Synchronises
+ * the stream when lambda_host != NULL. */
 mlc_status mlc_get_eigenpairs(struct mlc_ctx* ctx, double* lambda_host, double* u_dev);
 
 /* Replace the current state by (level, lambda_host[q], u_dev) given on the level grid
- * (device, q*(N_level+1)^2 doubles, values at non-interior nodes ignored).  Needs setup. */
+ * (device, q*(N_level+1)^2 doubles, values at non-interior nodes ignored).  Needs setup.
+ * The recorded tape of the levels up to `level` then no longer belongs to the state:
+ * mlc_backward and mlc_hf_gradient return MLC_ESTATE until the next mlc_coarse_setup and
+ * a run from level 0. */
 mlc_status mlc_set_state(struct mlc_ctx* ctx, int32_t level, const double* lambda_host,
                          const double* u_dev);
 
@@ -193,12 +214,14 @@ mlc_status mlc_phase_times(struct mlc_ctx* ctx, double* ms, int32_t n);
 /* Exact reverse-mode derivative of the computed finest eigenvalue lambda_1 with respect to
  * the coefficient, through every level: the coarse eigenproblem (Algorithm 4.2 step 1),
  * every correction step (local solves, gluing, Rayleigh-Ritz of Algorithm 4.1) and the
- * children-mean coefficients of coarser levels.  kappa_bar_dev (device, written) receives
+ * children-mean coefficients of coarser levels.  lambda_bar_host (host, one double, read)
+ * is the incoming adjoint of lambda_1; kappa_bar_dev (device, written) receives
  * lambda_bar * d lambda_1 / d kappa in the layout of desc->kappa: per finest cell
- * (coef_kind 2) or per coarse cell (coef_kind 1).  Needs opts.record_tape = 1 (else
- * MLC_EINVAL) and a complete forward run (else MLC_ESTATE).  Runs one adjoint local solve
- * per subdomain and level.  Synchronises. */
-mlc_status mlc_backward(struct mlc_ctx* ctx, double lambda_bar, double* kappa_bar_dev);
+ * (coef_kind 2) or per coarse cell (coef_kind 1).  MLC_EINVAL for a NULL pointer or
+ * without opts.record_tape = 1; MLC_ESTATE without a complete forward run from level 0
+ * (coarse_setup, then every level_correct; not after mlc_set_state).  Runs one adjoint
+ * local solve per subdomain and level.  Synchronises. */
+mlc_status mlc_backward(struct mlc_ctx* ctx, const double* lambda_bar_host, double* kappa_bar_dev);
 
 /* Hellmann-Feynman reference gradient: (u, dK/dkappa u) for the finest eigenvector
  * (b(u,u) = 1), same layout and requirements as mlc_backward.  It ignores how the
@@ -235,7 +258,8 @@ mlc_status mlc_batch_setup(mlc_batch* b);
  * before setup or after the last step. */
 mlc_status mlc_batch_step(mlc_batch* b, int32_t use_graph);
 
-/* All remaining steps (Algorithm 4.2 for every problem). */
+/* All remaining steps (Algorithm 4.2 for every problem); then synchronise and return
+ * MLC_ENOCONV if a local solve of any of these steps ended above rtol. */
 mlc_status mlc_batch_run(mlc_batch* b, int32_t use_graph);
 
 /* Step back once (the previous eigenpairs are still held), so a step can be repeated. */

@@ -216,21 +216,22 @@ class StepRecord:
     residual_norms: Optional[np.ndarray] = None
 
 
+def local_solve(hier: Hierarchy, m: int, s: Subdomain, rhs: np.ndarray):
+    """Equation (Aux_Problem) on one subdomain: e^j = K_j^-1 rhs|_{T_j} with K_j the
+    stiffness on V_0h(Omega_j) (sparse LU, exact to rounding).  rhs is (n_dof, q);
+    returns (tile_dofs, e_j)."""
+    idx = hier.tile_dofs(m, s)
+    if idx.size == 0:
+        return idx, np.zeros((0, rhs.shape[1]))
+    Kj = hier.K[m][idx][:, idx].tocsc()
+    lu = spla.splu(Kj)
+    return idx, lu.solve(np.ascontiguousarray(rhs[idx]))
+
+
 def local_solves(hier: Hierarchy, m: int, rhs: np.ndarray):
-    """Algorithm 4.1 step 1: for each subdomain j, e^j = K_j^-1 rhs|_{T_j} with
-    K_j the stiffness on V_0h(Omega_j) (sparse LU, exact to rounding).
-    rhs is (n_dof, q); returns a list of (tile_dofs, e_j) pairs."""
-    K = hier.K[m]
-    out = []
-    for s in hier.subs:
-        idx = hier.tile_dofs(m, s)
-        if idx.size == 0:
-            out.append((idx, np.zeros((0, rhs.shape[1]))))
-            continue
-        Kj = K[idx][:, idx].tocsc()
-        lu = spla.splu(Kj)
-        out.append((idx, lu.solve(np.ascontiguousarray(rhs[idx]))))
-    return out
+    """Algorithm 4.1 step 1: the independent solves of (Aux_Problem) on every subdomain;
+    returns a list of (tile_dofs, e_j) pairs."""
+    return [local_solve(hier, m, s, rhs) for s in hier.subs]
 
 
 def rayleigh_ritz(hier: Hierarchy, m: int, Ut: np.ndarray, q: int):

@@ -96,7 +96,7 @@ def load_library() -> C.CDLL:
     lib.mlc_set_state.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P]
     lib.mlc_phase_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
     lib.mlc_destroy.argtypes = [P]
-    lib.mlc_backward.argtypes = [P, C.c_double, P]
+    lib.mlc_backward.argtypes = [P, C.POINTER(C.c_double), P]
     lib.mlc_hf_gradient.argtypes = [P, P]
     lib.mlc_status_str.argtypes = [C.c_int]
     lib.mlc_status_str.restype = C.c_char_p
@@ -255,7 +255,8 @@ class Solver:
         """lambda_bar * d lambda_1 / d kappa (torch float64 on the device, kappa's layout)."""
         import torch
         out = torch.empty(self._kappa_shape(), dtype=torch.float64, device=self.device)
-        self._check(self.lib.mlc_backward(self.ctx, C.c_double(lambda_bar), C.c_void_p(out.data_ptr())),
+        lb = C.c_double(lambda_bar)
+        self._check(self.lib.mlc_backward(self.ctx, C.byref(lb), C.c_void_p(out.data_ptr())),
                     "mlc_backward")
         return out
 

@@ -23,6 +23,9 @@ __device__ __forceinline__ double interp2(const double* uc, int nc1, int x, int 
 // eigenpair, so the loads of all of them are in flight together).
 template <int KIND>
 __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, int m, int src) {
+  // the step's convergence record starts empty (the local solves follow on the stream)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+    probs[0].conv[m] = 0.0;
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
   const int i = blockIdx.z;
@@ -669,23 +672,76 @@ __global__ __launch_bounds__(NTG) void k_tile_inverse(const ProbDev* probs, cons
   for (int e = threadIdx.x; e < n * n; e += NTG) inv[it.inv_off + e] = A[e];
 }
 
-// Output: per-eigenvector nodal sums (two fixed-order stages), then a signed copy.
-__global__ __launch_bounds__(NTG) void k_sum_parts(const double* u, int64_t nn, int q,
-                                                   double* parts, int nblk) {
-  __shared__ double red[NTG / 64];
+// Output sign (b(u, u) = 1 in Algorithm 4.1 step 3 fixes u only up to sign).  Per
+// eigenvector: the nodal sum, the sum of magnitudes and the largest magnitude, each in two
+// fixed-order stages (64 blocks, then one pass over their partials).  The sum decides when
+// it exceeds 1e-8 of the magnitudes' sum; otherwise (an eigenvector odd under a symmetry
+// of the problem, whose sum is rounding noise) the first node in grid order whose
+// magnitude lies within a relative 1e-6 of the largest is made positive: the largest
+// magnitudes of such a vector come in pairs of opposite sign that tie in exact
+// arithmetic, and the relative band makes the choice stable under rounding.
+// Partials: parts[(k * 4 + c) * nblk + block], c = 0 sum, 1 magnitudes, 2 largest
+// magnitude, 3 first index within the band (as a double, exact below 2^53).
+constexpr double kSignSumRtol = 1e-8;
+constexpr double kSignMaxRtol = 1e-6;
+
+__global__ __launch_bounds__(NTG) void k_sign_parts(const double* u, int64_t nn, int q,
+                                                    double* parts, int nblk) {
+  __shared__ double red[3][NTG / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < q; ++k) {
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NTG + threadIdx.x; i < nn; i += (int64_t)nblk * NTG)
-      s += u[(int64_t)k * nn + i];
+    double s = 0.0, a = 0.0, mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NTG + threadIdx.x; i < nn; i += (int64_t)nblk * NTG) {
+      const double v = u[(int64_t)k * nn + i];
+      s += v;
+      a += fabs(v);
+      mx = fmax(mx, fabs(v));
+    }
     s = wave_sum(s);
+    a = wave_sum(a);
+    mx = read_lane_f64(group_reduce_last(mx, 64, 0.0, [](double x, double y) { return fmax(x, y); }), 63);
     __syncthreads();
-    if (lane == 0) red[wid] = s;
+    if (lane == 0) {
+      red[0][wid] = s;
+      red[1][wid] = a;
+      red[2][wid] = mx;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < NTG / 64; ++w) t += red[w];
-      parts[k * nblk + blockIdx.x] = t;
+      double ts = 0.0, ta = 0.0, tm = 0.0;
+      for (int w = 0; w < NTG / 64; ++w) {
+        ts += red[0][w];
+        ta += red[1][w];
+        tm = fmax(tm, red[2][w]);
+      }
+      parts[(k * 4 + 0) * nblk + blockIdx.x] = ts;
+      parts[(k * 4 + 1) * nblk + blockIdx.x] = ta;
+      parts[(k * 4 + 2) * nblk + blockIdx.x] = tm;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTG) void k_sign_first(const double* u, int64_t nn, int q,
+                                                    double* parts, int nblk) {
+  __shared__ double red[NTG / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double none = (double)nn;
+  for (int k = 0; k < q; ++k) {
+    double mx = 0.0;
+    for (int b = 0; b < nblk; ++b) mx = fmax(mx, parts[(k * 4 + 2) * nblk + b]);
+    const double thr = (1.0 - kSignMaxRtol) * mx;
+    double first = none;  // each thread visits its nodes in ascending order
+    for (int64_t i = (int64_t)blockIdx.x * NTG + threadIdx.x; i < nn; i += (int64_t)nblk * NTG)
+      if (first == none && fabs(u[(int64_t)k * nn + i]) >= thr) first = (double)i;
+    first = read_lane_f64(
+        group_reduce_last(first, 64, none, [](double x, double y) { return fmin(x, y); }), 63);
+    __syncthreads();
+    if (lane == 0) red[wid] = first;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = none;
+      for (int w = 0; w < NTG / 64; ++w) t = fmin(t, red[w]);
+      parts[(k * 4 + 3) * nblk + blockIdx.x] = t;
     }
   }
 }
@@ -695,9 +751,18 @@ __global__ __launch_bounds__(NTG) void k_copy_signed(const double* u, int64_t nn
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= nn) return;
   for (int k = 0; k < q; ++k) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += parts[k * nblk + b];
-    out[(int64_t)k * nn + idx] = (s < 0.0 ? -1.0 : 1.0) * u[(int64_t)k * nn + idx];
+    double s = 0.0, a = 0.0, first = (double)nn;
+    for (int b = 0; b < nblk; ++b) {
+      s += parts[(k * 4 + 0) * nblk + b];
+      a += parts[(k * 4 + 1) * nblk + b];
+      first = fmin(first, parts[(k * 4 + 3) * nblk + b]);
+    }
+    bool flip;
+    if (fabs(s) > kSignSumRtol * a)
+      flip = s < 0.0;
+    else
+      flip = first < (double)nn && u[(int64_t)k * nn + (int64_t)first] < 0.0;
+    out[(int64_t)k * nn + idx] = (flip ? -1.0 : 1.0) * u[(int64_t)k * nn + idx];
   }
 }
 
@@ -861,9 +926,12 @@ hipError_t launch_tile_inverse(int kind, const ProbDev* probs, const TileItem* i
 
 hipError_t launch_output_signed(const double* u, int64_t nn, int q, double* parts, double* out,
                                 hipStream_t s) {
-  const int nblk = 64;
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblk), dim3(NTG), 0, s, u, nn, q, parts, nblk);
+  const int nblk = 64;  // parts: 4 * q * nblk doubles
+  hipLaunchKernelGGL(k_sign_parts, dim3(nblk), dim3(NTG), 0, s, u, nn, q, parts, nblk);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sign_first, dim3(nblk), dim3(NTG), 0, s, u, nn, q, parts, nblk);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_copy_signed, dim3(nblocks(nn)), dim3(NTG), 0, s, u, nn, q, parts, nblk, out);
   return hipGetLastError();

@@ -85,6 +85,8 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     s.refine = refine;
     s.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     stats[blockIdx.x] = s;
+    atomicMax(reinterpret_cast<unsigned long long*>(P.conv + m),
+              (unsigned long long)__double_as_longlong(s.relres));
   }
 }
 

@@ -62,6 +62,9 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
     s.refine = 0;
     s.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     stats[blockIdx.x] = s;
+    if (!rhs_in_tile)  // forward solves: the step's largest relative residual
+      atomicMax(reinterpret_cast<unsigned long long*>(P.conv + m),
+                (unsigned long long)__double_as_longlong(s.relres));
   }
 }
 

@@ -59,6 +59,11 @@ struct ProbDev {
   double* rr_ab;              // alpha = u~^T K u~, beta = u~^T M u~ (q = 1: 2 values)
   double* cH_grid;            // q*(n_c+1)^2 coarse nodal coefficients
   double* sum_parts;          // output sign partial sums
+  // per level step s: the largest final relative residual of the step's local solves,
+  // [MLC_MAX_LEVELS + 1] doubles shared by every problem of a batch (non-negative doubles
+  // order as their bit patterns, so the solves raise it with an integer atomic maximum);
+  // cleared by the step's first kernel
+  double* conv;
 };
 
 // One local solve: subdomain Omega_j of problem prob, right-hand side rhs.

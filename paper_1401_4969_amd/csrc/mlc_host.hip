@@ -226,7 +226,7 @@ struct Plan {
   std::vector<ProbLayout> pl;
   std::vector<StepTables> steps;  // index s (1..Lmax); steps[0] unused
   int n = 0, q = 0, kind = 0, Lmax = 0, max_nH = 0, max_nc1sq = 0, precision = 0;
-  size_t probdev = 0, stats = 0, inv = 0, store = 0, store_bytes = 0, total = 0;
+  size_t probdev = 0, stats = 0, conv = 0, inv = 0, store = 0, store_bytes = 0, total = 0;
   int64_t max_items = 0, inv_total = 0;
 };
 
@@ -316,7 +316,7 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.rr_t = take(q * q * 8);
     L.rr_ab = take(2 * 8);
     L.cH = take(q * ncs * 8);
-    L.out_parts = take(64 * q * 8);
+    L.out_parts = take(4 * 64 * q * 8);  // output sign partials (4 per block)
     L.skel = L.skel_parts = L.skel_scal = 0;
     if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem on the finest grid
       L.skel = take(6 * q * nnL * 8);  // six vectors per right-hand side
@@ -394,6 +394,7 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     T.sub_item_off = take(T.sub_item.size() * 4);
   }
   P.stats = take((size_t)P.max_items * sizeof(ItemStat));
+  P.conv = take((MLC_MAX_LEVELS + 1) * 8);  // per step: the largest local relative residual
   P.inv = take((size_t)P.inv_total * 8);
   if (o->record_tape) {
     const Geometry& g = P.geo[0];
@@ -467,6 +468,8 @@ struct mlc_batch {
   std::vector<double> e0;  // unit coefficient vector (host copy kept for the async upload)
   int glue_it = 0;         // last step's G_{m+1} problem (MLC_POU_INTERFACE)
   double glue_relres = 0.0;
+  std::vector<double> glue_relres_step;  // per step (index s), MLC_POU_INTERFACE
+  bool tape_valid = false;  // every taped level comes from steps run from level 0
 };
 
 struct mlc_ctx {
@@ -532,6 +535,7 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
   b->blocks.assign(P.Lmax + 1, o->block ? o->block : 1024);
   b->graphs.assign(P.Lmax + 1, nullptr);
   b->graph_defs.assign(P.Lmax + 1, nullptr);
+  b->glue_relres_step.assign(P.Lmax + 1, 0.0);
   b->kappa.resize(n);
   b->hp.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -588,6 +592,7 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     D.rr_ab = (double*)(w + L.rr_ab);
     D.cH_grid = (double*)(w + L.cH);
     D.sum_parts = (double*)(w + L.out_parts);
+    D.conv = (double*)(w + P.conv);
   }
   b->dprob = (ProbDev*)(w + P.probdev);
   hipStream_t st = b->st;
@@ -694,8 +699,10 @@ mlc_status batch_setup(mlc_batch* b) {
       return MLC_EHIP;
     }
   }
+  MLC_HIP(b, hipMemset(w + P.conv, 0, (MLC_MAX_LEVELS + 1) * 8));
   b->step = 0;
   b->can_rewind = false;
+  b->tape_valid = true;
   std::fill(b->shift.begin(), b->shift.end(), 0);
   return MLC_OK;
 }
@@ -739,6 +746,7 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
                                     P.geo[0].nodes(s), b->o.rtol, 100000, (double*)(w + L.skel),
                                     (double*)(w + L.skel_parts), (double*)(w + L.skel_scal), st,
                                     &b->glue_it, &b->glue_relres));
+    b->glue_relres_step[s] = b->glue_relres;
   } else {
     MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, P.q, st));
   }
@@ -910,6 +918,32 @@ mlc_status phase_times(mlc_batch* b, double* ms, int32_t n) {
   return MLC_OK;
 }
 
+// After steps from+1 .. to: MLC_ENOCONV if a local solve of one of them (or, with the
+// interface gluing, its G_{m+1} problem) ended above the tolerance.  Synchronises.
+mlc_status check_converged(mlc_batch* b, int from, int to) {
+  if (to <= from) return MLC_OK;
+  double worst[MLC_MAX_LEVELS + 1];
+  MLC_HIP(b, hipStreamSynchronize(b->st));
+  MLC_HIP(b, hipMemcpy(worst, b->ws + b->plan.conv, (MLC_MAX_LEVELS + 1) * 8,
+                       hipMemcpyDeviceToHost));
+  const double lim = b->o.rtol * 1.0000001;
+  for (int s = from + 1; s <= to; ++s) {
+    if (!(worst[s] <= lim)) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg,
+                    "a local solve of level step %d ended at relative residual %.3e > rtol", s,
+                    worst[s]);
+      b->err = msg;
+      return MLC_ENOCONV;
+    }
+    if (b->plan.geo[0].pou == MLC_POU_INTERFACE && !(b->glue_relres_step[s] <= lim)) {
+      b->err = "the G_{m+1} problem of level step " + std::to_string(s) + " did not converge";
+      return MLC_ENOCONV;
+    }
+  }
+  return MLC_OK;
+}
+
 void batch_destroy(mlc_batch* b) {
   if (b->st) (void)hipStreamSynchronize(b->st);
   drop_graphs(b);
@@ -995,11 +1029,12 @@ mlc_status mlc_run(mlc_ctx* c) {
     c->b->err = "run needs coarse_setup";
     return MLC_ESTATE;
   }
+  const int from = c->b->step;
   while (c->b->step < c->b->plan.Lmax) {
     mlc_status s = batch_step(c->b, 0);
     if (s != MLC_OK) return s;
   }
-  return MLC_OK;
+  return check_converged(c->b, from, c->b->step);
 }
 
 mlc_status mlc_rewind(mlc_ctx* c) {
@@ -1037,6 +1072,7 @@ mlc_status mlc_set_state(mlc_ctx* c, int32_t level, const double* lam_host, cons
   b->step = level;
   b->shift[0] = level & 1;
   b->can_rewind = false;
+  b->tape_valid = false;  // the tape below `level` does not belong to this state
   drop_graphs(b);
   return MLC_OK;
 }
@@ -1126,18 +1162,18 @@ static mlc_status backward_impl(mlc_batch* b, double lambda_bar, double* out, bo
   return MLC_OK;
 }
 
-mlc_status mlc_backward(mlc_ctx* c, double lambda_bar, double* kappa_bar_dev) {
-  if (!c || !kappa_bar_dev) return MLC_EINVAL;
+mlc_status mlc_backward(mlc_ctx* c, const double* lambda_bar_host, double* kappa_bar_dev) {
+  if (!c || !lambda_bar_host || !kappa_bar_dev) return MLC_EINVAL;
   mlc_batch* b = c->b;
   if (!b->plan.tape.on) {
     b->err = "backward needs opts.record_tape = 1";
     return MLC_EINVAL;
   }
-  if (b->step != b->plan.Lmax || b->shift[0] != 0) {
+  if (b->step != b->plan.Lmax || b->shift[0] != 0 || !b->tape_valid) {
     b->err = "backward needs a complete forward run (coarse_setup, then every level_correct)";
     return MLC_ESTATE;
   }
-  return backward_impl(b, lambda_bar, kappa_bar_dev, false);
+  return backward_impl(b, *lambda_bar_host, kappa_bar_dev, false);
 }
 
 mlc_status mlc_hf_gradient(mlc_ctx* c, double* kappa_bar_dev) {
@@ -1147,7 +1183,7 @@ mlc_status mlc_hf_gradient(mlc_ctx* c, double* kappa_bar_dev) {
     b->err = "the Hellmann-Feynman gradient needs opts.record_tape = 1";
     return MLC_EINVAL;
   }
-  if (b->step != b->plan.Lmax || b->shift[0] != 0) {
+  if (b->step != b->plan.Lmax || b->shift[0] != 0 || !b->tape_valid) {
     b->err = "the Hellmann-Feynman gradient needs a complete forward run";
     return MLC_ESTATE;
   }
@@ -1210,11 +1246,12 @@ mlc_status mlc_batch_run(mlc_batch* b, int32_t use_graph) {
     b->err = "run needs setup";
     return MLC_ESTATE;
   }
+  const int from = b->step;
   while (b->step < b->plan.Lmax) {
     mlc_status s = batch_step(b, use_graph);
     if (s != MLC_OK) return s;
   }
-  return MLC_OK;
+  return check_converged(b, from, b->step);
 }
 
 mlc_status mlc_batch_rewind(mlc_batch* b) {
@@ -1237,6 +1274,7 @@ mlc_status mlc_batch_restart(mlc_batch* b) {
   MLC_HIP(b, launch_init_u0(b->dprob, b->plan.n, 0, b->plan.max_nc1sq, b->st));
   b->step = 0;
   b->can_rewind = false;
+  b->tape_valid = true;  // the next steps record every level again from level 0
   std::fill(b->shift.begin(), b->shift.end(), 0);
   return MLC_OK;
 }

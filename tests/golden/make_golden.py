@@ -4,11 +4,12 @@ Calls only the CPU oracle (``oracle/``) on the seeded workloads (``workloads.py`
 value here comes from the GPU path.  Output: tests/golden/oracle_<name>.json with the
 per-level eigenvalues and, for the finest level, eigenvector values at a seeded sample
 of interior nodes (each vector with non-negative nodal sum); configuration 4's per-level
-eigenvalues for all 256 problems; and for configuration 5, central differences of the
+eigenvalues for all 256 problems and the finest eigenvectors of four of them at seeded
+nodes; and for configuration 5, central differences of the
 finest eigenvalue along seeded kappa directions and with respect to 32 seeded single
 cells (checks of the reverse sweep).
 
-    python tests/golden/make_golden.py [c1 c2 c3 c5 c2iface ex62 c4 c5_fd c5_cells ...]
+    python tests/golden/make_golden.py [c1 c2 c3 c5 c2iface ex62 c4 c4_vectors c5_fd c5_cells ...]
 """
 import json
 import os
@@ -82,6 +83,30 @@ def make_batch(workers: int = 6):
     print(f"c4: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
 
 
+C4_VECTOR_PROBLEMS = (0, 17, 100, 255)
+
+
+def make_batch_vectors(n_samples: int = 256):
+    """Configuration 4: finest eigenvectors of four of the problems at seeded nodes."""
+    probs = W.config4()
+    t0 = time.perf_counter()
+    out = []
+    for i in C4_VECTOR_PROBLEMS:
+        res = solve(probs[i], keep_levels=False)
+        mesh = res.hier.meshes[probs[i].n_refine]
+        rng = np.random.Generator(np.random.PCG64(4000 + i))
+        pick = np.sort(rng.choice(mesh.dof.size, size=min(n_samples, mesh.dof.size),
+                                  replace=False))
+        out.append(dict(index=i, name=probs[i].name, lam=res.lam.tolist(),
+                        sample_nodes=mesh.dof[pick].tolist(),
+                        sample_values=res.U[pick, 0].tolist()))
+    path = os.path.join(HERE, "oracle_c4_vectors.json")
+    with open(path, "w") as f:
+        json.dump(dict(problems=out, source="oracle.solve (CPU FP64), written by "
+                       "tests/golden/make_golden.py from the oracle only"), f, indent=1)
+    print(f"c4 vectors: {time.perf_counter() - t0:.1f} s -> {path}", flush=True)
+
+
 def _lam_along(args):
     name, j, t = args
     prob = CONFIGS[name]()
@@ -146,9 +171,11 @@ def make_cell_fd(name: str = "c5", n_cells: int = 32, seed: int = 55,
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CONFIGS) + ["c4", "c5_fd", "c5_cells"]):
+    for n in (sys.argv[1:] or list(CONFIGS) + ["c4", "c4_vectors", "c5_fd", "c5_cells"]):
         if n == "c4":
             make_batch()
+        elif n == "c4_vectors":
+            make_batch_vectors()
         elif n == "c5_fd":
             make_fd("c5")
         elif n == "c5_cells":

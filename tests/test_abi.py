@@ -169,3 +169,55 @@ def test_plans_keep_tile_items_of_a_subdomain_adjacent():
         assert B.workspace_size(W.config1().with_(n_eig=q, n_refine=3)) > 0
     assert B.workspace_size(W.small_ragged()) > 0
     assert B.workspace_size(W.config2()) > 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_coarse=4098),                                   # n_coarse above 4096
+    dict(n_coarse=512, n_refine=7, sub_x=32, sub_y=32),    # finest grid of 65536 cells per side
+    dict(overlap=9),                                       # overlap above n_coarse = 8
+    dict(n_coarse=32, n_refine=1, sub_x=32, sub_y=32, overlap=5),  # 11 blocks reach a node
+    dict(n_coarse=64, n_refine=1, sub_x=16, sub_y=16, n_eig=1),    # n_H (1 + 3q) = 15876
+])
+def test_every_header_rejection_of_the_descriptor(bad):
+    """Each descriptor rejection that include/mlc.h lists for mlc_create, beyond the
+    field ranges checked above."""
+    p = W.config1().with_(**bad)
+    with pytest.raises(B.MLCError) as e:
+        B.workspace_size(p)
+    assert e.value.status == B.MLC_EINVAL
+
+
+def test_every_header_rejection_of_the_options():
+    for kw in (dict(max_it=0), dict(nu=9), dict(omega=0.0), dict(rtol=1.0),
+               dict(precision=1, max_refine=0), dict(precision=1, inner_rtol=1.5),
+               dict(block=2048)):
+        with pytest.raises(B.MLCError) as e:
+            B.workspace_size(W.config1(), B.default_opts(**kw))
+        assert e.value.status == B.MLC_EINVAL, kw
+    # a tape needs q = 1 and a per-cell coefficient (kind 1 or 2)
+    for p in (W.small_field().with_(n_eig=2), W.config1()):
+        with pytest.raises(B.MLCError) as e:
+            B.workspace_size(p, B.default_opts(record_tape=1))
+        assert e.value.status == B.MLC_EINVAL
+
+
+def test_workspace_checks_before_any_device_call():
+    """mlc_create rejects a misaligned workspace (MLC_EINVAL) and one that is too small
+    (MLC_ENOMEM) before it touches the device: the pointers below are never dereferenced."""
+    lib = B.load_library()
+    d, _k = B.make_desc(W.config1())
+    o = B.default_opts()
+    need = B.workspace_size(W.config1())
+    ctx = C.c_void_p()
+    assert lib.mlc_create(C.byref(d), C.byref(o), C.c_void_p(0x1000 + 8), need, None,
+                          C.byref(ctx)) == B.MLC_EINVAL
+    assert lib.mlc_create(C.byref(d), C.byref(o), C.c_void_p(0x1000 * 256), need - 256, None,
+                          C.byref(ctx)) == B.MLC_ENOMEM
+    assert not ctx.value
+
+
+def test_backward_argument_checks():
+    lib = B.load_library()
+    lb = C.c_double(1.0)
+    assert lib.mlc_backward(None, C.byref(lb), C.c_void_p(0x1000)) == B.MLC_EINVAL
+    assert lib.mlc_hf_gradient(None, C.c_void_p(0x1000)) == B.MLC_EINVAL

@@ -148,6 +148,26 @@ def test_backward_errors():
         s.backward()
     assert e.value.status == B.MLC_ESTATE
     s.close()
+    # a state set from outside leaves the tape of the levels below it stale: after
+    # set_state and the remaining steps the reverse sweep refuses, until a new setup
+    torch = _torch()
+    prob = W.small_field()
+    s = B.Solver(prob, B.default_opts(record_tape=1))
+    s.coarse_setup()
+    s.run()
+    g0 = s.backward(1.0)
+    s.rewind()
+    lam, u = s.eigenpairs()
+    s.set_state(prob.n_refine - 1, lam, u)
+    s.level_correct()
+    for call in (lambda: s.backward(1.0), s.hf_gradient):
+        with pytest.raises(B.MLCError) as e:
+            call()
+        assert e.value.status == B.MLC_ESTATE
+    s.coarse_setup()
+    s.run()
+    assert torch.equal(s.backward(1.0), g0)
+    s.close()
     with pytest.raises(B.MLCError):          # q > 1 has no tape
         B.workspace_size(W.small_ragged(), B.default_opts(record_tape=1))
 
@@ -190,9 +210,15 @@ def test_config5_gradient():
 
 def test_config5_gradient_single_cells():
     """Configuration 5: the gradient at 32 cells drawn with seed 55 against stored central
-    differences of the oracle with respect to single kappa entries.  The differences at
-    relative steps 1e-3 and 1e-2 agree to 1.5e-4 relative (rounding noise of the oracle's
-    eigenvalue over a change of ~1e-9 at the smallest entries), hence the tolerance."""
+    differences of the oracle with respect to single kappa entries, to 1e-4 of the largest
+    of them.  A difference quotient at relative step t carries the oracle eigenvalue's
+    rounding noise (about 1e-12 of lambda = 20.8) divided by 2 t kappa_c: about 1e-9 at
+    t = 1e-3, up to a quarter of 1e-4 relative at the smallest of these derivatives
+    (4e-6) but a few 1e-5 of the largest (6.6e-5); its truncation error is of order t^2,
+    which the step-1e-2 quotients show (they differ from the step-1e-3 ones by at most
+    3.4e-9, 5e-5 of the largest).  So the bound is absolute, 1e-4 max |fd|, and the
+    relative 1e-4 holds on the cells whose derivative exceeds half the largest, where the
+    noise is below 3e-5 relative."""
     _torch()
     path = os.path.join(os.path.dirname(__file__), "golden", "oracle_c5_cells.json")
     if not os.path.exists(path):
@@ -204,7 +230,14 @@ def test_config5_gradient_single_cells():
     _, g, _ = gpu_grad(prob)
     got = g.ravel()[np.asarray(gold["cells"])]
     fd = np.asarray(gold["fd"]["0.001"])
-    assert np.max(np.abs(got - fd) / np.abs(fd)) < 3e-4, (got, fd)
+    scale = np.max(np.abs(fd))
+    err = np.abs(got - fd)
+    print(f"c5 single cells: max |g - fd| = {np.max(err):.2e} = {np.max(err) / scale:.2e} "
+          f"of max |fd|; worst relative {np.max(err / np.abs(fd)):.2e}")
+    assert np.max(err) <= 1e-4 * scale, (got, fd)
+    big = np.abs(fd) >= 0.5 * scale
+    assert big.sum() >= 4
+    assert np.max(err[big] / np.abs(fd[big])) <= 1e-4, (got[big], fd[big])
 
 
 def test_autograd_function():

@@ -252,4 +252,17 @@ def test_config4_full_batch():
         lam1, u1 = _single(probs[i], precision=1)
         assert np.array_equal(lam, lam1)
         assert torch.equal(u, u1)
+    # finest eigenvectors of four problems at seeded nodes, signed, against the oracle
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_c4_vectors.json")) as f:
+        vec_gold = json.load(f)["problems"]
+    for g in vec_gold:
+        _, u = bs.get(g["index"])
+        idx = torch.as_tensor(np.asarray(g["sample_nodes"]), device=u.device)
+        vals = u[0].reshape(-1)[idx].cpu().numpy()
+        ref = np.asarray(g["sample_values"])
+        err = np.max(np.abs(vals - ref)) / np.max(np.abs(ref))
+        print(f"config 4 problem {g['index']}: max sample error {err:.2e} (signed)")
+        assert err < 1e-8, (g["index"], err)
     bs.close()

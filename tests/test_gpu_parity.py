@@ -1,9 +1,12 @@
 """GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
 
 Eigenvalues must agree to 1e-10 relative at every level (FP64 path).  Eigenvectors are
-compared up to sign (each is determined up to sign), or as subspaces (principal angles in
-the b-inner product) where eigenvalues are close, since there only the span is well
-conditioned.
+compared node by node over the whole finest grid with their signs: both paths apply the
+same sign rule (positive nodal sum, or for a vector odd under a symmetry the first node of
+largest magnitude positive), since b(u, u) = 1 fixes a vector only up to sign.  Where
+eigenvalues are close (relative gap below 1e-3) only their span is well conditioned, so
+there the b-orthogonal projectors onto the spans are compared node by node, applied to
+seeded vectors, together with the largest principal angle.
 """
 import numpy as np
 import pytest
@@ -35,8 +38,10 @@ def grid_to_dof(hier, m, u_grid):
 
 
 def check_vectors(hier, m, Ug_grid, Uo, lam, tol=1e-8):
-    """Per-vector sign-invariant comparison for well separated eigenvalues; principal
-    angles for clusters (relative gap below 1e-3)."""
+    """Signed node-by-node comparison (max |a - b| <= tol max |b| over every node, and the
+    b-norm of the difference below tol) for well separated eigenvalues; for clusters
+    (relative gap below 1e-3) the b-orthogonal projectors U U^T M applied to three seeded
+    vectors node by node, and the sine of the largest principal angle below tol."""
     M = hier.M[m]
     Ug = grid_to_dof(hier, m, Ug_grid)
     q = Uo.shape[1]
@@ -51,12 +56,21 @@ def check_vectors(hier, m, Ug_grid, Uo, lam, tol=1e-8):
         if j == i + 1:
             a = Ug[:, i]
             b = Uo[:, i]
-            d = min(np.sqrt((a - b) @ (M @ (a - b))), np.sqrt((a + b) @ (M @ (a + b))))
-            assert d < tol, (i, d)
+            e = np.max(np.abs(a - b)) / np.max(np.abs(b))
+            d = np.sqrt((a - b) @ (M @ (a - b)))
+            print(f"vector {i}: max node error {e:.2e} of max |u|, b-norm error {d:.2e}")
+            assert e < tol and d < tol, (i, e, d)
         else:
-            C = Uo[:, i:j].T @ (M @ Ug[:, i:j])
+            A, B = Ug[:, i:j], Uo[:, i:j]
+            C = B.T @ (M @ A)
             s = np.linalg.svd(C, compute_uv=False)
-            assert np.all(s > 1 - tol), (i, j, s)
+            sin_max = np.sqrt(max(0.0, 1.0 - float(np.min(s)) ** 2))
+            X = np.random.Generator(np.random.PCG64(7)).standard_normal((A.shape[0], 3))
+            pa = A @ (A.T @ (M @ X))
+            pb = B @ (B.T @ (M @ X))
+            e = np.max(np.abs(pa - pb)) / np.max(np.abs(pb))
+            print(f"vectors {i}..{j - 1}: projector node error {e:.2e}, sin angle {sin_max:.2e}")
+            assert e < tol and sin_max < tol, (i, j, e, sin_max)
         i = j
 
 
@@ -126,7 +140,7 @@ def test_solver_options_do_not_change_results(kw):
 
 def test_config2_full():
     """Configuration 2 at full size: h = 1/512, 8x8 subdomains, q = 3."""
-    lam, u, levels, stats, ref = compare(W.config2(), vec_tol=1e-6)
+    lam, u, levels, stats, ref = compare(W.config2())
     assert stats[-1]["n_dofs"] == 511 * 511
     assert stats[-1]["n_items"] == 64 * 3
 
@@ -170,14 +184,34 @@ def test_call_order_errors():
 
 
 def test_enoconv_flagged():
-    """max_it = 1 cannot reach 1e-12: the step reports MLC_ENOCONV with stats."""
-    _torch()
+    """max_it = 1 cannot reach 1e-12: the step reports MLC_ENOCONV with stats, and a run
+    without statistics (mlc_run, the device's per-step record of the largest local
+    residual) reports it too, FP64 and mixed; MultilevelEigen raises."""
+    torch = _torch()
     from paper_1401_4969_amd import binding as B
     s = B.Solver(W.config1(), B.default_opts(max_it=1))
     s.coarse_setup()
     d = s.level_correct(stats=True)
     assert d.get("enoconv") and d["relres_max"] > 1e-12
     s.close()
+    for prec in (0, 1):
+        s = B.Solver(W.config1(), B.default_opts(max_it=1, precision=prec, max_refine=1))
+        s.coarse_setup()
+        with pytest.raises(B.MLCError) as e:
+            s.run()
+        assert e.value.status == B.MLC_ENOCONV
+        s.close()
+    # a converged run after a failed one on another context reports nothing
+    s = B.Solver(W.config1())
+    s.coarse_setup()
+    s.run()
+    s.close()
+    import paper_1401_4969_amd as mlc
+    prob = W.small_field()
+    kappa = torch.tensor(prob.kappa, dtype=torch.float64, requires_grad=True)
+    with pytest.raises(B.MLCError) as e:
+        mlc.eigenvalue(kappa, prob, B.default_opts(max_it=1))
+    assert e.value.status == B.MLC_ENOCONV
 
 
 def test_set_state_resume():
@@ -225,23 +259,30 @@ def _golden(name):
 
 
 @pytest.mark.parametrize("name,factory,precision", [("c3", W.config3, 0), ("c5", W.config5, 0),
-                                                    ("c3", W.config3, 1)])
+                                                    ("c3", W.config3, 1), ("c2", W.config2, 1)])
 def test_full_size_against_stored_oracle(name, factory, precision):
     """Configurations 3 (h = 1/2048, 16x16 subdomains; FP64 and mixed precision) and 5
     (h = 1/1024, per-cell log-normal kappa) at full size: every level's eigenvalue against
-    the stored oracle values, and the finest eigenvector at 512 seeded nodes."""
+    the stored oracle values, and the finest eigenvector at 512 seeded nodes (signed)."""
     gold = _golden(name)
     prob = factory()
     lam, u, levels, stats = gpu_solve(prob, precision=precision)
     for k, (a, b) in enumerate(zip(levels, gold["lam_levels"])):
         rel = np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b)))
         assert rel < LAM_RTOL, (name, k, a, b, rel)
-    ug = u[0].reshape(-1)
     idx = np.asarray(gold["sample_nodes"])
     import torch
-    vals = ug[torch.as_tensor(idx, device=ug.device)].cpu().numpy()
-    ref = np.asarray(gold["sample_values"][0])
-    assert np.max(np.abs(vals - ref)) < 1e-8 * np.max(np.abs(ref))
+    for i in range(prob.n_eig):
+        if i > 0 and abs(levels[-1][i] - levels[-1][i - 1]) < 1e-3 * levels[-1][i]:
+            continue   # a close pair (configuration 2's 5 pi^2): only its span is fixed
+        if i + 1 < prob.n_eig and abs(levels[-1][i + 1] - levels[-1][i]) < 1e-3 * levels[-1][i]:
+            continue
+        ug = u[i].reshape(-1)
+        vals = ug[torch.as_tensor(idx, device=ug.device)].cpu().numpy()
+        ref = np.asarray(gold["sample_values"][i])
+        err = np.max(np.abs(vals - ref)) / np.max(np.abs(ref))
+        print(f"{name} vector {i}: max sample error {err:.2e} (signed)")
+        assert err < 1e-8
     for s in stats:
         assert s["relres_max"] <= 1e-12 * 1.0000001
 
@@ -352,9 +393,10 @@ def test_example62_full_size():
     for i in range(6):
         vals = u[i].reshape(-1)[idx].cpu().numpy()
         ref = np.asarray(gold["sample_values"][i])
-        # up to sign: the third eigenfunction is nearly odd, its nodal sum (which fixes the
-        # sign) is rounding noise
-        d = min(np.max(np.abs(vals - ref)), np.max(np.abs(vals + ref)))
+        # signed: the third eigenfunction is nearly odd (its nodal sum is rounding noise), so
+        # both paths sign it by its first node of largest magnitude
+        d = np.max(np.abs(vals - ref))
+        print(f"Example 6.2 vector {i}: max sample error {d / np.max(np.abs(ref)):.2e}")
         assert d < 1e-8 * np.max(np.abs(ref)), i
     printed = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                           "example62_eigenvalues.json")))["eigenvalues"]
