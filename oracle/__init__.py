@@ -9,7 +9,8 @@ local problem with a sparse direct factorisation and every small eigenproblem
 with a dense generalized symmetric eigensolver.
 
 Modules
-  fem  -- meshes, P1 element assembly, nodal interpolation (Section 2.1)
+  fem     -- meshes, P1 element assembly, nodal interpolation (Section 2.1)
+  fem_p2  -- the same for P2 elements (vertex and edge-midpoint nodes)
   mlc  -- the one correction step (Algorithm 4.1) and the multilevel driver
           (Algorithm 4.2), with the readings listed in the design notes.
 """

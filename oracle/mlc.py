@@ -39,6 +39,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fem import Mesh, assemble, interpolation, make_mesh, triangle_kappa, triangle_tensor
+from .fem_p2 import assemble_p2, interpolation_p2, make_mesh_p2
 
 
 # ---------------------------------------------------------------------------
@@ -110,6 +111,19 @@ class Hierarchy:
         self.prob = prob
         L = prob.n_refine
         self.L = L
+        self.order = getattr(prob, "order", 1)
+        if self.order == 2:
+            # P2 elements (Section 2.1 with k = 2): nodes on the grid of half cells
+            self.meshes = [make_mesh_p2(prob.domain, prob.n_cells(m), prob.side, prob.origin)
+                           for m in range(L + 1)]
+            fine = self.meshes[L]
+            assert prob.coef_kind in (0, 1), "P2 elements: kappa constant or per coarse cell"
+            Kf, Mf = assemble_p2(fine, triangle_kappa(fine, prob.coef_kind, prob.kappa,
+                                                      prob.n_coarse))
+            P = [interpolation_p2(prob.domain, self.meshes[m], self.meshes[m + 1], prob.side)
+                 for m in range(L)]
+            self._galerkin(Kf, Mf, P)
+            return
         self.meshes: List[Mesh] = [make_mesh(prob.domain, prob.n_cells(m), prob.side, prob.origin)
                                    for m in range(L + 1)]
         fine = self.meshes[L]
@@ -121,13 +135,19 @@ class Hierarchy:
         else:
             ktri = triangle_kappa(fine, prob.coef_kind, prob.kappa, prob.n_coarse)
             Kf, Mf = assemble(fine, ktri)
-        d = fine.dof
+        # P[m]: level m -> level m+1 nodal interpolation on dofs
+        self._galerkin(Kf, Mf, [interpolation(self.meshes[m], self.meshes[m + 1])
+                                for m in range(L)])
+
+    def _galerkin(self, Kf, Mf, P):
+        """Finest operators on the dofs, coarser ones as P^T A P (nested spaces)."""
+        prob, L = self.prob, self.L
+        d = self.meshes[L].dof
         self.K = [None] * (L + 1)
         self.M = [None] * (L + 1)
         self.K[L] = Kf[d][:, d].tocsr()
         self.M[L] = Mf[d][:, d].tocsr()
-        # P[m]: level m -> level m+1 nodal interpolation on dofs
-        self.P = [interpolation(self.meshes[m], self.meshes[m + 1]) for m in range(L)]
+        self.P = P
         for m in range(L - 1, -1, -1):
             Pm = self.P[m]
             self.K[m] = (Pm.T @ self.K[m + 1] @ Pm).tocsr()
@@ -141,15 +161,19 @@ class Hierarchy:
     def n_dof(self, m: int) -> int:
         return self.meshes[m].dof.size
 
+    def per_coarse(self, m: int) -> int:
+        """Node-grid intervals per coarse cell at level m (2^m, twice that for P2)."""
+        return self.order << m
+
     def node_ij(self, m: int, nodes: np.ndarray):
-        n1 = self.meshes[m].n + 1
+        n1 = self.order * self.meshes[m].n + 1
         return nodes % n1, nodes // n1
 
     def tile_dofs(self, m: int, s: Subdomain) -> np.ndarray:
         """Positions (into the level-m dof list) of the dofs strictly inside Omega_j:
         V_0h(Omega_j) = functions of V_0h supported in Omega_j."""
         i, j = self.node_ij(m, self.meshes[m].dof)
-        r = 1 << m
+        r = self.per_coarse(m)
         x0, x1, y0, y1 = s.Omega
         inside = (i > x0 * r) & (i < x1 * r) & (j > y0 * r) & (j < y1 * r)
         return np.nonzero(inside)[0]
@@ -157,7 +181,7 @@ class Hierarchy:
     def pou(self, m: int) -> np.ndarray:
         """chi_j at the level-m dofs, shape (m_sub, n_dof)."""
         i, j = self.node_ij(m, self.meshes[m].dof)
-        r = float(1 << m)
+        r = float(self.per_coarse(m))
         return pou_weights(self.prob, self.subs, i / r, j / r)
 
     def to_grid(self, m: int, v: np.ndarray) -> np.ndarray:
@@ -266,7 +290,7 @@ def interface_gluing(hier: Hierarchy, m: int, rhs: np.ndarray, sols) -> np.ndarr
     each closed G_j, and on the remaining dofs S the Dirichlet problem
     K_SS e_S = rhs_S - K_SG e_G (sparse LU).  Returns e at the level-m dofs."""
     i, j = hier.node_ij(m, hier.meshes[m].dof)
-    r = 1 << m
+    r = hier.per_coarse(m)
     half = r // 2
     n = hier.n_dof(m)
     e = np.zeros_like(rhs)

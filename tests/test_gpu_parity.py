@@ -62,9 +62,10 @@ def check_vectors(hier, m, Ug_grid, Uo, lam, tol=1e-8):
             assert e < tol and d < tol, (i, e, d)
         else:
             A, B = Ug[:, i:j], Uo[:, i:j]
-            C = B.T @ (M @ A)
-            s = np.linalg.svd(C, compute_uv=False)
-            sin_max = np.sqrt(max(0.0, 1.0 - float(np.min(s)) ** 2))
+            # sine of the largest principal angle: the b-norm of the part of span A outside
+            # span B (1 - cos^2 would lose it to rounding near 1)
+            R = A - B @ (B.T @ (M @ A))
+            sin_max = float(np.sqrt(max(0.0, np.max(np.linalg.eigvalsh(R.T @ (M @ R))))))
             X = np.random.Generator(np.random.PCG64(7)).standard_normal((A.shape[0], 3))
             pa = A @ (A.T @ (M @ X))
             pb = B @ (B.T @ (M @ X))

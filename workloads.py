@@ -49,6 +49,7 @@ class Problem:
     kappa: Optional[np.ndarray] = field(default=None, repr=False)
     name: str = ""
     pou: int = 0               # gluing weights: 0 ramp across the overlap, 1 indicator of D_j
+    order: int = 1             # polynomial degree of the elements: 1 (P1) or 2 (P2)
 
     # --- geometry helpers (no method arithmetic) ---
     @property
@@ -220,6 +221,31 @@ def kappa_directions(kappa: np.ndarray, seed: int = 501) -> List[np.ndarray]:
     x = (np.arange(nx) + 0.5) / nx
     d3 = k * np.outer(np.sin(np.pi * y), np.cos(2 * np.pi * x))
     return [d1, d2, d3]
+
+
+# ---------------------------------------------------------------------------
+# P2 elements (Example 6.1 runs P1 and P2)
+# ---------------------------------------------------------------------------
+
+def config1_p2() -> Problem:
+    """P2 on the unit square, H=1/8 -> h=1/32 (63^2 = 3,969 fine dofs), 4x4 subdomains,
+    overlap 1, q=1, kappa=1."""
+    return Problem(DOMAIN_SQUARE, 8, 2, 4, 4, 1, 1, 0, None, "c1p2_square_H8_h32_4x4_q1",
+                   order=2)
+
+
+def config2_p2() -> Problem:
+    """P2 on the unit square, H=1/16 -> h=1/256: 511^2 = 261,121 fine dofs, the size of
+    configuration 2; 8x8 subdomains, overlap 1, q=3 (lambda ~ 2 pi^2, 5 pi^2, 5 pi^2)."""
+    return Problem(DOMAIN_SQUARE, 16, 4, 8, 8, 1, 3, 0, None, "c2p2_square_H16_h256_8x8_q3",
+                   order=2)
+
+
+def small_ragged_p2(seed: int = 13) -> Problem:
+    """P2 on the L-shape with uneven subdomain splits and a per-coarse-cell kappa, q=2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return Problem(DOMAIN_LSHAPE, 10, 2, 3, 3, 1, 2, 1, loguniform_coarse_kappa(10, rng),
+                   "ragged_p2_L_nc10_L2_3x3_q2", order=2)
 
 
 def small_ragged(seed: int = 11) -> Problem:
