@@ -132,7 +132,8 @@ def source_sha(kernel: str) -> str:
     import hashlib
     c = os.path.join(ROOT, "paper_1401_4969_amd", "csrc")
     files = {"k_local_pcg64": ["kernels_pcg.hip", "pcg_ops.h", "mlc_device.h"],
-             "k_local_mixed": ["kernels_mixed.hip", "pcg_ops.h", "mlc_device.h"]}[kernel]
+             "k_local_mixed": ["kernels_mixed.hip", "pcg_ops.h", "mlc_device.h"],
+             "k_local_p2": ["kernels_p2.hip", "p2_ops.h", "pcg_ops.h", "mlc_device.h"]}[kernel]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(c, f)) as fh:
@@ -172,7 +173,9 @@ def subdomain_shapes(prob):
 
 
 def interior_nodes(prob, level: int) -> int:
-    n = prob.n_coarse << level
+    """Interior nodes of the level's node grid (mesh nodes for P1; vertices and edge
+    midpoints, the grid of half cells, for P2)."""
+    n = prob.n_coarse << (level + getattr(prob, "order", 1) - 1)
     if prob.domain != 1:
         return (n - 1) ** 2
     h = n // 2
@@ -310,6 +313,8 @@ def workload(name: str):
         return W.example62(n_refine=5, sub=5, n_eig=6), dict(precision=0)
     if name == "ex62mixed":
         return W.example62(n_refine=5, sub=5, n_eig=6), dict(precision=1)
+    if name == "c2p2":
+        return W.config2_p2(), dict(precision=0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -478,7 +483,8 @@ def roofline(prob, opts, st, pcg_ms, lds_limit):
     """The local-solve kernel against the HBM peak: algorithmic bytes of one launch by the
     reference count (18 passes per tile unknown and iteration) over its event-timed
     duration, and the same under the kernel's own fused schedule."""
-    m = prob.n_refine
+    order = getattr(prob, "order", 1)
+    m = prob.n_refine + order - 1   # level of the node grid (P2: the half-cell grid)
     shapes = subdomain_shapes(prob)
     cw, ch = max(shapes, key=lambda x: x[0] * x[1])
     S0 = tile_levels(cw, ch, m)[0]
@@ -489,7 +495,7 @@ def roofline(prob, opts, st, pcg_ms, lds_limit):
     # the tensor kind streams its three stiffness planes (FP64, or FP32 in inner solves)
     coef = (24 if opts.precision == 0 else 12) if prob.coef_kind == 3 else 0
     if opts.precision == 0:
-        kernel = "k_local_pcg64"
+        kernel = "k_local_pcg64" if order == 1 else "k_local_p2"
         sched_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode, coef=coef) / S0
         sched = sched_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
         surv_it = survey_bytes_per_iteration(8, prob.coef_kind)
@@ -534,14 +540,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3",
                     choices=["c3", "c2", "c3mixed", "c4", "c5adj", "c2iface", "c3iface",
-                             "ex62", "ex62mixed"],
+                             "ex62", "ex62mixed", "c2p2"],
                     help="c3 (default): unit square, h = 1/2048, 16x16 subdomains, q = 1, FP64, "
                          "with the same in FP32 + FP64 refinement beside it; c2: h = 1/512, "
                          "8x8 subdomains, q = 3; c3mixed: c3 in FP32 + FP64 refinement only; "
                          "c4: 256 problems batched; c5adj: reverse sweep at h = 1/1024; "
                          "c2iface, c3iface: c2 / c3 with the paper's own gluing (interface "
                          "problem); ex62, ex62mixed: the operator of Example 6.2 (tensor A, "
-                         "weight phi) on (-1,1)^2, H = 0.1, h = 1/320, 5x5 subdomains, q = 6")
+                         "weight phi) on (-1,1)^2, H = 0.1, h = 1/320, 5x5 subdomains, q = 6; "
+                         "c2p2: P2 elements at h = 1/256 (the 261,121 dofs of c2), 8x8, q = 3")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
@@ -599,6 +606,7 @@ def main():
         "dtype": "f64" if opts.precision == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": prob.name, "level": prob.n_refine, "h": prob.h(prob.n_refine),
+                   "elements": f"P{getattr(prob, 'order', 1)}",
                    "fine_dofs": n_dofs, "n_eig": prob.n_eig,
                    "subdomains": f"{prob.sub_x}x{prob.sub_y}", "overlap": prob.overlap,
                    "precision": "fp64" if opts.precision == 0 else "mixed",

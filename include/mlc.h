@@ -6,9 +6,9 @@
  * Section 2.2, A = kappa I): find (lambda, u) with -div(kappa grad u) = lambda u in Omega,
  * u = 0 on the boundary, b(u, u) = 1 -- or, with MLC_COEF_TENSOR, the operator of
  * Example 6.2: -div(A grad u) = lambda phi u, A a full symmetric tensor and phi > 0 a
- * weight, b(u, v) = (phi u, v) -- discretised by conforming P1 elements on nested
- * uniform right-triangle meshes (each square cell cut by its lower-left to upper-right
- * diagonal; regular refinement, beta = 2, Section 6).
+ * weight, b(u, v) = (phi u, v) -- discretised by conforming P1 or P2 elements (Section
+ * 2.1) on nested uniform right-triangle meshes (each square cell cut by its lower-left to
+ * upper-right diagonal; regular refinement, beta = 2, Section 6).
  *
  * Method (Algorithm 4.2 driving Algorithm 4.1):
  *   mlc_coarse_setup    -- Algorithm 4.2 step 1: the eigenproblem on the coarse space
@@ -31,7 +31,8 @@
  *     stream-ordered; only calls that return host data synchronise that stream.
  *   - Grid vectors are full node grids of the bounding box, row-major: the value at node
  *     (i, j) (x = x0 + i h, y = y0 + j h) is at index j*(N+1)+i, N = n_coarse*2^level
- *     cells per side; boundary and removed-quadrant nodes hold 0.  q eigenvectors are
+ *     cells per side (P1); with P2 elements the grid has 2N intervals of h/2 (vertices and
+ *     edge midpoints); boundary and removed-quadrant nodes hold 0.  q eigenvectors are
  *     stored one after another.
  *   - A context is not thread-safe; distinct contexts are independent.
  */
@@ -102,6 +103,10 @@ typedef struct mlc_problem_desc {
                           layout of MLC_COEF_TENSOR); read during mlc_create only (copied);
                           NULL for MLC_COEF_ONE.  Must be > 0 and finite. */
   int32_t pou;         /* MLC_POU_* (0 unless set) */
+  int32_t order;       /* element degree: 1 (P1, also 0) or 2 (P2: values at the vertices and
+                          edge midpoints, i.e. the nodes of the grid with twice the cells'
+                          intervals; coef_kind 0 or 1, pou 0 or 1, FP64, no tape).  Grid
+                          vectors of level l then have n_coarse*2^(l+1)+1 nodes per side. */
 } mlc_problem_desc;
 
 /* Solver options; mlc_default_opts fills the defaults shown. */
@@ -156,11 +161,13 @@ mlc_status mlc_workspace_size(const mlc_problem_desc* desc, const mlc_solver_opt
  *   otherwise); an Omega_j narrower than 2 coarse cells either way; more than 8 blocks
  *   D_j whose Omega_j reach one node along an axis (overlap too wide for the blocks);
  *   a subdomain whose coarse interior exceeds 1024 nodes; n_eig outside 1..8 or above the
- *   number of coarse interior nodes n_H; n_H (1 + 3 n_eig) above 8192 (the device
- *   Rayleigh-Ritz solve); kappa NULL when the kind needs it, or a value not > 0 and
+ *   number of coarse interior nodes n_H; n_H (1 + 4 n_eig) + n_eig^2 above 18432 (the
+ *   LDS of the device Rayleigh-Ritz solve, 144 KiB); kappa NULL when the kind needs it, or a value not > 0 and
  *   finite (kind 3: A not positive definite or phi not > 0 on some triangle);
  *   MLC_POU_INTERFACE with a tape or in a batch of more than one problem; record_tape
- *   with n_eig != 1 or coef_kind other than 1 and 2;
+ *   with n_eig != 1 or coef_kind other than 1 and 2; order other than 0, 1 and 2; order 2
+ *   with coef_kind 2 or 3, MLC_POU_INTERFACE, mixed precision or a tape, or a finest node
+ *   grid above 32768 intervals per side; problems of one batch with different order;
  *   options: NULL; precision not 0 or 1; rtol outside (0, 1); max_it < 1; nu outside
  *   1..8; omega outside (0, 1); mixed precision with max_refine < 1 or inner_rtol outside
  *   (0, 1); block not 0, 256, 512 or 1024;

@@ -37,7 +37,7 @@ class ProblemDesc(C.Structure):
     _fields_ = [("domain", C.c_int32), ("n_coarse", C.c_int32), ("n_refine", C.c_int32),
                 ("sub_x", C.c_int32), ("sub_y", C.c_int32), ("overlap", C.c_int32),
                 ("n_eig", C.c_int32), ("coef_kind", C.c_int32),
-                ("kappa", C.POINTER(C.c_double)), ("pou", C.c_int32)]
+                ("kappa", C.POINTER(C.c_double)), ("pou", C.c_int32), ("order", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
@@ -143,7 +143,7 @@ def make_desc(prob) -> Tuple[ProblemDesc, Optional[np.ndarray]]:
     kap = None
     d = ProblemDesc(int(prob.domain), int(prob.n_coarse), int(prob.n_refine), int(prob.sub_x),
                     int(prob.sub_y), int(prob.overlap), int(prob.n_eig), int(prob.coef_kind),
-                    None, int(getattr(prob, "pou", 0)))
+                    None, int(getattr(prob, "pou", 0)), int(getattr(prob, "order", 1)))
     if prob.coef_kind != 0:
         kap = np.ascontiguousarray(prob.kappa, dtype=np.float64)
         d.kappa = kap.ctypes.data_as(C.POINTER(C.c_double))
@@ -216,8 +216,9 @@ class Solver:
         return int(v.value)
 
     def grid_n(self, level: Optional[int] = None) -> int:
+        """Nodes per side of the level's grid vectors (twice the cells' intervals for P2)."""
         lv = self.level if level is None else level
-        return (self.prob.n_coarse << lv) + 1
+        return (self.prob.n_coarse << (lv + int(getattr(self.prob, "order", 1)) - 1)) + 1
 
     def eigenpairs(self, with_vectors: bool = True):
         """(lambda numpy[q], u torch[q, n1, n1] float64 on the device or None)."""
@@ -304,6 +305,7 @@ def _problem_with_kappa(prob, kappa: np.ndarray):
     f = {k: getattr(prob, k) for k in ("domain", "n_coarse", "n_refine", "sub_x", "sub_y",
                                        "overlap", "n_eig", "coef_kind")}
     f["pou"] = getattr(prob, "pou", 0)
+    f["order"] = getattr(prob, "order", 1)
     return SimpleNamespace(kappa=kappa, **f)
 
 
@@ -454,7 +456,7 @@ class BatchSolver:
         if with_vectors:
             p = self.probs[i]
             lvl = min(self.current_step, p.n_refine)
-            n1 = (p.n_coarse << lvl) + 1
+            n1 = (p.n_coarse << (lvl + int(getattr(p, "order", 1)) - 1)) + 1
             u = torch.empty((self.q, n1, n1), dtype=torch.float64, device=self.device)
             uptr = C.c_void_p(u.data_ptr())
         self._check(self.lib.mlc_batch_get(self.b, int(i), lam.ctypes.data_as(C.POINTER(C.c_double)),

@@ -105,8 +105,9 @@ template <int QM>
 __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const TileItem* items,
                                                    const int32_t* sub_item, const char* store,
                                                    int m) {
+  // m: level of the node grid (the mesh level for P1, one more for P2)
   const ProbDev& P = probs[blockIdx.y];
-  if (m > P.L) return;
+  if (m > P.Lg) return;
   const int N = P.n_c << m;
   const int n1 = N + 1;
   const int64_t nn = (int64_t)n1 * n1;
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
   const int lane = threadIdx.x & 63;
   if (c >= P.nH) return;
   const int nH = P.nH, q = P.q;
-  const int nc1 = P.n_c + 1;
+  const int nc1 = P.c1;
   const double* a = P.rchain + P.rchain_off[0];
   const double* col = P.V + (int64_t)c * nH;
   const int v = blockIdx.z;  // border vector (one grid slice each)
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
 // per coarse node and eigenpair sweeping a row of V^T.
 __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
   const ProbDev& P = probs[blockIdx.y];
-  const int nc1 = P.n_c + 1;
+  const int nc1 = P.c1;
   const int node = blockIdx.x * (NTG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (node >= nc1 * nc1) return;
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(NTG) void k_coarse_matrices(const ProbDev* probs) {
 
 __global__ __launch_bounds__(NTG) void k_init_u0(const ProbDev* probs, int dst) {
   const ProbDev& P = probs[blockIdx.y];
-  const int nc1 = P.n_c + 1;
+  const int nc1 = P.c1;
   const int idx = blockIdx.x * NTG + threadIdx.x;
   if (idx >= nc1 * nc1) return;
   const int r = P.coarse_index[idx];
@@ -769,7 +770,7 @@ __global__ __launch_bounds__(NTG) void k_copy_signed(const double* u, int64_t nn
 __global__ __launch_bounds__(NTG) void k_set_state(const ProbDev* probs, int level, int dst,
                                                    const double* in) {
   const ProbDev& P = probs[0];
-  const int N = P.n_c << level;
+  const int N = P.n_c << (level + P.order - 1);
   const int n1 = N + 1;
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   // 1. finish the fine-grid reductions (alpha, beta) in a fixed order; stage the
   //    coarse quantities in LDS
   {
-    const int N = P.n_c << m;
+    const int N = P.n_c << (m + P.order - 1);  // grid of the level's element nodes
     const int64_t nn = (int64_t)(N + 1) * (N + 1);
     const int nblk = (int)((nn + 255) / 256);
     const int nvp = 2 * Q * Q + Q;

@@ -21,6 +21,11 @@
 // Per-problem device record.  Pointers are into the caller's workspace.
 struct ProbDev {
   int32_t domain, n_c, L, q, coef_kind, sub_x, sub_y, overlap;
+  // element degree (1 or 2).  A level-l grid vector holds the element's nodes: the mesh
+  // nodes for P1, the vertices and edge midpoints for P2, i.e. the nodes of the grid with
+  // n_c 2^(l + order - 1) intervals per side.  Lg = L + order - 1 is that grid's level at
+  // the finest mesh; c1 = n_c * order + 1 nodes per side on the coarse mesh.
+  int32_t order, Lg, c1;
   int32_t nH;                 // coarse interior nodes (dofs of V_0H)
   int32_t nparts;             // blocks of the fine-level reductions at the finest level
   double side;                // bounding-box side length

@@ -23,6 +23,20 @@
 
 int64_t item_bytes_fp64(int cw, int ch, int m);
 int64_t item_bytes_mixed(int cw, int ch, int m);
+hipError_t launch_p2_prolong_residual(int kind, const ProbDev* probs, int nprob, int m, int src,
+                                      int64_t max_nodes, int max_q, hipStream_t s);
+hipError_t launch_p2_rr_apply(int kind, const ProbDev* probs, int nprob, int m, int64_t max_nodes,
+                              int max_q, hipStream_t s);
+hipError_t launch_p2_restrict(const ProbDev* probs, int nprob, int l, int m, int64_t max_nodes_l,
+                              int max_q, hipStream_t s);
+hipError_t launch_p2_assemble(const ProbDev* probs, int nprob, int m, int dst, int64_t max_nodes,
+                              int max_q, hipStream_t s);
+hipError_t launch_p2_coarse_matrices(int kind, const ProbDev* probs, int nprob, int max_nH,
+                                     hipStream_t s);
+hipError_t launch_local_p2(int kind, int nt, const ProbDev* probs, const TileItem* items,
+                           int nitems, char* store, const double* inv, int m, ItemStat* stats,
+                           double rtol, int max_it, int nu, double omega, int max_tile_nx,
+                           hipStream_t s);
 
 namespace {
 
@@ -39,14 +53,17 @@ struct SubBox {
 // Geometry derived from one problem description (host tables only).
 struct Geometry {
   int L = 0, q = 0, nc = 0, nH = 0, kind = 0, domain = 0, sub_x = 1, sub_y = 1, overlap = 1, pou = 0;
+  int order = 1;  // element degree: level-l vectors live on the grid of nc 2^(l+order-1) intervals
   double side = 1.0;
   std::vector<int> bx, by;
   std::vector<SubBox> subs;     // kept subdomains, largest first
   std::vector<int> coarse_nodes, coarse_index;
   std::vector<int64_t> inv_off; // per kept subdomain (doubles, relative to the problem)
   int64_t inv_total = 0;
-  int64_t N(int l) const { return (int64_t)nc << l; }
+  int64_t cells(int l) const { return (int64_t)nc << l; }  // mesh cells per side
+  int64_t N(int l) const { return (int64_t)nc << (l + order - 1); }  // node-grid intervals
   int64_t nodes(int l) const { return (N(l) + 1) * (N(l) + 1); }
+  int per_coarse(int l) const { return order << l; }  // node-grid intervals per coarse cell
 };
 
 bool is_dof_host(int domain, int N, int gx, int gy) {
@@ -92,6 +109,17 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
     return MLC_EINVAL;
   }
   if (d->n_eig < 1 || d->n_eig > MLC_MAX_Q) { msg = "n_eig must be in 1..8"; return MLC_EINVAL; }
+  const int order = d->order == 0 ? 1 : d->order;
+  if (order != 1 && order != 2) { msg = "order must be 0, 1 or 2"; return MLC_EINVAL; }
+  if (order == 2 && (d->coef_kind > 1 || d->pou == MLC_POU_INTERFACE)) {
+    msg = "P2 elements need coef_kind 0 or 1 and a partition-of-unity gluing";
+    return MLC_EINVAL;
+  }
+  if ((int64_t)d->n_coarse << (d->n_refine + order - 1) > 32768) {
+    msg = "finest node grid above 32768 intervals per side";
+    return MLC_EINVAL;
+  }
+  g.order = order;
   g.L = d->n_refine;
   g.q = d->n_eig;
   g.nc = d->n_coarse;
@@ -105,7 +133,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
   const int nc = g.nc;
   if (g.kind == 1 || g.kind == 2) {
     if (!d->kappa) { msg = "kappa is NULL"; return MLC_EINVAL; }
-    const int64_t n = g.kind == 1 ? (int64_t)nc * nc : g.N(g.L) * g.N(g.L);
+    const int64_t n = g.kind == 1 ? (int64_t)nc * nc : g.cells(g.L) * g.cells(g.L);
     for (int64_t i = 0; i < n; ++i) {
       const double k = d->kappa[i];
       if (!(k > 0.0) || !std::isfinite(k)) { msg = "kappa must be positive and finite"; return MLC_EINVAL; }
@@ -113,7 +141,7 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
   }
   if (g.kind == 3) {  // per finest triangle: A symmetric positive definite, phi > 0
     if (!d->kappa) { msg = "kappa is NULL"; return MLC_EINVAL; }
-    const int64_t n = 2 * g.N(g.L) * g.N(g.L);
+    const int64_t n = 2 * g.cells(g.L) * g.cells(g.L);
     const double* a11 = d->kappa;
     const double* a12 = d->kappa + n;
     const double* a22 = d->kappa + 2 * n;
@@ -125,16 +153,24 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
       if (!ok) { msg = "coef_kind 3 needs finite values, A positive definite and phi > 0 on every triangle"; return MLC_EINVAL; }
     }
   }
-  g.coarse_index.assign((size_t)(nc + 1) * (nc + 1), -1);
-  for (int j = 0; j <= nc; ++j)
-    for (int i = 0; i <= nc; ++i)
-      if (is_dof_host(g.domain, nc, i, j)) {
-        g.coarse_index[(size_t)j * (nc + 1) + i] = (int)g.coarse_nodes.size();
-        g.coarse_nodes.push_back(j * (nc + 1) + i);
+  // coarse dofs: the interior nodes of the level-0 node grid (the mesh nodes for P1, the
+  // vertices and edge midpoints for P2)
+  const int n0 = (int)g.N(0);
+  g.coarse_index.assign((size_t)(n0 + 1) * (n0 + 1), -1);
+  for (int j = 0; j <= n0; ++j)
+    for (int i = 0; i <= n0; ++i)
+      if (is_dof_host(g.domain, n0, i, j)) {
+        g.coarse_index[(size_t)j * (n0 + 1) + i] = (int)g.coarse_nodes.size();
+        g.coarse_nodes.push_back(j * (n0 + 1) + i);
       }
   g.nH = (int)g.coarse_nodes.size();
   if (g.q > g.nH) { msg = "n_eig exceeds the number of coarse interior nodes"; return MLC_EINVAL; }
-  if ((int64_t)g.nH * (1 + 3 * g.q) > 8192) { msg = "coarse space too large for the device Rayleigh-Ritz solve"; return MLC_EINVAL; }
+  // the device Rayleigh-Ritz solve keeps Lambda, Z, f, g and the q eigenvectors of the
+  // reduced problem in LDS: n_H (1 + 4 q) + q^2 doubles, at most 144 KiB of the 160 KiB
+  if ((int64_t)g.nH * (1 + 4 * g.q) + g.q * g.q > 18432) {
+    msg = "coarse space too large for the device Rayleigh-Ritz solve";
+    return MLC_EINVAL;
+  }
   // subdomains (Section 4): D_j blocks, Omega_j = D_j grown by `overlap` coarse cells
   for (int b = 0; b <= d->sub_x; ++b) g.bx.push_back((b * nc) / d->sub_x);
   for (int b = 0; b <= d->sub_y; ++b) g.by.push_back((b * nc) / d->sub_y);
@@ -225,7 +261,7 @@ struct Plan {
   std::vector<Geometry> geo;
   std::vector<ProbLayout> pl;
   std::vector<StepTables> steps;  // index s (1..Lmax); steps[0] unused
-  int n = 0, q = 0, kind = 0, Lmax = 0, max_nH = 0, max_nc1sq = 0, precision = 0;
+  int n = 0, q = 0, kind = 0, order = 1, Lmax = 0, max_nH = 0, max_nc1sq = 0, precision = 0;
   size_t probdev = 0, stats = 0, conv = 0, inv = 0, store = 0, store_bytes = 0, total = 0;
   int64_t max_items = 0, inv_total = 0;
 };
@@ -247,15 +283,23 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
   }
   P.q = P.geo[0].q;
   P.kind = P.geo[0].kind;
+  P.order = P.geo[0].order;
   for (const Geometry& g : P.geo) {
-    if (g.q != P.q || g.kind != P.kind) { msg = "all problems of a batch need the same n_eig and coef_kind"; return MLC_EINVAL; }
+    if (g.q != P.q || g.kind != P.kind || g.order != P.order) {
+      msg = "all problems of a batch need the same n_eig, coef_kind and order";
+      return MLC_EINVAL;
+    }
+    if (g.order == 2 && (o->precision != 0 || o->record_tape)) {
+      msg = "P2 elements run in FP64 without a tape";
+      return MLC_EINVAL;
+    }
     if (g.pou == MLC_POU_INTERFACE && (n != 1 || o->record_tape)) {
       msg = "the interface gluing runs on single-problem contexts without a tape";
       return MLC_EINVAL;
     }
     P.Lmax = std::max(P.Lmax, g.L);
     P.max_nH = std::max(P.max_nH, g.nH);
-    P.max_nc1sq = std::max(P.max_nc1sq, (g.nc + 1) * (g.nc + 1));
+    P.max_nc1sq = std::max(P.max_nc1sq, (int)g.nodes(0));
   }
   size_t p = 0;
   auto take = [&](size_t bytes) {
@@ -271,7 +315,7 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     const Geometry& g = P.geo[i];
     ProbLayout& L = P.pl[i];
     const size_t nnL = (size_t)g.nodes(g.L);
-    const size_t ncs = (size_t)(g.nc + 1) * (g.nc + 1);
+    const size_t ncs = (size_t)g.nodes(0);
     L.bx = take(g.bx.size() * 4);
     L.by = take(g.by.size() * 4);
     L.coarse_nodes = take((size_t)g.nH * 4);
@@ -281,12 +325,12 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.coef3 = 0;
     if (g.kind == 2)
       for (int l = 0; l <= g.L; ++l) {
-        const size_t c = (size_t)(g.N(l) * g.N(l)) * 8;
+        const size_t c = (size_t)(g.cells(l) * g.cells(l)) * 8;
         L.kLR[l] = take(c);
         L.kUL[l] = (l == g.L) ? L.kLR[l] : take(c);
       }
     if (g.kind == 3) {
-      L.coef3 = take((size_t)(8 * g.N(g.L) * g.N(g.L)) * 8);
+      L.coef3 = take((size_t)(8 * g.cells(g.L) * g.cells(g.L)) * 8);
       for (int l = 0; l <= g.L; ++l) {
         L.st7[l] = take((size_t)(7 * g.nodes(l)) * 8);
         L.st7f[l] = take((size_t)(3 * g.nodes(l)) * 4);
@@ -368,9 +412,11 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     for (size_t k = 0; k < all.size(); ++k) {
       TileItem& it = all[k];
       it.off = (int64_t)o;
-      T.max_tile_nx = std::max(T.max_tile_nx, it.cw * (1 << s) - 1);
-      const int64_t b = fp64_items ? item_bytes_fp64(it.cw, it.ch, s)
-                                   : item_bytes_mixed(it.cw, it.ch, s);
+      // tiles hold the nodes of the level's node grid strictly inside Omega_j
+      const int sg = s + P.order - 1;
+      T.max_tile_nx = std::max(T.max_tile_nx, it.cw * (1 << sg) - 1);
+      const int64_t b = fp64_items ? item_bytes_fp64(it.cw, it.ch, sg)
+                                   : item_bytes_mixed(it.cw, it.ch, sg);
       o = align_up(o + (size_t)b);
       it.rhs_stride = (int32_t)(align_up((size_t)b));
       T.sub_item[(size_t)P.pl[it.prob].sub_item_off + (size_t)it.sub * P.q + it.rhs] = (int32_t)k;
@@ -418,8 +464,8 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
       T.trr[m] = take((size_t)(3 * g.nH + 4) * 8);
     }
     for (int l = 0; l <= g.L; ++l) {
-      T.klo[l] = take((size_t)(g.N(l) * g.N(l)) * 8);
-      T.kup[l] = take((size_t)(g.N(l) * g.N(l)) * 8);
+      T.klo[l] = take((size_t)(g.cells(l) * g.cells(l)) * 8);
+      T.kup[l] = take((size_t)(g.cells(l) * g.cells(l)) * 8);
     }
     const size_t nnL = (size_t)g.nodes(g.L);
     T.adj_u = take(nnL * 8);
@@ -543,9 +589,10 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     const ProbLayout& L = P.pl[i];
     if (g.kind == 1) b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)g.nc * g.nc);
     if (g.kind == 0) b->kappa[i].assign((size_t)g.nc * g.nc, 1.0);
-    if (g.kind == 2) b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(g.N(g.L) * g.N(g.L)));
+    if (g.kind == 2)
+      b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(g.cells(g.L) * g.cells(g.L)));
     if (g.kind == 3)
-      b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(8 * g.N(g.L) * g.N(g.L)));
+      b->kappa[i].assign(descs[i].kappa, descs[i].kappa + (size_t)(8 * g.cells(g.L) * g.cells(g.L)));
     ProbDev& D = b->hp[i];
     std::memset(&D, 0, sizeof(D));
     D.domain = g.domain;
@@ -557,6 +604,9 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     D.sub_y = g.sub_y;
     D.overlap = g.overlap;
     D.pou = g.pou;
+    D.order = g.order;
+    D.Lg = g.L + g.order - 1;
+    D.c1 = (int)g.N(0) + 1;
     D.nH = g.nH;
     D.side = g.side;
     D.kH = (const double*)(w + L.kH);
@@ -663,7 +713,10 @@ mlc_status batch_setup(mlc_batch* b) {
     MLC_HIP(b, hipMemsetAsync(w + L.Kc, 0, nH * nH * 8, st));
     MLC_HIP(b, hipMemsetAsync(w + L.Mc, 0, nH * nH * 8, st));
   }
-  MLC_HIP(b, launch_coarse_matrices(P.kind, b->dprob, P.n, P.max_nH, st));
+  if (P.order == 2)
+    MLC_HIP(b, launch_p2_coarse_matrices(P.kind, b->dprob, P.n, P.max_nH, st));
+  else
+    MLC_HIP(b, launch_coarse_matrices(P.kind, b->dprob, P.n, P.max_nH, st));
   if (!b->rb && rocblas_create_handle(&b->rb) != rocblas_status_success) {
     b->err = "rocblas_create_handle failed";
     return MLC_EHIP;
@@ -726,9 +779,17 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
     }
     MLC_HIP(b, hipEventRecord(ev[0], st));
   }
-  MLC_HIP(b, launch_prolong_residual(P.kind, b->dprob, P.n, s, src, T.max_nodes, P.q, st));
+  const bool p2 = P.order == 2;
+  if (p2)
+    MLC_HIP(b, launch_p2_prolong_residual(P.kind, b->dprob, P.n, s, src, T.max_nodes, P.q, st));
+  else
+    MLC_HIP(b, launch_prolong_residual(P.kind, b->dprob, P.n, s, src, T.max_nodes, P.q, st));
   if (timing) MLC_HIP(b, hipEventRecord(ev[1], st));
-  if (P.precision == 0) {
+  if (p2) {
+    MLC_HIP(b, launch_local_p2(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
+                               (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
+                               b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, T.max_tile_nx, st));
+  } else if (P.precision == 0) {
     MLC_HIP(b, launch_local_pcg(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                 (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
                                 b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 0, T.max_tile_nx,
@@ -748,15 +809,26 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
                                     &b->glue_it, &b->glue_relres));
     b->glue_relres_step[s] = b->glue_relres;
   } else {
-    MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s, T.max_nodes, P.q, st));
+    // the gluing works on the node grid (level s + order - 1 of the P1 grids)
+    MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s + P.order - 1,
+                               T.max_nodes, P.q, st));
   }
-  MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, P.q, st));
-  for (int l = s - 1; l >= 0; --l)
-    MLC_HIP(b, launch_restrict(b->dprob, P.n, l, s, T.nodes_l[l], P.q, st));
+  if (p2) {
+    MLC_HIP(b, launch_p2_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, P.q, st));
+    for (int l = s - 1; l >= 0; --l)
+      MLC_HIP(b, launch_p2_restrict(b->dprob, P.n, l, s, T.nodes_l[l], P.q, st));
+  } else {
+    MLC_HIP(b, launch_rr_apply(P.kind, b->dprob, P.n, s, T.max_nodes, P.q, st));
+    for (int l = s - 1; l >= 0; --l)
+      MLC_HIP(b, launch_restrict(b->dprob, P.n, l, s, T.nodes_l[l], P.q, st));
+  }
   MLC_HIP(b, launch_rr_project(b->dprob, P.n, P.max_nH, P.q, st));
   MLC_HIP(b, launch_rr_solve(P.q, b->dprob, P.n, s, P.max_nH, dst, st));
   MLC_HIP(b, launch_rr_combine(b->dprob, P.n, P.max_nc1sq, P.q, st));
-  MLC_HIP(b, launch_assemble(b->dprob, P.n, s, dst, T.max_nodes, P.q, st));
+  if (p2)
+    MLC_HIP(b, launch_p2_assemble(b->dprob, P.n, s, dst, T.max_nodes, P.q, st));
+  else
+    MLC_HIP(b, launch_assemble(b->dprob, P.n, s, dst, T.max_nodes, P.q, st));
   if (P.tape.on) {  // keep this level's forward state for the reverse sweep
     const TapeLayout& TL = P.tape;
     const ProbDev& D = b->hp[0];
@@ -857,7 +929,8 @@ mlc_status step_stats(mlc_batch* b, mlc_level_stats* stt) {
   }
   for (size_t k = 0; k < T.items.size(); ++k) {
     const TileItem& it = T.items[k];
-    const int64_t S = (int64_t)(it.cw * (1 << s) - 1) * (it.ch * (1 << s) - 1);
+    const int r = P.order << s;
+    const int64_t S = (int64_t)(it.cw * r - 1) * (it.ch * r - 1);
     stt->n_tile_dofs += S;
     stt->it_max = std::max(stt->it_max, is[k].iters);
     stt->refine_max = std::max(stt->refine_max, is[k].refine);

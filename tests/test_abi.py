@@ -176,7 +176,7 @@ def test_plans_keep_tile_items_of_a_subdomain_adjacent():
     dict(n_coarse=512, n_refine=7, sub_x=32, sub_y=32),    # finest grid of 65536 cells per side
     dict(overlap=9),                                       # overlap above n_coarse = 8
     dict(n_coarse=32, n_refine=1, sub_x=32, sub_y=32, overlap=5),  # 11 blocks reach a node
-    dict(n_coarse=64, n_refine=1, sub_x=16, sub_y=16, n_eig=1),    # n_H (1 + 3q) = 15876
+    dict(n_coarse=64, n_refine=1, sub_x=16, sub_y=16, n_eig=1),    # n_H (1 + 4q) + q^2 = 19846
 ])
 def test_every_header_rejection_of_the_descriptor(bad):
     """Each descriptor rejection that include/mlc.h lists for mlc_create, beyond the
@@ -221,3 +221,31 @@ def test_backward_argument_checks():
     lb = C.c_double(1.0)
     assert lib.mlc_backward(None, C.byref(lb), C.c_void_p(0x1000)) == B.MLC_EINVAL
     assert lib.mlc_hf_gradient(None, C.c_void_p(0x1000)) == B.MLC_EINVAL
+
+
+def test_p2_limits():
+    """P2 elements: coefficient kinds 0 and 1, partition-of-unity gluings, FP64, no tape;
+    a batch shares one order; the node grid (twice the cells' intervals) sizes the work."""
+    p = W.config1_p2()
+    assert B.workspace_size(p) > B.workspace_size(W.config1())
+    for bad in (dict(coef_kind=2, kappa=np.ones((32, 32))), dict(pou=2), dict(order=3)):
+        with pytest.raises(B.MLCError) as e:
+            B.workspace_size(p.with_(**bad))
+        assert e.value.status == B.MLC_EINVAL
+    for kw in (dict(precision=1), dict(record_tape=1)):
+        with pytest.raises(B.MLCError) as e:
+            B.workspace_size(p.with_(coef_kind=1, kappa=np.ones((8, 8))), B.default_opts(**kw))
+        assert e.value.status == B.MLC_EINVAL
+    with pytest.raises(B.MLCError) as e:
+        B.batch_workspace_size([p, W.config1()])
+    assert e.value.status == B.MLC_EINVAL
+    assert B.batch_workspace_size([p.with_(coef_kind=1, kappa=np.ones((8, 8))),
+                                   W.small_ragged_p2().with_(n_eig=1)]) > 0
+
+
+def test_rayleigh_ritz_lds_limit():
+    """n_H (1 + 4q) + q^2 <= 18432 doubles: the P2 space of H = 1/16 (n_H = 961) with q = 3
+    fits; q = 4 on n_H = 3969 does not."""
+    assert B.workspace_size(W.config2_p2()) > 0
+    with pytest.raises(B.MLCError):
+        B.workspace_size(W.config2_p2().with_(n_coarse=32, sub_x=16, sub_y=16, n_eig=4))
