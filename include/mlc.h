@@ -289,9 +289,13 @@ mlc_status mlc_batch_get(mlc_batch* b, int32_t i, double* lambda_host, double* u
 mlc_status mlc_batch_step_stats(mlc_batch* b, mlc_level_stats* st);
 
 /* Autotuner: for every step, time the local-solve launch with 256, 512 and 1024 threads
- * per workgroup (HIP events, full runs from level 0) and keep the fastest; blocks_out
- * (may be NULL) receives the choice per step (index s-1, n entries).  Leaves the batch at
- * step 0.  Synchronises. */
+ * per workgroup (HIP events, three full runs from level 0 each, the median per step) and
+ * keep the fastest; blocks_out (may be NULL) receives the choice per step (index s-1, n
+ * entries).  The choice is cached in a text file (MLC_AUTOTUNE_CACHE, else
+ * $HOME/.cache/mlc_autotune.txt; one line per key) under a key of the device architecture
+ * and a hash of what decides the launches (element order, coefficient kind, precision, q,
+ * nu, every item's subdomain shape); a later call with the same key, in any process, takes
+ * the cached choice without timing.  Leaves the batch at step 0.  Synchronises. */
 mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n);
 
 /* Use these workgroup sizes per step (index s-1; 256, 512 or 1024), e.g. a cached

@@ -16,7 +16,8 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 SOURCES = ["mlc_host.hip", "kernels_grid.hip", "kernels_pcg.hip", "kernels_mixed.hip",
-           "kernels_rr.hip", "kernels_adj.hip", "kernels_glue.hip", "kernels_p2.hip"]
+           "kernels_rr.hip", "kernels_adj.hip", "kernels_glue.hip", "kernels_p2.hip",
+           "kernels_eig.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

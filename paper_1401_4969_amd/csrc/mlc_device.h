@@ -17,6 +17,7 @@
 #define MLC_MAX_TILE_COARSE 64      // coarse tile grids up to this size are inverted in LDS
 #define MLC_MAX_TILE_COARSE_ALL 1024  // larger ones (up to this) in HBM
 #define MLC_MAX_CAND 8
+#define MLC_JACOBI_MAX_NH 400       // coarse spaces up to this size are decomposed on the device
 
 // Per-problem device record.  Pointers are into the caller's workspace.
 struct ProbDev {
@@ -69,6 +70,10 @@ struct ProbDev {
   // order as their bit patterns, so the solves raise it with an integer atomic maximum);
   // cleared by the step's first kernel
   double* conv;
+  // setup: scratch of the device eigensolver (n_H^2 + 2 (n_H + 1)^2 doubles), NULL when the
+  // coarse space goes to rocSOLVER; its status (0 = success)
+  double* eig_ws;
+  int32_t* info;
 };
 
 // One local solve: subdomain Omega_j of problem prob, right-hand side rhs.

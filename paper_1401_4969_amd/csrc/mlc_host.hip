@@ -11,6 +11,10 @@
 
 #include <algorithm>
 #include <array>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+#include <sys/stat.h>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -229,6 +233,7 @@ struct ProbLayout {
   size_t st7[MLC_MAX_LEVELS + 1], st7f[MLC_MAX_LEVELS + 1], coef3;  // coef kind 3: stencil
                                                                      // planes, input
   int64_t rchain_off[MLC_MAX_LEVELS + 1];
+  int64_t eig_off = -1;  // bytes into the local-solve store: device eigensolver scratch (setup)
   int64_t inv_base;      // doubles, into the batch inverse region
   int32_t sub_item_off;  // into every step's subdomain -> item table
 };
@@ -362,8 +367,8 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.cH = take(q * ncs * 8);
     L.out_parts = take(4 * 64 * q * 8);  // output sign partials (4 per block)
     L.skel = L.skel_parts = L.skel_scal = 0;
-    if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem on the finest grid
-      L.skel = take(6 * q * nnL * 8);  // six vectors per right-hand side
+    if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem and its V-cycle
+      L.skel = take((size_t)skel_stride(g.nc, g.L) * q * 8);
       L.skel_parts = take(((nnL + 255) / 256) * 2 * q * 8);
       L.skel_scal = take(8 * q * 8);
     }
@@ -484,6 +489,16 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     T.ygrid = take((size_t)(g.nc + 1) * (g.nc + 1) * 8);
     T.v0grid = take((size_t)(g.nc + 1) * (g.nc + 1) * 8);
   }
+  // the device eigensolver of setup works in the local-solve store (unused until the
+  // first step): n_H^2 + 2 (n_H + 1)^2 doubles per problem it handles
+  size_t eig_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    const int nH = P.geo[i].nH;
+    if (nH > MLC_JACOBI_MAX_NH) continue;
+    P.pl[i].eig_off = (int64_t)eig_bytes;
+    eig_bytes = align_up(eig_bytes + ((size_t)nH * nH + 2 * (size_t)(nH + 1) * (nH + 1)) * 8);
+  }
+  store_bytes = std::max(store_bytes, eig_bytes);
   P.store_bytes = store_bytes;
   P.store = take(store_bytes);
   P.total = p;
@@ -643,6 +658,8 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
     D.cH_grid = (double*)(w + L.cH);
     D.sum_parts = (double*)(w + L.out_parts);
     D.conv = (double*)(w + P.conv);
+    D.eig_ws = L.eig_off >= 0 ? (double*)(w + P.store + L.eig_off) : nullptr;
+    D.info = (int32_t*)(w + L.info);
   }
   b->dprob = (ProbDev*)(w + P.probdev);
   hipStream_t st = b->st;
@@ -717,18 +734,23 @@ mlc_status batch_setup(mlc_batch* b) {
     MLC_HIP(b, launch_p2_coarse_matrices(P.kind, b->dprob, P.n, P.max_nH, st));
   else
     MLC_HIP(b, launch_coarse_matrices(P.kind, b->dprob, P.n, P.max_nH, st));
-  if (!b->rb && rocblas_create_handle(&b->rb) != rocblas_status_success) {
-    b->err = "rocblas_create_handle failed";
-    return MLC_EHIP;
-  }
-  if (rocblas_set_stream(b->rb, st) != rocblas_status_success) {
-    b->err = "rocblas_set_stream failed";
-    return MLC_EHIP;
-  }
-  // Algorithm 4.2 step 1 on V_0H: K_H V = M_H V Lambda, V^T M_H V = I (full spectrum)
+  // Algorithm 4.2 step 1 on V_0H: K_H V = M_H V Lambda, V^T M_H V = I (full spectrum):
+  // coarse spaces up to MLC_JACOBI_MAX_NH nodes on the device, every problem of the batch
+  // in one launch; larger ones by rocSOLVER (the choice depends on the problem alone, so a
+  // problem's results in a batch equal those of a single run)
+  MLC_HIP(b, launch_coarse_eig(b->dprob, P.n, st));
   for (int i = 0; i < P.n; ++i) {
     const Geometry& g = P.geo[i];
     const ProbLayout& L = P.pl[i];
+    if (g.nH <= MLC_JACOBI_MAX_NH) continue;
+    if (!b->rb && rocblas_create_handle(&b->rb) != rocblas_status_success) {
+      b->err = "rocblas_create_handle failed";
+      return MLC_EHIP;
+    }
+    if (rocblas_set_stream(b->rb, st) != rocblas_status_success) {
+      b->err = "rocblas_set_stream failed";
+      return MLC_EHIP;
+    }
     rocblas_status rs = rocsolver_dsygvd(b->rb, rocblas_eform_ax, rocblas_evect_original,
                                          rocblas_fill_upper, g.nH, (double*)(w + L.Kc), g.nH,
                                          (double*)(w + L.Mc), g.nH, (double*)(w + L.Lam),
@@ -804,7 +826,8 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
   if (P.geo[0].pou == MLC_POU_INTERFACE) {  // single problem (checked at plan time)
     const ProbLayout& L = P.pl[0];
     MLC_HIP(b, run_interface_gluing(P.kind, b->dprob, items, sub_item, w + P.store, s, P.q,
-                                    P.geo[0].nodes(s), b->o.rtol, 100000, (double*)(w + L.skel),
+                                    P.geo[0].nc, skel_stride(P.geo[0].nc, P.geo[0].L),
+                                    b->o.rtol, 100000, (double*)(w + L.skel),
                                     (double*)(w + L.skel_parts), (double*)(w + L.skel_scal), st,
                                     &b->glue_it, &b->glue_relres));
     b->glue_relres_step[s] = b->glue_relres;
@@ -989,6 +1012,97 @@ mlc_status phase_times(mlc_batch* b, double* ms, int32_t n) {
   b->ev_pending.clear();
   for (int i = 0; ms && i < n; ++i) ms[i] = i < 2 ? acc[i] : 0.0;
   return MLC_OK;
+}
+
+// ---- autotuner cache: one line per batch signature, "<key> <block per step>..." ----
+
+// The device architecture and a hash (FNV-1a) of everything that decides the local-solve
+// launches of every step: element order, coefficient kind, precision, q, nu, and each
+// item's subdomain shape.  Two batches with the same key launch the same work.
+std::string tune_key(const mlc_batch* b) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return std::string();
+  const Plan& P = b->plan;
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(P.order);
+  mix(P.kind);
+  mix(P.precision);
+  mix(P.q);
+  mix(b->o.nu);
+  mix(P.Lmax);
+  for (int s = 1; s <= P.Lmax; ++s) {
+    mix((int64_t)P.steps[s].items.size());
+    for (const TileItem& it : P.steps[s].items) {
+      mix(it.cw);
+      mix(it.ch);
+    }
+  }
+  std::string arch(prop.gcnArchName);
+  for (char& c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return arch + "/" + buf;
+}
+
+// MLC_AUTOTUNE_CACHE, else $HOME/.cache/mlc_autotune.txt; empty: no cache.
+std::string tune_cache_path() {
+  if (const char* p = std::getenv("MLC_AUTOTUNE_CACHE")) return std::string(p);
+  if (const char* home = std::getenv("HOME")) return std::string(home) + "/.cache/mlc_autotune.txt";
+  return std::string();
+}
+
+bool tune_cache_read(const std::string& path, const std::string& key, int L,
+                     std::vector<int>& choice) {
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string k;
+    if (!(in >> k) || k != key) continue;
+    std::vector<int> v(L + 1, 1024);
+    bool ok = true;
+    for (int s = 1; s <= L && ok; ++s) ok = (bool)(in >> v[s]) && (v[s] == 256 || v[s] == 512 || v[s] == 1024);
+    if (ok) {
+      choice = v;
+      return true;
+    }
+  }
+  return false;
+}
+
+void tune_cache_write(const std::string& path, const std::string& key, int L,
+                      const std::vector<int>& choice) {
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+      std::istringstream in(line);
+      std::string k;
+      if ((in >> k) && k != key) keep.push_back(line);
+    }
+  }
+  std::ostringstream o;
+  o << key;
+  for (int s = 1; s <= L; ++s) o << ' ' << choice[s];
+  keep.push_back(o.str());
+  const size_t slash = path.find_last_of('/');
+  if (slash != std::string::npos) {
+    const std::string dir = path.substr(0, slash);  // create missing directories
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') (void)::mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  std::ofstream f(path, std::ios::trunc);
+  for (const std::string& l : keep) f << l << '\n';
 }
 
 // After steps from+1 .. to: MLC_ENOCONV if a local solve of one of them (or, with the
@@ -1374,41 +1488,59 @@ mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n) {
     return MLC_ESTATE;
   }
   const Plan& P = b->plan;
-  const int cand[3] = {256, 512, 1024};
-  std::vector<double> best(P.Lmax + 1, 1e300);
   std::vector<int> choice(P.Lmax + 1, 1024);
-  const int saved_timing = b->o.timing;
-  b->o.timing = 1;
-  drop_graphs(b);
-  mlc_status e = phase_times(b, nullptr, 0);  // drop stale events
-  for (int c = 0; c < 3 && e == MLC_OK; ++c) {
-    std::fill(b->blocks.begin(), b->blocks.end(), cand[c]);
-    // back to level 0 from the stored coarse eigenbasis, then every step once
-    if (launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st) != hipSuccess) {
-      b->err = "launch_init_u0 failed";
-      e = MLC_EHIP;
-      break;
-    }
-    b->step = 0;
-    std::fill(b->shift.begin(), b->shift.end(), 0);
-    for (int s = 1; s <= P.Lmax && e == MLC_OK; ++s) {
-      e = batch_step(b, 0);
-      double ms[2] = {0.0, 0.0};
-      if (e == MLC_OK) e = phase_times(b, ms, 2);
-      if (e == MLC_OK && ms[0] < best[s]) {
-        best[s] = ms[0];
-        choice[s] = cand[c];
+  const std::string key = tune_key(b);
+  const std::string path = tune_cache_path();
+  bool cached = !key.empty() && !path.empty() && tune_cache_read(path, key, P.Lmax, choice);
+  if (!cached) {
+    // every candidate: kReps full runs from level 0, per step the median local-solve time
+    const int cand[3] = {256, 512, 1024};
+    constexpr int kReps = 3;
+    std::vector<double> best(P.Lmax + 1, 1e300);
+    const int saved_timing = b->o.timing;
+    b->o.timing = 1;
+    drop_graphs(b);
+    mlc_status e = phase_times(b, nullptr, 0);  // drop stale events
+    for (int c = 0; c < 3 && e == MLC_OK; ++c) {
+      std::fill(b->blocks.begin(), b->blocks.end(), cand[c]);
+      std::vector<std::vector<double>> t(P.Lmax + 1);
+      for (int rep = 0; rep < kReps && e == MLC_OK; ++rep) {
+        if (launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st) != hipSuccess) {
+          b->err = "launch_init_u0 failed";
+          e = MLC_EHIP;
+          break;
+        }
+        b->step = 0;
+        std::fill(b->shift.begin(), b->shift.end(), 0);
+        for (int s = 1; s <= P.Lmax && e == MLC_OK; ++s) {
+          e = batch_step(b, 0);
+          double ms[2] = {0.0, 0.0};
+          if (e == MLC_OK) e = phase_times(b, ms, 2);
+          t[s].push_back(ms[0]);
+        }
+      }
+      for (int s = 1; s <= P.Lmax && e == MLC_OK; ++s) {
+        std::vector<double> v = t[s];
+        std::sort(v.begin(), v.end());
+        const double med = v[v.size() / 2];
+        if (med < best[s]) {
+          best[s] = med;
+          choice[s] = cand[c];
+        }
       }
     }
+    b->o.timing = saved_timing;
+    if (e != MLC_OK) return e;
+    if (!key.empty() && !path.empty()) tune_cache_write(path, key, P.Lmax, choice);
   }
-  b->o.timing = saved_timing;
-  if (e != MLC_OK) return e;
   for (int s = 1; s <= P.Lmax; ++s) b->blocks[s] = choice[s];
   for (int s = 1; s <= P.Lmax && blocks_out && s - 1 < n; ++s) blocks_out[s - 1] = choice[s];
+  drop_graphs(b);
   MLC_HIP(b, launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st));
   MLC_HIP(b, hipStreamSynchronize(b->st));
   b->step = 0;
   b->can_rewind = false;
+  std::fill(b->shift.begin(), b->shift.end(), 0);
   return MLC_OK;
 }
 

@@ -17,14 +17,16 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
                               double omega, int max_tile_nx, hipStream_t s);
 // Algorithm 4.1 step 2 as stated (MLC_POU_INTERFACE), single problem: u~ from the tile
-// solutions on the closed G_j and a global Jacobi-PCG on the rest (vec: 6 full-grid
-// vectors of `nodes` doubles, parts: 2 per 256 nodes, scal: 8 doubles).  Synchronises
-// the stream to test convergence every 8 iterations.
+// solutions on the closed G_j and a global CG on the rest, preconditioned by a multigrid
+// V-cycle on that region (vec: skel_stride(nc, L) doubles per right-hand side, parts: 2 per
+// 256 nodes of level m per right-hand side, scal: 8 doubles per right-hand side).
+// Synchronises the stream to test convergence every 4 iterations.
 hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* items,
-                                const int32_t* sub_item, const char* store, int m, int q,
-                                int64_t nodes, double rtol, int max_it, double* vec,
+                                const int32_t* sub_item, const char* store, int m, int q, int nc,
+                                int64_t stride, double rtol, int max_it, double* vec,
                                 double* parts, double* scal, hipStream_t s, int* iters_out,
                                 double* relres_out);
+int64_t skel_stride(int nc, int L);
 
 // Widest tile row (interior nodes) whose banded smoothing passes fit the device's
 // per-workgroup LDS with nt threads (three rings of nt/64 + 2 rows, plus the LDS tail of
@@ -66,6 +68,9 @@ hipError_t launch_galerkin7(const double* fine, double* coarse, float* coarsef, 
                             hipStream_t s);
 hipError_t launch_coarse_matrices(int kind, const ProbDev* probs, int nprob, int max_nH,
                                   hipStream_t s);
+// Full generalized eigendecomposition of the coarse matrices of every problem whose eig_ws
+// is set (Cholesky, two-sided Jacobi, back substitution; one workgroup per problem).
+hipError_t launch_coarse_eig(const ProbDev* probs, int nprob, hipStream_t s);
 hipError_t launch_init_u0(const ProbDev* probs, int nprob, int dst, int max_nc1sq, hipStream_t s);
 hipError_t launch_tile_inverse(int kind, const ProbDev* probs, const TileItem* items,
                                int nitems, double* inv, hipStream_t s);

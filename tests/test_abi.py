@@ -249,3 +249,4 @@ def test_rayleigh_ritz_lds_limit():
     assert B.workspace_size(W.config2_p2()) > 0
     with pytest.raises(B.MLCError):
         B.workspace_size(W.config2_p2().with_(n_coarse=32, sub_x=16, sub_y=16, n_eig=4))
+

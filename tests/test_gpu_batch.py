@@ -266,3 +266,45 @@ def test_config4_full_batch():
         print(f"config 4 problem {g['index']}: max sample error {err:.2e} (signed)")
         assert err < 1e-8, (g["index"], err)
     bs.close()
+
+
+def test_autotune_cache_across_processes(tmp_path, monkeypatch):
+    """The autotuner's choice is stored under a key of the device architecture and the
+    batch's launch signature (MLC_AUTOTUNE_CACHE); a later batch with the same signature,
+    here in another process, takes it from the file without timing; a batch with another
+    signature gets its own line."""
+    _torch()
+    import subprocess
+    import sys
+    from paper_1401_4969_amd import binding as B
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MLC_AUTOTUNE_CACHE", str(cache))
+    probs = _small_batch(1, 1)
+    bs = B.BatchSolver(probs)
+    bs.setup()
+    blocks = bs.autotune()
+    bs.close()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    key, *vals = lines[0].split()
+    assert key.startswith("gfx") and [int(v) for v in vals] == blocks
+    # another process: the cached choice comes back without timing
+    code = ("import sys; sys.path.insert(0, %r); import workloads as W\n"
+            "from test_gpu_batch import _small_batch\n"
+            "from paper_1401_4969_amd import binding as B\n"
+            "bs = B.BatchSolver(_small_batch(1, 1)); bs.setup()\n"
+            "import time; t = time.perf_counter(); b = bs.autotune(); t = time.perf_counter() - t\n"
+            "print(' '.join(map(str, b)), t)\n") % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MLC_AUTOTUNE_CACHE=str(cache),
+               PYTHONPATH=os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    *got, secs = r.stdout.split()
+    assert [int(v) for v in got] == blocks
+    # a different batch: a second line
+    bs = B.BatchSolver(_small_batch(1, 1, n=3, seed0=900))
+    bs.setup()
+    bs.autotune()
+    bs.close()
+    assert len(cache.read_text().splitlines()) == 2

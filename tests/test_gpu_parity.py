@@ -332,6 +332,7 @@ def test_interface_gluing(which, overlap):
     else:
         prob = W.small_field().with_(overlap=overlap, pou=2)
     lam, u, levels, stats, ref = compare(prob)
+    print("G_m+1 CG iterations per level:", [st["glue_it"] for st in stats])
     for st in stats:
         assert st["glue_it"] > 0 and st["glue_relres"] <= 1e-12 * 1.0000001
 
@@ -340,6 +341,24 @@ def test_interface_gluing_four_eigenpairs():
     """The G_{m+1} solves of four right-hand sides share their launches (each frozen once it
     has converged): parity with the oracle on every level."""
     compare(W.Problem(0, 8, 3, 4, 4, 1, 4, 0, None, "iface_q4", pou=2))
+
+
+def test_interface_gluing_config2_size():
+    """The paper's gluing at configuration 2's size (h = 1/512, 8x8, q = 3) against the
+    stored oracle values of that workload: every level's eigenvalues to 1e-10, and the
+    multigrid-preconditioned G_{m+1} solves converge in a number of iterations that stays
+    bounded as h halves (a diagonal preconditioner needed 407 at h = 1/512)."""
+    _torch()
+    gold = _golden("c2iface")
+    prob = W.config2().with_(pou=2, name="c2_iface")
+    lam, u, levels, stats = gpu_solve(prob)
+    for k, (a, b) in enumerate(zip(levels, gold["lam_levels"])):
+        rel = np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b)))
+        assert rel < LAM_RTOL, (k, a, b, rel)
+    its = [st["glue_it"] for st in stats]
+    print("c2 interface problem: CG iterations per level", its)
+    assert max(its) <= 40, its
+    assert its[-1] <= its[1] + 10, its
 
 
 def test_interface_gluing_mixed_precision():
