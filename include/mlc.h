@@ -238,6 +238,21 @@ mlc_status mlc_hf_gradient(struct mlc_ctx* ctx, double* kappa_bar_dev);
 
 mlc_status mlc_destroy(struct mlc_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the whole of Algorithm 4.2 in one call --
+ * mlc_create, mlc_coarse_setup, mlc_run, mlc_get_eigenpairs and mlc_destroy -- with the
+ * library's static device scratch array (64 MiB per device, held until the process ends) as
+ * the workspace instead of a caller's buffer.  Calls no hipMalloc, hipFree or allocating
+ * library routine: the coarse eigendecomposition runs on the device, so the problem's
+ * coarse space may have at most 400 nodes (MLC_EINVAL above that, and with record_tape or
+ * timing set); MLC_ENOMEM when mlc_workspace_size exceeds 64 MiB.  lambda_host (host, q
+ * doubles) and u_dev (device, q*(N_L+1)^2 doubles, may be NULL) as in mlc_get_eigenpairs;
+ * MLC_ENOCONV as mlc_run (results written).  Synchronises the stream.  Every call on one
+ * device shares that device's scratch array and leaves its contents behind: calls that
+ * overlap on one device (other threads, other streams) race. */
+mlc_status mlc_solve_static(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
+                            void* hip_stream, double* lambda_host, double* u_dev);
+
 /* ---- Batches: many independent problems, one launch per kernel and level step ----
  *
  * All problems of a batch share q (n_eig) and coef_kind; domains, meshes, subdomain

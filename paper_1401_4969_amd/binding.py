@@ -29,7 +29,7 @@ EXPORTS = [
     "mlc_backward", "mlc_hf_gradient", "mlc_batch_workspace_size", "mlc_batch_create", "mlc_batch_setup", "mlc_batch_step",
     "mlc_batch_run", "mlc_batch_rewind", "mlc_batch_restart", "mlc_batch_current_step", "mlc_batch_get",
     "mlc_batch_step_stats", "mlc_batch_autotune", "mlc_batch_set_blocks",
-    "mlc_batch_phase_times", "mlc_batch_destroy", "mlc_batch_last_error",
+    "mlc_batch_phase_times", "mlc_batch_destroy", "mlc_batch_last_error", "mlc_solve_static",
 ]
 
 
@@ -118,6 +118,8 @@ def load_library() -> C.CDLL:
     lib.mlc_batch_set_blocks.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
     lib.mlc_batch_phase_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
     lib.mlc_batch_destroy.argtypes = [P]
+    lib.mlc_solve_static.argtypes = [C.POINTER(ProblemDesc), C.POINTER(SolverOpts), P,
+                                      C.POINTER(C.c_double), P]
     lib.mlc_batch_last_error.argtypes = [P]
     lib.mlc_batch_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -297,6 +299,29 @@ def solve(prob, opts: Optional[SolverOpts] = None, device: str = "cuda:0", stats
         levels.append(lam)
     s.close()
     return lam, u, levels, st
+
+
+def solve_static(prob, opts: Optional[SolverOpts] = None, device: str = "cuda:0",
+                 with_vectors: bool = True):
+    """mlc_solve_static: the whole solve in the library's static device scratch (no device
+    allocation by the library; the output vectors here are torch's)."""
+    import torch
+    lib = load_library()
+    opts = opts or default_opts()
+    d, _k = make_desc(prob)
+    q = int(prob.n_eig)
+    lam = np.zeros(q)
+    u = None
+    if with_vectors:
+        n1 = (prob.n_coarse << (prob.n_refine + int(getattr(prob, "order", 1)) - 1)) + 1
+        u = torch.empty((q, n1, n1), dtype=torch.float64, device=device)
+    stream = torch.cuda.current_stream(torch.device(device))
+    st = lib.mlc_solve_static(C.byref(d), C.byref(opts), C.c_void_p(stream.cuda_stream),
+                              lam.ctypes.data_as(C.POINTER(C.c_double)),
+                              C.c_void_p(u.data_ptr()) if u is not None else None)
+    if st != MLC_OK:
+        raise MLCError(st, "mlc_solve_static failed (see stderr)")
+    return lam, u
 
 
 def _problem_with_kappa(prob, kappa: np.ndarray):

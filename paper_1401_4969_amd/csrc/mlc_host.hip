@@ -13,6 +13,7 @@
 #include <array>
 #include <cstdlib>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <sys/stat.h>
 #include <cmath>
@@ -1402,6 +1403,78 @@ const char* mlc_status_str(mlc_status s) {
 }
 
 const char* mlc_last_error(const mlc_ctx* c) { return c ? c->b->err.c_str() : "null context"; }
+
+// ---------------- without device allocation ----------------
+
+}  // extern "C"
+
+// The workspace of mlc_solve_static: a file-scope device array (every device the library
+// runs on holds its own copy until the process ends).  In host code its name is only a
+// stand-in: kernels and copies use the address hipGetSymbolAddress returns per device.
+#define MLC_STATIC_BYTES ((size_t)64 << 20)
+#define MLC_STATIC_DEVICES 64
+__device__ __align__(256) char scratch[MLC_STATIC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch[MLC_STATIC_DEVICES] = {};
+}  // namespace
+
+extern "C" {
+
+mlc_status mlc_solve_static(const mlc_problem_desc* d, const mlc_solver_opts* o, void* stream,
+                            double* lam_host, double* u_dev) {
+  if (!d || !o || !lam_host) return MLC_EINVAL;
+  Plan P;
+  std::string msg;
+  mlc_status s = make_plan(1, d, o, P, msg);
+  if (s != MLC_OK) {
+    std::fprintf(stderr, "mlc: %s\n", msg.c_str());
+    return s;
+  }
+  if (P.total > MLC_STATIC_BYTES) {
+    std::fprintf(stderr, "mlc: mlc_solve_static needs %zu bytes of workspace, above the static "
+                 "scratch of %zu bytes (use mlc_create with a caller's workspace)\n",
+                 P.total, (size_t)MLC_STATIC_BYTES);
+    return MLC_ENOMEM;
+  }
+  if (P.geo[0].nH > MLC_JACOBI_MAX_NH || o->record_tape || o->timing) {
+    std::fprintf(stderr, "mlc: mlc_solve_static needs a coarse space of at most %d nodes (the "
+                 "device eigensolver), no tape and no timing events\n", MLC_JACOBI_MAX_NH);
+    return MLC_EINVAL;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MLC_STATIC_DEVICES) return MLC_EHIP;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        std::fprintf(stderr, "mlc: hipGetSymbolAddress(scratch): %s\n", hipGetErrorString(e));
+        return MLC_EHIP;
+      }
+      g_scratch[dev] = p;
+    }
+    ws = g_scratch[dev];
+  }
+  mlc_batch* b = nullptr;
+  s = batch_create(1, d, o, ws, MLC_STATIC_BYTES, stream, &b);
+  if (s != MLC_OK) return s;
+  s = batch_setup(b);
+  if (s == MLC_OK) {
+    while (s == MLC_OK && b->step < b->plan.Lmax) s = batch_step(b, 0);
+    if (s == MLC_OK) s = check_converged(b, 0, b->step);
+    if (s == MLC_OK || s == MLC_ENOCONV) {
+      const mlc_status g = batch_get(b, 0, lam_host, u_dev);
+      if (g != MLC_OK) s = g;
+    }
+  }
+  if (s != MLC_OK && s != MLC_ENOCONV) std::fprintf(stderr, "mlc: %s\n", b->err.c_str());
+  batch_destroy(b);
+  return s;
+}
 
 // ---------------- batches ----------------
 

@@ -250,3 +250,17 @@ def test_rayleigh_ritz_lds_limit():
     with pytest.raises(B.MLCError):
         B.workspace_size(W.config2_p2().with_(n_coarse=32, sub_x=16, sub_y=16, n_eig=4))
 
+
+def test_solve_static_size_checks_before_device_calls():
+    """mlc_solve_static plans first: a problem whose workspace exceeds the 64 MiB static
+    scratch (config 2: 180 MiB, config 3: 1 GiB) is MLC_ENOMEM and invalid options are
+    MLC_EINVAL, before any device call."""
+    lib = B.load_library()
+    lam = (C.c_double * 8)()
+    for prob, want in ((W.config2(), B.MLC_ENOMEM), (W.config3(), B.MLC_ENOMEM)):
+        d, _k = B.make_desc(prob)
+        o = B.default_opts()
+        assert lib.mlc_solve_static(C.byref(d), C.byref(o), None, lam, None) == want
+    d, _k = B.make_desc(W.config1())
+    o = B.default_opts(record_tape=1)
+    assert lib.mlc_solve_static(C.byref(d), C.byref(o), None, lam, None) == B.MLC_EINVAL
