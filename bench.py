@@ -315,6 +315,8 @@ def workload(name: str):
         return W.example62(n_refine=5, sub=5, n_eig=6), dict(precision=1)
     if name == "c2p2":
         return W.config2_p2(), dict(precision=0)
+    if name == "c3p2":
+        return W.config3_p2(), dict(precision=0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -540,7 +542,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3",
                     choices=["c3", "c2", "c3mixed", "c4", "c5adj", "c2iface", "c3iface",
-                             "ex62", "ex62mixed", "c2p2"],
+                             "ex62", "ex62mixed", "c2p2", "c3p2"],
                     help="c3 (default): unit square, h = 1/2048, 16x16 subdomains, q = 1, FP64, "
                          "with the same in FP32 + FP64 refinement beside it; c2: h = 1/512, "
                          "8x8 subdomains, q = 3; c3mixed: c3 in FP32 + FP64 refinement only; "
@@ -548,7 +550,8 @@ def main():
                          "c2iface, c3iface: c2 / c3 with the paper's own gluing (interface "
                          "problem); ex62, ex62mixed: the operator of Example 6.2 (tensor A, "
                          "weight phi) on (-1,1)^2, H = 0.1, h = 1/320, 5x5 subdomains, q = 6; "
-                         "c2p2: P2 elements at h = 1/256 (the 261,121 dofs of c2), 8x8, q = 3")
+                         "c2p2: P2 elements at h = 1/256 (the 261,121 dofs of c2), 8x8, q = 3; "
+                         "c3p2: P2 at h = 1/512 (1,046,529 dofs), 16x16, q = 1")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",

@@ -263,30 +263,25 @@ __device__ __forceinline__ double tile_at(const LevelDesc& l0, int ix, int iy, i
   return in ? v : 0.0;
 }
 
-// p = z + beta p_old, stored, and this thread's share of p . K2 p (K2: the P2 stiffness,
-// applied to p formed at the node's neighbours).
-template <int NT, int KIND>
-__device__ void pass_dir_p2(const ProbDev& P, const LevelDesc& l0, const double* Z,
-                            const double* Po, double* Pn, double beta, bool first, double* acc) {
+// p = z + beta p_old (beta = 0 and p_old unread on the first iteration): a streaming pass.
+template <int NT>
+__device__ void pass_dir_p2(const LevelDesc& l0, const double* Z, const double* Po, double* Pn,
+                            double beta, bool first) {
   const double bet = first ? 0.0 : beta;
   const double* Pold = first ? Z : Po;  // any valid vector: its values are multiplied by 0
-  const int lm = l0.l - 1;              // P2 mesh level of the tile's node grid
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
-    auto pv = [&](unsigned j) -> double { return Z[j] + bet * Pold[j]; };
-    const double pc = pv(i);
-    if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + iy)) {
-      auto u = [&](int dx, int dy) -> double { return tile_at(l0, ix, iy, dx, dy, pv); };
-      *acc += pc * p2::apply_k<KIND>(P, lm, l0.gx0 + ix, l0.gy0 + iy, u);
-    }
-    Pn[i] = pc;
+    Pn[i] = Z[i] + bet * Pold[i];
   }
 }
 
+// q = K2 p (the P2 stiffness of the tile), stored, and this thread's share of p . q.  The
+// P2 stencil gathers up to 19 nodes, so q is kept for the update pass instead of being
+// formed again there.
 template <int NT, int KIND>
-__device__ void pass_xr_p2(const ProbDev& P, const LevelDesc& l0, double* X, double* R,
-                           const double* Pn, double alpha, double* acc) {
-  const int lm = l0.l - 1;
+__device__ void pass_apply_p2(const ProbDev& P, const LevelDesc& l0, const double* Pn, double* Q,
+                              double* acc) {
+  const int lm = l0.l - 1;  // P2 mesh level of the tile's node grid
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
     double q = 0.0;
@@ -294,9 +289,20 @@ __device__ void pass_xr_p2(const ProbDev& P, const LevelDesc& l0, double* X, dou
       auto pv = [&](unsigned j) -> double { return Pn[j]; };
       auto u = [&](int dx, int dy) -> double { return tile_at(l0, ix, iy, dx, dy, pv); };
       q = p2::apply_k<KIND>(P, lm, l0.gx0 + ix, l0.gy0 + iy, u);
+      *acc += Pn[i] * q;
     }
+    Q[i] = q;
+  }
+}
+
+// x += alpha p, r -= alpha q: a streaming pass.
+template <int NT>
+__device__ void pass_xr_p2(const LevelDesc& l0, double* X, double* R, const double* Pn,
+                           const double* Q, double alpha, double* acc) {
+  FOR_TILE(l0) {
+    const unsigned i = (unsigned)(iy * l0.nx + ix);
     X[i] += alpha * Pn[i];
-    const double r = R[i] - alpha * q;
+    const double r = R[i] - alpha * Q[i];
     R[i] = r;
     *acc += r * r;
   }
@@ -316,6 +322,7 @@ __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, i
   double* R = base + l0.ob;
   double* Po = base + 4 * S0;
   double* Pn = base + 5 * S0;
+  double* Q = base + l0.ot;  // the V-cycle's level-0 temporary, free between V-cycles
   int iters = 0;
   rr = bb;
   if (!(bb > 0.0)) return 0;
@@ -328,11 +335,13 @@ __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, i
       if (iters >= max_it) break;
       ++iters;
       acc[0] = acc[1] = 0.0;
-      pass_dir_p2<NT, KIND>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
+      pass_dir_p2<NT>(l0, Z, Po, Pn, beta, first);
+      __syncthreads();
+      pass_apply_p2<NT, KIND>(P, l0, Pn, Q, &acc[0]);
       block_sum<NT, 2>(acc, red);
       const double alpha = rho / acc[0];
       acc[0] = acc[1] = 0.0;
-      pass_xr_p2<NT, KIND>(P, l0, X, R, Pn, alpha, &acc[0]);
+      pass_xr_p2<NT>(l0, X, R, Pn, Q, alpha, &acc[0]);
       block_sum<NT, 2>(acc, red);
       rr = acc[0];
       if (rr <= tol2) break;

@@ -93,3 +93,25 @@ def test_p2_batch_equals_single_runs():
         assert np.array_equal(lam, lam1), i
         assert torch.equal(u, u1), i
     bs.close()
+
+
+def test_p2_config3_size_against_stored_oracle():
+    """P2 at h = 1/512 (1,046,529 fine dofs, 16 x 16 subdomains of one coarse cell, tiles of
+    191^2 P2 nodes): every level's eigenvalue against the stored oracle values and the
+    eigenvector at 512 seeded nodes (signed)."""
+    torch = _torch()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_c3p2.json")) as f:
+        gold = json.load(f)
+    prob = W.config3_p2()
+    lam, u, levels, stats = gpu_solve(prob)
+    for k, (a, b) in enumerate(zip(levels, gold["lam_levels"])):
+        rel = np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b)))
+        assert rel < LAM_RTOL, (k, a, b, rel)
+    idx = torch.as_tensor(np.asarray(gold["sample_nodes"]), device=u.device)
+    vals = u[0].reshape(-1)[idx].cpu().numpy()
+    ref = np.asarray(gold["sample_values"][0])
+    err = np.max(np.abs(vals - ref)) / np.max(np.abs(ref))
+    print(f"c3p2 vector 0: max sample error {err:.2e}; local iterations",
+          [s["it_max"] for s in stats])
+    assert err < 1e-8
+    assert stats[-1]["n_dofs"] == 1023 * 1023

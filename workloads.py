@@ -241,6 +241,14 @@ def config2_p2() -> Problem:
                    order=2)
 
 
+def config3_p2() -> Problem:
+    """P2 on the unit square, H=1/16 -> h=1/512: 1023^2 = 1,046,529 fine dofs; 16x16
+    subdomains of one coarse cell (Omega_j of 3x3 cells: tiles of 191^2 P2 nodes), overlap 1,
+    q=1.  The tiles' storage (about 0.6 GB) is far beyond the last-level cache."""
+    return Problem(DOMAIN_SQUARE, 16, 5, 16, 16, 1, 1, 0, None, "c3p2_square_H16_h512_16x16_q1",
+                   order=2)
+
+
 def small_ragged_p2(seed: int = 13) -> Problem:
     """P2 on the L-shape with uneven subdomain splits and a per-coarse-cell kappa, q=2."""
     rng = np.random.Generator(np.random.PCG64(seed))
