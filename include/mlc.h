@@ -81,7 +81,7 @@ enum { MLC_POU_RAMP = 0,        /* phi_j = rho(x) rho(y): 1 on D_j, linear to 0 
                                    u~ = u~^j on G_j = D_j shrunk by half a coarse cell, and on
                                    G_{m+1} (the rest) the Dirichlet problem of equation
                                    (G_m+1_Problem), solved by a global CG; single-problem
-                                   contexts without a tape only, no hipGraph steps */
+                                   contexts without a tape only */
 
 enum { MLC_PREC_FP64 = 0,       /* every local solve in FP64 */
        MLC_PREC_MIXED = 1 };    /* FP32 inner PCG with FP64 residual refinement */
@@ -122,6 +122,12 @@ typedef struct mlc_solver_opts {
   int32_t timing;      /* 1: record HIP events around the local-solve kernel (see mlc_phase_times) */
   int32_t record_tape; /* 1: keep every level's forward state for mlc_backward (single problem,
                           q = 1, coef_kind 1 or 2; enlarges the workspace) */
+  int32_t glue_graph_it; /* MLC_POU_INTERFACE in hipGraph batch steps: CG iterations of the
+                          G_{m+1} problem in the captured sequence (24; 1..1000); right-hand
+                          sides that converge earlier are frozen, and one that has not
+                          converged by then makes the step's statistics and mlc_batch_run
+                          report MLC_ENOCONV.  Eager steps iterate to convergence (at most
+                          1000 iterations). */
 } mlc_solver_opts;
 
 /* Per-level statistics, filled by mlc_level_correct when st != NULL (this synchronises
@@ -170,7 +176,7 @@ mlc_status mlc_workspace_size(const mlc_problem_desc* desc, const mlc_solver_opt
  *   grid above 32768 intervals per side; problems of one batch with different order;
  *   options: NULL; precision not 0 or 1; rtol outside (0, 1); max_it < 1; nu outside
  *   1..8; omega outside (0, 1); mixed precision with max_refine < 1 or inner_rtol outside
- *   (0, 1); block not 0, 256, 512 or 1024;
+ *   (0, 1); block not 0, 256, 512 or 1024; glue_graph_it outside 1..1000;
  *   workspace: NULL or not 256-byte aligned (MLC_ENOMEM when smaller than needed). */
 mlc_status mlc_create(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
                       void* dev_workspace, size_t workspace_bytes, void* hip_stream,

@@ -50,8 +50,8 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   int total = 0, refine = 0;
   const int rows = l0.nx <= ring_cap ? 1 : 0;  // banded passes where the rings fit (per item)
   float* ring = rows ? ring_lds_f : nullptr;
-  // no LDS V-cycle tail here: its registers would crowd out the prefetching passes
-  float* tail = nullptr;
+  // the LDS V-cycle tail with 1024-thread workgroups (one per CU), as in the FP64 solver
+  float* tail = (rows && NT == 1024) ? ring_lds_f + ring_elems(NT / 64, ring_cap, 0) : nullptr;
   while (rr > rtol * rtol * bb && refine < max_refine) {
     ++refine;
     double rr_inner;
@@ -113,9 +113,9 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
   int cap2 = 0;
-  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, false, &lds, &cap2);
+  const int cap = ring_capacity(ntv, nu, max_tile_nx, 4, ntv == 1024, &lds, &cap2);
   cap2 = 0;  // one band row per wave here
-  lds = cap > 0 ? (size_t)ring_elems(ntv / 64, cap, 0) * 4 : 0;
+  lds = cap > 0 ? (size_t)ring_elems(ntv / 64, cap, 0) * 4 + (ntv == 1024 ? (size_t)TAIL_ELEMS * 4 : 0) : 0;
 #define MLC_MIX(NTV, KV)                                                                     \
   hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
                      store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \

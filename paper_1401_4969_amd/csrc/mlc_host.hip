@@ -46,6 +46,7 @@ hipError_t launch_local_p2(int kind, int nt, const ProbDev* probs, const TileIte
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kGlueMaxIt = 1000;  // eager G_{m+1} CG: iteration cap (MLC_ENOCONV beyond)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -91,6 +92,10 @@ mlc_status check_opts(const mlc_solver_opts* o, std::string& msg) {
   }
   if (o->block != 0 && o->block != 256 && o->block != 512 && o->block != 1024) {
     msg = "block must be 0, 256, 512 or 1024";
+    return MLC_EINVAL;
+  }
+  if (o->glue_graph_it < 1 || o->glue_graph_it > 1000) {
+    msg = "glue_graph_it must be in 1..1000";
     return MLC_EINVAL;
   }
   return MLC_OK;
@@ -229,7 +234,8 @@ mlc_status build_geometry(const mlc_problem_desc* d, Geometry& g, std::string& m
 // Byte offsets (from the workspace base) of one problem's buffers.
 struct ProbLayout {
   size_t bx, by, coarse_nodes, coarse_index, kH, u[2], lam, ubar, res, ut, rchain, Kc, Mc, Lam,
-      E, info, fg, partials, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal;
+      E, info, fg, partials, rr_y, rr_t, rr_ab, cH, out_parts, skel, skel_parts, skel_scal,
+      skel_rec;
   size_t kLR[MLC_MAX_LEVELS + 1], kUL[MLC_MAX_LEVELS + 1];
   size_t st7[MLC_MAX_LEVELS + 1], st7f[MLC_MAX_LEVELS + 1], coef3;  // coef kind 3: stencil
                                                                      // planes, input
@@ -367,11 +373,12 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.rr_ab = take(2 * 8);
     L.cH = take(q * ncs * 8);
     L.out_parts = take(4 * 64 * q * 8);  // output sign partials (4 per block)
-    L.skel = L.skel_parts = L.skel_scal = 0;
+    L.skel = L.skel_parts = L.skel_scal = L.skel_rec = 0;
     if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem and its V-cycle
       L.skel = take((size_t)skel_stride(g.nc, g.L) * q * 8);
       L.skel_parts = take(((nnL + 255) / 256) * 2 * q * 8);
       L.skel_scal = take(8 * q * 8);
+      L.skel_rec = take((MLC_MAX_LEVELS + 1) * 2 * 8);  // per step: iterations, relres
     }
     L.inv_base = P.inv_total;
     P.inv_total += g.inv_total;
@@ -528,9 +535,6 @@ struct mlc_batch {
   std::vector<hipEvent_t> ev_free;
   std::vector<std::array<hipEvent_t, 4>> ev_pending;
   std::vector<double> e0;  // unit coefficient vector (host copy kept for the async upload)
-  int glue_it = 0;         // last step's G_{m+1} problem (MLC_POU_INTERFACE)
-  double glue_relres = 0.0;
-  std::vector<double> glue_relres_step;  // per step (index s), MLC_POU_INTERFACE
   bool tape_valid = false;  // every taped level comes from steps run from level 0
 };
 
@@ -597,7 +601,6 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
   b->blocks.assign(P.Lmax + 1, o->block ? o->block : 1024);
   b->graphs.assign(P.Lmax + 1, nullptr);
   b->graph_defs.assign(P.Lmax + 1, nullptr);
-  b->glue_relres_step.assign(P.Lmax + 1, 0.0);
   b->kappa.resize(n);
   b->hp.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -784,7 +787,8 @@ mlc_status batch_setup(mlc_batch* b) {
 }
 
 // Enqueue one level step s (src/dst: eigenvector buffers of levels s-1 and s).
-mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipStream_t st) {
+mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, bool capture,
+                        hipStream_t st) {
   const Plan& P = b->plan;
   const StepTables& T = P.steps[s];
   char* w = b->ws;
@@ -826,12 +830,14 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, hipS
   if (timing) MLC_HIP(b, hipEventRecord(ev[2], st));
   if (P.geo[0].pou == MLC_POU_INTERFACE) {  // single problem (checked at plan time)
     const ProbLayout& L = P.pl[0];
+    // eager: CG until every right-hand side has converged (flags polled every 4
+    // iterations); captured: a fixed glue_graph_it iterations (converged ones frozen)
     MLC_HIP(b, run_interface_gluing(P.kind, b->dprob, items, sub_item, w + P.store, s, P.q,
                                     P.geo[0].nc, skel_stride(P.geo[0].nc, P.geo[0].L),
-                                    b->o.rtol, 100000, (double*)(w + L.skel),
-                                    (double*)(w + L.skel_parts), (double*)(w + L.skel_scal), st,
-                                    &b->glue_it, &b->glue_relres));
-    b->glue_relres_step[s] = b->glue_relres;
+                                    b->o.rtol, capture ? b->o.glue_graph_it : kGlueMaxIt,
+                                    !capture, (double*)(w + L.skel),
+                                    (double*)(w + L.skel_parts), (double*)(w + L.skel_scal),
+                                    (double*)(w + L.skel_rec) + 2 * s, st));
   } else {
     // the gluing works on the node grid (level s + order - 1 of the P1 grids)
     MLC_HIP(b, launch_pou_glue(b->dprob, P.n, items, sub_item, w + P.store, s + P.order - 1,
@@ -887,17 +893,13 @@ mlc_status batch_step(mlc_batch* b, int use_graph) {
   // every problem stepping here holds level s-1 in buffer (s-1+shift)&1; the shift is
   // zero except after mlc_set_state on a single-problem context
   const int src = (s - 1 + b->shift[0]) & 1, dst = 1 - src;
-  if (use_graph && P.geo[0].pou == MLC_POU_INTERFACE) {
-    b->err = "the interface gluing tests convergence on the host: no hipGraph steps";
-    return MLC_EINVAL;
-  }
   if (use_graph) {
     if (!b->graphs[s]) {
       // capture on a private stream (default priority); the instantiated graph is then
       // launched on the caller's stream, which orders it with the caller's work
       if (!b->cap) MLC_HIP(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
       MLC_HIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-      mlc_status e = enqueue_step(b, s, src, dst, false, b->cap);
+      mlc_status e = enqueue_step(b, s, src, dst, false, true, b->cap);
       hipGraph_t g = nullptr;
       hipError_t he = hipStreamEndCapture(b->cap, &g);
       if (e != MLC_OK) {
@@ -920,7 +922,7 @@ mlc_status batch_step(mlc_batch* b, int use_graph) {
     }
     MLC_HIP(b, hipGraphLaunch(b->graphs[s], b->st));
   } else {
-    mlc_status e = enqueue_step(b, s, src, dst, b->o.timing != 0, b->st);
+    mlc_status e = enqueue_step(b, s, src, dst, b->o.timing != 0, false, b->st);
     if (e != MLC_OK) return e;
   }
   b->step = s;
@@ -968,9 +970,12 @@ mlc_status step_stats(mlc_batch* b, mlc_level_stats* stt) {
     return MLC_ENOCONV;
   }
   if (P.geo[0].pou == MLC_POU_INTERFACE) {
-    stt->glue_it = b->glue_it;
-    stt->glue_relres = b->glue_relres;
-    if (b->glue_relres > b->o.rtol * 1.0000001) {
+    double rec[2];
+    MLC_HIP(b, hipMemcpy(rec, b->ws + P.pl[0].skel_rec + 2 * s * sizeof(double), sizeof rec,
+                         hipMemcpyDeviceToHost));
+    stt->glue_it = (int32_t)rec[0];
+    stt->glue_relres = rec[1];
+    if (!(rec[1] <= b->o.rtol * 1.0000001)) {
       b->err = "the G_{m+1} problem did not converge";
       return MLC_ENOCONV;
     }
@@ -1115,6 +1120,9 @@ mlc_status check_converged(mlc_batch* b, int from, int to) {
   MLC_HIP(b, hipMemcpy(worst, b->ws + b->plan.conv, (MLC_MAX_LEVELS + 1) * 8,
                        hipMemcpyDeviceToHost));
   const double lim = b->o.rtol * 1.0000001;
+  double rec[2 * (MLC_MAX_LEVELS + 1)];
+  if (b->plan.geo[0].pou == MLC_POU_INTERFACE)
+    MLC_HIP(b, hipMemcpy(rec, b->ws + b->plan.pl[0].skel_rec, sizeof rec, hipMemcpyDeviceToHost));
   for (int s = from + 1; s <= to; ++s) {
     if (!(worst[s] <= lim)) {
       char msg[160];
@@ -1124,7 +1132,7 @@ mlc_status check_converged(mlc_batch* b, int from, int to) {
       b->err = msg;
       return MLC_ENOCONV;
     }
-    if (b->plan.geo[0].pou == MLC_POU_INTERFACE && !(b->glue_relres_step[s] <= lim)) {
+    if (b->plan.geo[0].pou == MLC_POU_INTERFACE && !(rec[2 * s + 1] <= lim)) {
       b->err = "the G_{m+1} problem of level step " + std::to_string(s) + " did not converge";
       return MLC_ENOCONV;
     }
@@ -1159,6 +1167,7 @@ mlc_status mlc_default_opts(mlc_solver_opts* o) {
   o->block = 0;
   o->timing = 0;
   o->record_tape = 0;
+  o->glue_graph_it = 24;
   return MLC_OK;
 }
 

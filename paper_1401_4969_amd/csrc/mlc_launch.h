@@ -19,13 +19,16 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
 // Algorithm 4.1 step 2 as stated (MLC_POU_INTERFACE), single problem: u~ from the tile
 // solutions on the closed G_j and a global CG on the rest, preconditioned by a multigrid
 // V-cycle on that region (vec: skel_stride(nc, L) doubles per right-hand side, parts: 2 per
-// 256 nodes of level m per right-hand side, scal: 8 doubles per right-hand side).
-// Synchronises the stream to test convergence every 4 iterations.
+// 256 nodes of level m per right-hand side, scal: 8 doubles per right-hand side, rec: 2
+// doubles that receive the maximum over right-hand sides of the iterations and of the final
+// ||r|| / ||r_0||).  poll: stop when every right-hand side has converged (the stream is
+// synchronised every 4 iterations to read the flags) or after max_it iterations; otherwise
+// enqueue exactly max_it iterations (converged right-hand sides frozen), with no host
+// synchronisation, e.g. for graph capture.
 hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* items,
                                 const int32_t* sub_item, const char* store, int m, int q, int nc,
-                                int64_t stride, double rtol, int max_it, double* vec,
-                                double* parts, double* scal, hipStream_t s, int* iters_out,
-                                double* relres_out);
+                                int64_t stride, double rtol, int max_it, bool poll, double* vec,
+                                double* parts, double* scal, double* rec, hipStream_t s);
 int64_t skel_stride(int nc, int L);
 
 // Widest tile row (interior nodes) whose banded smoothing passes fit the device's

@@ -166,6 +166,43 @@ def test_graph_replays_match_eager(kind):
     graph.close()
 
 
+def test_interface_gluing_graph_steps():
+    """The paper's gluing in captured steps: the G_{m+1} CG runs a fixed number of
+    iterations with converged right-hand sides frozen, so every replay (eager work and
+    synchronisations in between) equals the eager run, which stops at convergence, bitwise;
+    too few captured iterations are reported as MLC_ENOCONV."""
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    rng = np.random.Generator(np.random.PCG64(77))
+    prob = W.Problem(0, 8, 3, 4, 4, 1, 2, 1, W.loguniform_coarse_kappa(8, rng), "iface_graph",
+                     pou=2)
+    eager = B.BatchSolver([prob])
+    eager.setup()
+    eager.run(use_graph=False)
+    ref = eager.get(0)
+    graph = B.BatchSolver([prob])
+    graph.setup()
+    graph.run(use_graph=True)
+    for replay in range(3):
+        lam, u = graph.get(0)
+        assert np.array_equal(lam, ref[0])
+        assert torch.equal(u, ref[1])
+        st = graph.stats()
+        assert 0 < st["glue_it"] <= 24 and st["glue_relres"] <= 1e-12 * 1.0000001
+        x = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+        (x * 2).sum().item()
+        torch.cuda.synchronize()
+        graph.rewind()
+        graph.step(use_graph=True)
+    short = B.BatchSolver([prob], opts=B.default_opts(glue_graph_it=2))
+    short.setup()
+    with pytest.raises(B.MLCError) as e:
+        short.run(use_graph=True)
+    assert e.value.status == B.MLC_ENOCONV
+    for s in (eager, graph, short):
+        s.close()
+
+
 def test_autotune_choices_and_results():
     _torch()
     from paper_1401_4969_amd import binding as B
