@@ -25,7 +25,7 @@
 // The strips of G_{m+1} are a coarse cell wide, so a diagonal preconditioner needs
 // O(H / h) iterations; the V-cycle keeps the count bounded in h.
 //
-// Each level l >= 2 of the cycle is two launches over tiles of 32 x 32 nodes staged in LDS
+// Each level l >= 2 of the cycle is two launches over tiles of 32 x 32 (or 16 x 16) nodes staged in LDS
 // with a halo of three nodes (recomputed by the neighbouring tiles, so no tile waits on
 // another): the down leg (both pre-sweeps, the residual and its restriction) and the up leg
 // (the interpolated coarse correction and both post-sweeps).  The CG update of w and e is
@@ -204,10 +204,26 @@ __global__ __launch_bounds__(NTS) void k_skel_upd(const ProbDev* probs, int m, d
 
 // ---- the V-cycle on G_{m+1}; vectors are offsets (doubles) from vec + i * stride ----
 
-constexpr int TT = 32;           // owned nodes per tile side (even: coarse twins align)
-constexpr int TH = 3;            // halo: two sweeps and a residual reach three nodes out
-constexpr int TR = TT + 2 * TH;  // side of the staged square
-constexpr int S2 = TT + 4, S1 = TT + 2;
+// Tiles of TT x TT owned nodes (TT even, so coarse twins align): 32 on levels with many
+// tiles, 16 where fewer tiles would leave compute units idle.
+constexpr int TH = 3;  // halo: two sweeps and a residual reach three nodes out
+
+// Skeleton membership of the staged square of side R at grid origin (ox, oy): per axis,
+// whether the index lies in the closed G_b of its block (both axes in: inside a G_j), so a
+// node's test is two LDS reads and is_dof instead of six integer divisions.
+template <int R>
+__device__ __forceinline__ void stage_axes(const ProbDev& P, int N, int r, int ox, int oy,
+                                           unsigned char* ax, unsigned char* ay) {
+  for (int t = threadIdx.x; t < 2 * R; t += NTS) {
+    if (t < R) {
+      const int g = ox + t;
+      ax[t] = (g > 0 && g < N && g_block(P.n_c, P.sub_x, g, r) >= 0) ? 1 : 0;
+    } else {
+      const int g = oy + t - R;
+      ay[t - R] = (g > 0 && g < N && g_block(P.n_c, P.sub_y, g, r) >= 0) ? 1 : 0;
+    }
+  }
+}
 
 // K v at the staged node li of a square of row length ld (its neighbours are staged too);
 // d receives the diagonal.
@@ -231,7 +247,7 @@ __device__ __forceinline__ double lds_apply(const ProbDev& P, int l, int N, int 
 // twins the tile owns.  Stores y on the owned nodes.  With upd (level m) the CG update is
 // fused in: b = w - alpha q wherever it is read, stored as w_new (and e += alpha p) on the
 // owned nodes.
-template <int KIND>
+template <int KIND, int TT>
 __global__ __launch_bounds__(NTS) void k_mg_down(const ProbDev* probs, int l, double* vec,
                                                  int64_t stride, int64_t b_off, int64_t y_off,
                                                  int64_t bc_off, int upd, int64_t wn_off,
@@ -240,8 +256,9 @@ __global__ __launch_bounds__(NTS) void k_mg_down(const ProbDev* probs, int l, do
   const int i_rhs = blockIdx.y;
   const double* scal = scal_all + i_rhs * SKEL_NS;
   if (scal[5] != 0.0) return;  // converged: frozen (uniform over the workgroup)
+  constexpr int TR = TT + 2 * TH, S2 = TT + 4, S1 = TT + 2;
   __shared__ double sb[TR * TR], sx[TR * TR], sy[TR * TR];
-  __shared__ unsigned char sm[TR * TR];
+  __shared__ unsigned char sm[TR * TR], ax[TR], ay[TR];
   const int N = P.n_c << l, n1 = N + 1, r = 1 << l;
   const int64_t nn = (int64_t)n1 * n1;
   const int tiles_x = (n1 + TT - 1) / TT;
@@ -249,9 +266,11 @@ __global__ __launch_bounds__(NTS) void k_mg_down(const ProbDev* probs, int l, do
   const int ox = (int)(blockIdx.x % tiles_x) * TT - TH, oy = (int)(blockIdx.x / tiles_x) * TT - TH;
   double* base = vec + (int64_t)i_rhs * stride;
   const double alpha = upd ? scal[1] : 0.0;
+  stage_axes<TR>(P, N, r, ox, oy, ax, ay);
+  __syncthreads();
   for (int t = threadIdx.x; t < TR * TR; t += NTS) {
     const int lx = t % TR, ly = t / TR, gx = ox + lx, gy = oy + ly;
-    const bool mk = skel_dof(P, N, r, gx, gy);
+    const bool mk = is_dof(P.domain, N, gx, gy) && !(ax[lx] && ay[ly]);
     const int64_t g = (int64_t)gy * n1 + gx;
     double b = 0.0, x = 0.0;
     if (mk) {
@@ -317,7 +336,7 @@ __global__ __launch_bounds__(NTS) void k_mg_down(const ProbDev* probs, int l, do
 // or of the coarse node it coincides with), then x = y^ + omega D^-1 (b - A y^) and
 // out = x + omega D^-1 (b - A x) on the owned nodes.  With dot (level m): the block partials
 // (w.z, w.w) of b = w and z = out.
-template <int KIND>
+template <int KIND, int TT>
 __global__ __launch_bounds__(NTS) void k_mg_up(const ProbDev* probs, int l, double* vec,
                                                int64_t stride, int64_t b_off, int64_t y_off,
                                                int64_t xc_off, int64_t out_off, int dot,
@@ -325,17 +344,20 @@ __global__ __launch_bounds__(NTS) void k_mg_up(const ProbDev* probs, int l, doub
   const ProbDev& P = probs[0];
   const int i_rhs = blockIdx.y;
   if (scal_all[i_rhs * SKEL_NS + 5] != 0.0) return;  // converged: frozen
+  constexpr int TR = TT + 2 * TH, S2 = TT + 4, S1 = TT + 2;
   __shared__ double sb[TR * TR], sx[TR * TR], sy[TR * TR];
-  __shared__ unsigned char sm[TR * TR];
+  __shared__ unsigned char sm[TR * TR], ax[TR], ay[TR];
   const int N = P.n_c << l, n1 = N + 1, r = 1 << l, nc1 = (N >> 1) + 1;
   const int tiles_x = (n1 + TT - 1) / TT;
   const int ox = (int)(blockIdx.x % tiles_x) * TT - TH, oy = (int)(blockIdx.x / tiles_x) * TT - TH;
   double* base = vec + (int64_t)i_rhs * stride;
   const double* Xc = base + xc_off;
+  stage_axes<TR>(P, N, r, ox, oy, ax, ay);
+  __syncthreads();
   for (int t = threadIdx.x; t < S2 * S2; t += NTS) {
     const int lx = 1 + t % S2, ly = 1 + t / S2, li = ly * TR + lx;
     const int gx = ox + lx, gy = oy + ly;
-    const bool mk = skel_dof(P, N, r, gx, gy);
+    const bool mk = is_dof(P.domain, N, gx, gy) && !(ax[lx] && ay[ly]);
     double yh = 0.0, b = 0.0;
     if (mk) {
       const int64_t g = (int64_t)gy * n1 + gx;
@@ -592,8 +614,14 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
                                 double* parts, double* scal, double* rec, hipStream_t s) {
   auto nodes_of = [&](int l) { return (int64_t)((nc << l) + 1) * ((nc << l) + 1); };
   auto grid_of = [&](int l) { return dim3((unsigned)((nodes_of(l) + NTS - 1) / NTS), (unsigned)q); };
+  // tile side per level: 32 when that gives at least 8 workgroups per compute unit
+  auto tile_side = [&](int l) {
+    const int64_t t = ((nc << l) + 1 + 31) / 32;
+    return t * t * q >= 2048 ? 32 : 16;
+  };
   auto tiles_of = [&](int l) {
-    const unsigned t = (unsigned)(((nc << l) + 1 + TT - 1) / TT);
+    const int tt = tile_side(l);
+    const unsigned t = (unsigned)(((nc << l) + 1 + tt - 1) / tt);
     return dim3(t * t, (unsigned)q);
   };
   const int64_t nnm = nodes_of(m);
@@ -605,6 +633,24 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
   };
   const unsigned nblk = (unsigned)((nnm + NTS - 1) / NTS);
   const unsigned ntile = tiles_of(m).x;
+#define MLC_LEG(K, l, ...)                                                                \
+  do {                                                                                    \
+    if (tile_side(l) == 32)                                                               \
+      MLC_SKEL2(K, 32, tiles_of(l), __VA_ARGS__);                                         \
+    else                                                                                  \
+      MLC_SKEL2(K, 16, tiles_of(l), __VA_ARGS__);                                         \
+  } while (0)
+#define MLC_SKEL2(K, T, G, ...)                                                           \
+  do {                                                                                    \
+    if (kind == 0)                                                                        \
+      hipLaunchKernelGGL((K<0, T>), G, dim3(NTS), 0, s, __VA_ARGS__);                     \
+    else if (kind == 1)                                                                   \
+      hipLaunchKernelGGL((K<1, T>), G, dim3(NTS), 0, s, __VA_ARGS__);                     \
+    else if (kind == 2)                                                                   \
+      hipLaunchKernelGGL((K<2, T>), G, dim3(NTS), 0, s, __VA_ARGS__);                     \
+    else                                                                                  \
+      hipLaunchKernelGGL((K<3, T>), G, dim3(NTS), 0, s, __VA_ARGS__);                     \
+  } while (0)
   const dim3 g(nblk, (unsigned)q);
 #define MLC_SKEL(K, G, B, L, ...)                                                         \
   do {                                                                                    \
@@ -648,13 +694,13 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
     }
     for (int l = m; l >= 2; --l) {
       const bool top = l == m;
-      MLC_SKEL(k_mg_down, tiles_of(l), NTS, 0, dprob, l, vec, stride, top ? w_off : off(l, 0),
+      MLC_LEG(k_mg_down, l, dprob, l, vec, stride, top ? w_off : off(l, 0),
                top ? V_Y * nnm : off(l, 1), off(l - 1, 0), top ? upd : 0, wn_off, p_off, scal);
     }
     coarse(1, off(1, 0), off(1, 1), off(1, 2));
     for (int l = 2; l <= m; ++l) {
       const bool top = l == m;
-      MLC_SKEL(k_mg_up, tiles_of(l), NTS, 0, dprob, l, vec, stride, top ? wz : off(l, 0),
+      MLC_LEG(k_mg_up, l, dprob, l, vec, stride, top ? wz : off(l, 0),
                top ? V_Y * nnm : off(l, 1), off(l - 1, 2), top ? V_Z * nnm : off(l, 2),
                top ? 1 : 0, parts, scal);
     }
@@ -690,6 +736,8 @@ hipError_t run_interface_gluing(int kind, const ProbDev* dprob, const TileItem* 
     if (all) break;
   }
 #undef MLC_SKEL
+#undef MLC_SKEL2
+#undef MLC_LEG
   hipLaunchKernelGGL(k_skel_finish, g, dim3(NTS), 0, s, dprob, m, vec, stride, scal, rec);
   return hipGetLastError();
 }

@@ -376,7 +376,9 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     L.skel = L.skel_parts = L.skel_scal = L.skel_rec = 0;
     if (g.pou == MLC_POU_INTERFACE) {  // vectors of the G_{m+1} problem and its V-cycle
       L.skel = take((size_t)skel_stride(g.nc, g.L) * q * 8);
-      L.skel_parts = take(((nnL + 255) / 256) * 2 * q * 8);
+      // block partials: one per 256 nodes, or per tile of 16 x 16 nodes (at least as many)
+      const size_t t16 = ((size_t)g.N(g.L) + 1 + 15) / 16;
+      L.skel_parts = take(t16 * t16 * 2 * q * 8);
       L.skel_scal = take(8 * q * 8);
       L.skel_rec = take((MLC_MAX_LEVELS + 1) * 2 * 8);  // per step: iterations, relres
     }

@@ -19,7 +19,7 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
 // Algorithm 4.1 step 2 as stated (MLC_POU_INTERFACE), single problem: u~ from the tile
 // solutions on the closed G_j and a global CG on the rest, preconditioned by a multigrid
 // V-cycle on that region (vec: skel_stride(nc, L) doubles per right-hand side, parts: 2 per
-// 256 nodes of level m per right-hand side, scal: 8 doubles per right-hand side, rec: 2
+// 16 x 16 nodes (rounded up per side) of level m per right-hand side, scal: 8 doubles per right-hand side, rec: 2
 // doubles that receive the maximum over right-hand sides of the iterations and of the final
 // ||r|| / ||r_0||).  poll: stop when every right-hand side has converged (the stream is
 // synchronised every 4 iterations to read the flags) or after max_it iterations; otherwise
