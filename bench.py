@@ -227,7 +227,10 @@ def bench_batch(args):
     bs.close()
     opts_t = B.default_opts(precision=1, timing=1)
     bt = B.BatchSolver(probs, opts_t)
-    bt.setup()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.setup()   # again, with the kernels already loaded
+    setup_warm_ms = (time.perf_counter() - t0) * 1e3
     bt.set_blocks(blocks)
     bt.phase_times()
     bt.run(use_graph=False)
@@ -242,7 +245,7 @@ def bench_batch(args):
                    "fine_dofs_all_levels": dofs, "precision": "mixed", "graph": True,
                    "blocks_per_step": blocks},
         "lambda_rel_err_vs_oracle": err,
-        "setup_ms": setup_ms,
+        "setup_ms": setup_warm_ms, "setup_first_call_ms": setup_ms,
         "local_solve": {"ms_all_steps": ph[0], "ms_all_steps_total": ph[1]},
     }
     print(json.dumps(out), flush=True)

@@ -5,40 +5,71 @@
 // call (nor its workspace allocation) is involved.
 //
 //   1. Cholesky M_H = L L^T (right-looking, column by column);
-//   2. C = L^-1 K_H L^-T by two forward substitutions (one thread per column), symmetrised;
-//   3. cyclic Jacobi on C with the round-robin ordering: each round rotates n/2 disjoint
-//      index pairs at once (Golub and Van Loan's symmetric Schur step, tan of the smaller
-//      rotation angle), the rotations applied to C in 2 x 2 blocks of pair rows and pair
-//      columns and accumulated in W; sweeps until no pair has |C_pq| above 1e-16
-//      sqrt(|C_pp C_qq|);
+//   2. C = L^-1 K_H L^-T by two forward substitutions (one thread per column), symmetrised
+//      and padded with decoupled zero rows to n2 = a multiple of 32 (eig_padded);
+//   3. block Jacobi on C: the n2 indices form nb blocks of 16, and a round pairs the blocks
+//      by the round-robin ordering.  For each block pair the 32 x 32 diagonal block S is
+//      staged in LDS and swept once by scalar cyclic Jacobi (round-robin pairs, Golub and
+//      Van Loan's symmetric Schur step with the tan of the smaller angle; a pair rotates
+//      when |S_pq| > 1e-16 sqrt(|S_pp S_qq|)), accumulating its rotations in Q (32 x 32).
+//      The round's Q then act on the whole matrix in three streaming passes,
+//      Y = (C Q)^T, C = Y Q (= Q^T C Q, C being symmetric) and W = W Q, each a 32-wide
+//      product per row and block pair.  Sweeps (nb - 1 rounds) repeat until one applies no
+//      rotation.  A pass over C and W covers 16 scalar rounds' worth of rotations, so the
+//      traffic per sweep is that of about nb scalar rounds instead of n2;
 //   4. Lambda = diag(C) sorted ascending, V = L^-T W (back substitution).
-// C, W and L live in a scratch area of the problem (3 (n+1)^2 doubles); K_H is read from
-// Kc and V written there (column-major), Lambda to Lam, 0 to info -- the layout the
-// rocSOLVER path leaves.  The cost is O(n^3) per sweep on one compute unit, so the host
-// sends only coarse spaces up to MLC_JACOBI_MAX_NH here.
+// L, C, W and Y live in a scratch area of the problem (eig_scratch_doubles(n)); K_H is read
+// from Kc and V written there (column-major), Lambda to Lam, 0 to info -- the layout the
+// rocSOLVER path leaves.  The host sends only coarse spaces up to MLC_JACOBI_MAX_NH here.
 #include "mlc_launch.h"
 
 namespace {
 
 constexpr int NTE = 1024;
+constexpr int BJ = 16;        // indices per Jacobi block
+constexpr int PB = 2 * BJ;    // indices of a block pair
+constexpr int QB = PB * PB;   // doubles of a staged 32 x 32 block
+constexpr int kMaxPairs = eig_padded(MLC_JACOBI_MAX_NH) / PB;
 constexpr double kJacobiRtol = 1e-16;
 constexpr int kMaxSweeps = 60;
+// dynamic LDS: the round's Q of every block pair, then the S of a group of pairs swept
+// together (as many as fit)
+constexpr int kLdsBlocks = 19;  // 152 KiB of 32 x 32 doubles
+static_assert(kMaxPairs < kLdsBlocks, "the Q of every block pair must fit in LDS");
 
-__global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs) {
+// Round-robin pairing of m slots (m even), round r: slot 0 fixed, slots 1..m-1 rotate;
+// pair k couples slot k with slot m-1-k.  Returns the smaller slot in *p, the larger in *q.
+__device__ __forceinline__ void rr_pair(int m, int r, int k, int* p, int* q) {
+  const int a = k, b = m - 1 - k;
+  const int p0 = a == 0 ? 0 : (a - 1 + r) % (m - 1) + 1;
+  const int q0 = (b - 1 + r) % (m - 1) + 1;
+  *p = min(p0, q0);
+  *q = max(p0, q0);
+}
+
+// Matrix index of local index a (0..31) of the block pair (bp, bq).
+__device__ __forceinline__ int pair_index(int bp, int bq, int a) {
+  return a < BJ ? bp * BJ + a : bq * BJ + (a - BJ);
+}
+
+__global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs, int lds_blocks) {
   const ProbDev& P = probs[blockIdx.x];
   if (!P.eig_ws) return;  // this problem's coarse space goes to rocSOLVER
   const int n = P.nH;
-  const int n2 = n + (n & 1);  // even: the round-robin pairs every index once per round
-  const int h = n2 / 2;
+  const int n2 = eig_padded(n);
+  const int nb = n2 / BJ, np = nb / 2;
+  const int group = min(np, lds_blocks - np);  // block pairs swept together
   const int tid = threadIdx.x;
-  double* L = P.eig_ws;               // n x n, row-major, lower triangle
-  double* C = L + (int64_t)n * n;     // n2 x n2, row-major
-  double* W = C + (int64_t)n2 * n2;   // n2 x n2, row-major
-  const double* K = P.Kc;             // symmetric: row-major = column-major
+  double* L = P.eig_ws;              // n x n, row-major, lower triangle
+  double* C = L + (int64_t)n * n;    // n2 x n2, row-major
+  double* W = C + (int64_t)n2 * n2;  // n2 x n2, row-major
+  double* Y = W + (int64_t)n2 * n2;  // n2 x n2, row-major
+  const double* K = P.Kc;            // symmetric: row-major = column-major
   const double* M = P.Mc;
-  __shared__ double s_c[MLC_JACOBI_MAX_NH / 2 + 1], s_s[MLC_JACOBI_MAX_NH / 2 + 1],
-      s_t[MLC_JACOBI_MAX_NH / 2 + 1];
-  __shared__ int s_p[MLC_JACOBI_MAX_NH / 2 + 1], s_q[MLC_JACOBI_MAX_NH / 2 + 1];
+  extern __shared__ double eig_lds[];
+  double* Qs = eig_lds;                    // [np][32 x 32], row-major
+  double* Ss = eig_lds + (int64_t)np * QB;  // [group][32 x 32]
+  __shared__ double s_c[kMaxPairs * BJ], s_s[kMaxPairs * BJ], s_t[kMaxPairs * BJ];
   __shared__ int s_changed;
   __shared__ double s_piv;
 
@@ -61,17 +92,17 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs) {
     }
     __syncthreads();
   }
-  // 2. X = L^-1 K (into W, row-major), then C = L^-1 X^T, symmetrised
+  // 2. X = L^-1 K (into Y, row-major), then C = L^-1 X^T, symmetrised and padded
   for (int j = tid; j < n; j += NTE)
     for (int i = 0; i < n; ++i) {
       double x = K[(int64_t)i * n + j];
-      for (int k = 0; k < i; ++k) x -= L[(int64_t)i * n + k] * W[(int64_t)k * n2 + j];
-      W[(int64_t)i * n2 + j] = x / L[(int64_t)i * n + i];
+      for (int k = 0; k < i; ++k) x -= L[(int64_t)i * n + k] * Y[(int64_t)k * n2 + j];
+      Y[(int64_t)i * n2 + j] = x / L[(int64_t)i * n + i];
     }
   __syncthreads();
   for (int j = tid; j < n; j += NTE)  // column j of X^T is row j of X
     for (int i = 0; i < n; ++i) {
-      double x = W[(int64_t)j * n2 + i];
+      double x = Y[(int64_t)j * n2 + i];
       for (int k = 0; k < i; ++k) x -= L[(int64_t)i * n + k] * C[(int64_t)k * n2 + j];
       C[(int64_t)i * n2 + j] = x / L[(int64_t)i * n + i];
     }
@@ -87,79 +118,134 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs) {
   __syncthreads();
   for (int e = tid; e < n2 * n2; e += NTE) {
     const int i = e / n2, j = e % n2;
-    if (i >= n || j >= n) C[e] = 0.0;  // the padding index stays decoupled
+    if (i >= n || j >= n) C[e] = 0.0;  // the padding indices stay decoupled
     W[e] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
 
-  // 3. cyclic Jacobi, round-robin ordering
+  // 3. block Jacobi
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) s_changed = 0;
     __syncthreads();
-    for (int r = 0; r < n2 - 1; ++r) {
-      for (int k = tid; k < h; k += NTE) {
-        // slot 0 fixed, slots 1..n2-1 rotate by r; pair slot k with slot n2-1-k
-        const int a = k, b = n2 - 1 - k;
-        const int p0 = a == 0 ? 0 : (a - 1 + r) % (n2 - 1) + 1;
-        const int q0 = (b - 1 + r) % (n2 - 1) + 1;
-        const int p = min(p0, q0), q = max(p0, q0);
-        const double app = C[(int64_t)p * n2 + p], aqq = C[(int64_t)q * n2 + q];
-        const double apq = C[(int64_t)p * n2 + q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (apq != 0.0 && fabs(apq) > kJacobiRtol * sqrt(fabs(app * aqq))) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          s_changed = 1;
+    for (int br = 0; br < nb - 1; ++br) {
+      // sweep the diagonal block of every block pair once, a group of pairs at a time
+      for (int g0 = 0; g0 < np; g0 += group) {
+        const int gn = min(group, np - g0);
+        for (int e = tid; e < gn * QB; e += NTE) {
+          const int g = e / QB, a = (e % QB) / PB, b = e % PB;
+          int bp, bq;
+          rr_pair(nb, br, g0 + g, &bp, &bq);
+          const int ia = pair_index(bp, bq, a), ib = pair_index(bp, bq, b);
+          Ss[e] = 0.5 * (C[(int64_t)ia * n2 + ib] + C[(int64_t)ib * n2 + ia]);
+          Qs[(int64_t)(g0 + g) * QB + a * PB + b] = a == b ? 1.0 : 0.0;
         }
-        s_p[k] = p;
-        s_q[k] = q;
-        s_c[k] = c;
-        s_s[k] = s;
-        s_t[k] = t;
-      }
-      __syncthreads();
-      // C <- J^T C J on 2 x 2 blocks (pair rows k1, pair columns k2 >= k1; the mirrored
-      // block is written from the same values), W <- W J
-      for (int e = tid; e < h * h; e += NTE) {
-        const int k1 = e / h, k2 = e % h;
-        if (k2 < k1) continue;
-        const int p1 = s_p[k1], q1 = s_q[k1], p2 = s_p[k2], q2 = s_q[k2];
-        const double c1 = s_c[k1], sn1 = s_s[k1], c2 = s_c[k2], sn2 = s_s[k2];
-        if (k1 == k2) {
-          const double t = s_t[k1];
-          const double apq = C[(int64_t)p1 * n2 + q1];
-          C[(int64_t)p1 * n2 + p1] -= t * apq;
-          C[(int64_t)q1 * n2 + q1] += t * apq;
-          C[(int64_t)p1 * n2 + q1] = t != 0.0 ? 0.0 : apq;
-          C[(int64_t)q1 * n2 + p1] = t != 0.0 ? 0.0 : apq;
-          continue;
+        __syncthreads();
+        for (int r = 0; r < PB - 1; ++r) {
+          for (int e = tid; e < gn * BJ; e += NTE) {
+            const int g = e / BJ, k = e % BJ;
+            int p, q;
+            rr_pair(PB, r, k, &p, &q);
+            const double* S = Ss + (int64_t)g * QB;
+            const double app = S[p * PB + p], aqq = S[q * PB + q], apq = S[p * PB + q];
+            double c = 1.0, s = 0.0, t = 0.0;
+            if (apq != 0.0 && fabs(apq) > kJacobiRtol * sqrt(fabs(app * aqq))) {
+              const double tau = (aqq - app) / (2.0 * apq);
+              t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              c = 1.0 / sqrt(1.0 + t * t);
+              s = t * c;
+              s_changed = 1;
+            }
+            s_c[e] = c;
+            s_s[e] = s;
+            s_t[e] = t;
+          }
+          __syncthreads();
+          // S <- J^T S J on 2 x 2 blocks of pair rows k1 and pair columns k2 >= k1 (the
+          // mirrored block written from the same values); Q <- Q J
+          constexpr int NBLK = BJ * (BJ + 1) / 2;
+          for (int e = tid; e < gn * (NBLK + PB * BJ); e += NTE) {
+            const int g = e / (NBLK + PB * BJ), f = e % (NBLK + PB * BJ);
+            double* S = Ss + (int64_t)g * QB;
+            const double* cc = s_c + g * BJ;
+            const double* ss = s_s + g * BJ;
+            if (f < NBLK) {
+              int k1 = 0, rem = f;  // f-th pair (k1, k2 >= k1) in row order
+              while (rem >= BJ - k1) {
+                rem -= BJ - k1;
+                ++k1;
+              }
+              const int k2 = k1 + rem;
+              int p1, q1, p2, q2;
+              rr_pair(PB, r, k1, &p1, &q1);
+              rr_pair(PB, r, k2, &p2, &q2);
+              const double c1 = cc[k1], sn1 = ss[k1];
+              if (k1 == k2) {
+                const double t = s_t[g * BJ + k1];
+                const double apq = S[p1 * PB + q1];
+                S[p1 * PB + p1] -= t * apq;
+                S[q1 * PB + q1] += t * apq;
+                S[p1 * PB + q1] = t != 0.0 ? 0.0 : apq;
+                S[q1 * PB + p1] = t != 0.0 ? 0.0 : apq;
+                continue;
+              }
+              const double c2 = cc[k2], sn2 = ss[k2];
+              const double a = S[p1 * PB + p2], b = S[p1 * PB + q2];
+              const double d = S[q1 * PB + p2], h = S[q1 * PB + q2];
+              const double t00 = c1 * a - sn1 * d, t01 = c1 * b - sn1 * h;
+              const double t10 = sn1 * a + c1 * d, t11 = sn1 * b + c1 * h;
+              const double n00 = c2 * t00 - sn2 * t01, n01 = sn2 * t00 + c2 * t01;
+              const double n10 = c2 * t10 - sn2 * t11, n11 = sn2 * t10 + c2 * t11;
+              S[p1 * PB + p2] = n00;
+              S[p1 * PB + q2] = n01;
+              S[q1 * PB + p2] = n10;
+              S[q1 * PB + q2] = n11;
+              S[p2 * PB + p1] = n00;
+              S[q2 * PB + p1] = n01;
+              S[p2 * PB + q1] = n10;
+              S[q2 * PB + q1] = n11;
+            } else {
+              const int i = (f - NBLK) / BJ, k = (f - NBLK) % BJ;
+              int p, q;
+              rr_pair(PB, r, k, &p, &q);
+              double* Q = Qs + (int64_t)(g0 + g) * QB;
+              const double c = cc[k], s = ss[k];
+              const double wp = Q[i * PB + p], wq = Q[i * PB + q];
+              Q[i * PB + p] = c * wp - s * wq;
+              Q[i * PB + q] = s * wp + c * wq;
+            }
+          }
+          __syncthreads();
         }
-        const double a = C[(int64_t)p1 * n2 + p2], b = C[(int64_t)p1 * n2 + q2];
-        const double d = C[(int64_t)q1 * n2 + p2], f = C[(int64_t)q1 * n2 + q2];
-        const double t00 = c1 * a - sn1 * d, t01 = c1 * b - sn1 * f;
-        const double t10 = sn1 * a + c1 * d, t11 = sn1 * b + c1 * f;
-        const double n00 = c2 * t00 - sn2 * t01, n01 = sn2 * t00 + c2 * t01;
-        const double n10 = c2 * t10 - sn2 * t11, n11 = sn2 * t10 + c2 * t11;
-        C[(int64_t)p1 * n2 + p2] = n00;
-        C[(int64_t)p1 * n2 + q2] = n01;
-        C[(int64_t)q1 * n2 + p2] = n10;
-        C[(int64_t)q1 * n2 + q2] = n11;
-        C[(int64_t)p2 * n2 + p1] = n00;
-        C[(int64_t)q2 * n2 + p1] = n01;
-        C[(int64_t)p2 * n2 + q1] = n10;
-        C[(int64_t)q2 * n2 + q1] = n11;
       }
-      for (int e = tid; e < n2 * h; e += NTE) {
-        const int i = e / h, k = e % h;
-        const int p = s_p[k], q = s_q[k];
-        const double c = s_c[k], s = s_s[k];
-        const double wp = W[(int64_t)i * n2 + p], wq = W[(int64_t)i * n2 + q];
-        W[(int64_t)i * n2 + p] = c * wp - s * wq;
-        W[(int64_t)i * n2 + q] = s * wp + c * wq;
+      // apply the round's rotations: Y = (C Q)^T and W = W Q, then C = Y Q.  A task is one
+      // row and one block pair: 32 values in, 32 out (lanes take consecutive rows)
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int task = tid; task < 2 * np * n2; task += NTE) {
+          const int which = task / (np * n2);  // pass 0: 0 = C -> Y^T, 1 = W; pass 1: C = Y Q
+          if (pass == 1 && which == 1) break;
+          const int k = (task % (np * n2)) / n2, i = task % n2;
+          int bp, bq;
+          rr_pair(nb, br, k, &bp, &bq);
+          const double* src = pass == 1 ? Y : (which == 0 ? C : W);
+          double* dst = pass == 1 ? C : W;
+          const double* Q = Qs + (int64_t)k * QB;
+          double v[PB];
+#pragma unroll
+          for (int a = 0; a < PB; ++a) v[a] = src[(int64_t)i * n2 + pair_index(bp, bq, a)];
+#pragma unroll 4
+          for (int j = 0; j < PB; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < PB; ++a) acc += v[a] * Q[a * PB + j];
+            const int ij = pair_index(bp, bq, j);
+            if (pass == 0 && which == 0)
+              Y[(int64_t)ij * n2 + i] = acc;
+            else
+              dst[(int64_t)i * n2 + ij] = acc;
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     if (s_changed == 0) break;
     __syncthreads();
@@ -178,21 +264,21 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs) {
     P.Lam[rank] = di;
   }
   __syncthreads();
-  // back substitution L^T v = w for every eigenvector, one thread per column; C holds the
-  // results row-major (its eigenvalues have been read)
+  // back substitution L^T v = w for every eigenvector, one thread per column; Y holds the
+  // results row-major
   for (int r = tid; r < n; r += NTE) {
     const int src = s_perm[r];
     for (int i = n - 1; i >= 0; --i) {
       double v = W[(int64_t)i * n2 + src];
-      for (int k = i + 1; k < n; ++k) v -= L[(int64_t)k * n + i] * C[(int64_t)k * n2 + r];
-      C[(int64_t)i * n2 + r] = v / L[(int64_t)i * n + i];
+      for (int k = i + 1; k < n; ++k) v -= L[(int64_t)k * n + i] * Y[(int64_t)k * n2 + r];
+      Y[(int64_t)i * n2 + r] = v / L[(int64_t)i * n + i];
     }
   }
   __syncthreads();
   double* V = P.Kc;
   for (int e = tid; e < n * n; e += NTE) {
     const int r = e / n, i = e % n;  // column r, row i
-    V[e] = C[(int64_t)i * n2 + r];
+    V[e] = Y[(int64_t)i * n2 + r];
   }
   if (tid == 0) *P.info = 0;
 }
@@ -200,6 +286,7 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs) {
 }  // namespace
 
 hipError_t launch_coarse_eig(const ProbDev* probs, int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_eig, dim3(nprob), dim3(NTE), 0, s, probs);
+  const size_t lds = (size_t)kLdsBlocks * QB * sizeof(double);
+  hipLaunchKernelGGL(k_coarse_eig, dim3(nprob), dim3(NTE), lds, s, probs, kLdsBlocks);
   return hipGetLastError();
 }

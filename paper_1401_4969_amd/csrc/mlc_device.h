@@ -18,6 +18,17 @@
 #define MLC_MAX_TILE_COARSE_ALL 1024  // larger ones (up to this) in HBM
 #define MLC_MAX_CAND 8
 #define MLC_JACOBI_MAX_NH 400       // coarse spaces up to this size are decomposed on the device
+// The device eigensolver pads the order to an even number of Jacobi blocks of 16, and its
+// scratch per problem is L (n x n) and three n2 x n2 matrices.
+__host__ __device__ constexpr int eig_padded(int n) {
+  int nb = (n + 15) / 16;
+  nb += nb & 1;
+  return nb * 16;
+}
+__host__ __device__ inline int64_t eig_scratch_doubles(int n) {
+  const int64_t n2 = eig_padded(n);
+  return (int64_t)n * n + 3 * n2 * n2;
+}
 
 // Per-problem device record.  Pointers are into the caller's workspace.
 struct ProbDev {

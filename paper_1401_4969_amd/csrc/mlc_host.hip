@@ -500,13 +500,13 @@ mlc_status make_plan(int32_t n, const mlc_problem_desc* descs, const mlc_solver_
     T.v0grid = take((size_t)(g.nc + 1) * (g.nc + 1) * 8);
   }
   // the device eigensolver of setup works in the local-solve store (unused until the
-  // first step): n_H^2 + 2 (n_H + 1)^2 doubles per problem it handles
+  // first step): eig_scratch_doubles(n_H) per problem it handles
   size_t eig_bytes = 0;
   for (int i = 0; i < n; ++i) {
     const int nH = P.geo[i].nH;
     if (nH > MLC_JACOBI_MAX_NH) continue;
     P.pl[i].eig_off = (int64_t)eig_bytes;
-    eig_bytes = align_up(eig_bytes + ((size_t)nH * nH + 2 * (size_t)(nH + 1) * (nH + 1)) * 8);
+    eig_bytes = align_up(eig_bytes + (size_t)eig_scratch_doubles(nH) * 8);
   }
   store_bytes = std::max(store_bytes, eig_bytes);
   P.store_bytes = store_bytes;

@@ -297,6 +297,45 @@ def test_mixed_precision_matches_oracle(factory):
     assert max(s["refine_max"] for s in stats) >= 2   # the refinement loop did its job
 
 
+@pytest.mark.parametrize("domain,nc", [(0, 2), (0, 6), (1, 8), (0, 17), (1, 22), (0, 21)])
+def test_device_coarse_eigensolver(domain, nc):
+    """Algorithm 4.2 step 1 by the device block Jacobi, for coarse spaces of 1, 25, 33, 256,
+    320 and 400 nodes (orders padded to 32, 32, 64, 256, 320 and 416: one to thirteen block
+    pairs, the largest swept in three groups): the level-0 eigenpairs (up to eight) equal a
+    dense generalized eigensolve of the oracle's coarse matrices, eigenvalues to 1e-12 and
+    signed vectors node by node to 1e-9 of max |u|."""
+    import scipy.linalg as sla
+    _torch()
+    from paper_1401_4969_amd import binding as B
+    from oracle import fem
+    from oracle.mlc import sign_normalise
+    rng = np.random.Generator(np.random.PCG64(500 + 10 * domain + nc))
+    kap = W.loguniform_coarse_kappa(nc, rng)
+    mesh = fem.make_mesh(domain, nc, 1.0 if domain == 0 else 2.0, 0.0 if domain == 0 else -1.0)
+    K, M = fem.assemble(mesh, fem.triangle_kappa(mesh, 1, kap, nc))
+    d = mesh.dof
+    K = K.tocsr()[d][:, d].toarray()
+    M = M.tocsr()[d][:, d].toarray()
+    nH = len(d)
+    assert nH <= 400
+    q = min(8, nH)
+    lam_ref, V = sla.eigh(K, M, subset_by_index=[0, q - 1])
+    V = sign_normalise(V)
+    prob = W.Problem(domain, nc, 1, 1, 1, 0, q, 1, kap, f"eig_{domain}_{nc}", pou=1)
+    s = B.Solver(prob)
+    s.coarse_setup()
+    lam, u = s.eigenpairs()
+    assert np.max(np.abs(lam - lam_ref) / lam_ref) < 1e-12, (lam, lam_ref)
+    Ug = u.cpu().numpy().reshape(q, -1)[:, d].T
+    gaps = np.diff(lam_ref) / lam_ref[1:]
+    for k in range(q):
+        if (k > 0 and gaps[k - 1] < 1e-3) or (k < q - 1 and gaps[k] < 1e-3):
+            continue  # a cluster: the basis is not unique
+        err = np.max(np.abs(Ug[:, k] - V[:, k])) / np.max(np.abs(V[:, k]))
+        assert err < 1e-9, (k, err)
+    s.close()
+
+
 @pytest.mark.parametrize("overlap", [0, 1, 2])
 @pytest.mark.parametrize("which", ["square", "lshape_q2", "field"])
 def test_indicator_gluing(which, overlap):
