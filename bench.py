@@ -198,7 +198,8 @@ def bench_batch(args):
     bs.setup()   # Algorithm 4.2 step 1 for all problems (synchronises)
     setup_ms = (time.perf_counter() - t0) * 1e3
     blocks = bs.autotune()
-    print(f"[bench] c4: autotuned blocks per step {blocks}", file=sys.stderr, flush=True)
+    tuning = bs.tuning()
+    print(f"[bench] c4: autotuned per step {tuning}", file=sys.stderr, flush=True)
     for _ in range(max(args.warmup, 1)):
         bs.restart()
         bs.run(use_graph=True)
@@ -231,7 +232,7 @@ def bench_batch(args):
     t0 = time.perf_counter()
     bt.setup()   # again, with the kernels already loaded
     setup_warm_ms = (time.perf_counter() - t0) * 1e3
-    bt.set_blocks(blocks)
+    bt.set_tuning(tuning)
     bt.phase_times()
     bt.run(use_graph=False)
     ph = bt.phase_times()
@@ -243,7 +244,8 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "c4_batch_256_problems", "problems": len(probs),
                    "fine_dofs_all_levels": dofs, "precision": "mixed", "graph": True,
-                   "blocks_per_step": blocks},
+                   "blocks_per_step": blocks, "nu_per_step": tuning["nu"],
+                   "inner_rtol_per_step": tuning["inner_rtol"]},
         "lambda_rel_err_vs_oracle": err,
         "setup_ms": setup_warm_ms, "setup_first_call_ms": setup_ms,
         "local_solve": {"ms_all_steps": ph[0], "ms_all_steps_total": ph[1]},

@@ -309,19 +309,35 @@ mlc_status mlc_batch_get(mlc_batch* b, int32_t i, double* lambda_host, double* u
  * step, n_dofs the interior nodes of all problems at that step, lambda[] unused. */
 mlc_status mlc_batch_step_stats(mlc_batch* b, mlc_level_stats* st);
 
-/* Autotuner: for every step, time the local-solve launch with 256, 512 and 1024 threads
- * per workgroup (HIP events, three full runs from level 0 each, the median per step) and
- * keep the fastest; blocks_out (may be NULL) receives the choice per step (index s-1, n
- * entries).  The choice is cached in a text file (MLC_AUTOTUNE_CACHE, else
- * $HOME/.cache/mlc_autotune.txt; one line per key) under a key of the device architecture
- * and a hash of what decides the launches (element order, coefficient kind, precision, q,
- * nu, every item's subdomain shape); a later call with the same key, in any process, takes
- * the cached choice without timing.  Leaves the batch at step 0.  Synchronises. */
+/* Autotuner: per step, the workgroup size of the local solves (256, 512 or 1024 threads),
+ * nu (1..3) and, with mixed precision, the inner FP32 tolerance (1e-3, 1e-4, 1e-5), by a
+ * coordinate search: the sizes at the batch's nu and tolerance, then nu at the chosen
+ * sizes, then the tolerance.  Each candidate is timed over three full runs from level 0
+ * (HIP events around the local-solve launches, the median per step); every setting
+ * solves to the same rtol, so the choice changes only the time (and rounding).
+ * blocks_out (may be NULL) receives the sizes per step (index s-1, n entries); see
+ * mlc_batch_get_tuning for the rest.  The choice is cached in a text file
+ * (MLC_AUTOTUNE_CACHE, else $HOME/.cache/mlc_autotune.txt; one line per key, "block nu
+ * inner_rtol" per step) under a key of the device architecture and a hash of what decides
+ * the launches (element order, coefficient kind, precision, q, the created nu and inner
+ * tolerance, every item's subdomain shape); a later call with the same key, in any
+ * process, takes the cached choice without timing.  Leaves the batch at step 0.
+ * Synchronises. */
 mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n);
 
 /* Use these workgroup sizes per step (index s-1; 256, 512 or 1024), e.g. a cached
  * autotuner result.  Drops captured graphs. */
 mlc_status mlc_batch_set_blocks(mlc_batch* b, const int32_t* blocks, int32_t n);
+
+/* The per-step settings of the local solves (index s-1, up to n steps; any output may be
+ * NULL): workgroup size, nu, inner FP32 tolerance (used with mixed precision). */
+mlc_status mlc_batch_get_tuning(const mlc_batch* b, int32_t* blocks, int32_t* nu,
+                                double* inner_rtol, int32_t n);
+
+/* Set them (e.g. an autotuner result of another batch): MLC_EINVAL unless every step has
+ * block 256, 512 or 1024, nu in 1..8 and inner_rtol in (0, 1).  Drops captured graphs. */
+mlc_status mlc_batch_set_tuning(mlc_batch* b, const int32_t* blocks, const int32_t* nu,
+                                const double* inner_rtol, int32_t n);
 
 /* As mlc_phase_times, for steps run without graphs. */
 mlc_status mlc_batch_phase_times(mlc_batch* b, double* ms, int32_t n);

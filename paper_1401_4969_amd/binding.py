@@ -29,6 +29,7 @@ EXPORTS = [
     "mlc_backward", "mlc_hf_gradient", "mlc_batch_workspace_size", "mlc_batch_create", "mlc_batch_setup", "mlc_batch_step",
     "mlc_batch_run", "mlc_batch_rewind", "mlc_batch_restart", "mlc_batch_current_step", "mlc_batch_get",
     "mlc_batch_step_stats", "mlc_batch_autotune", "mlc_batch_set_blocks",
+    "mlc_batch_get_tuning", "mlc_batch_set_tuning",
     "mlc_batch_phase_times", "mlc_batch_destroy", "mlc_batch_last_error", "mlc_solve_static",
 ]
 
@@ -116,6 +117,10 @@ def load_library() -> C.CDLL:
     lib.mlc_batch_step_stats.argtypes = [P, C.POINTER(LevelStats)]
     lib.mlc_batch_autotune.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
     lib.mlc_batch_set_blocks.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    lib.mlc_batch_get_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double), C.c_int32]
+    lib.mlc_batch_set_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double), C.c_int32]
     lib.mlc_batch_phase_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
     lib.mlc_batch_destroy.argtypes = [P]
     lib.mlc_solve_static.argtypes = [C.POINTER(ProblemDesc), C.POINTER(SolverOpts), P,
@@ -496,6 +501,20 @@ class BatchSolver:
     def set_blocks(self, blocks: List[int]):
         arr = (C.c_int32 * len(blocks))(*blocks)
         self._check(self.lib.mlc_batch_set_blocks(self.b, arr, len(blocks)), "mlc_batch_set_blocks")
+
+    def tuning(self) -> dict:
+        """Per-step local-solve settings: lists of blocks, nu and inner_rtol."""
+        n = self.n_steps
+        bl, nu, tol = (C.c_int32 * n)(), (C.c_int32 * n)(), (C.c_double * n)()
+        self._check(self.lib.mlc_batch_get_tuning(self.b, bl, nu, tol, n), "mlc_batch_get_tuning")
+        return {"blocks": list(bl), "nu": list(nu), "inner_rtol": list(tol)}
+
+    def set_tuning(self, tuning: dict):
+        n = len(tuning["blocks"])
+        bl = (C.c_int32 * n)(*tuning["blocks"])
+        nu = (C.c_int32 * n)(*tuning["nu"])
+        tol = (C.c_double * n)(*tuning["inner_rtol"])
+        self._check(self.lib.mlc_batch_set_tuning(self.b, bl, nu, tol, n), "mlc_batch_set_tuning")
 
     def phase_times(self) -> List[float]:
         ms = (C.c_double * 2)()

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <array>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <mutex>
 #include <sstream>
@@ -529,6 +530,8 @@ struct mlc_batch {
   bool can_rewind = false;
   std::vector<int> shift;     // per problem: eigenvector buffer = (level + shift) & 1
   std::vector<int> blocks;    // workgroup size of the local solves per step (index s)
+  std::vector<int> nu_s;      // damped Jacobi sweeps per step (index s)
+  std::vector<double> inner_s;  // mixed precision: inner FP32 tolerance per step (index s)
   std::vector<hipGraphExec_t> graphs;  // per step
   std::vector<hipGraph_t> graph_defs;
   hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
@@ -601,6 +604,8 @@ mlc_status batch_create(int32_t n, const mlc_problem_desc* descs, const mlc_solv
   char* w = b->ws;
   b->shift.assign(n, 0);
   b->blocks.assign(P.Lmax + 1, o->block ? o->block : 1024);
+  b->nu_s.assign(P.Lmax + 1, o->nu);
+  b->inner_s.assign(P.Lmax + 1, o->inner_rtol);
   b->graphs.assign(P.Lmax + 1, nullptr);
   b->graph_defs.assign(P.Lmax + 1, nullptr);
   b->kappa.resize(n);
@@ -817,17 +822,18 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, bool
   if (p2) {
     MLC_HIP(b, launch_local_p2(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
-                               b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, T.max_tile_nx, st));
+                               b->o.rtol, b->o.max_it, b->nu_s[s], b->o.omega, T.max_tile_nx,
+                               st));
   } else if (P.precision == 0) {
     MLC_HIP(b, launch_local_pcg(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                 (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
-                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 0, T.max_tile_nx,
-                                st));
+                                b->o.rtol, b->o.max_it, b->nu_s[s], b->o.omega, 0,
+                                T.max_tile_nx, st));
   } else {
     MLC_HIP(b, launch_local_mixed(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                   (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
-                                  b->o.rtol, b->o.max_it, b->o.max_refine, b->o.inner_rtol,
-                                  b->o.nu, b->o.omega, T.max_tile_nx, st));
+                                  b->o.rtol, b->o.max_it, b->o.max_refine, b->inner_s[s],
+                                  b->nu_s[s], b->o.omega, T.max_tile_nx, st));
   }
   if (timing) MLC_HIP(b, hipEventRecord(ev[2], st));
   if (P.geo[0].pou == MLC_POU_INTERFACE) {  // single problem (checked at plan time)
@@ -1022,11 +1028,18 @@ mlc_status phase_times(mlc_batch* b, double* ms, int32_t n) {
   return MLC_OK;
 }
 
-// ---- autotuner cache: one line per batch signature, "<key> <block per step>..." ----
+// ---- autotuner: per step the workgroup size, nu and (mixed precision) the inner FP32
+// tolerance of the local solves; cache lines "<key> <block nu inner_rtol per step>..." ----
 
-// The device architecture and a hash (FNV-1a) of everything that decides the local-solve
-// launches of every step: element order, coefficient kind, precision, q, nu, and each
-// item's subdomain shape.  Two batches with the same key launch the same work.
+struct Tuning {
+  int block, nu;
+  double inner;
+};
+
+// The device architecture, the cache format and a hash (FNV-1a) of everything that
+// decides the local-solve work of every step: element order, coefficient kind, precision,
+// q, the nu and inner tolerance the batch was created with, and each item's subdomain
+// shape.  Two batches with the same key launch the same work.
 std::string tune_key(const mlc_batch* b) {
   int dev = 0;
   hipDeviceProp_t prop;
@@ -1045,6 +1058,9 @@ std::string tune_key(const mlc_batch* b) {
   mix(P.precision);
   mix(P.q);
   mix(b->o.nu);
+  int64_t bits;
+  std::memcpy(&bits, &b->o.inner_rtol, sizeof bits);
+  mix(P.precision ? bits : 0);
   mix(P.Lmax);
   for (int s = 1; s <= P.Lmax; ++s) {
     mix((int64_t)P.steps[s].items.size());
@@ -1058,7 +1074,7 @@ std::string tune_key(const mlc_batch* b) {
     if (c == ' ' || c == ':') c = '_';
   char buf[32];
   std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
-  return arch + "/" + buf;
+  return arch + "/t2/" + buf;
 }
 
 // MLC_AUTOTUNE_CACHE, else $HOME/.cache/mlc_autotune.txt; empty: no cache.
@@ -1068,17 +1084,23 @@ std::string tune_cache_path() {
   return std::string();
 }
 
+bool valid_tuning(const Tuning& t) {
+  return (t.block == 256 || t.block == 512 || t.block == 1024) && t.nu >= 1 && t.nu <= 8 &&
+         t.inner > 0.0 && t.inner < 1.0;
+}
+
 bool tune_cache_read(const std::string& path, const std::string& key, int L,
-                     std::vector<int>& choice) {
+                     std::vector<Tuning>& choice) {
   std::ifstream f(path);
   std::string line;
   while (std::getline(f, line)) {
     std::istringstream in(line);
     std::string k;
     if (!(in >> k) || k != key) continue;
-    std::vector<int> v(L + 1, 1024);
+    std::vector<Tuning> v(L + 1, Tuning{1024, 2, 1e-4});
     bool ok = true;
-    for (int s = 1; s <= L && ok; ++s) ok = (bool)(in >> v[s]) && (v[s] == 256 || v[s] == 512 || v[s] == 1024);
+    for (int s = 1; s <= L && ok; ++s)
+      ok = (bool)(in >> v[s].block >> v[s].nu >> v[s].inner) && valid_tuning(v[s]);
     if (ok) {
       choice = v;
       return true;
@@ -1088,7 +1110,7 @@ bool tune_cache_read(const std::string& path, const std::string& key, int L,
 }
 
 void tune_cache_write(const std::string& path, const std::string& key, int L,
-                      const std::vector<int>& choice) {
+                      const std::vector<Tuning>& choice) {
   std::vector<std::string> keep;
   {
     std::ifstream f(path);
@@ -1101,7 +1123,8 @@ void tune_cache_write(const std::string& path, const std::string& key, int L,
   }
   std::ostringstream o;
   o << key;
-  for (int s = 1; s <= L; ++s) o << ' ' << choice[s];
+  o.precision(17);
+  for (int s = 1; s <= L; ++s) o << ' ' << choice[s].block << ' ' << choice[s].nu << ' ' << choice[s].inner;
   keep.push_back(o.str());
   const size_t slash = path.find_last_of('/');
   if (slash != std::string::npos) {
@@ -1572,22 +1595,31 @@ mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n) {
     return MLC_ESTATE;
   }
   const Plan& P = b->plan;
-  std::vector<int> choice(P.Lmax + 1, 1024);
+  const Tuning base{b->blocks[1], b->o.nu, b->o.inner_rtol};
+  std::vector<Tuning> choice(P.Lmax + 1, base);
   const std::string key = tune_key(b);
   const std::string path = tune_cache_path();
   bool cached = !key.empty() && !path.empty() && tune_cache_read(path, key, P.Lmax, choice);
   if (!cached) {
-    // every candidate: kReps full runs from level 0, per step the median local-solve time
-    const int cand[3] = {256, 512, 1024};
+    // Coordinate search, each candidate timed over kReps full runs from level 0 (per step
+    // the median local-solve time): the workgroup size at the batch's nu and tolerance;
+    // then nu in 1..3 at the chosen sizes; then (mixed precision) the inner tolerance
+    // 1e-3 .. 1e-5 at the chosen sizes and nu.  Every setting solves to the same rtol.
     constexpr int kReps = 3;
     std::vector<double> best(P.Lmax + 1, 1e300);
     const int saved_timing = b->o.timing;
     b->o.timing = 1;
     drop_graphs(b);
     mlc_status e = phase_times(b, nullptr, 0);  // drop stale events
-    for (int c = 0; c < 3 && e == MLC_OK; ++c) {
-      std::fill(b->blocks.begin(), b->blocks.end(), cand[c]);
-      std::vector<std::vector<double>> t(P.Lmax + 1);
+    auto trial = [&](auto&& set) {
+      std::vector<Tuning> t = choice;
+      for (int s = 1; s <= P.Lmax; ++s) set(t[s]);
+      for (int s = 1; s <= P.Lmax; ++s) {
+        b->blocks[s] = t[s].block;
+        b->nu_s[s] = t[s].nu;
+        b->inner_s[s] = t[s].inner;
+      }
+      std::vector<std::vector<double>> ms_s(P.Lmax + 1);
       for (int rep = 0; rep < kReps && e == MLC_OK; ++rep) {
         if (launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st) != hipSuccess) {
           b->err = "launch_init_u0 failed";
@@ -1600,31 +1632,71 @@ mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n) {
           e = batch_step(b, 0);
           double ms[2] = {0.0, 0.0};
           if (e == MLC_OK) e = phase_times(b, ms, 2);
-          t[s].push_back(ms[0]);
+          ms_s[s].push_back(ms[0]);
         }
       }
       for (int s = 1; s <= P.Lmax && e == MLC_OK; ++s) {
-        std::vector<double> v = t[s];
+        std::vector<double> v = ms_s[s];
         std::sort(v.begin(), v.end());
         const double med = v[v.size() / 2];
         if (med < best[s]) {
           best[s] = med;
-          choice[s] = cand[c];
+          choice[s] = t[s];
         }
       }
-    }
+    };
+    for (int blk : {256, 512, 1024})
+      if (e == MLC_OK) trial([&](Tuning& t) { t = Tuning{blk, base.nu, base.inner}; });
+    for (int nu : {1, 2, 3})
+      if (e == MLC_OK && nu != base.nu) trial([&](Tuning& t) { t.nu = nu; });
+    if (P.precision == 1)
+      for (double tol : {1e-3, 1e-4, 1e-5})
+        if (e == MLC_OK && tol != base.inner) trial([&](Tuning& t) { t.inner = tol; });
     b->o.timing = saved_timing;
     if (e != MLC_OK) return e;
     if (!key.empty() && !path.empty()) tune_cache_write(path, key, P.Lmax, choice);
   }
-  for (int s = 1; s <= P.Lmax; ++s) b->blocks[s] = choice[s];
-  for (int s = 1; s <= P.Lmax && blocks_out && s - 1 < n; ++s) blocks_out[s - 1] = choice[s];
+  for (int s = 1; s <= P.Lmax; ++s) {
+    b->blocks[s] = choice[s].block;
+    b->nu_s[s] = choice[s].nu;
+    b->inner_s[s] = choice[s].inner;
+  }
+  for (int s = 1; s <= P.Lmax && blocks_out && s - 1 < n; ++s) blocks_out[s - 1] = choice[s].block;
   drop_graphs(b);
   MLC_HIP(b, launch_init_u0(b->dprob, P.n, 0, P.max_nc1sq, b->st));
   MLC_HIP(b, hipStreamSynchronize(b->st));
   b->step = 0;
   b->can_rewind = false;
   std::fill(b->shift.begin(), b->shift.end(), 0);
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_get_tuning(const mlc_batch* b, int32_t* blocks, int32_t* nu,
+                                double* inner_rtol, int32_t n) {
+  if (!b || n < 0) return MLC_EINVAL;
+  for (int s = 1; s <= b->plan.Lmax && s - 1 < n; ++s) {
+    if (blocks) blocks[s - 1] = b->blocks[s];
+    if (nu) nu[s - 1] = b->nu_s[s];
+    if (inner_rtol) inner_rtol[s - 1] = b->inner_s[s];
+  }
+  return MLC_OK;
+}
+
+mlc_status mlc_batch_set_tuning(mlc_batch* b, const int32_t* blocks, const int32_t* nu,
+                                const double* inner_rtol, int32_t n) {
+  if (!b || !blocks || !nu || !inner_rtol) return MLC_EINVAL;
+  for (int s = 1; s <= b->plan.Lmax && s - 1 < n; ++s) {
+    if (!valid_tuning(Tuning{blocks[s - 1], nu[s - 1], inner_rtol[s - 1]})) {
+      b->err = "tuning: block 256, 512 or 1024, nu in 1..8, inner_rtol in (0, 1)";
+      return MLC_EINVAL;
+    }
+  }
+  for (int s = 1; s <= b->plan.Lmax && s - 1 < n; ++s) {
+    b->blocks[s] = blocks[s - 1];
+    b->nu_s[s] = nu[s - 1];
+    b->inner_s[s] = inner_rtol[s - 1];
+  }
+  drop_graphs(b);
   return MLC_OK;
 }
 

@@ -203,22 +203,47 @@ def test_interface_gluing_graph_steps():
         s.close()
 
 
-def test_autotune_choices_and_results():
-    _torch()
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_choices_and_results(precision, tmp_path, monkeypatch):
+    """The autotuner picks, per step, a workgroup size, nu in 1..3 and (mixed precision) an
+    inner tolerance among 1e-3 .. 1e-5; every choice solves to rtol, so the results match
+    the oracle to 1e-10; the tuning transfers to another batch of the same problems, whose
+    results are then bitwise those of the tuned batch."""
+    torch = _torch()
     from paper_1401_4969_amd import binding as B
+    monkeypatch.setenv("MLC_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     probs = _small_batch(1, 1)
-    bs = B.BatchSolver(probs)
+    opts = B.default_opts(precision=precision)
+    bs = B.BatchSolver(probs, opts)
     bs.setup()
     blocks = bs.autotune()
-    assert len(blocks) == bs.n_steps and all(b in (256, 512, 1024) for b in blocks)
+    t = bs.tuning()
+    assert t["blocks"] == blocks and all(b in (256, 512, 1024) for b in blocks)
+    assert len(blocks) == bs.n_steps and all(v in (1, 2, 3) for v in t["nu"])
+    if precision:
+        assert all(v in (1e-3, 1e-4, 1e-5) for v in t["inner_rtol"])
+    else:
+        assert all(v == opts.inner_rtol for v in t["inner_rtol"])
     assert bs.current_step == 0
     bs.run()
+    res = [bs.get(i) for i in range(len(probs))]
     for i, p in enumerate(probs):
-        lam, _ = bs.get(i, with_vectors=False)
         ref = oracle_solve(p)
-        assert np.allclose(lam, ref.lam, rtol=1e-10, atol=0)
+        assert np.allclose(res[i][0], ref.lam, rtol=1e-10, atol=0)
+    other = B.BatchSolver(probs, opts)
+    other.setup()
+    other.set_tuning(t)
+    assert other.tuning() == t
+    other.run()
+    for i in range(len(probs)):
+        lam, u = other.get(i)
+        assert np.array_equal(lam, res[i][0]) and torch.equal(u, res[i][1])
+    with pytest.raises(B.MLCError) as e:
+        other.set_tuning(dict(t, nu=[0] * len(blocks)))
+    assert e.value.status == B.MLC_EINVAL
     bs.set_blocks(blocks)
     bs.close()
+    other.close()
 
 
 def test_batch_mixed_gluing():
@@ -324,7 +349,8 @@ def test_autotune_cache_across_processes(tmp_path, monkeypatch):
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     key, *vals = lines[0].split()
-    assert key.startswith("gfx") and [int(v) for v in vals] == blocks
+    assert key.startswith("gfx") and len(vals) == 3 * len(blocks)
+    assert [int(v) for v in vals[0::3]] == blocks
     # another process: the cached choice comes back without timing
     code = ("import sys; sys.path.insert(0, %r); import workloads as W\n"
             "from test_gpu_batch import _small_batch\n"
