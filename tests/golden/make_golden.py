@@ -9,7 +9,7 @@ nodes; and for configuration 5, central differences of the
 finest eigenvalue along seeded kappa directions and with respect to 32 seeded single
 cells (checks of the reverse sweep).
 
-    python tests/golden/make_golden.py [c1 c2 c3 c5 c2iface ex62 c2p2 c3p2 c4 c4_vectors c5_fd c5_cells ...]
+    python tests/golden/make_golden.py [c1 c2 c3 c5 c2iface c3iface ex62 c2p2 c3p2 c4 c4_vectors c5_fd c5_cells ...]
 """
 import json
 import os
@@ -31,6 +31,7 @@ CONFIGS = {
     "c3": W.config3,
     "c5": W.config5,
     "c2iface": lambda: W.config2().with_(pou=2, name="c2_iface"),
+    "c3iface": lambda: W.config3().with_(pou=2, name="c3_iface"),
     "ex62": lambda: W.example62(n_refine=5, sub=5, n_eig=6),
     "c2p2": W.config2_p2,
     "c3p2": W.config3_p2,
