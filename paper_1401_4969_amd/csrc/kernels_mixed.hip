@@ -12,6 +12,79 @@ namespace {
 // One band row per wave: taller bands' registers would crowd out the prefetching passes.
 constexpr int MIXED_MAX_ROWS = 1;
 
+// e += d and the FP64 residual r = b - K e of the updated correction in one banded pass:
+// the workgroup walks the tile in bands of NW rows with an LDS ring of NW + 2 FP64 rows
+// of e (rows -1 and ny zero, the Dirichlet values).  At step k wave w forms row
+// k NW + w - 1 of e + d (stored), and after a barrier the residual of the row above it
+// from the ring, stored in FP32 as the next inner solve's right-hand side with that
+// solve's iterate cleared; acc receives this thread's share of ||r||^2.  A ring row is
+// overwritten only after the barrier that follows its last reader.  Rows of at most
+// RING_CHUNKS * 64 nodes.
+template <int NT, int KIND>
+__device__ void refine_banded(const ProbDev& P, const LevelDesc& l0, double* E, float* X,
+                              float* R, const double* bglob, int n1, double* ring,
+                              double* acc) {
+  constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nch = (nx + 63) >> 6;
+  auto row = [&](int y) -> double* { return ring + ((y + 1) % RING) * nx; };
+  for (int k = 0; k * NW - 2 < ny; ++k) {
+    const int ya = k * NW + w - 1, yb = ya - 1;
+    const bool inA = ya >= 0 && ya < ny, inB = yb >= 0 && yb < ny;
+    double ev[CM], bv[CM];
+    float xv[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      if (c < nch) {
+        const int ix = lane + 64 * c;
+        const unsigned i = (inA && ix < nx) ? (unsigned)(ya * nx + ix) : 0u;
+        ev[c] = E[i];
+        xv[c] = X[i];
+        // b of the row the second stage takes (a node of the tile's first row otherwise)
+        const int bx = ix < nx ? ix : nx - 1, by = inB ? yb : 0;
+        bv[c] = bglob[(int64_t)(l0.gy0 + by) * n1 + (l0.gx0 + bx)];
+      }
+    }
+    if (ya >= -1 && ya <= ny) {
+      double* dst = row(ya);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) {
+          double v = 0.0;
+          if (inA) {
+            v = ev[c] + (double)xv[c];
+            E[(unsigned)(ya * nx + ix)] = v;
+          }
+          dst[ix] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (inB) {
+      const double* rs = row(yb - 1);
+      const double* rc = row(yb);
+      const double* rn = row(yb + 1);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) {
+          double r = 0.0;
+          if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + yb)) {
+            double d;
+            r = bv[c] - apply_rows<KIND, double>(P, l0, rs, rc, rn, ix, yb, d);
+          }
+          const unsigned i = (unsigned)(yb * nx + ix);
+          R[i] = (float)r;
+          X[i] = 0.0f;
+          *acc += r * r;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const TileItem* items,
                                                     char* store, const double* inv, int m,
@@ -58,13 +131,21 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     total += pcg_solve<NT, KIND, float, MIXED_MAX_ROWS>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
                                         max_it, nu, omega, red, ring, rows, tail,
                                         rr_inner);
+    acc[0] = acc[1] = 0.0;
+    if (rows && l0.nx <= 64 * RING_CHUNKS) {
+      // the ring space (three FP32 rings) holds the one FP64 ring of this pass
+      refine_banded<NT, KIND>(P, l0, E, X, R, bglob, n1, reinterpret_cast<double*>(ring_lds_f),
+                              &acc[0]);
+      block_sum<NT, 2>(acc, red);
+      rr = acc[0];
+      continue;
+    }
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
       E[i] += (double)X[i];
     }
     __syncthreads();
     // FP64 residual of the accumulated correction, handed to the next FP32 solve
-    acc[0] = acc[1] = 0.0;
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
       double r = 0.0;

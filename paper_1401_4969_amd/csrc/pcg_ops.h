@@ -1227,6 +1227,70 @@ __device__ void pass_dir(const ProbDev& P, const LevelDesc& l0, const T* Z, cons
   }
 }
 
+// p_new = z + beta p_old (stored) and this thread's share of p_new . A p_new, banded:
+// the workgroup walks the tile in bands of NW rows with one LDS ring of NW + 2 rows.  At
+// step k wave w forms row k NW + w - 1 of p_new from z and p_old (two loads per node, the
+// row's chunks issued together) into HBM and the ring, and after a barrier applies A to
+// the row above it (k NW + w - 2) from the ring, so A p_new takes no global gathers.
+// Rows -1 and ny of the ring hold zeros (the Dirichlet values); a ring row is overwritten
+// only after the barrier that follows its last reader.  Rows of at most RING_CHUNKS * 64
+// nodes.
+template <int NT, int KIND, typename T>
+__device__ void pass_dir_banded(const ProbDev& P, const LevelDesc& l0, const T* Z, const T* Po,
+                                T* Pn, T beta, bool first, T* ring, double* acc) {
+  constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nch = (nx + 63) >> 6;
+  const T bet = first ? T(0) : beta;
+  const T* Pold = first ? Z : Po;  // any valid vector: its values are multiplied by 0
+  auto row = [&](int y) -> T* { return ring + ((y + 1) % RING) * nx; };
+  for (int k = 0; k * NW - 2 < ny; ++k) {
+    const int ya = k * NW + w - 1, yb = ya - 1;
+    if (ya >= -1 && ya <= ny) {
+      const bool inA = ya >= 0 && ya < ny;
+      T zv[CM], pv[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        if (c < nch) {
+          const int ix = lane + 64 * c;
+          const unsigned i = (inA && ix < nx) ? (unsigned)(ya * nx + ix) : 0u;
+          zv[c] = Z[i];
+          pv[c] = Pold[i];
+        }
+      }
+      T* dst = row(ya);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) {
+          T v = T(0);
+          if (inA) {
+            v = zv[c] + bet * pv[c];
+            Pn[(unsigned)(ya * nx + ix)] = v;
+          }
+          dst[ix] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (yb >= 0 && yb < ny) {
+      const T* rs = row(yb - 1);
+      const T* rc = row(yb);
+      const T* rn = row(yb + 1);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx && is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + yb)) {
+          T d;
+          const T q = apply_rows<KIND, T>(P, l0, rs, rc, rn, ix, yb, d);
+          *acc += (double)rc[ix] * (double)q;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // The same two passes without pipelining: one chunk at a time.  With a variable
 // coefficient the edge-weight loads need the registers the pipelining would take.
 template <int NT, int KIND, typename T>
@@ -1309,7 +1373,9 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
       // p_new = z + beta p_old and p_new . A p_new, with A p_new formed from p_new at the
       // node and its neighbours
       acc[0] = acc[1] = 0.0;
-      if constexpr (KIND == 0)
+      if (ring != nullptr && l0.nx <= 64 * RING_CHUNKS)
+        pass_dir_banded<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, ring, &acc[0]);
+      else if constexpr (KIND == 0)
         pass_dir<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
       else
         pass_dir_plain<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
