@@ -117,7 +117,7 @@ typedef struct mlc_solver_opts {
   int32_t max_refine;  /* mixed precision: FP64 refinement steps (10) */
   double inner_rtol;   /* mixed precision: FP32 inner solve relative tolerance (1e-4) */
   int32_t nu;          /* damped Jacobi sweeps before and after each coarse correction (2) */
-  double omega;        /* Jacobi damping (0.8) */
+  double omega;        /* Jacobi damping (0.8) of every sweep with smoother 0, or with nu != 2 */
   int32_t block;       /* threads per workgroup of the local solver: 256, 512 or 1024 (0 = 1024) */
   int32_t timing;      /* 1: record HIP events around the local-solve kernel (see mlc_phase_times) */
   int32_t record_tape; /* 1: keep every level's forward state for mlc_backward (single problem,
@@ -128,6 +128,10 @@ typedef struct mlc_solver_opts {
                           converged by then makes the step's statistics and mlc_batch_run
                           report MLC_ENOCONV.  Eager steps iterate to convergence (at most
                           1000 iterations). */
+  int32_t smoother;    /* sweeps of the local solves' V-cycle with nu = 2: 1 (default) the two
+                          damping factors of the degree-2 Chebyshev polynomial of [1/2, 2]
+                          (1.3895, 0.5617; the part of the spectrum of D^-1 K that the coarse
+                          grid leaves), 0 damped Jacobi with omega for both */
 } mlc_solver_opts;
 
 /* Per-level statistics, filled by mlc_level_correct when st != NULL (this synchronises
@@ -176,7 +180,8 @@ mlc_status mlc_workspace_size(const mlc_problem_desc* desc, const mlc_solver_opt
  *   grid above 32768 intervals per side; problems of one batch with different order;
  *   options: NULL; precision not 0 or 1; rtol outside (0, 1); max_it < 1; nu outside
  *   1..8; omega outside (0, 1); mixed precision with max_refine < 1 or inner_rtol outside
- *   (0, 1); block not 0, 256, 512 or 1024; glue_graph_it outside 1..1000;
+ *   (0, 1); block not 0, 256, 512 or 1024; glue_graph_it outside 1..1000; smoother not 0
+ *   or 1;
  *   workspace: NULL or not 256-byte aligned (MLC_ENOMEM when smaller than needed). */
 mlc_status mlc_create(const mlc_problem_desc* desc, const mlc_solver_opts* opts,
                       void* dev_workspace, size_t workspace_bytes, void* hip_stream,

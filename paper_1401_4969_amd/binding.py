@@ -45,7 +45,8 @@ class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_it", C.c_int32),
                 ("max_refine", C.c_int32), ("inner_rtol", C.c_double), ("nu", C.c_int32),
                 ("omega", C.c_double), ("block", C.c_int32), ("timing", C.c_int32),
-                ("record_tape", C.c_int32), ("glue_graph_it", C.c_int32)]
+                ("record_tape", C.c_int32), ("glue_graph_it", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class LevelStats(C.Structure):

@@ -90,7 +90,8 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
                                                     char* store, const double* inv, int m,
                                                     ItemStat* stats, double rtol, int max_it,
                                                     int max_refine, double inner_rtol, int nu,
-                                                    double omega, int ring_cap, int ring_cap2) {
+                                                    double omega, double omega2, int ring_cap,
+                                                    int ring_cap2) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ float ring_lds_f[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     ++refine;
     double rr_inner;
     total += pcg_solve<NT, KIND, float, MIXED_MAX_ROWS>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
-                                        max_it, nu, omega, red, ring, rows, tail,
+                                        max_it, nu, omega, omega2, red, ring, rows, tail,
                                         rr_inner);
     acc[0] = acc[1] = 0.0;
     if (rows && l0.nx <= 64 * RING_CHUNKS) {
@@ -189,7 +190,7 @@ int64_t item_bytes_mixed(int cw, int ch, int m) {
 hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
-                              double omega, int max_tile_nx, hipStream_t s) {
+                              double omega, double omega2, int max_tile_nx, hipStream_t s) {
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
@@ -200,7 +201,7 @@ hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const Tile
 #define MLC_MIX(NTV, KV)                                                                     \
   hipLaunchKernelGGL((k_local_mixed<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
                      store, inv, m, stats, rtol, max_it, max_refine, inner_rtol, nu, omega,   \
-                     cap, cap2)
+                     omega2, cap, cap2)
 #define MLC_MIX_NT(NTV) \
   if (kind == 0)        \
     MLC_MIX(NTV, 0);    \

@@ -314,7 +314,7 @@ __device__ void pass_xr_p2(const LevelDesc& l0, double* X, double* R, const doub
 template <int NT, int KIND>
 __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, int mg,
                             const double* Kinv, double bb, double tol2, int max_it, int nu,
-                            double omega, double* red, double* ring, int ring_rows,
+                            double omega, double omega2, double* red, double* ring, int ring_rows,
                             double* tail, double& rr) {
   const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
@@ -348,7 +348,8 @@ __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, i
     }
     acc[0] = acc[1] = 0.0;
     const bool init = Z == nullptr;
-    Z = vcycle<NT, KIND, double, 2>(P, lev, base, mg, Kinv, nu, omega, &acc[0], ring, ring_rows,
+    Z = vcycle<NT, KIND, double, 2>(P, lev, base, mg, Kinv, nu, omega, omega2, &acc[0], ring,
+                                    ring_rows,
                                     tail);
     block_sum<NT, 2>(acc, red);
     if (init) {
@@ -369,7 +370,7 @@ template <int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_local_p2(const ProbDev* probs, const TileItem* items,
                                                   char* store, const double* inv, int m,
                                                   ItemStat* stats, double rtol, int max_it,
-                                                  int nu, double omega, int ring_cap,
+                                                  int nu, double omega, double omega2, int ring_cap,
                                                   int ring_cap2) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ double ring_lds_p2[];
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_local_p2(const ProbDev* probs, const Til
   double* tail =
       (rows && NT == 1024) ? ring_lds_p2 + ring_elems(NT / 64, ring_cap, ring_cap2) : nullptr;
   const int iters = pcg_solve_p2<NT, KIND>(P, lev, base, mg, inv + it.inv_off, bb,
-                                           rtol * rtol * bb, max_it, nu, omega, red, ring, rows,
+                                           rtol * rtol * bb, max_it, nu, omega, omega2, red, ring, rows,
                                            tail, rr);
   if (threadIdx.x == 0) {
     ItemStat s;
@@ -476,7 +477,8 @@ hipError_t launch_p2_coarse_matrices(int kind, const ProbDev* probs, int nprob, 
 
 hipError_t launch_local_p2(int kind, int nt, const ProbDev* probs, const TileItem* items,
                            int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                           double rtol, int max_it, int nu, double omega, int max_tile_nx,
+                           double rtol, int max_it, int nu, double omega, double omega2,
+                           int max_tile_nx,
                            hipStream_t s) {
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
@@ -484,7 +486,7 @@ hipError_t launch_local_p2(int kind, int nt, const ProbDev* probs, const TileIte
   const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, ntv == 1024, &lds, &cap2);
 #define MLC_LP2(NTV, KV)                                                                    \
   hipLaunchKernelGGL((k_local_p2<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items, \
-                     store, inv, m, stats, rtol, max_it, nu, omega, cap, cap2)
+                     store, inv, m, stats, rtol, max_it, nu, omega, omega2, cap, cap2)
 #define MLC_LP2_NT(NTV) \
   if (kind == 0)        \
     MLC_LP2(NTV, 0);    \

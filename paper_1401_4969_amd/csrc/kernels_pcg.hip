@@ -20,7 +20,8 @@ template <int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const TileItem* items,
                                                      char* store, const double* inv, int m,
                                                      ItemStat* stats, double rtol, int max_it,
-                                                     int nu, double omega, int rhs_in_tile,
+                                                     int nu, double omega, double omega2,
+                                                     int rhs_in_tile,
                                                      int ring_cap, int ring_cap2) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ double ring_lds[];  // banded smoothing rings (dynamic size)
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   // extra LDS costs no concurrency there)
   double* tail = (rows && NT == 1024) ? ring_lds + ring_elems(NT / 64, ring_cap, ring_cap2) : nullptr;
   const int iters = pcg_solve<NT, KIND, double, 2>(P, lev, base, m, inv + it.inv_off, bb,
-                                                rtol * rtol * bb, max_it, nu, omega, red, ring,
+                                                rtol * rtol * bb, max_it, nu, omega, omega2, red, ring,
                                                 rows, tail, rr);
   if (threadIdx.x == 0) {
     ItemStat s;
@@ -111,7 +112,8 @@ int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tai
 
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                            double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
+                            double rtol, int max_it, int nu, double omega, double omega2,
+                            int64_t rhs_in_tile,
                             int max_tile_nx, hipStream_t s) {
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
@@ -120,7 +122,7 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
   const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, ntv == 1024, &lds, &cap2);
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
-                     store, inv, m, stats, rtol, max_it, nu, omega, (int)rhs_in_tile,           \
+                     store, inv, m, stats, rtol, max_it, nu, omega, omega2, (int)rhs_in_tile,   \
                      cap, cap2)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \

@@ -41,13 +41,29 @@ hipError_t launch_p2_coarse_matrices(int kind, const ProbDev* probs, int nprob, 
                                      hipStream_t s);
 hipError_t launch_local_p2(int kind, int nt, const ProbDev* probs, const TileItem* items,
                            int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                           double rtol, int max_it, int nu, double omega, int max_tile_nx,
-                           hipStream_t s);
+                           double rtol, int max_it, int nu, double omega, double omega2,
+                           int max_tile_nx, hipStream_t s);
 
 namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kGlueMaxIt = 1000;  // eager G_{m+1} CG: iteration cap (MLC_ENOCONV beyond)
+
+// Damping of the first and second sweep of each smoothing pair of the local solves'
+// V-cycle.  smoother 1 with nu = 2: the reciprocals of the roots of the degree-2
+// Chebyshev polynomial of [1/2, 2], the part of the spectrum of D^-1 K that the coarse
+// grid does not reduce (D^-1 K lies in (0, 2] for these stencils, rows summing to zero off
+// the boundary), so the pair damps it by at most 1/T_2(5/3) = 0.22 instead of the 0.36 of
+// two sweeps at 0.8; otherwise (smoother 0, or nu != 2) omega for every sweep.
+void sweep_weights(const mlc_solver_opts& o, int nu, double* w1, double* w2) {
+  if (o.smoother == 1 && nu == 2) {
+    const double c = 1.25, d = 0.75 / std::sqrt(2.0);
+    *w1 = 1.0 / (c - d);
+    *w2 = 1.0 / (c + d);
+  } else {
+    *w1 = *w2 = o.omega;
+  }
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -93,6 +109,10 @@ mlc_status check_opts(const mlc_solver_opts* o, std::string& msg) {
   }
   if (o->block != 0 && o->block != 256 && o->block != 512 && o->block != 1024) {
     msg = "block must be 0, 256, 512 or 1024";
+    return MLC_EINVAL;
+  }
+  if (o->smoother != 0 && o->smoother != 1) {
+    msg = "smoother must be 0 (damped Jacobi) or 1 (Chebyshev weights)";
     return MLC_EINVAL;
   }
   if (o->glue_graph_it < 1 || o->glue_graph_it > 1000) {
@@ -819,21 +839,22 @@ mlc_status enqueue_step(mlc_batch* b, int s, int src, int dst, bool timing, bool
   else
     MLC_HIP(b, launch_prolong_residual(P.kind, b->dprob, P.n, s, src, T.max_nodes, P.q, st));
   if (timing) MLC_HIP(b, hipEventRecord(ev[1], st));
+  double w1, w2;
+  sweep_weights(b->o, b->nu_s[s], &w1, &w2);
   if (p2) {
     MLC_HIP(b, launch_local_p2(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
-                               b->o.rtol, b->o.max_it, b->nu_s[s], b->o.omega, T.max_tile_nx,
-                               st));
+                               b->o.rtol, b->o.max_it, b->nu_s[s], w1, w2, T.max_tile_nx, st));
   } else if (P.precision == 0) {
     MLC_HIP(b, launch_local_pcg(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                 (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
-                                b->o.rtol, b->o.max_it, b->nu_s[s], b->o.omega, 0,
-                                T.max_tile_nx, st));
+                                b->o.rtol, b->o.max_it, b->nu_s[s], w1, w2, 0, T.max_tile_nx,
+                                st));
   } else {
     MLC_HIP(b, launch_local_mixed(P.kind, b->blocks[s], b->dprob, items, nitems, w + P.store,
                                   (const double*)(w + P.inv), s, (ItemStat*)(w + P.stats),
                                   b->o.rtol, b->o.max_it, b->o.max_refine, b->inner_s[s],
-                                  b->nu_s[s], b->o.omega, T.max_tile_nx, st));
+                                  b->nu_s[s], w1, w2, T.max_tile_nx, st));
   }
   if (timing) MLC_HIP(b, hipEventRecord(ev[2], st));
   if (P.geo[0].pou == MLC_POU_INTERFACE) {  // single problem (checked at plan time)
@@ -1193,6 +1214,7 @@ mlc_status mlc_default_opts(mlc_solver_opts* o) {
   o->timing = 0;
   o->record_tape = 0;
   o->glue_graph_it = 24;
+  o->smoother = 1;
   return MLC_OK;
 }
 
@@ -1354,9 +1376,11 @@ static mlc_status backward_impl(mlc_batch* b, double lambda_bar, double* out, bo
                                 D(T.utbar), st));
     // adjoint local solves z_j = K_j^-1 (chi_j u~_bar)
     MLC_HIP(b, launch_adj_tile_rhs(dp, items, nitems, sub_item, w + P.store, m, D(T.utbar), st));
+    double w1, w2;
+    sweep_weights(b->o, b->o.nu, &w1, &w2);
     MLC_HIP(b, launch_local_pcg(g.kind, b->blocks[m], dp, items, nitems, w + P.store,
                                 (const double*)(w + P.inv), m, (ItemStat*)(w + P.stats),
-                                b->o.rtol, b->o.max_it, b->o.nu, b->o.omega, 1,
+                                b->o.rtol, b->o.max_it, b->o.nu, w1, w2, 1,
                                 P.steps[m].max_tile_nx, st));
     MLC_HIP(b, launch_adj_rbar(dp, items, sub_item, w + P.store, m, nn, D(T.rbar), st));
     const double* u_k = (k == 0) ? D(T.v0grid) : D(T.tu[k]);

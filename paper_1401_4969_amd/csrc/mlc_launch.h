@@ -10,12 +10,13 @@ hipError_t launch_prolong_residual(int kind, const ProbDev* probs, int nprob, in
                                    int64_t max_nodes, int max_q, hipStream_t s);
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
-                            double rtol, int max_it, int nu, double omega, int64_t rhs_in_tile,
+                            double rtol, int max_it, int nu, double omega, double omega2,
+                            int64_t rhs_in_tile,
                             int max_tile_nx, hipStream_t s);
 hipError_t launch_local_mixed(int kind, int nt, const ProbDev* probs, const TileItem* items,
                               int nitems, char* store, const double* inv, int m, ItemStat* stats,
                               double rtol, int max_it, int max_refine, double inner_rtol, int nu,
-                              double omega, int max_tile_nx, hipStream_t s);
+                              double omega, double omega2, int max_tile_nx, hipStream_t s);
 // Algorithm 4.1 step 2 as stated (MLC_POU_INTERFACE), single problem: u~ from the tile
 // solutions on the closed G_j and a global CG on the rest, preconditioned by a multigrid
 // V-cycle on that region (vec: skel_stride(nc, L) doubles per right-hand side, parts: 2 per

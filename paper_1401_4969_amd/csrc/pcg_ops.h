@@ -82,7 +82,8 @@ __device__ __forceinline__ double diag_at(const ProbDev& P, const LevelDesc& lv,
 }
 
 template <int NT, int KIND, typename T>
-__device__ void op_first2(const ProbDev& P, const LevelDesc& lv, const T* b, T* z, T omega) {
+__device__ void op_first2(const ProbDev& P, const LevelDesc& lv, const T* b, T* z, T omega,
+                          T omega2) {
   FOR_TILE(lv) {
     const unsigned i = (unsigned)(iy * lv.nx + ix);
     // first-sweep value at tile node (jx, jy) = index j, zero when `in` is false
@@ -112,7 +113,7 @@ __device__ void op_first2(const ProbDev& P, const LevelDesc& lv, const T* b, T* 
     }
     T dd;
     const T az = apply_k<KIND, T>(W, zc, ze, zw, zn, zs, zne, zsw, dd);
-    const T v = zc + omega * (bc - az) / d;
+    const T v = zc + omega2 * (bc - az) / d;
     z[i] = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + iy) ? v : T(0);
   }
 }
@@ -236,7 +237,7 @@ __device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, 
 // coefficients, or in FP32, the extra registers measured slower.)
 template <int NT, int KIND, typename T, int R, int CMP = 0>
 __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
-                             const T* b, T* za, T* bc, T omega, T* ring) {
+                             const T* b, T* za, T* bc, T omega, T omega2, T* ring) {
   constexpr int NW = NT / 64, BH = NW * R, RING = BH + 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = lv.nx, ny = lv.ny, ncx = lc.nx, ncy = lc.ny;
@@ -333,7 +334,7 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
               const int ix = lane + 64 * c;
               if (ix < nx) {
                 const unsigned i = (unsigned)(yb * nx + ix);
-                T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bb2[q][c], ix, yb, omega);
+                T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bb2[q][c], ix, yb, omega2);
                 v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
                 dst[ix] = v;
                 za[i] = v;
@@ -342,7 +343,7 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
           } else {
             for (int ix = lane; ix < nx; ix += 64) {
               const unsigned i = (unsigned)(yb * nx + ix);
-              T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega);
+              T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, b[i], ix, yb, omega2);
               v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
               dst[ix] = v;
               za[i] = v;
@@ -418,7 +419,8 @@ __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelD
 // interpolates from are staged in LDS during this step.
 template <int NT, int KIND, typename T, bool DOT, int R, int CMP = 0>
 __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
-                              const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
+                              const T* zc, const T* b, T* za, T omega, T omega2, T* ring,
+                              double* acc) {
   constexpr int NW = NT / 64, BH = NW * R, RING = BH + 2;
   constexpr int CP = CMP > 0 ? CMP : 1;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -598,7 +600,7 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
             if (ix < nx) {
               const unsigned i = (unsigned)(yc * nx + ix);
               const T bi = bb3[q][c];
-              const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega);
+              const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega2);
               const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
               za[i] = dof ? v : T(0);
               if (DOT && dof) *acc += (double)bi * (double)v;
@@ -609,7 +611,7 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
         for (int ix = lane; ix < nx; ix += 64) {
           const unsigned i = (unsigned)(yc * nx + ix);
           const T bi = b[i];
-          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega);
+          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bi, ix, yc, omega2);
           const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
           za[i] = dof ? v : T(0);
           if (DOT && dof) *acc += (double)bi * (double)v;
@@ -641,7 +643,7 @@ constexpr int RING_CHUNKS = 4;
 // follows its last reader.
 template <int NT, int KIND, typename T>
 __device__ void op_pre_fused_pf(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
-                             const T* b, T* za, T* bc, T omega, T* ring) {
+                             const T* b, T* za, T* bc, T omega, T omega2, T* ring) {
   constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = lv.nx, ny = lv.ny, ncx = lc.nx, ncy = lc.ny;
@@ -691,7 +693,7 @@ __device__ void op_pre_fused_pf(const ProbDev& P, const LevelDesc& lv, const Lev
         if (c < nch && ix < nx) {
           T v = T(0);
           if (inB) {
-            v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bB[c], ix, yb, omega);
+            v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bB[c], ix, yb, omega2);
             v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
             za[(unsigned)(yb * nx + ix)] = v;
           }
@@ -748,7 +750,8 @@ __device__ void op_pre_fused_pf(const ProbDev& P, const LevelDesc& lv, const Lev
 // sweeps.
 template <int NT, int KIND, typename T, bool DOT>
 __device__ void op_post_fused_pf(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
-                              const T* zc, const T* b, T* za, T omega, T* ring, double* acc) {
+                              const T* zc, const T* b, T* za, T omega, T omega2, T* ring,
+                              double* acc) {
   constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = lv.nx, ny = lv.ny;
@@ -821,7 +824,7 @@ __device__ void op_post_fused_pf(const ProbDev& P, const LevelDesc& lc, const Le
       for (int c = 0; c < CM; ++c) {
         const int ix = lane + 64 * c;
         if (c < nch && ix < nx) {
-          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bC[c], ix, yc, omega);
+          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bC[c], ix, yc, omega2);
           const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
           za[(unsigned)(yc * nx + ix)] = dof ? v : T(0);
           if (DOT && dof) *acc += (double)bC[c] * (double)v;
@@ -899,7 +902,8 @@ __device__ __forceinline__ bool tail_level(const LevelDesc& lv) {
 // thread's share of b.z to *rz.
 template <int NT, int KIND, typename T>
 __device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
-                            const double* Kinv, int nu, T omega, T* base, T* sm, double* rz) {
+                            const double* Kinv, int nu, T omega, T omega2, T* base, T* sm,
+                            double* rz) {
   auto loff = [&](int t) -> int {
     int o = 0;
     for (int u = t0; u < t; ++u) o += 3 * (int)lev.size(u);
@@ -921,12 +925,12 @@ __device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
     T* za = b + S;
     T* zb = za + S;
     if (nu >= 2)
-      op_first2<NT, KIND, T>(P, lv, b, za, omega);
+      op_first2<NT, KIND, T>(P, lv, b, za, omega, omega2);
     else
       op_first<NT, KIND, T>(P, lv, b, za, omega);
     __syncthreads();
     for (int s = 2; s < nu; ++s) {
-      op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+      op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega2);
       __syncthreads();
       T* tmp = za;
       za = zb;
@@ -955,10 +959,11 @@ __device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
     op_prolong_add<NT, T>(P, lev[t + 1], lv, zc, za);
     __syncthreads();
     for (int s = 0; s < nu; ++s) {
+      const T w = s == 0 ? omega : omega2;
       if (t == 0 && s == nu - 1)
-        op_jacobi<NT, KIND, T, true>(P, lv, b, za, zb, omega, rz);
+        op_jacobi<NT, KIND, T, true>(P, lv, b, za, zb, w, rz);
       else
-        op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+        op_jacobi<NT, KIND, T>(P, lv, b, za, zb, w);
       __syncthreads();
       T* tmp = za;
       za = zb;
@@ -983,7 +988,7 @@ __device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
 // the post-smoothing of every level run as one banded pass each.
 template <int NT, int KIND, typename T, int MAXR>
 __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
-                     int nu, T omega, double* rz, T* ring, int ring_rows, T* tail) {
+                     int nu, T omega, T omega2, double* rz, T* ring, int ring_rows, T* tail) {
   constexpr bool PREFETCH = sizeof(T) == 4 && KIND == 0;
   int tl = m + 1;  // first level handled in LDS (none when m + 1)
   if (tail != nullptr) {
@@ -1005,27 +1010,27 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
       constexpr bool PF64 = KIND == 0 && sizeof(T) == 8;
       if (MAXR >= 2 && ring_rows == 2) {
         if (PF64 && lv.nx <= 128)
-          op_pre_fused<NT, KIND, T, MAXR, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+          op_pre_fused<NT, KIND, T, MAXR, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
         else
-          op_pre_fused<NT, KIND, T, MAXR>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+          op_pre_fused<NT, KIND, T, MAXR>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       } else if (PF64 && lv.nx <= 128)
-        op_pre_fused<NT, KIND, T, 1, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+        op_pre_fused<NT, KIND, T, 1, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       else if (PF64 && lv.nx <= 256)
-        op_pre_fused<NT, KIND, T, 1, PF64 ? 4 : 0>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+        op_pre_fused<NT, KIND, T, 1, PF64 ? 4 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       else if (PREFETCH && lv.nx <= 64 * RING_CHUNKS)
-        op_pre_fused_pf<NT, KIND, T>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+        op_pre_fused_pf<NT, KIND, T>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       else
-        op_pre_fused<NT, KIND, T, 1>(P, lv, lev[t + 1], b, za, bc, omega, ring);
+        op_pre_fused<NT, KIND, T, 1>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       __syncthreads();
       continue;
     }
     if (nu >= 2)
-      op_first2<NT, KIND, T>(P, lv, b, za, omega);
+      op_first2<NT, KIND, T>(P, lv, b, za, omega, omega2);
     else
       op_first<NT, KIND, T>(P, lv, b, za, omega);
     __syncthreads();
     for (int s = 2; s < nu; ++s) {
-      op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+      op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega2);
       __syncthreads();
       T* tmp = za;
       za = zb;
@@ -1038,7 +1043,7 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
   }
   T* zc;
   if (tl <= m) {
-    vcycle_tail<NT, KIND, T>(P, lev, tl, m, Kinv, nu, omega, base, tail, rz);
+    vcycle_tail<NT, KIND, T>(P, lev, tl, m, Kinv, nu, omega, omega2, base, tail, rz);
     __syncthreads();
     zc = base + lev[tl].oz;
   } else {
@@ -1067,29 +1072,29 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
       if (MAXR >= 2 && ring_rows == 2) {
         if (PF64 && lv.nx <= 128) {
           if (t == 0)
-            op_post_fused<NT, KIND, T, true, MAXR, C2>(P, lc, lv, zc, b, za, omega, ring, rz);
+            op_post_fused<NT, KIND, T, true, MAXR, C2>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
           else
-            op_post_fused<NT, KIND, T, false, MAXR, C2>(P, lc, lv, zc, b, za, omega, ring,
+            op_post_fused<NT, KIND, T, false, MAXR, C2>(P, lc, lv, zc, b, za, omega, omega2, ring,
                                                         nullptr);
         } else if (t == 0)
-          op_post_fused<NT, KIND, T, true, MAXR>(P, lc, lv, zc, b, za, omega, ring, rz);
+          op_post_fused<NT, KIND, T, true, MAXR>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
         else
-          op_post_fused<NT, KIND, T, false, MAXR>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+          op_post_fused<NT, KIND, T, false, MAXR>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
       } else if (PF64 && lv.nx <= 256) {
         if (t == 0)
-          op_post_fused<NT, KIND, T, true, 1, C4>(P, lc, lv, zc, b, za, omega, ring, rz);
+          op_post_fused<NT, KIND, T, true, 1, C4>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
         else
-          op_post_fused<NT, KIND, T, false, 1, C4>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+          op_post_fused<NT, KIND, T, false, 1, C4>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
       } else if (pf) {
         if (t == 0)
-          op_post_fused_pf<NT, KIND, T, true>(P, lc, lv, zc, b, za, omega, ring, rz);
+          op_post_fused_pf<NT, KIND, T, true>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
         else
-          op_post_fused_pf<NT, KIND, T, false>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+          op_post_fused_pf<NT, KIND, T, false>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
       } else {
         if (t == 0)
-          op_post_fused<NT, KIND, T, true, 1>(P, lc, lv, zc, b, za, omega, ring, rz);
+          op_post_fused<NT, KIND, T, true, 1>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
         else
-          op_post_fused<NT, KIND, T, false, 1>(P, lc, lv, zc, b, za, omega, ring, nullptr);
+          op_post_fused<NT, KIND, T, false, 1>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
       }
       __syncthreads();
       zc = za;
@@ -1098,10 +1103,11 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     op_prolong_add<NT, T>(P, lev[t + 1], lv, zc, za);
     __syncthreads();
     for (int s = 0; s < nu; ++s) {
+      const T w = s == 0 ? omega : omega2;
       if (t == 0 && s == nu - 1)
-        op_jacobi<NT, KIND, T, true>(P, lv, b, za, zb, omega, rz);
+        op_jacobi<NT, KIND, T, true>(P, lv, b, za, zb, w, rz);
       else
-        op_jacobi<NT, KIND, T>(P, lv, b, za, zb, omega);
+        op_jacobi<NT, KIND, T>(P, lv, b, za, zb, w);
       __syncthreads();
       T* tmp = za;
       za = zb;
@@ -1347,7 +1353,8 @@ __device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R,
 // old one and the preconditioned residual while neighbours still read the old one).
 template <int NT, int KIND, typename T, int MAXR>
 __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
-                         double bb, double tol2, int max_it, int nu, double omega, double* red,
+                         double bb, double tol2, int max_it, int nu, double omega,
+                         double omega2, double* red,
                          T* ring, int ring_rows, T* tail, double& rr) {
   const LevelDesc l0 = lev[0];
   const int64_t S0 = (int64_t)l0.nx * l0.ny;
@@ -1355,7 +1362,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   T* R = base + l0.ob;
   T* Po = base + 4 * S0;
   T* Pn = base + 5 * S0;
-  const T om = T(omega);
+  const T om = T(omega), om2 = T(omega2);
   int iters = 0;
   rr = bb;
   if (!(bb > 0.0)) return 0;
@@ -1393,7 +1400,8 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
     }
     acc[0] = acc[1] = 0.0;
     const bool init = Z == nullptr;
-    Z = vcycle<NT, KIND, T, MAXR>(P, lev, base, m, Kinv, nu, om, &acc[0], ring, ring_rows, tail);
+    Z = vcycle<NT, KIND, T, MAXR>(P, lev, base, m, Kinv, nu, om, om2, &acc[0], ring, ring_rows,
+                                  tail);
     block_sum<NT, 2>(acc, red);
     if (init) {
       rho = acc[0];

@@ -190,7 +190,8 @@ def test_every_header_rejection_of_the_descriptor(bad):
 def test_every_header_rejection_of_the_options():
     for kw in (dict(max_it=0), dict(nu=9), dict(omega=0.0), dict(rtol=1.0),
                dict(precision=1, max_refine=0), dict(precision=1, inner_rtol=1.5),
-               dict(block=2048), dict(glue_graph_it=0), dict(glue_graph_it=1001)):
+               dict(block=2048), dict(glue_graph_it=0), dict(glue_graph_it=1001),
+               dict(smoother=2), dict(smoother=-1)):
         with pytest.raises(B.MLCError) as e:
             B.workspace_size(W.config1(), B.default_opts(**kw))
         assert e.value.status == B.MLC_EINVAL, kw
