@@ -453,6 +453,21 @@ def cpu_baseline(prob, serial_budget_s: float = 8.0, glue_sample: int = 16):
 LLC_BYTES = 256 * 2 ** 20   # MI355X last-level (Infinity) cache
 
 
+def autotuned_mixed_opts(prob, block):
+    """Mixed-precision options for one problem from the library's autotuner
+    (mlc_batch_autotune on a batch of this one problem): the workgroup size, nu and inner
+    FP32 tolerance it picks for the finest step, which the timed step is."""
+    from paper_1401_4969_amd import binding as B
+    bs = B.BatchSolver([prob], B.default_opts(precision=1, block=block))
+    bs.setup()
+    bs.autotune()
+    t = bs.tuning()
+    bs.close()
+    pick = {"block": t["blocks"][-1], "nu": t["nu"][-1], "inner_rtol": t["inner_rtol"][-1]}
+    print(f"[bench] {prob.name} mixed: autotuned finest step {pick}", file=sys.stderr, flush=True)
+    return B.default_opts(timing=1, precision=1, **pick), pick
+
+
 def run_steps(prob, opts, args):
     """Bring a solver to the finest level, then time args.steps repetitions of the last
     correction (HIP events on the library's stream; the library's own events around the
@@ -595,6 +610,9 @@ def main():
     lds_limit = getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", 65536)
     prob, okw = workload(args.workload)
     opts = B.default_opts(timing=1, block=args.block, **okw)
+    tuning = None
+    if opts.precision == 1:
+        opts, tuning = autotuned_mixed_opts(prob, args.block)
     ms_step, pcg_ms, st, lam = run_steps(prob, opts, args)
     n_dofs = st["n_dofs"]
     rl = roofline(prob, opts, st, pcg_ms, lds_limit)
@@ -635,12 +653,14 @@ def main():
                         "relres_max": st["relres_max"]},
         "roofline": rl,
     }
+    if tuning is not None:
+        out["config"]["tuning"] = dict(tuning, source="mlc_batch_autotune, finest step")
     if getattr(prob, "pou", 0) == 2:
         out["interface_problem"] = {"cg_iterations": st["glue_it"],
                                     "relres": st["glue_relres"]}
     if args.workload == "c3" and not args.no_mixed:
         # the same workload with FP32 inner solves and FP64 residual refinement
-        mopts = B.default_opts(timing=1, block=args.block, precision=1)
+        mopts, mtuning = autotuned_mixed_opts(prob, args.block)
         mms, mpcg, mst, mlam = run_steps(prob, mopts, args)
         mrl = roofline(prob, mopts, mst, mpcg, lds_limit)
         out["mixed"] = {
@@ -654,6 +674,7 @@ def main():
                             "refine_max": mst["refine_max"], "refine_dofs": mst["refine_dofs"],
                             "relres_max": mst["relres_max"]},
             "roofline": mrl,
+            "tuning": dict(mtuning, source="mlc_batch_autotune, finest step"),
         }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)

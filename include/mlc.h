@@ -315,7 +315,8 @@ mlc_status mlc_batch_get(mlc_batch* b, int32_t i, double* lambda_host, double* u
 mlc_status mlc_batch_step_stats(mlc_batch* b, mlc_level_stats* st);
 
 /* Autotuner: per step, the workgroup size of the local solves (256, 512 or 1024 threads),
- * nu (1..3) and, with mixed precision, the inner FP32 tolerance (1e-3, 1e-4, 1e-5), by a
+ * nu (1..3) and, with mixed precision, the inner FP32 tolerance (1e-3, 3e-4, 1e-4, 3e-5,
+ * 1e-5), by a
  * coordinate search: the sizes at the batch's nu and tolerance, then nu at the chosen
  * sizes, then the tolerance.  Each candidate is timed over three full runs from level 0
  * (HIP events around the local-solve launches, the median per step); every setting

@@ -1628,7 +1628,9 @@ mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n) {
     // Coordinate search, each candidate timed over kReps full runs from level 0 (per step
     // the median local-solve time): the workgroup size at the batch's nu and tolerance;
     // then nu in 1..3 at the chosen sizes; then (mixed precision) the inner tolerance
-    // 1e-3 .. 1e-5 at the chosen sizes and nu.  Every setting solves to the same rtol.
+    // 1e-3, 3e-4, .. 1e-5 at the chosen sizes and nu (the inner solves stop after whole
+    // iterations, so the best tolerance varies with the problem).  Every setting solves
+    // to the same rtol.
     constexpr int kReps = 3;
     std::vector<double> best(P.Lmax + 1, 1e300);
     const int saved_timing = b->o.timing;
@@ -1674,7 +1676,7 @@ mlc_status mlc_batch_autotune(mlc_batch* b, int32_t* blocks_out, int32_t n) {
     for (int nu : {1, 2, 3})
       if (e == MLC_OK && nu != base.nu) trial([&](Tuning& t) { t.nu = nu; });
     if (P.precision == 1)
-      for (double tol : {1e-3, 1e-4, 1e-5})
+      for (double tol : {1e-3, 3e-4, 1e-4, 3e-5, 1e-5})
         if (e == MLC_OK && tol != base.inner) trial([&](Tuning& t) { t.inner = tol; });
     b->o.timing = saved_timing;
     if (e != MLC_OK) return e;
