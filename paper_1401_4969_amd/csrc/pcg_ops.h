@@ -1297,6 +1297,66 @@ __device__ void pass_dir_banded(const ProbDev& P, const LevelDesc& l0, const T* 
   }
 }
 
+// x += alpha p, r -= alpha A p and this thread's share of ||r||^2, banded like
+// pass_dir_banded: at step k wave w stages row k NW + w - 1 of p in the ring and loads x
+// and r of the row above it, and after a barrier updates that row with A p from the ring
+// (three loads per node instead of seven).  Rows of at most RING_CHUNKS * 64 nodes.
+template <int NT, int KIND, typename T>
+__device__ void pass_xr_banded(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const T* Pn,
+                               T alpha, T* ring, double* acc) {
+  constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nch = (nx + 63) >> 6;
+  auto row = [&](int y) -> T* { return ring + ((y + 1) % RING) * nx; };
+  for (int k = 0; k * NW - 2 < ny; ++k) {
+    const int ya = k * NW + w - 1, yb = ya - 1;
+    const bool inA = ya >= 0 && ya < ny, inB = yb >= 0 && yb < ny;
+    T pv[CM], xv[CM], rv[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      if (c < nch) {
+        const int ix = lane + 64 * c;
+        const int jx = ix < nx ? ix : nx - 1;
+        pv[c] = Pn[inA ? (unsigned)(ya * nx + jx) : 0u];
+        const unsigned ib = inB ? (unsigned)(yb * nx + jx) : 0u;
+        xv[c] = X[ib];
+        rv[c] = R[ib];
+      }
+    }
+    if (ya >= -1 && ya <= ny) {
+      T* dst = row(ya);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) dst[ix] = inA ? pv[c] : T(0);
+      }
+    }
+    __syncthreads();
+    if (inB) {
+      const T* rs = row(yb - 1);
+      const T* rc = row(yb);
+      const T* rn = row(yb + 1);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) {
+          T q = T(0);
+          if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + yb)) {
+            T d;
+            q = apply_rows<KIND, T>(P, l0, rs, rc, rn, ix, yb, d);
+          }
+          const unsigned i = (unsigned)(yb * nx + ix);
+          X[i] = xv[c] + alpha * rc[ix];
+          const T r = rv[c] - alpha * q;
+          R[i] = r;
+          *acc += (double)r * (double)r;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // The same two passes without pipelining: one chunk at a time.  With a variable
 // coefficient the edge-weight loads need the registers the pipelining would take.
 template <int NT, int KIND, typename T>
@@ -1390,7 +1450,9 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
       const T alpha = T(rho / acc[0]);
       // x += alpha p, r -= alpha A p, ||r||^2
       acc[0] = acc[1] = 0.0;
-      if constexpr (KIND == 0)
+      if (ring != nullptr && l0.nx <= 64 * RING_CHUNKS)
+        pass_xr_banded<NT, KIND, T>(P, l0, X, R, Pn, alpha, ring, &acc[0]);
+      else if constexpr (KIND == 0)
         pass_xr<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
       else
         pass_xr_plain<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
