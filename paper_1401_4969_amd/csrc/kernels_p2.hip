@@ -308,6 +308,152 @@ __device__ void pass_xr_p2(const LevelDesc& l0, double* X, double* R, const doub
   }
 }
 
+// Banded forms of the CG passes (tile rows of at most RING_CHUNKS * 64 nodes): the
+// workgroup walks the tile in bands of BH = RW * NW rows (RW rows per wave) with one LDS
+// ring of BH + 4 rows of p (the P2 stencil reaches two rows; rows -2, -1, ny and ny + 1
+// hold zeros, the Dirichlet values).  At step k the waves form or stage rows k BH - 2 to
+// k BH + BH - 3 of p in the ring (first stage), and after a barrier apply K2 to the rows
+// two above them from the ring (second stage), so K2 p needs no global gathers and
+// q = K2 p is not stored.  A ring row is overwritten only after the barrier that follows
+// its last reader.  BH + 4 rows fit the three-ring space of the smoothing passes
+// (3 (NW + 2) rows) for RW = 3; tall bands keep the barriers per pass few.
+template <int NT>
+struct P2Ring {
+  static constexpr int NW = NT / 64, RW = 3, BH = RW * NW, RING = BH + 4, CM = RING_CHUNKS;
+  double* ring;
+  int nx;
+  __device__ double* row(int y) const { return ring + ((y + 2) % RING) * nx; }
+  // row j of wave w in the first stage of step k
+  __device__ static int row_a(int k, int j, int w) { return k * BH + j * NW + w - 2; }
+  __device__ static bool more(int k, int ny) { return k * BH - 4 < ny; }
+};
+
+// K2 p at tile node (ix, y) (a dof) from the ring.
+template <int NT, int KIND>
+__device__ __forceinline__ double ring_k2(const ProbDev& P, const LevelDesc& l0, int lm,
+                                          const P2Ring<NT>& rg, int ix, int y) {
+  auto u = [&](int dx, int dy) -> double {
+    const int jx = ix + dx;
+    const bool in = jx >= 0 && jx < l0.nx;
+    const double v = rg.row(y + dy)[in ? jx : ix];
+    return in ? v : 0.0;
+  };
+  return p2::apply_k<KIND>(P, lm, l0.gx0 + ix, l0.gy0 + y, u);
+}
+
+// p_new = z + beta p_old (stored) and this thread's share of p_new . K2 p_new.
+template <int NT, int KIND>
+__device__ void pass_dir_p2_banded(const ProbDev& P, const LevelDesc& l0, const double* Z,
+                                   const double* Po, double* Pn, double beta, bool first,
+                                   double* ring, double* acc) {
+  using RG = P2Ring<NT>;
+  constexpr int RW = RG::RW, CM = RG::CM;
+  const RG rg{ring, l0.nx};
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nch = (nx + 63) >> 6, lm = l0.l - 1;
+  const double bet = first ? 0.0 : beta;
+  const double* Pold = first ? Z : Po;  // any valid vector: its values are multiplied by 0
+  for (int k = 0; RG::more(k, ny); ++k) {
+#pragma unroll 1
+    for (int j = 0; j < RW; ++j) {
+      const int ya = RG::row_a(k, j, w);
+      if (ya > ny + 1) break;
+      const bool inA = ya >= 0 && ya < ny;
+      double zv[CM], pv[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        if (c < nch) {
+          const int ix = lane + 64 * c;
+          const unsigned i = (inA && ix < nx) ? (unsigned)(ya * nx + ix) : 0u;
+          zv[c] = Z[i];
+          pv[c] = Pold[i];
+        }
+      }
+      double* dst = rg.row(ya);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) {
+          double v = 0.0;
+          if (inA) {
+            v = zv[c] + bet * pv[c];
+            Pn[(unsigned)(ya * nx + ix)] = v;
+          }
+          dst[ix] = v;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < RW; ++j) {
+      const int yb = RG::row_a(k, j, w) - 2;
+      if (yb < 0 || yb >= ny) continue;
+      const double* rc = rg.row(yb);
+#pragma unroll 1
+      for (int ix = lane; ix < nx; ix += 64) {
+        if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + yb))
+          *acc += rc[ix] * ring_k2<NT, KIND>(P, l0, lm, rg, ix, yb);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// x += alpha p, r -= alpha K2 p and this thread's share of ||r||^2, with p staged in the
+// ring.
+template <int NT, int KIND>
+__device__ void pass_xr_p2_banded(const ProbDev& P, const LevelDesc& l0, double* X, double* R,
+                                  const double* Pn, double alpha, double* ring, double* acc) {
+  using RG = P2Ring<NT>;
+  constexpr int RW = RG::RW, CM = RG::CM;
+  const RG rg{ring, l0.nx};
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nx = l0.nx, ny = l0.ny, nch = (nx + 63) >> 6, lm = l0.l - 1;
+  for (int k = 0; RG::more(k, ny); ++k) {
+#pragma unroll 1
+    for (int j = 0; j < RW; ++j) {
+      const int ya = RG::row_a(k, j, w);
+      if (ya > ny + 1) break;
+      const bool inA = ya >= 0 && ya < ny;
+      double pv[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        if (c < nch) {
+          const int ix = lane + 64 * c;
+          const int jx = ix < nx ? ix : nx - 1;
+          pv[c] = Pn[inA ? (unsigned)(ya * nx + jx) : 0u];
+        }
+      }
+      double* dst = rg.row(ya);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int ix = lane + 64 * c;
+        if (c < nch && ix < nx) dst[ix] = inA ? pv[c] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < RW; ++j) {
+      const int yb = RG::row_a(k, j, w) - 2;
+      if (yb < 0 || yb >= ny) continue;
+      const double* rc = rg.row(yb);
+#pragma unroll 1
+      for (int ix = lane; ix < nx; ix += 64) {
+        const unsigned i = (unsigned)(yb * nx + ix);
+        const double xo = X[i], ro = R[i];
+        double q = 0.0;
+        if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + yb))
+          q = ring_k2<NT, KIND>(P, l0, lm, rg, ix, yb);
+        X[i] = xo + alpha * rc[ix];
+        const double r = ro - alpha * q;
+        R[i] = r;
+        *acc += r * r;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Conjugate gradients on the P2 tile problem K2 e = r, preconditioned by the P1 V-cycle
 // on the same nodes (levels: the tile's node grid, then the coarser P1 grids down to the
 // coarse-cell grid of Omega_j, solved exactly); the same loop as the P1 solver.
@@ -335,13 +481,21 @@ __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, i
       if (iters >= max_it) break;
       ++iters;
       acc[0] = acc[1] = 0.0;
-      pass_dir_p2<NT>(l0, Z, Po, Pn, beta, first);
-      __syncthreads();
-      pass_apply_p2<NT, KIND>(P, l0, Pn, Q, &acc[0]);
+      const bool banded = ring != nullptr && l0.nx <= 64 * RING_CHUNKS;
+      if (banded) {
+        pass_dir_p2_banded<NT, KIND>(P, l0, Z, Po, Pn, beta, first, ring, &acc[0]);
+      } else {
+        pass_dir_p2<NT>(l0, Z, Po, Pn, beta, first);
+        __syncthreads();
+        pass_apply_p2<NT, KIND>(P, l0, Pn, Q, &acc[0]);
+      }
       block_sum<NT, 2>(acc, red);
       const double alpha = rho / acc[0];
       acc[0] = acc[1] = 0.0;
-      pass_xr_p2<NT>(l0, X, R, Pn, Q, alpha, &acc[0]);
+      if (banded)
+        pass_xr_p2_banded<NT, KIND>(P, l0, X, R, Pn, alpha, ring, &acc[0]);
+      else
+        pass_xr_p2<NT>(l0, X, R, Pn, Q, alpha, &acc[0]);
       block_sum<NT, 2>(acc, red);
       rr = acc[0];
       if (rr <= tol2) break;
