@@ -46,6 +46,21 @@ def test_p2_variants(kw):
     compare(W.config1_p2().with_(**kw))
 
 
+@pytest.mark.parametrize("kw", [dict(nu=1), dict(nu=3, omega=0.6), dict(smoother=0)])
+def test_p2_solver_options(kw):
+    """Smoothing counts without the LDS rings (nu = 1, 3: the gathering CG passes) and damped
+    Jacobi in place of the Chebyshev weights: same results."""
+    _torch()
+    compare(W.small_ragged_p2(), **kw)
+
+
+def test_p2_rows_wider_than_banded_cg_passes():
+    """One subdomain over n_c = 9 at h = 1/576: P2 tile rows of 287 nodes, past the 256 of
+    the banded CG passes but within the smoothing rings."""
+    _torch()
+    compare(W.Problem(0, 9, 4, 1, 1, 1, 1, 0, None, "wide_rows_p2", order=2))
+
+
 @pytest.mark.parametrize("block", [256, 512])
 def test_p2_block_sizes(block):
     _torch()

@@ -139,6 +139,16 @@ def test_solver_options_do_not_change_results(kw):
     compare(W.small_ragged(), **kw)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rows_wider_than_banded_cg_passes(precision):
+    """One subdomain over n_c = 9 at h = 1/288: tile rows of 287 nodes, past the 256 of the
+    banded CG and refinement passes but within the smoothing rings, so the gathering CG
+    passes run beside the banded V-cycle; per-coarse-cell kappa."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    kap = W.loguniform_coarse_kappa(9, rng)
+    compare(W.Problem(0, 9, 5, 1, 1, 1, 1, 1, kap, "wide_rows"), precision=precision)
+
+
 def test_config2_full():
     """Configuration 2 at full size: h = 1/512, 8x8 subdomains, q = 3."""
     lam, u, levels, stats, ref = compare(W.config2())
