@@ -75,7 +75,7 @@ __global__ __launch_bounds__(NTA) void k_restrict1(const ProbDev* probs, const d
   const int Nc = P.n_c << l, nc1 = Nc + 1, nf1 = 2 * Nc + 1;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)nc1 * nc1) return;
-  const int Iy = (int)(idx / nc1), Ix = (int)(idx - (int64_t)Iy * nc1);
+  const int Iy = grid_row(idx, nc1), Ix = (int)(idx - (int64_t)Iy * nc1);
   double v = 0.0;
   if (is_dof(P.domain, Nc, Ix, Iy)) {
     const int64_t c = (int64_t)(2 * Iy) * nf1 + 2 * Ix;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NTA) void k_dot(const ProbDev* probs, int m, const 
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   double v = 0.0;
   if (idx < nn) {
-    const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+    const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
     if (is_dof(P.domain, N, gx, gy)) {
       if (MASS) {
         const double h = P.side / N;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(NTA) void k_adj_shat(const ProbDev* probs, int m, c
   const int N = P.n_c << m, n1 = N + 1;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)n1 * n1) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, gx, gy)) v = interp_coarse(ygrid, P.n_c, m, gx, gy) + coef[4] * ut[idx];
   s[idx] = v;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NTA) void k_adj_utbar(const ProbDev* probs, int m, 
   const int N = P.n_c << m, n1 = N + 1;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)n1 * n1) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, gx, gy)) {
     const double mu = rr[3 * P.nH + 3];
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(NTA) void k_adj_rbar(const ProbDev* probs, const Ti
   const int N = P.n_c << m, n1 = N + 1;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)n1 * n1) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, gx, gy)) {
     const int r = 1 << m;
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(NTA) void k_adj_next(const ProbDev* probs, int m, c
   const int N = P.n_c << m, n1 = N + 1;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)n1 * n1) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double ub = 0.0, nx = 0.0;
   if (is_dof(P.domain, N, gx, gy)) {
     ub = interp2(uk, (N >> 1) + 1, gx, gy);
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(NTA) void k_adj_products(const ProbDev* probs, int 
   const int N = P.n_c << m, n1 = N + 1;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)N * N) return;
-  const int J = (int)(idx / N), I = (int)(idx - (int64_t)J * N);
+  const int J = grid_row(idx, N), I = (int)(idx - (int64_t)J * N);
   const int64_t sw = (int64_t)J * n1 + I, se = sw + 1, nw = sw + n1, ne = nw + 1;
   double lo, up, l2, u2;
   tri_prods(u[sw], u[se], u[ne], u[nw], u[sw], u[se], u[ne], u[nw], lo, up);
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(NTA) void k_adj_down(const double* plo, const doubl
   const int Nf = 2 * Nc;
   const int64_t idx = (int64_t)blockIdx.x * NTA + threadIdx.x;
   if (idx >= (int64_t)Nf * Nf) return;
-  const int j = (int)(idx / Nf), i = (int)(idx - (int64_t)j * Nf);
+  const int j = grid_row(idx, Nf), i = (int)(idx - (int64_t)j * Nf);
   const int64_t p = (int64_t)(j >> 1) * Nc + (i >> 1);
   const bool xi = i & 1, yj = j & 1;
   // parents: lower(I,J) <- lower(2I,2J), lower(2I+1,2J), upper(2I+1,2J), lower(2I+1,2J+1)
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(NTA) void k_adj_out(const double* lo, const double*
     return;
   }
   if (idx >= (int64_t)nc * nc) return;
-  const int J = (int)(idx / nc), I = (int)(idx - (int64_t)J * nc);
+  const int J = grid_row(idx, nc), I = (int)(idx - (int64_t)J * nc);
   const int r = N / nc;
   double s = 0.0;
   for (int y = J * r; y < (J + 1) * r; ++y)

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(NTS) void k_skel_fill(const ProbDev* probs, const T
   double* E = vec + (int64_t)i_rhs * stride;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, gx, gy)) {
     const int bx = g_block(P.n_c, P.sub_x, gx, r), by = g_block(P.n_c, P.sub_y, gy, r);
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NTS) void k_skel_init(const ProbDev* probs, int m, 
   double* Wv = base + nn;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double w = 0.0;
   if (skel_dof(P, N, r, gx, gy)) {
     double d;
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(NTS) void k_skel_upd(const ProbDev* probs, int m, d
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   if (idx >= nn) return;
   const double alpha = scal[1];
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double w = 0.0;
   if (skel_dof(P, N, r, gx, gy)) {
     base[V_E * nn + idx] += alpha * base[p_off + idx];
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(NTC) void k_mg_coarse(const ProbDev* probs, int l, 
   unsigned char* sm = reinterpret_cast<unsigned char*>(coarse_lds + 3 * nn);
   double* base = vec + (int64_t)i_rhs * stride;
   for (int idx = threadIdx.x; idx < nn; idx += NTC) {
-    const int gy = idx / n1, gx = idx - gy * n1;
+    const int gy = grid_row(idx, n1), gx = idx - gy * n1;
     const bool mk = skel_dof(P, N, r, gx, gy);
     double b = 0.0, x = 0.0;
     if (mk) {
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(NTC) void k_mg_coarse(const ProbDev* probs, int l, 
     for (int idx = threadIdx.x; idx < nn; idx += NTC) {
       double v = 0.0;
       if (sm[idx]) {  // an interior node: its neighbours are in the square
-        const int gy = idx / n1, gx = idx - gy * n1;
+        const int gy = grid_row(idx, n1), gx = idx - gy * n1;
         double d;
         const double a = lds_apply<KIND>(P, l, N, gx, gy, in, idx, n1, d);
         v = in[idx] + kMgOmega * (sb[idx] - a) / d;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(NTS) void k_mg_sweep(const ProbDev* probs, int l, d
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   if (idx >= (int64_t)n1 * n1) return;
   double* base = vec + (int64_t)i_rhs * stride;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   double v = 0.0;
   if (skel_dof(P, N, r, gx, gy)) {
     const double b = base[b_off + idx];
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(NTS) void k_skel_dir(const ProbDev* probs, int m, d
   const double* Pold = first ? Z : Po;  // any valid vector: multiplied by 0
   double pq = 0.0;
   if (idx < nn) {
-    const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+    const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
     double pc = 0.0, q = 0.0;
     if (skel_dof(P, N, r, gx, gy)) {
       auto pv = [&](int64_t j) -> double { return Z[j] + beta * Pold[j]; };
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(NTS) void k_skel_finish(const ProbDev* probs, int m
   const double* E = vec + (int64_t)i_rhs * stride;
   const int64_t idx = (int64_t)blockIdx.x * NTS + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   const int64_t o = (int64_t)i_rhs * nn + idx;
   P.ut[o] = is_dof(P.domain, N, gx, gy) ? P.ubar[o] + E[idx] : 0.0;
 }

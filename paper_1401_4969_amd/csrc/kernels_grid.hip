@@ -35,7 +35,7 @@ __global__ __launch_bounds__(NTG) void k_prolong_residual(const ProbDev* probs, 
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   const int nc1 = (N >> 1) + 1;
   const bool dof = is_dof(P.domain, N, gx, gy);
   const double h = P.side / N;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   if (!is_dof(P.domain, N, gx, gy)) {
     for (int i = 0; i < P.q; ++i) P.ut[(int64_t)i * nn + idx] = 0.0;
     return;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
   const bool inr = idx < nn;
   int gx = 0, gy = 0;
   if (inr) {
-    gy = (int)(idx / n1);
+    gy = grid_row(idx, n1);
     gx = (int)(idx - (int64_t)gy * n1);
   }
   const bool dof = inr && is_dof(P.domain, N, gx, gy);
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, i
   const int64_t nnc = (int64_t)nc1 * nc1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= nnc) return;
-  const int Iy = (int)(idx / nc1), Ix = (int)(idx - (int64_t)Iy * nc1);
+  const int Iy = grid_row(idx, nc1), Ix = (int)(idx - (int64_t)Iy * nc1);
   const int nf1 = 2 * Nc + 1;
   const int64_t nnf = (int64_t)nf1 * nf1;
   const bool dof = is_dof(P.domain, Nc, Ix, Iy);
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(NTG) void k_assemble(const ProbDev* probs, int m, i
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   const bool dof = is_dof(P.domain, N, gx, gy);
   const int q = P.q;
   const int nc = P.n_c, nc1 = nc + 1;
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(NTG) void k_coarsen_kappa(const double* lo_f, const
                                                        double* lo_c, double* up_c, int Nc) {
   const int idx = blockIdx.x * NTG + threadIdx.x;
   if (idx >= Nc * Nc) return;
-  const int J = idx / Nc, I = idx - J * Nc;
+  const int J = grid_row(idx, Nc), I = idx - J * Nc;
   const int Nf = 2 * Nc;
   const int a = (2 * J) * Nf + 2 * I;  // fine cell (2I, 2J)
   lo_c[idx] = 0.25 * (lo_f[a] + lo_f[a + 1] + up_f[a + 1] + lo_f[a + Nf + 1]);
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(NTG) void k_tensor_fine(const double* coef, double*
   const int64_t pl = (int64_t)n1 * n1, cells = (int64_t)N * N;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= pl) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   // vertices (lattice offsets from the cell's SW corner) and scaled gradients
   const int vx[2][3] = {{0, 1, 1}, {0, 1, 0}}, vy[2][3] = {{0, 0, 1}, {0, 1, 1}};
   const double gxv[2][3] = {{-1.0, 1.0, 0.0}, {0.0, 1.0, -1.0}};
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(NTG) void k_galerkin7(const double* fine, double* c
   const int64_t plc = (int64_t)nc1 * nc1, plf = (int64_t)nf1 * nf1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= plc) return;
-  const int Y = (int)(idx / nc1), X = (int)(idx - (int64_t)Y * nc1);
+  const int Y = grid_row(idx, nc1), X = (int)(idx - (int64_t)Y * nc1);
   const int ox[7] = {0, 1, -1, 0, 0, 1, -1}, oy[7] = {0, 0, 0, 1, -1, 1, -1};
   const double ow[7] = {1.0, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5};
   const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
@@ -775,7 +775,7 @@ __global__ __launch_bounds__(NTG) void k_set_state(const ProbDev* probs, int lev
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTG + threadIdx.x;
   if (idx >= nn) return;
-  const int gy = (int)(idx / n1), gx = (int)(idx - (int64_t)gy * n1);
+  const int gy = grid_row(idx, n1), gx = (int)(idx - (int64_t)gy * n1);
   const bool dof = is_dof(P.domain, N, gx, gy);
   for (int k = 0; k < P.q; ++k)
     P.u[dst][(int64_t)k * nn + idx] = dof ? in[(int64_t)k * nn + idx] : 0.0;

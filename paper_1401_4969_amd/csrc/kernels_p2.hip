@@ -31,7 +31,7 @@ __global__ __launch_bounds__(NTP) void k_p2_prolong(const ProbDev* probs, int m,
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTP + threadIdx.x;
   if (idx >= nn) return;
-  const int y = (int)(idx / n1), x = (int)(idx - (int64_t)y * n1);
+  const int y = grid_row(idx, n1), x = (int)(idx - (int64_t)y * n1);
   double v = 0.0;
   if (is_dof(P.domain, N, x, y)) {
     const int nc1 = N / 2 + 1;  // coarse node grid
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(NTP) void k_p2_residual(const ProbDev* probs, int m
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTP + threadIdx.x;
   if (idx >= nn) return;
-  const int y = (int)(idx / n1), x = (int)(idx - (int64_t)y * n1);
+  const int y = grid_row(idx, n1), x = (int)(idx - (int64_t)y * n1);
   double r = 0.0;
   if (is_dof(P.domain, N, x, y)) {
     const double* ub = P.ubar + (int64_t)i * nn;
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NTP) void k_p2_rr_apply(const ProbDev* probs, int m
   const bool inr = idx < nn;
   int x = 0, y = 0;
   if (inr) {
-    y = (int)(idx / n1);
+    y = grid_row(idx, n1);
     x = (int)(idx - (int64_t)y * n1);
   }
   const bool dof = inr && is_dof(P.domain, N, x, y);
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NTP) void k_p2_restrict(const ProbDev* probs, int l
   const int64_t nnc = (int64_t)nc1 * nc1;
   const int64_t idx = (int64_t)blockIdx.x * NTP + threadIdx.x;
   if (idx >= nnc) return;
-  const int cy = (int)(idx / nc1), cx = (int)(idx - (int64_t)cy * nc1);
+  const int cy = grid_row(idx, nc1), cx = (int)(idx - (int64_t)cy * nc1);
   const int Nf = 2 * Nc;
   const int nf1 = Nf + 1;
   const int64_t nnf = (int64_t)nf1 * nf1;
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NTP) void k_p2_assemble(const ProbDev* probs, int m
   const int64_t nn = (int64_t)n1 * n1;
   const int64_t idx = (int64_t)blockIdx.x * NTP + threadIdx.x;
   if (idx >= nn) return;
-  const int y = (int)(idx / n1), x = (int)(idx - (int64_t)y * n1);
+  const int y = grid_row(idx, n1), x = (int)(idx - (int64_t)y * n1);
   double val = 0.0;
   if (is_dof(P.domain, N, x, y)) {
     const p2::Loc L = p2::locate(x, y, 2 << m, m + 1, P.n_c);

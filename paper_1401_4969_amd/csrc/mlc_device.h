@@ -102,6 +102,21 @@ struct ItemStat {
   double relres;
 };
 
+// Row of entry idx of a row-major array with n columns, floor(idx / n), for
+// 0 <= idx < n^2 <= 2^31: a float reciprocal estimate (error below 2^-20 of a quotient
+// under 2^16) corrected by one step either way.  A 64-bit integer division costs about a
+// hundred vector instructions, which the one-thread-per-node grid kernels would otherwise
+// spend on every node.
+__device__ __forceinline__ int grid_row(int64_t idx, int n) {
+  const unsigned u = (unsigned)idx, un = (unsigned)n;
+  unsigned q = (unsigned)((float)u * __builtin_amdgcn_rcpf((float)n));
+  if (q * un > u)
+    --q;
+  else if ((q + 1u) * un <= u)
+    ++q;
+  return (int)q;
+}
+
 __device__ __forceinline__ bool is_dof(int domain, int N, int gx, int gy) {
   if (gx <= 0 || gy <= 0 || gx >= N || gy >= N) return false;
   if (domain == 1 && gx >= (N >> 1) && gy <= (N >> 1)) return false;
