@@ -131,9 +131,9 @@ def source_sha(kernel: str) -> str:
     """Hash of the code the kernel is built from (comments ignored)."""
     import hashlib
     c = os.path.join(ROOT, "paper_1401_4969_amd", "csrc")
-    files = {"k_local_pcg64": ["kernels_pcg.hip", "pcg_ops.h", "mlc_device.h"],
-             "k_local_mixed": ["kernels_mixed.hip", "pcg_ops.h", "mlc_device.h"],
-             "k_local_p2": ["kernels_p2.hip", "p2_ops.h", "pcg_ops.h", "mlc_device.h"]}[kernel]
+    files = {"k_local_pcg64": ["kernels_pcg.hip", "pcg_ops.h", "mlc_launch.h", "mlc_device.h"],
+             "k_local_mixed": ["kernels_mixed.hip", "pcg_ops.h", "mlc_launch.h", "mlc_device.h"],
+             "k_local_p2": ["kernels_p2.hip", "p2_ops.h", "pcg_ops.h", "mlc_launch.h", "mlc_device.h"]}[kernel]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(c, f)) as fh:
