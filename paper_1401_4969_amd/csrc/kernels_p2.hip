@@ -151,13 +151,33 @@ __global__ __launch_bounds__(NTP) void k_p2_rr_apply(const ProbDev* probs, int m
 // a5 (continued): one level of the transposed interpolation, P2 level l+1 -> l, for the 2q
 // border vectors: every coarse node gathers the fine values in its basis function's
 // support (fine nodes within two coarse half steps), each weighted by that basis function
-// at the fine node (found in the coarse triangle that holds the node, as a1 does).
+// at the fine node.  The coarse basis functions of one node class (vertex, x-, y- or
+// diagonal-edge midpoint) are translates of each other on the uniform mesh, so each
+// workgroup first tabulates the four classes' weights at the 9 x 9 fine offsets in LDS,
+// evaluated at a coarse node away from the boundary (the node's triangles located as a1
+// does; exact dyadic values), and every node then reads its class's row.
 __global__ __launch_bounds__(NTP) void k_p2_restrict(const ProbDev* probs, int l, int m) {
+  __shared__ double wt[4][81];
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
   const int q = P.q;
   const int v = blockIdx.z;
   if (v >= 2 * q) return;
+  for (int e = threadIdx.x; e < 4 * 81; e += NTP) {
+    const int c = e / 81, k = e - 81 * c;
+    const int dy = k / 9 - 4, dx = k - 9 * (k / 9) - 4;
+    const int cx = 4 + (c & 1), cy = 4 + (c >> 1);  // a class-c node of an unbounded mesh
+    const p2::Loc L = p2::locate(2 * cx + dx, 2 * cy + dy, 4, 2, 1 << 20);
+    double sh[6];
+    p2::shape(L.l0, L.l1, L.l2, sh);
+    double w = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < 6; ++bb)
+      if (2 * L.I + p2::node_dx_rt(L.up, bb) == cx && 2 * L.J + p2::node_dy_rt(L.up, bb) == cy)
+        w = sh[bb];
+    wt[c][k] = w;
+  }
+  __syncthreads();
   const int Nc = P.n_c << (l + 1);  // coarse node grid
   const int nc1 = Nc + 1;
   const int64_t nnc = (int64_t)nc1 * nc1;
@@ -175,22 +195,15 @@ __global__ __launch_bounds__(NTP) void k_p2_restrict(const ProbDev* probs, int l
     f = P.rchain + P.rchain_off[l + 1] + (int64_t)v * nnf;
   double val = 0.0;
   if (is_dof(P.domain, Nc, cx, cy)) {
-    const int ncell = P.n_c << l;  // coarse mesh cells per side
+    const double* w = wt[(cx & 1) | ((cy & 1) << 1)];
     for (int dy = -4; dy <= 4; ++dy) {
       const int fy = 2 * cy + dy;
       if (fy < 0 || fy > Nf) continue;
+#pragma unroll
       for (int dx = -4; dx <= 4; ++dx) {
         const int fx = 2 * cx + dx;
-        if (fx < 0 || fx > Nf) continue;
-        const p2::Loc L = p2::locate(fx, fy, 4, 2, ncell);
-        double w = 0.0;
-        double sh[6];
-        p2::shape(L.l0, L.l1, L.l2, sh);
-#pragma unroll
-        for (int b = 0; b < 6; ++b)
-          if (2 * L.I + p2::node_dx_rt(L.up, b) == cx && 2 * L.J + p2::node_dy_rt(L.up, b) == cy)
-            w = sh[b];
-        if (w != 0.0) val += w * f[(int64_t)fy * nf1 + fx];
+        const double ww = w[9 * (dy + 4) + dx + 4];
+        if (fx >= 0 && fx <= Nf && ww != 0.0) val += ww * f[(int64_t)fy * nf1 + fx];
       }
     }
   }
