@@ -22,7 +22,7 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
                                                      ItemStat* stats, double rtol, int max_it,
                                                      int nu, double omega, double omega2,
                                                      int rhs_in_tile,
-                                                     int ring_cap, int ring_cap2) {
+                                                     int ring_cap, int ring_cap2, int ring_cap2n) {
   __shared__ double red[2 * (NT / 64)];
   extern __shared__ double ring_lds[];  // banded smoothing rings (dynamic size)
   const TileItem it = items[blockIdx.x];
@@ -48,12 +48,17 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   double rr = bb;
   // banded passes when this tile's rows fit the rings (a per-item decision, so the
   // arithmetic of an item does not depend on the other items of the launch)
-  // band rows per wave: two where this tile's rows fit the taller rings, else one
-  const int rows = l0.nx <= ring_cap2 ? 2 : (l0.nx <= ring_cap ? 1 : 0);
+  // band rows per wave: two where this tile's rows fit the taller rings, else one; tiles
+  // too wide for the taller rings beside the LDS V-cycle tail but narrow enough without
+  // it (ring_cap2 < nx <= ring_cap2n) give the tail up for them
+  const bool tall_no_tail = l0.nx > ring_cap2 && l0.nx <= ring_cap2n;
+  const int rows = (l0.nx <= ring_cap2 || tall_no_tail) ? 2 : (l0.nx <= ring_cap ? 1 : 0);
   double* ring = rows ? ring_lds : nullptr;
   // the LDS V-cycle tail, after the rings, with 1024-thread workgroups (one per CU: the
   // extra LDS costs no concurrency there)
-  double* tail = (rows && NT == 1024) ? ring_lds + ring_elems(NT / 64, ring_cap, ring_cap2) : nullptr;
+  double* tail = (rows && NT == 1024 && !tall_no_tail)
+                     ? ring_lds + ring_elems(NT / 64, ring_cap, ring_cap2)
+                     : nullptr;
   const int iters = pcg_solve<NT, KIND, double, 2>(P, lev, base, m, inv + it.inv_off, bb,
                                                 rtol * rtol * bb, max_it, nu, omega, omega2, red, ring,
                                                 rows, tail, rr);
@@ -110,6 +115,23 @@ int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tai
   return cap1;
 }
 
+int ring_layout(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds, int* cap2,
+                int* cap2n) {
+  const bool tail = nt == 1024;
+  const int cap = ring_capacity(nt, nu, max_tile_nx, elem_bytes, tail, lds, cap2);
+  *cap2n = 0;
+  if (tail && cap > 0 && *cap2 < max_tile_nx) {
+    size_t lds_n = 0;
+    int c2n = 0;
+    ring_capacity(nt, nu, max_tile_nx, elem_bytes, false, &lds_n, &c2n);
+    if (c2n > *cap2) {
+      *cap2n = c2n;
+      *lds = std::max(*lds, lds_n);
+    }
+  }
+  return cap;
+}
+
 hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileItem* items,
                             int nitems, char* store, const double* inv, int m, ItemStat* stats,
                             double rtol, int max_it, int nu, double omega, double omega2,
@@ -118,12 +140,15 @@ hipError_t launch_local_pcg(int kind, int nt, const ProbDev* probs, const TileIt
   // the ring is sized for the workgroup size actually launched
   const int ntv = nt == 256 ? 256 : (nt == 512 ? 512 : 1024);
   size_t lds = 0;
-  int cap2 = 0;
-  const int cap = ring_capacity(ntv, nu, max_tile_nx, 8, ntv == 1024, &lds, &cap2);
+  int cap2 = 0, cap2n = 0;
+  const int cap = ring_layout(ntv, nu, max_tile_nx, 8, &lds, &cap2, &cap2n);
+  // a constant coefficient keeps one band row with the tail: its one-row passes prefetch
+  // the next band's rows (config 3's 191-wide tiles: 6% slower on two rows without tail)
+  if (kind == 0) cap2n = 0;
 #define MLC_PCG(NTV, KV)                                                                        \
   hipLaunchKernelGGL((k_local_pcg64<NTV, KV>), dim3(nitems), dim3(NTV), lds, s, probs, items,    \
                      store, inv, m, stats, rtol, max_it, nu, omega, omega2, (int)rhs_in_tile,   \
-                     cap, cap2)
+                     cap, cap2, cap2n)
 #define MLC_PCG_NT(NTV)    \
   if (kind == 0)           \
     MLC_PCG(NTV, 0);       \

@@ -39,6 +39,12 @@ int64_t skel_stride(int nc, int L);
 // 2 nt/64 + 2 rows), *lds the bytes to allocate.
 int ring_capacity(int nt, int nu, int max_tile_nx, int elem_bytes, bool with_tail, size_t* lds,
                   int* cap2);
+// The rings of a launch: ring_capacity with the LDS V-cycle tail for 1024 threads, and in
+// *cap2n the widest tile that takes two band rows per wave when it gives the tail up (0
+// when that adds nothing); *lds covers both layouts.  Every cap depends on the device only
+// (or is at least the widest tile), so each item's choice depends on its own width alone.
+int ring_layout(int nt, int nu, int max_tile_nx, int elem_bytes, size_t* lds, int* cap2,
+                int* cap2n);
 // Elements of the ring region for nw waves and the two caps above (the tail follows it).
 __host__ __device__ inline long ring_elems(int nw, int cap1, int cap2) {
   const long a = 3L * (nw + 2) * cap1, b = 3L * (2 * nw + 2) * cap2;

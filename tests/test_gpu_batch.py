@@ -105,6 +105,29 @@ def _wide_batch(kind, q, n=6, seed0=300):
     return [p.with_(n_eig=qb) for p in out]
 
 
+def test_batch_tile_widths_around_ring_caps():
+    """Tiles of 95, 127, 191 and 255 nodes a row in one FP64 launch: 191 takes two band rows
+    per wave only without the LDS V-cycle tail, 255 one row with it.  Each item chooses from
+    its own width against caps that depend on the device only, so every problem of the
+    batch is bitwise a single run of itself (whose widest tile differs)."""
+    torch = _torch()
+    from paper_1401_4969_amd import binding as B
+    rng = np.random.Generator(np.random.PCG64(404))
+    probs = [W.Problem(0, 6, 6, 3, 3, 1, 1, 1, W.loguniform_coarse_kappa(6, rng), "cap_a"),
+             W.Problem(0, 8, 5, 4, 4, 1, 1, 1, W.loguniform_coarse_kappa(8, rng), "cap_b"),
+             W.Problem(1, 6, 6, 6, 6, 1, 1, 1, W.loguniform_coarse_kappa(6, rng), "cap_c")]
+    bs = B.BatchSolver(probs, B.default_opts())
+    bs.setup()
+    bs.run()
+    assert bs.stats()["relres_max"] <= 1e-12 * 1.0000001
+    res = [bs.get(i) for i in range(len(probs))]
+    bs.close()
+    for i, p in enumerate(probs):
+        lam1, u1 = _single(p)
+        assert np.array_equal(res[i][0], lam1), (i, res[i][0], lam1)
+        assert torch.equal(res[i][1], u1)
+
+
 @pytest.mark.parametrize("kind,q,precision", [(0, 3, 0), (1, 2, 1), (2, 1, 0), (3, 4, 0),
                                               (3, 1, 1)])
 def test_wide_batch_matches_single_and_oracle(kind, q, precision):
