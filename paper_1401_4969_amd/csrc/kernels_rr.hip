@@ -162,10 +162,10 @@ __device__ __forceinline__ void lu_solve(const double (&A)[Q][Q], const int (&pi
 }
 
 // Lanes per multisection point: the largest power of two up to 64 that leaves at least
-// 16 points per round.
-constexpr int rr_group_lanes(int ntr) {
+// `points` points per round.
+constexpr int rr_group_lanes(int ntr, int points) {
   int gs = 64;
-  while (gs > 1 && ntr / gs < 16) gs >>= 1;
+  while (gs > 1 && ntr / gs < points) gs >>= 1;
   return gs;
 }
 
@@ -390,8 +390,8 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   lo -= 1e-12 * fabs(lo) + 1e-300;
   // 6. multisection for all q eigenvalues at once: each round evaluates G points over the
   //    q brackets (G/q per bracket, GS lanes per point; the work of a round grows with G
-  //    while the rounds fall only with log G, so G is kept small: 16 points, at least 2
-  //    per bracket); every point's inertia count c tightens every bracket: mu is an upper
+  //    while the rounds fall only with log G, so G is kept small: 16 points, 32 for
+  //    q >= 5, at least 2 per bracket); every point's inertia count c tightens every bracket: mu is an upper
   //    bound of eigenvalue k when c >= k + 1 and a lower bound when c <= k.  Upper bounds
   //    start from interlacing (mu_k <= Lambda_k).
   //    A bracket's points are spread uniformly until it holds exactly one eigenvalue and no
@@ -409,8 +409,10 @@ __global__ __launch_bounds__(rr_threads<Q>()) void k_rr_solve(const ProbDev* pro
   //    predicted value +-(0.2 ... 0.02) of that change (level 1 has no such model: there
   //    they sit below lambda_k at 1e-1 down to 1e-6 of it).  Where the points go changes
   //    only how fast the brackets shrink, never what they contain.
-  constexpr int GS = rr_group_lanes(NTR);
-  constexpr int G = NTR / GS;  // 16 >= 2 Q
+  // 16 points per round, 32 from q = 5 on (Example 6.2, q = 6: 2 points a bracket needed
+  // so many rounds that doubling the points gained 36 us per step; at q = 3 it lost 27 us)
+  constexpr int GS = rr_group_lanes(NTR, Q >= 5 ? 32 : 16);
+  constexpr int G = NTR / GS;  // >= 2 Q, <= 64
   constexpr int GQ = G / Q;    // points per bracket, >= 2
   const int pnt = tid / GS, gl = tid % GS;
   const int kb = pnt / GQ, j = pnt % GQ;  // this point's bracket and position
