@@ -99,6 +99,39 @@ __device__ __forceinline__ int pou_axis_fast(int nc, int nb, int g, int m, int o
   return n;
 }
 
+// pou_axis_fast for nodes with at most two covering blocks, without the candidate arrays
+// (their run-time indices cost a conditional move per slot and candidate).  A block's
+// Omega range holds g strictly inside when lo - d < g < hi + d, and lo, hi grow with the
+// block, so the covering blocks run from the block holding fine position g - d to the one
+// holding g + d - 1 (coarse cells (g >> m) - ov and ((g - 1) >> m) + ov, clamped; g is an
+// interior node).  Returns their number (0 on a block boundary without overlap) and the
+// first in *b0; rho[0..1] receive the factors of the first two, the values pou_axis_fast
+// gives (with an overlap of a power of two coarse cells the division by d is a scaling by a
+// power of two, which is exact, so it is done as one).
+__device__ __forceinline__ int pou_axis2(int nc, int nb, int g, int m, int ov, int pou, int* b0,
+                                         double (&rho)[2]) {
+  const int r = 1 << m, d = ov * r;
+  const float rnb = 1.0f / (float)nb, rnc = 1.0f / (float)nc;
+  const int c1 = max(0, (g >> m) - ov), c2 = min(nc - 1, ((g - 1) >> m) + ov);
+  const int bf = div_small((c1 + 1) * nb - 1, nc, rnc);
+  const int bl = div_small((c2 + 1) * nb - 1, nc, rnc);
+  const int n = max(0, bl - bf + 1);
+  *b0 = bf;
+  const int l0 = div_small(bf * nc, nb, rnb) * r;
+  const int l1 = div_small(min(bf + 1, nb) * nc, nb, rnb) * r;
+  const int l2 = div_small(min(bf + 2, nb) * nc, nb, rnb) * r;
+  const int sh = pou == 0 ? m + __builtin_ctz((unsigned)max(ov, 1)) : 0;
+  const bool pow2 = (ov & (ov - 1)) == 0;
+  auto factor = [&](int lo, int hi) -> double {
+    if (pou != 0) return (g >= lo && g <= hi) ? 1.0 : 0.0;
+    const double v = (double)min(min(g - lo + d, hi + d - g), d);
+    return pow2 ? ldexp(v, -sh) : v / (double)d;
+  };
+  rho[0] = n > 0 ? factor(l0, l1) : 0.0;
+  rho[1] = n > 1 ? factor(l1, l2) : 0.0;
+  return n;
+}
+
 // a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
 // QM: a bound on q (1, 2, 4 or 8) that sizes the per-eigenpair registers.
 template <int QM>
@@ -119,18 +152,18 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
     return;
   }
   const int r = 1 << m;
-  int ix[MLC_MAX_CAND], iy[MLC_MAX_CAND];
-  double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
   const bool fast = P.n_c * max(P.sub_x, P.sub_y) < (1 << 22);
-  const int nxc = fast ? pou_axis_fast(P.n_c, P.sub_x, gx, m, P.overlap, P.pou, ix, rx)
-                       : pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
-  const int nyc = fast ? pou_axis_fast(P.n_c, P.sub_y, gy, m, P.overlap, P.pou, iy, ry)
-                       : pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
   // one item lookup per covering subdomain: its q right-hand sides follow at rhs_stride
   double acc[QM], tot = 0.0;
 #pragma unroll
   for (int i = 0; i < QM; ++i) acc[i] = 0.0;
-  if (nxc <= 2 && nyc <= 2) {
+  int bx0 = 0, by0 = 0;
+  double rx[2], ry[2];
+  const int sx = fast ? pou_axis2(P.n_c, P.sub_x, gx, m, P.overlap, P.pou, &bx0, rx) : 3;
+  const int sy = fast ? pou_axis2(P.n_c, P.sub_y, gy, m, P.overlap, P.pou, &by0, ry) : 3;
+  if (sx <= 2 && sy <= 2) {
+    const int nxc = sx, nyc = sy;
+    const int ix[2] = {bx0, bx0 + 1}, iy[2] = {by0, by0 + 1};
     // at most 2 x 2 covering subdomains (overlap 1 on blocks of two or more coarse cells):
     // every index load first, then every item, then every tile value, so the three
     // dependent loads of the subdomains overlap instead of following one another.  Slots
@@ -177,22 +210,29 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
       }
     }
   } else {
-  for (int a = 0; a < nyc; ++a) {
-    for (int b = 0; b < nxc; ++b) {
-      const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q];
-      if (item < 0) continue;
-      const TileItem it = items[item];
-      const int nx = it.cw * r - 1;
-      const int lx = gx - (it.cx0 * r + 1), ly = gy - (it.cy0 * r + 1);
-      const char* e0 = store + it.off + ((int64_t)ly * nx + lx) * (int64_t)sizeof(double);
-      const double phi = rx[b] * ry[a];
+    // more covering subdomains (wider overlaps, narrow blocks) or the general division
+    int ix[MLC_MAX_CAND], iy[MLC_MAX_CAND];
+    double rx[MLC_MAX_CAND], ry[MLC_MAX_CAND];
+    const int nxc = fast ? pou_axis_fast(P.n_c, P.sub_x, gx, m, P.overlap, P.pou, ix, rx)
+                         : pou_axis(P.n_c, P.sub_x, gx, r, P.overlap, P.pou, ix, rx);
+    const int nyc = fast ? pou_axis_fast(P.n_c, P.sub_y, gy, m, P.overlap, P.pou, iy, ry)
+                         : pou_axis(P.n_c, P.sub_y, gy, r, P.overlap, P.pou, iy, ry);
+    for (int a = 0; a < nyc; ++a) {
+      for (int b = 0; b < nxc; ++b) {
+        const int item = sub_item[P.sub_item_off + (iy[a] * P.sub_x + ix[b]) * P.q];
+        if (item < 0) continue;
+        const TileItem it = items[item];
+        const int nx = it.cw * r - 1;
+        const int lx = gx - (it.cx0 * r + 1), ly = gy - (it.cy0 * r + 1);
+        const char* e0 = store + it.off + ((int64_t)ly * nx + lx) * (int64_t)sizeof(double);
+        const double phi = rx[b] * ry[a];
 #pragma unroll
-      for (int i = 0; i < QM; ++i)
-        if (i < P.q)
-          acc[i] += phi * *reinterpret_cast<const double*>(e0 + (int64_t)i * it.rhs_stride);
-      tot += phi;
+        for (int i = 0; i < QM; ++i)
+          if (i < P.q)
+            acc[i] += phi * *reinterpret_cast<const double*>(e0 + (int64_t)i * it.rhs_stride);
+        tot += phi;
+      }
     }
-  }
   }
   // tot = 0 only on D_j block boundaries with overlap 0, where every e^j vanishes
 #pragma unroll
