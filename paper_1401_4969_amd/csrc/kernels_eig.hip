@@ -72,6 +72,27 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs, int ld
   __shared__ double s_c[kMaxPairs * BJ], s_s[kMaxPairs * BJ], s_t[kMaxPairs * BJ];
   __shared__ int s_changed;
   __shared__ double s_piv;
+  // the scalar sweep's index tables: round r's pair k is (s_pp, s_pq)[r][k], and the f-th
+  // (k1, k2 >= k1) pair of pairs in row order is (s_k1, s_k2)[f] (integer divisions and a
+  // search per task otherwise)
+  constexpr int NBLK = BJ * (BJ + 1) / 2;
+  __shared__ unsigned char s_pp[PB - 1][BJ], s_pq[PB - 1][BJ], s_k1[NBLK], s_k2[NBLK];
+  for (int e = tid; e < (PB - 1) * BJ; e += NTE) {
+    const int r = e / BJ, k = e % BJ;
+    int p, q;
+    rr_pair(PB, r, k, &p, &q);
+    s_pp[r][k] = (unsigned char)p;
+    s_pq[r][k] = (unsigned char)q;
+  }
+  for (int f = tid; f < NBLK; f += NTE) {
+    int k1 = 0, rem = f;
+    while (rem >= BJ - k1) {
+      rem -= BJ - k1;
+      ++k1;
+    }
+    s_k1[f] = (unsigned char)k1;
+    s_k2[f] = (unsigned char)(k1 + rem);
+  }
 
   // 1. L = chol(M)
   for (int e = tid; e < n * n; e += NTE) L[e] = M[e];
@@ -143,8 +164,7 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs, int ld
         for (int r = 0; r < PB - 1; ++r) {
           for (int e = tid; e < gn * BJ; e += NTE) {
             const int g = e / BJ, k = e % BJ;
-            int p, q;
-            rr_pair(PB, r, k, &p, &q);
+            const int p = s_pp[r][k], q = s_pq[r][k];
             const double* S = Ss + (int64_t)g * QB;
             const double app = S[p * PB + p], aqq = S[q * PB + q], apq = S[p * PB + q];
             double c = 1.0, s = 0.0, t = 0.0;
@@ -162,22 +182,14 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs, int ld
           __syncthreads();
           // S <- J^T S J on 2 x 2 blocks of pair rows k1 and pair columns k2 >= k1 (the
           // mirrored block written from the same values); Q <- Q J
-          constexpr int NBLK = BJ * (BJ + 1) / 2;
           for (int e = tid; e < gn * (NBLK + PB * BJ); e += NTE) {
             const int g = e / (NBLK + PB * BJ), f = e % (NBLK + PB * BJ);
             double* S = Ss + (int64_t)g * QB;
             const double* cc = s_c + g * BJ;
             const double* ss = s_s + g * BJ;
             if (f < NBLK) {
-              int k1 = 0, rem = f;  // f-th pair (k1, k2 >= k1) in row order
-              while (rem >= BJ - k1) {
-                rem -= BJ - k1;
-                ++k1;
-              }
-              const int k2 = k1 + rem;
-              int p1, q1, p2, q2;
-              rr_pair(PB, r, k1, &p1, &q1);
-              rr_pair(PB, r, k2, &p2, &q2);
+              const int k1 = s_k1[f], k2 = s_k2[f];  // f-th pair (k1, k2 >= k1) in row order
+              const int p1 = s_pp[r][k1], q1 = s_pq[r][k1], p2 = s_pp[r][k2], q2 = s_pq[r][k2];
               const double c1 = cc[k1], sn1 = ss[k1];
               if (k1 == k2) {
                 const double t = s_t[g * BJ + k1];
@@ -205,8 +217,7 @@ __global__ __launch_bounds__(NTE) void k_coarse_eig(const ProbDev* probs, int ld
               S[q2 * PB + q1] = n11;
             } else {
               const int i = (f - NBLK) / BJ, k = (f - NBLK) % BJ;
-              int p, q;
-              rr_pair(PB, r, k, &p, &q);
+              const int p = s_pp[r][k], q = s_pq[r][k];
               double* Q = Qs + (int64_t)(g0 + g) * QB;
               const double c = cc[k], s = ss[k];
               const double wp = Q[i * PB + p], wq = Q[i * PB + q];

@@ -118,8 +118,11 @@ def test_random_problems_wide(seed):
 
 
 @pytest.mark.parametrize("kw", [dict(sub_x=1, sub_y=1), dict(overlap=2), dict(n_refine=1),
-                                dict(sub_x=3, sub_y=5), dict(n_eig=4)])
+                                dict(sub_x=3, sub_y=5), dict(n_eig=4),
+                                dict(sub_x=2, sub_y=2, overlap=3)])
 def test_config1_variants(kw):
+    """Subdomain grids and overlaps around config 1; overlap 3 on 2 x 2 blocks keeps at most
+    two covering subdomains a node with a ramp width that is not a power of two."""
     compare(W.config1().with_(**kw))
 
 
