@@ -86,24 +86,24 @@ def pcg_bytes_per_iteration(cw: int, ch: int, m: int, nu: int, elem: int = 8,
     return elem * (8 * S[0] + v) + coef * c
 
 
-SURVEY_PASSES = 18     # vector passes per PCG iteration in the reference count of the work
+REFERENCE_PASSES = 18     # vector passes per PCG iteration in the reference count of the work
 
 
-def survey_bytes_per_iteration(elem: int = 8, coef_kind: int = 0) -> float:
+def reference_bytes_per_iteration(elem: int = 8, coef_kind: int = 0) -> float:
     """Reference count of the bytes per tile unknown and PCG iteration: 18 vector passes
     (SpMV + fused dot 2, x/r update 6, V-cycle about 7.3 fine-level passes, direction
     update 3) of elem bytes, and for a variable coefficient 2 more passes for each of the
     4 operator applications of an iteration."""
-    return elem * (SURVEY_PASSES + (8 if coef_kind != 0 else 0))
+    return elem * (REFERENCE_PASSES + (8 if coef_kind != 0 else 0))
 
 
-def survey_mixed_bytes(it_dofs: int, refine_dofs: int, tile_dofs: int,
+def reference_mixed_bytes(it_dofs: int, refine_dofs: int, tile_dofs: int,
                        coef_kind: int = 0) -> float:
     """The reference count for FP32 inner iterations with FP64 residual refinement: 18
     FP32 passes per inner iteration, per refinement step the FP64 residual r = b - K e
     (read b, e, write r: 24 bytes) and e += d (read e, d, write e: 20), and the first pass
     (read b, write e, r, d: 24)."""
-    return (survey_bytes_per_iteration(4, coef_kind) * it_dofs + 44.0 * refine_dofs
+    return (reference_bytes_per_iteration(4, coef_kind) * it_dofs + 44.0 * refine_dofs
             + 24.0 * tile_dofs)
 
 
@@ -524,8 +524,8 @@ def roofline(prob, opts, st, pcg_ms, lds_limit):
         kernel = "k_local_pcg64" if order == 1 else "k_local_p2"
         sched_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, mode=rmode, coef=coef) / S0
         sched = sched_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
-        surv_it = survey_bytes_per_iteration(8, prob.coef_kind)
-        surv = surv_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
+        ref_it = reference_bytes_per_iteration(8, prob.coef_kind)
+        ref_bytes = ref_it * st["it_dofs"] + 8.0 * st["n_tile_dofs"]
     else:
         kernel = "k_local_mixed"
         sched_it = pcg_bytes_per_iteration(cw, ch, m, opts.nu, elem=4, mode=rmode,
@@ -533,23 +533,23 @@ def roofline(prob, opts, st, pcg_ms, lds_limit):
         sched = mixed_bytes(cw, ch, m, opts.nu, st["it_dofs"], st["refine_dofs"],
                             st["n_tile_dofs"], mode=rmode, coef=coef,
                             coef64=24 if prob.coef_kind == 3 else 0)
-        surv_it = survey_bytes_per_iteration(4, prob.coef_kind)
-        surv = survey_mixed_bytes(st["it_dofs"], st["refine_dofs"], st["n_tile_dofs"],
+        ref_it = reference_bytes_per_iteration(4, prob.coef_kind)
+        ref_bytes = reference_mixed_bytes(st["it_dofs"], st["refine_dofs"], st["n_tile_dofs"],
                                   prob.coef_kind)
     # tile storage the launch works in (every item's vectors on every level of its V-cycle)
     ws = sum(8 * (6 * S[0] + 3 * sum(S[1:])) if opts.precision == 0 else
              8 * S[0] + 4 * (6 * S[0] + 3 * sum(S[1:]))
              for S in (tile_levels(a, b, m) for a, b in shapes)) * prob.n_eig
-    achieved = surv / (pcg_ms * 1e-3) / 1e9
+    achieved = ref_bytes / (pcg_ms * 1e-3) / 1e9
     a_sched = sched / (pcg_ms * 1e-3) / 1e9
     rl = {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
           "traffic": measured_traffic(kernel, prob.name),
-          "count": (f"{surv_it:g} B per tile unknown per PCG iteration (18 vector passes of "
+          "count": (f"{ref_it:g} B per tile unknown per PCG iteration (18 vector passes of "
                     f"{elem} B{', +8 passes for the variable coefficient' if prob.coef_kind else ''}"
                     f"{'; FP64 refinement passes 44 B per unknown and step' if opts.precision else ''})"
                     f" + {8 if opts.precision == 0 else 24} B per tile unknown"),
-          "bytes_per_launch": surv,
+          "bytes_per_launch": ref_bytes,
           "schedule_count": {"achieved": a_sched, "frac": a_sched / HBM_PEAK_GBS,
                              "bytes_per_launch": sched, "bytes_per_tile_dof_iter": sched_it},
           "tile_working_set_bytes": ws}
