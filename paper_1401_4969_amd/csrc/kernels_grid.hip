@@ -18,7 +18,7 @@ __device__ __forceinline__ double interp2(const double* uc, int nc1, int x, int 
   return 0.5 * (a + b);
 }
 
-// a1 + a2: u_bar = I u_k on level m and the right-hand side of (Aux_Problem),
+// Algorithm 4.1, step 1: u_bar = I u_k on level m and the right-hand side of (Aux_Problem),
 // r = lambda_k M u_bar - K u_bar, for eigenpair i = blockIdx.z (one grid slice per
 // eigenpair, so the loads of all of them are in flight together).
 template <int KIND>
@@ -132,7 +132,8 @@ __device__ __forceinline__ int pou_axis2(int nc, int nb, int g, int m, int ov, i
   return n;
 }
 
-// a4: partition-of-unity gluing u~ = u_bar + sum_j chi_j e^j, chi_j = phi_j / sum_l phi_l.
+// Algorithm 4.1, step 2 in its partition-of-unity form: the gluing
+//   u~ = u_bar + sum_j chi_j e^j,  chi_j = phi_j / sum_l phi_l.
 // QM: a bound on q (1, 2, 4 or 8) that sizes the per-eigenpair registers.
 template <int QM>
 __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const TileItem* items,
@@ -241,8 +242,9 @@ __global__ __launch_bounds__(NTG) void k_pou_glue(const ProbDev* probs, const Ti
       P.ut[(int64_t)i * nn + idx] = P.ubar[(int64_t)i * nn + idx] + (tot > 0.0 ? acc[i] / tot : 0.0);
 }
 
-// a5: y_K = K u~ (into res), y_M = M u~ (into ubar), and per-block partial sums of
-// alpha_ij = u~_i . y_K,j, beta_ij = u~_i . y_M,j and s_i = sum u~_i.
+// Algorithm 4.1, step 3 (the border of (Eigen_Augment_Problem)): y_K = K u~ (into res),
+// y_M = M u~ (into ubar), and per-block partial sums of alpha_ij = u~_i . y_K,j,
+// beta_ij = u~_i . y_M,j and s_i = sum u~_i.
 constexpr int RNV = 2 * MLC_MAX_Q * MLC_MAX_Q + MLC_MAX_Q;
 
 // QM: a bound on q (1, 2, 4 or 8) that sizes the per-eigenpair registers.
@@ -335,9 +337,10 @@ __global__ __launch_bounds__(NTG) void k_rr_apply(const ProbDev* probs, int m) {
   }
 }
 
-// a5 (continued): one level of the transposed interpolation P^T (full weighting on the
-// SW-NE mesh: centre 1, E/W/N/S/NE/SW 1/2) for the 2q border vectors, level l+1 -> l;
-// blockIdx.z selects the vector, so the loads of all vectors are in flight together.
+// Algorithm 4.1, step 3 (continued): one level of the transposed interpolation P^T (full
+// weighting on the SW-NE mesh: centre 1, E/W/N/S/NE/SW 1/2) for the 2q border vectors,
+// level l+1 -> l; blockIdx.z selects the vector, so the loads of all vectors are in flight
+// together.
 __global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, int m) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
@@ -369,8 +372,8 @@ __global__ __launch_bounds__(NTG) void k_restrict(const ProbDev* probs, int l, i
   outb[(int64_t)v * nnc + idx] = val;
 }
 
-// a6 (first half): f = V^T a, g = V^T b for the coarse eigenbasis V, one wave per column
-// and border vector.
+// Algorithm 4.1, step 3 (the small eigenproblem, first half): f = V^T a, g = V^T b for the
+// coarse eigenbasis V, one wave per column and border vector.
 __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
   const ProbDev& P = probs[blockIdx.y];
   const int c = blockIdx.x * (NTG / 64) + (threadIdx.x >> 6);
@@ -389,8 +392,9 @@ __global__ __launch_bounds__(NTG) void k_rr_project(const ProbDev* probs) {
   if (lane == 0) P.fg[(int64_t)v * nH + c] = s;
 }
 
-// a7 (first half): coarse nodal coefficients c_H = V y_hat on the coarse grid, one wave
-// per coarse node and eigenpair sweeping a row of V^T.
+// Algorithm 4.1, step 3 (the new eigenfunction, first half): coarse nodal coefficients
+// c_H = V y_hat on the coarse grid, one wave per coarse node and eigenpair sweeping a row
+// of V^T.
 __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
   const ProbDev& P = probs[blockIdx.y];
   const int nc1 = P.c1;
@@ -411,7 +415,8 @@ __global__ __launch_bounds__(NTG) void k_rr_combine(const ProbDev* probs) {
   if (lane == 0) P.cH_grid[(int64_t)k * nc1 * nc1 + node] = s;
 }
 
-// a7: u_{k+1} = P_{0->m} c_H + sum_i t_i u~_i on level m.
+// Algorithm 4.1, step 3 (the new eigenfunction): u_{k+1} = P_{0->m} c_H + sum_i t_i u~_i on
+// level m.
 __global__ __launch_bounds__(NTG) void k_assemble(const ProbDev* probs, int m, int dst) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;

@@ -3,14 +3,14 @@
 // per side, i.e. the nodes of the grid with n_c 2^(m+1) intervals (p2_ops.h).  The
 // gluing, the Rayleigh-Ritz solve and the output kernels are the P1 ones on that grid;
 // this file holds what the element changes:
-//   a1  quadratic interpolation of u_k onto level k+1 (nested P2 spaces);
-//   a2  the residual lambda M u - K u with the P2 stencils;
-//   a3  local solves: conjugate gradients on the P2 stiffness of each tile, preconditioned
-//       by the P1 V-cycle on the same nodes (the P1 stiffness of the half-cell mesh is
-//       spectrally equivalent to the P2 one, so the iteration count stays bounded in h);
-//   a5  K u~, M u~ and the transposed interpolation chain to the coarse P2 space;
-//   a7  the coarse P2 part of the new eigenvector evaluated on the fine nodes;
-//   setup: the coarse P2 stiffness and mass.
+//   step 1: quadratic interpolation of u_k onto level k+1 (nested P2 spaces), the
+//           residual lambda M u - K u with the P2 stencils, and the local solves:
+//           conjugate gradients on the P2 stiffness of each tile, preconditioned by the P1
+//           V-cycle on the same nodes (the P1 stiffness of the half-cell mesh is
+//           spectrally equivalent to the P2 one, so the iteration count stays bounded in h);
+//   step 3: K u~, M u~ and the transposed interpolation chain to the coarse P2 space, and
+//           the coarse P2 part of the new eigenvector evaluated on the fine nodes;
+//   setup (Algorithm 4.2 step 1): the coarse P2 stiffness and mass.
 #include "p2_ops.h"
 #include "pcg_ops.h"
 
@@ -20,7 +20,8 @@ constexpr int NTP = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + NTP - 1) / NTP); }
 
-// a1: u_bar = I u_k on P2 level m from level m-1: the coarse quadratic at every fine node.
+// Algorithm 4.1, step 1 (u_{h_k} in the finer space): u_bar = I u_k on P2 level m from
+// level m-1: the coarse quadratic at every fine node.
 __global__ __launch_bounds__(NTP) void k_p2_prolong(const ProbDev* probs, int m, int src) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
@@ -48,7 +49,8 @@ __global__ __launch_bounds__(NTP) void k_p2_prolong(const ProbDev* probs, int m,
   P.ubar[(int64_t)i * nn + idx] = v;
 }
 
-// a2: r = lambda_k M u_bar - K u_bar (the right-hand side of (Aux_Problem)).
+// Algorithm 4.1, step 1: r = lambda_k M u_bar - K u_bar (the right-hand side of
+// (Aux_Problem)).
 template <int KIND>
 __global__ __launch_bounds__(NTP) void k_p2_residual(const ProbDev* probs, int m, int src) {
   // the step's convergence record starts empty (the local solves follow on the stream)
@@ -77,9 +79,9 @@ __global__ __launch_bounds__(NTP) void k_p2_residual(const ProbDev* probs, int m
   P.res[(int64_t)i * nn + idx] = r;
 }
 
-// a5: y_K = K u~ (into res), y_M = M u~ (into ubar), and per-block partial sums of
-// alpha_ij = u~_i . y_K,j, beta_ij = u~_i . y_M,j and s_i = sum u~_i (the layout the
-// Rayleigh-Ritz solve reads).
+// Algorithm 4.1, step 3 (the border of (Eigen_Augment_Problem)): y_K = K u~ (into res),
+// y_M = M u~ (into ubar), and per-block partial sums of alpha_ij = u~_i . y_K,j,
+// beta_ij = u~_i . y_M,j and s_i = sum u~_i (the layout the Rayleigh-Ritz solve reads).
 constexpr int RNV2 = 2 * MLC_MAX_Q * MLC_MAX_Q + MLC_MAX_Q;
 
 template <int KIND, int QM>
@@ -148,14 +150,15 @@ __global__ __launch_bounds__(NTP) void k_p2_rr_apply(const ProbDev* probs, int m
   }
 }
 
-// a5 (continued): one level of the transposed interpolation, P2 level l+1 -> l, for the 2q
-// border vectors: every coarse node gathers the fine values in its basis function's
-// support (fine nodes within two coarse half steps), each weighted by that basis function
-// at the fine node.  The coarse basis functions of one node class (vertex, x-, y- or
-// diagonal-edge midpoint) are translates of each other on the uniform mesh, so each
-// workgroup first tabulates the four classes' weights at the 9 x 9 fine offsets in LDS,
-// evaluated at a coarse node away from the boundary (the node's triangles located as a1
-// does; exact dyadic values), and every node then reads its class's row.
+// Algorithm 4.1, step 3 (continued): one level of the transposed interpolation, P2 level
+// l+1 -> l, for the 2q border vectors: every coarse node gathers the fine values in its
+// basis function's support (fine nodes within two coarse half steps), each weighted by
+// that basis function at the fine node.  The coarse basis functions of one node class
+// (vertex, x-, y- or diagonal-edge midpoint) are translates of each other on the uniform
+// mesh, so each workgroup first tabulates the four classes' weights at the 9 x 9 fine
+// offsets in LDS, evaluated at a coarse node away from the boundary (its triangles located
+// as the interpolation locates them; exact dyadic values), and every node then reads its
+// class's row.
 __global__ __launch_bounds__(NTP) void k_p2_restrict(const ProbDev* probs, int l, int m) {
   __shared__ double wt[4][81];
   const ProbDev& P = probs[blockIdx.y];
@@ -210,8 +213,9 @@ __global__ __launch_bounds__(NTP) void k_p2_restrict(const ProbDev* probs, int l
   outb[(int64_t)v * nnc + idx] = val;
 }
 
-// a7: u_{k+1} = P_{0->m} c_H + sum_i t_i u~_i on P2 level m, the coarse quadratic evaluated
-// at every fine node (a coarse cell spans 2^(m+1) fine half steps).
+// Algorithm 4.1, step 3 (the new eigenfunction): u_{k+1} = P_{0->m} c_H + sum_i t_i u~_i on
+// P2 level m, the coarse quadratic evaluated at every fine node (a coarse cell spans
+// 2^(m+1) fine half steps).
 __global__ __launch_bounds__(NTP) void k_p2_assemble(const ProbDev* probs, int m, int dst) {
   const ProbDev& P = probs[blockIdx.y];
   if (m > P.L) return;
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(NTP) void k_p2_coarse_matrices(const ProbDev* probs
     }
 }
 
-// ---- a3: local solves ----
+// ---- Algorithm 4.1, step 1: local solves ----
 
 // Tile vectors: the value at the node offset by (dx, dy), 0 off the tile (the Dirichlet
 // boundary of Omega_j); loads are issued from clamped indices and then selected.
