@@ -40,7 +40,6 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
     // right-hand side: the global residual window, or (adjoint solves) already in R
     const double v = rhs_in_tile ? R[i] : bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
     R[i] = v;
-    X[i] = 0.0;
     acc[0] += v * v;
   }
   block_sum<NT, 2>(acc, red);

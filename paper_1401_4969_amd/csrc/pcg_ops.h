@@ -1124,7 +1124,7 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
 // computes and stores the current one, so two memory round trips are in flight.
 template <int NT, int KIND, typename T>
 __device__ void pass_xr(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const T* Pn, T alpha,
-                        double* acc) {
+                        bool first, double* acc) {
   constexpr int NW = NT / 64;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = l0.nx, ny = l0.ny, nxc = (nx + 63) >> 6;
@@ -1140,7 +1140,7 @@ __device__ void pass_xr(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const
     L.w = Pn[hw ? i - 1 : i];
     L.n = Pn[hn ? i + nx : i];
     L.s = Pn[hs ? i - nx : i];
-    L.x = X[i];
+    L.x = first ? T(0) : X[i];  // x_0 = 0 is not read
     L.r = R[i];
   };
   int iy = w, cix = 0;
@@ -1303,7 +1303,7 @@ __device__ void pass_dir_banded(const ProbDev& P, const LevelDesc& l0, const T* 
 // (three loads per node instead of seven).  Rows of at most RING_CHUNKS * 64 nodes.
 template <int NT, int KIND, typename T>
 __device__ void pass_xr_banded(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const T* Pn,
-                               T alpha, T* ring, double* acc) {
+                               T alpha, bool first, T* ring, double* acc) {
   constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nx = l0.nx, ny = l0.ny, nch = (nx + 63) >> 6;
@@ -1319,7 +1319,7 @@ __device__ void pass_xr_banded(const ProbDev& P, const LevelDesc& l0, T* X, T* R
         const int jx = ix < nx ? ix : nx - 1;
         pv[c] = Pn[inA ? (unsigned)(ya * nx + jx) : 0u];
         const unsigned ib = inB ? (unsigned)(yb * nx + jx) : 0u;
-        xv[c] = X[ib];
+        xv[c] = first ? T(0) : X[ib];  // x_0 = 0 is not read
         rv[c] = R[ib];
       }
     }
@@ -1389,7 +1389,7 @@ __device__ void pass_dir_plain(const ProbDev& P, const LevelDesc& l0, const T* Z
 
 template <int NT, int KIND, typename T>
 __device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const T* Pn,
-                              T alpha, double* acc) {
+                              T alpha, bool first, double* acc) {
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
     T q = T(0);
@@ -1397,7 +1397,7 @@ __device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R,
       T d;
       q = stencil<KIND, T>(P, l0, Pn, ix, iy, i, d);
     }
-    X[i] += alpha * Pn[i];
+    X[i] = (first ? T(0) : X[i]) + alpha * Pn[i];  // x_0 = 0 is not read
     const T r = R[i] - alpha * q;
     R[i] = r;
     *acc += (double)r * (double)r;
@@ -1406,7 +1406,9 @@ __device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R,
 
 // Preconditioned conjugate gradients on K_j x = r with the V-cycle preconditioner, in
 // the vector type T of the tile buffers (reductions in FP64).  On entry R (level-0
-// right-hand side buffer) holds r and X is zero; bb = ||r||^2.  Iterates until
+// right-hand side buffer) holds r; X need not be set: the first update writes
+// x_1 = alpha p without reading it (with r = 0 the iteration runs once with p = 0 and
+// alpha = 0, so x_1 = 0); bb = ||r||^2.  Iterates until
 // ||r_k||^2 <= tol2 or max_it; returns the iteration count and the final ||r_k||^2 in rr.
 // MAXR: the most band rows per wave the caller's rings may ask for (1 or 2).
 // The search direction alternates between two buffers (the new one is formed from the
@@ -1425,7 +1427,6 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   const T om = T(omega), om2 = T(omega2);
   int iters = 0;
   rr = bb;
-  if (!(bb > 0.0)) return 0;
   double acc[2];
   // One call site for the V-cycle (it is inlined, and a second copy would cost
   // registers): the first pass through the loop only preconditions r_0.
@@ -1447,15 +1448,16 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
       else
         pass_dir_plain<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
       block_sum<NT, 2>(acc, red);
-      const T alpha = T(rho / acc[0]);
+      // a zero right-hand side gives p = 0: alpha = 0 writes x_1 = 0 and r stays 0
+      const T alpha = acc[0] > 0.0 ? T(rho / acc[0]) : T(0);
       // x += alpha p, r -= alpha A p, ||r||^2
       acc[0] = acc[1] = 0.0;
       if (ring != nullptr && l0.nx <= 64 * RING_CHUNKS)
-        pass_xr_banded<NT, KIND, T>(P, l0, X, R, Pn, alpha, ring, &acc[0]);
+        pass_xr_banded<NT, KIND, T>(P, l0, X, R, Pn, alpha, first, ring, &acc[0]);
       else if constexpr (KIND == 0)
-        pass_xr<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
+        pass_xr<NT, KIND, T>(P, l0, X, R, Pn, alpha, first, &acc[0]);
       else
-        pass_xr_plain<NT, KIND, T>(P, l0, X, R, Pn, alpha, &acc[0]);
+        pass_xr_plain<NT, KIND, T>(P, l0, X, R, Pn, alpha, first, &acc[0]);
       block_sum<NT, 2>(acc, red);
       rr = acc[0];
       if (rr <= tol2) break;
