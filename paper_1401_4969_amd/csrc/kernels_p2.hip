@@ -312,13 +312,13 @@ __device__ void pass_apply_p2(const ProbDev& P, const LevelDesc& l0, const doubl
   }
 }
 
-// x += alpha p, r -= alpha q: a streaming pass.
+// x += alpha p, r -= alpha q: a streaming pass (x_0 = 0 is not read).
 template <int NT>
 __device__ void pass_xr_p2(const LevelDesc& l0, double* X, double* R, const double* Pn,
-                           const double* Q, double alpha, double* acc) {
+                           const double* Q, double alpha, bool first, double* acc) {
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
-    X[i] += alpha * Pn[i];
+    X[i] = (first ? 0.0 : X[i]) + alpha * Pn[i];
     const double r = R[i] - alpha * Q[i];
     R[i] = r;
     *acc += r * r;
@@ -420,7 +420,8 @@ __device__ void pass_dir_p2_banded(const ProbDev& P, const LevelDesc& l0, const 
 // ring.
 template <int NT, int KIND>
 __device__ void pass_xr_p2_banded(const ProbDev& P, const LevelDesc& l0, double* X, double* R,
-                                  const double* Pn, double alpha, double* ring, double* acc) {
+                                  const double* Pn, double alpha, bool first, double* ring,
+                                  double* acc) {
   using RG = P2Ring<NT>;
   constexpr int RW = RG::RW, CM = RG::CM;
   const RG rg{ring, l0.nx};
@@ -457,7 +458,7 @@ __device__ void pass_xr_p2_banded(const ProbDev& P, const LevelDesc& l0, double*
 #pragma unroll 1
       for (int ix = lane; ix < nx; ix += 64) {
         const unsigned i = (unsigned)(yb * nx + ix);
-        const double xo = X[i], ro = R[i];
+        const double xo = first ? 0.0 : X[i], ro = R[i];  // x_0 = 0 is not read
         double q = 0.0;
         if (is_dof(P.domain, l0.N, l0.gx0 + ix, l0.gy0 + yb))
           q = ring_k2<NT, KIND>(P, l0, lm, rg, ix, yb);
@@ -488,7 +489,6 @@ __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, i
   double* Q = base + l0.ot;  // the V-cycle's level-0 temporary, free between V-cycles
   int iters = 0;
   rr = bb;
-  if (!(bb > 0.0)) return 0;
   double acc[2];
   const double* Z = nullptr;
   double rho = 0.0, beta = 0.0;
@@ -507,12 +507,13 @@ __device__ int pcg_solve_p2(const ProbDev& P, const Levels& lev, double* base, i
         pass_apply_p2<NT, KIND>(P, l0, Pn, Q, &acc[0]);
       }
       block_sum<NT, 2>(acc, red);
-      const double alpha = rho / acc[0];
+      // a zero right-hand side gives p = 0: alpha = 0 writes x_1 = 0 and r stays 0
+      const double alpha = acc[0] > 0.0 ? rho / acc[0] : 0.0;
       acc[0] = acc[1] = 0.0;
       if (banded)
-        pass_xr_p2_banded<NT, KIND>(P, l0, X, R, Pn, alpha, ring, &acc[0]);
+        pass_xr_p2_banded<NT, KIND>(P, l0, X, R, Pn, alpha, first, ring, &acc[0]);
       else
-        pass_xr_p2<NT>(l0, X, R, Pn, Q, alpha, &acc[0]);
+        pass_xr_p2<NT>(l0, X, R, Pn, Q, alpha, first, &acc[0]);
       block_sum<NT, 2>(acc, red);
       rr = acc[0];
       if (rr <= tol2) break;
@@ -559,8 +560,7 @@ __global__ __launch_bounds__(NT) void k_local_p2(const ProbDev* probs, const Til
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
     const double v = bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
-    R[i] = v;
-    X[i] = 0.0;
+    R[i] = v;  // x is written by the first update, without being read
     acc[0] += v * v;
   }
   block_sum<NT, 2>(acc, red);
