@@ -12,7 +12,8 @@ namespace {
 // One band row per wave: taller bands' registers would crowd out the prefetching passes.
 constexpr int MIXED_MAX_ROWS = 1;
 
-// e += d and the FP64 residual r = b - K e of the updated correction in one banded pass:
+// e += d (e = d on the first refinement: e is not cleared beforehand, nor read then) and
+// the FP64 residual r = b - K e of the updated correction in one banded pass:
 // the workgroup walks the tile in bands of NW rows with an LDS ring of NW + 2 FP64 rows
 // of e (rows -1 and ny zero, the Dirichlet values).  At step k wave w forms row
 // k NW + w - 1 of e + d (stored), and after a barrier the residual of the row above it
@@ -22,7 +23,7 @@ constexpr int MIXED_MAX_ROWS = 1;
 // RING_CHUNKS * 64 nodes.
 template <int NT, int KIND>
 __device__ void refine_banded(const ProbDev& P, const LevelDesc& l0, double* E, float* X,
-                              float* R, const double* bglob, int n1, double* ring,
+                              float* R, const double* bglob, int n1, bool first, double* ring,
                               double* acc) {
   constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -38,7 +39,7 @@ __device__ void refine_banded(const ProbDev& P, const LevelDesc& l0, double* E, 
       if (c < nch) {
         const int ix = lane + 64 * c;
         const unsigned i = (inA && ix < nx) ? (unsigned)(ya * nx + ix) : 0u;
-        ev[c] = E[i];
+        ev[c] = first ? 0.0 : E[i];  // e_0 = 0 is not read
         xv[c] = X[i];
         // b of the row the second stage takes (a node of the tile's first row otherwise)
         const int bx = ix < nx ? ix : nx - 1, by = inB ? yb : 0;
@@ -113,8 +114,7 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
     const double v = bat(ix, iy);
-    E[i] = 0.0;
-    R[i] = (float)v;
+    R[i] = (float)v;  // e is written by the first refinement, without being read
     X[i] = 0.0f;
     acc[0] += v * v;
   }
@@ -126,7 +126,8 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
   float* ring = rows ? ring_lds_f : nullptr;
   // the LDS V-cycle tail with 1024-thread workgroups (one per CU), as in the FP64 solver
   float* tail = (rows && NT == 1024) ? ring_lds_f + ring_elems(NT / 64, ring_cap, 0) : nullptr;
-  while (rr > rtol * rtol * bb && refine < max_refine) {
+  // at least one refinement, which writes e (with a zero right-hand side it adds x = 0)
+  do {
     ++refine;
     double rr_inner;
     total += pcg_solve<NT, KIND, float, MIXED_MAX_ROWS>(P, lev, base, m, Kinv, rr, inner_rtol * inner_rtol * rr,
@@ -135,15 +136,15 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     acc[0] = acc[1] = 0.0;
     if (rows && l0.nx <= 64 * RING_CHUNKS) {
       // the ring space (three FP32 rings) holds the one FP64 ring of this pass
-      refine_banded<NT, KIND>(P, l0, E, X, R, bglob, n1, reinterpret_cast<double*>(ring_lds_f),
-                              &acc[0]);
+      refine_banded<NT, KIND>(P, l0, E, X, R, bglob, n1, refine == 1,
+                              reinterpret_cast<double*>(ring_lds_f), &acc[0]);
       block_sum<NT, 2>(acc, red);
       rr = acc[0];
       continue;
     }
     FOR_TILE(l0) {
       const unsigned i = (unsigned)(iy * l0.nx + ix);
-      E[i] += (double)X[i];
+      E[i] = (refine == 1 ? 0.0 : E[i]) + (double)X[i];
     }
     __syncthreads();
     // FP64 residual of the accumulated correction, handed to the next FP32 solve
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_local_mixed(const ProbDev* probs, const 
     }
     block_sum<NT, 2>(acc, red);
     rr = acc[0];
-  }
+  } while (rr > rtol * rtol * bb && refine < max_refine);
   if (threadIdx.x == 0) {
     ItemStat s;
     s.iters = total;
