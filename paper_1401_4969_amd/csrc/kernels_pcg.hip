@@ -7,8 +7,8 @@
 // conjugate gradient to convergence with workgroup barriers only: the items are
 // independent, so no grid-wide synchronisation is needed and the hardware dispatcher
 // acts as the work queue (items are ordered largest first).  The preconditioner is a
-// symmetric multigrid V-cycle over the nested grids of the tile (nu damped-Jacobi sweeps
-// before and after each coarse correction, restriction P^T, interpolation P, Galerkin
+// symmetric multigrid V-cycle over the nested grids of the tile (nu Jacobi sweeps, with
+// the two Chebyshev weights for nu = 2, before and after each coarse correction, restriction P^T, interpolation P, Galerkin
 // coarse operators = the same stencil with children-mean kappa, exact solve on the
 // coarse-cell grid of Omega_j), so the work per item is O(tile size) (the multigrid remark
 // after the work estimate of Section 5).
@@ -37,7 +37,8 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   double acc[2] = {0.0, 0.0};
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
-    // right-hand side: the global residual window, or (adjoint solves) already in R
+    // right-hand side: the global residual window, or (adjoint solves) already in R; x is
+    // not cleared (the first update writes it)
     const double v = rhs_in_tile ? R[i] : bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
     R[i] = v;
     acc[0] += v * v;
