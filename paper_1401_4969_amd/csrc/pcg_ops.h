@@ -233,8 +233,8 @@ __device__ __forceinline__ T jacobi_rows(const ProbDev& P, const LevelDesc& lv, 
 // their memory latency overlaps the three later stages instead of opening the next step;
 // the second and third stages' rows (cache hits) are loaded one stage ahead, at the start
 // of the step and of the second stage, so each waits behind the stage before it and its
-// barrier rather than after it.  (Used with a constant coefficient in FP64: with variable
-// coefficients, or in FP32, the extra registers measured slower.)
+// barrier rather than after it.  (Used with a constant coefficient, in FP64 and FP32: with
+// variable coefficients the extra registers measured slower.)
 template <int NT, int KIND, typename T, int R, int CMP = 0>
 __device__ void op_pre_fused(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
                              const T* b, T* za, T* bc, T omega, T omega2, T* ring) {
@@ -623,216 +623,9 @@ __device__ void op_post_fused(const ProbDev& P, const LevelDesc& lc, const Level
   }
 }
 
-// Prefetching forms of the two banded passes: every global load of a band step is issued
-// at the start of the step, into registers holding a row as up to RING_CHUNKS chunks of
-// 64 nodes (rows of at most 256 nodes), so a step waits for memory once instead of once
-// per stage.  The extra registers pay off for FP32 vectors with a constant coefficient;
-// elsewhere they cost more in register pressure than they save.
+// Rows of at most RING_CHUNKS chunks of 64 nodes are held in registers by the prefetching
+// forms of the banded passes and the banded CG passes.
 constexpr int RING_CHUNKS = 4;
-
-// Prefetching form of op_pre_fused below:
-//   z = J(J(0)) (two damped-Jacobi sweeps from zero), r = b - A z, bc = P^T r.
-// The workgroup walks the tile in bands of NW rows, one row per wave, with three LDS
-// rings of NW + 2 rows (first sweep, second sweep, residual): at step k wave w forms the
-// first sweep on row k NW + w - 1 (stage A), the second sweep one row below, also
-// written to za (B), the residual two rows below (C), and waves w < NW/2 restrict the
-// three residual rows 2cy .. 2cy+2 into coarse row cy = k NW/2 + w - 2 (D).  All b rows
-// a step needs are loaded at its start, so a step waits for memory once.  b is read
-// once from HBM (the later stages hit cache); z and bc are written once, instead of the
-// 6 passes of separate sweeps.  A ring row is overwritten only after the barrier that
-// follows its last reader.
-template <int NT, int KIND, typename T>
-__device__ void op_pre_fused_pf(const ProbDev& P, const LevelDesc& lv, const LevelDesc& lc,
-                             const T* b, T* za, T* bc, T omega, T omega2, T* ring) {
-  constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nx = lv.nx, ny = lv.ny, ncx = lc.nx, ncy = lc.ny;
-  const int nch = (nx + 63) >> 6;
-  T* r1 = ring;
-  T* r2 = ring + RING * nx;
-  T* rr = ring + 2 * RING * nx;
-  auto row = [&](T* r, int y) -> T* { return r + ((y + 1) % RING) * nx; };
-  for (int k = 0; k * NW - 3 < ny || k * (NW / 2) - 2 < ncy; ++k) {
-    const int ya = k * NW + w - 1, yb = ya - 1, yc = ya - 2;
-    const bool inA = ya >= 0 && ya < ny, inB = yb >= 0 && yb < ny, inC = yc >= 0 && yc < ny;
-    T bA[CM], bB[CM], bC[CM];
-#pragma unroll
-    for (int c = 0; c < CM; ++c) {
-      if (c < nch) {
-        const int ix = lane + 64 * c;
-        const bool ok = ix < nx;
-        bA[c] = b[(inA && ok) ? (unsigned)(ya * nx + ix) : 0u];
-        bB[c] = b[(inB && ok) ? (unsigned)(yb * nx + ix) : 0u];
-        bC[c] = b[(inC && ok) ? (unsigned)(yc * nx + ix) : 0u];
-      }
-    }
-    if (ya >= -1 && ya <= ny) {
-      T* dst = row(r1, ya);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int ix = lane + 64 * c;
-        if (c < nch && ix < nx) {
-          T v = T(0);
-          if (inA) {
-            const T d = T(diag_at<KIND, T>(P, lv, ix, ya));
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? omega * bA[c] / d : T(0);
-          }
-          dst[ix] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (yb >= -1 && yb <= ny) {
-      T* dst = row(r2, yb);
-      const T* rs = row(r1, inB ? yb - 1 : -1);
-      const T* rc = row(r1, inB ? yb : -1);
-      const T* rn = row(r1, inB ? yb + 1 : -1);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int ix = lane + 64 * c;
-        if (c < nch && ix < nx) {
-          T v = T(0);
-          if (inB) {
-            v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bB[c], ix, yb, omega2);
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
-            za[(unsigned)(yb * nx + ix)] = v;
-          }
-          dst[ix] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (yc >= -1 && yc <= ny) {
-      T* dst = row(rr, yc);
-      const T* rs = row(r2, inC ? yc - 1 : -1);
-      const T* rc = row(r2, inC ? yc : -1);
-      const T* rn = row(r2, inC ? yc + 1 : -1);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int ix = lane + 64 * c;
-        if (c < nch && ix < nx) {
-          T v = T(0);
-          if (inC) {
-            T d;
-            v = bC[c] - apply_rows<KIND, T>(P, lv, rs, rc, rn, ix, yc, d);
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc) ? v : T(0);
-          }
-          dst[ix] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (w < NW / 2) {
-      const int y = k * NW - 2 + 2 * w;  // even: the top fine row 2cy + 2 of coarse row cy
-      const int cy = (y - 2) / 2;
-      if (cy >= 0 && cy < ncy) {
-        const T* rs = row(rr, y - 2);
-        const T* rc = row(rr, y - 1);
-        const T* rn = row(rr, y);
-        for (int cx = lane; cx < ncx; cx += 64) {
-          const int x = 2 * cx + 1;
-          const T v = rc[x] + T(0.5) * (rc[x + 1] + rc[x - 1] + rn[x] + rs[x] + rn[x + 1] + rs[x - 1]);
-          bc[(unsigned)(cy * ncx + cx)] = is_dof(P.domain, lc.N, lc.gx0 + cx, lc.gy0 + cy) ? v : T(0);
-        }
-      }
-    }
-  }
-}
-
-// Prefetching form of op_post_fused below:
-//   za <- J(J(za + P zc)),   J(z) = z + omega D^-1 (b - A z).
-// Same banded walk with two LDS rings (the prolonged iterate, the first sweep): at step
-// k wave w forms row k NW + w - 1 of za + P zc (stage A), the first sweep on the row
-// below (B) and the second sweep two rows below (C, written into za in place: no later
-// stage reads za at or below that row).  All global loads of a step (the za row, its
-// coarse values, two b rows) are issued at its start.  za is read and written once and
-// b read once from HBM, instead of the 8 passes of a separate interpolation and two
-// sweeps.
-template <int NT, int KIND, typename T, bool DOT>
-__device__ void op_post_fused_pf(const ProbDev& P, const LevelDesc& lc, const LevelDesc& lv,
-                              const T* zc, const T* b, T* za, T omega, T omega2, T* ring,
-                              double* acc) {
-  constexpr int NW = NT / 64, RING = NW + 2, CM = RING_CHUNKS;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nx = lv.nx, ny = lv.ny;
-  const int nch = (nx + 63) >> 6;
-  T* ringA = ring;
-  T* ringB = ring + RING * nx;
-  auto row = [&](T* r, int y) -> T* { return r + ((y + 1) % RING) * nx; };
-  const int ncx = lc.nx, ncy = lc.ny;
-  auto cin = [&](int cx, int cy) -> bool { return cx >= 0 && cy >= 0 && cx < ncx && cy < ncy; };
-  for (int k = 0; k * NW - 3 < ny; ++k) {
-    const int ya = k * NW + w - 1, yb = ya - 1, yc = ya - 2;
-    const bool inA = ya >= 0 && ya < ny, inB = yb >= 0 && yb < ny, inC = yc >= 0 && yc < ny;
-    T zA[CM], c0[CM], c1[CM], bB[CM], bC[CM];
-#pragma unroll
-    for (int c = 0; c < CM; ++c) {
-      if (c < nch) {
-        const int ix = lane + 64 * c;
-        const bool ok = ix < nx;
-        const int cx = ix >> 1, cy = ya >> 1;
-        const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
-        zA[c] = za[(inA && ok) ? (unsigned)(ya * nx + ix) : 0u];
-        c0[c] = zc[(inA && ok && cin(ax, ay)) ? (unsigned)(ay * ncx + ax) : 0u];
-        c1[c] = zc[(inA && ok && cin(cx, cy)) ? (unsigned)(cy * ncx + cx) : 0u];
-        bB[c] = b[(inB && ok) ? (unsigned)(yb * nx + ix) : 0u];
-        bC[c] = b[(inC && ok) ? (unsigned)(yc * nx + ix) : 0u];
-      }
-    }
-    if (ya >= -1 && ya <= ny) {
-      T* dst = row(ringA, ya);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int ix = lane + 64 * c;
-        if (c < nch && ix < nx) {
-          T v = T(0);
-          if (inA) {
-            const int cx = ix >> 1, cy = ya >> 1;
-            const int ax = cx - ((ix & 1) ^ 1), ay = cy - ((ya & 1) ^ 1);
-            const T pz = T(0.5) * ((cin(ax, ay) ? c0[c] : T(0)) + (cin(cx, cy) ? c1[c] : T(0)));
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + ya) ? zA[c] + pz : zA[c];
-          }
-          dst[ix] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (yb >= -1 && yb <= ny) {
-      T* dst = row(ringB, yb);
-      const T* rs = row(ringA, inB ? yb - 1 : -1);
-      const T* rc = row(ringA, inB ? yb : -1);
-      const T* rn = row(ringA, inB ? yb + 1 : -1);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int ix = lane + 64 * c;
-        if (c < nch && ix < nx) {
-          T v = T(0);
-          if (inB) {
-            v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bB[c], ix, yb, omega);
-            v = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yb) ? v : T(0);
-          }
-          dst[ix] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (inC) {
-      const T* rs = row(ringB, yc - 1);
-      const T* rc = row(ringB, yc);
-      const T* rn = row(ringB, yc + 1);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int ix = lane + 64 * c;
-        if (c < nch && ix < nx) {
-          const T v = jacobi_rows<KIND, T>(P, lv, rs, rc, rn, bC[c], ix, yc, omega2);
-          const bool dof = is_dof(P.domain, lv.N, lv.gx0 + ix, lv.gy0 + yc);
-          za[(unsigned)(yc * nx + ix)] = dof ? v : T(0);
-          if (DOT && dof) *acc += (double)bC[c] * (double)v;
-        }
-      }
-    }
-  }
-}
 
 // z = K_c^-1 b on the coarse-cell grid of the tile (dense inverse from setup)
 template <int NT, typename T>
@@ -989,7 +782,6 @@ __device__ void vcycle_tail(const ProbDev& P, const Levels& lev, int t0, int m,
 template <int NT, int KIND, typename T, int MAXR>
 __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const double* Kinv,
                      int nu, T omega, T omega2, double* rz, T* ring, int ring_rows, T* tail) {
-  constexpr bool PREFETCH = sizeof(T) == 4 && KIND == 0;
   int tl = m + 1;  // first level handled in LDS (none when m + 1)
   if (tail != nullptr) {
     for (int t = 0; t < m; ++t)
@@ -1005,20 +797,18 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     T* zb = base + lv.ot;
     if (ring_rows > 0 && nu == 2) {
       T* bc = base + lev[t + 1].ob;
-      // FP64 with a constant coefficient: the next band's first-stage rows are prefetched
-      // (the variable coefficients' weight loads leave no registers for it)
-      constexpr bool PF64 = KIND == 0 && sizeof(T) == 8;
+      // a constant coefficient: the next band's first-stage rows are prefetched (the
+      // variable coefficients' weight loads leave no registers for it)
+      constexpr bool PFC = KIND == 0;
       if (MAXR >= 2 && ring_rows == 2) {
-        if (PF64 && lv.nx <= 128)
-          op_pre_fused<NT, KIND, T, MAXR, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
+        if (PFC && lv.nx <= 128)
+          op_pre_fused<NT, KIND, T, MAXR, PFC ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
         else
           op_pre_fused<NT, KIND, T, MAXR>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
-      } else if (PF64 && lv.nx <= 128)
-        op_pre_fused<NT, KIND, T, 1, PF64 ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
-      else if (PF64 && lv.nx <= 256)
-        op_pre_fused<NT, KIND, T, 1, PF64 ? 4 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
-      else if (PREFETCH && lv.nx <= 64 * RING_CHUNKS)
-        op_pre_fused_pf<NT, KIND, T>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
+      } else if (PFC && lv.nx <= 128)
+        op_pre_fused<NT, KIND, T, 1, PFC ? 2 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
+      else if (PFC && lv.nx <= 256)
+        op_pre_fused<NT, KIND, T, 1, PFC ? 4 : 0>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       else
         op_pre_fused<NT, KIND, T, 1>(P, lv, lev[t + 1], b, za, bc, omega, omega2, ring);
       __syncthreads();
@@ -1066,11 +856,10 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
     }
     if (ring_rows > 0 && nu == 2) {
       const LevelDesc lc = lev[t + 1];
-      const bool pf = ring_rows == 1 && PREFETCH && lv.nx <= 64 * RING_CHUNKS;
-      constexpr bool PF64 = KIND == 0 && sizeof(T) == 8;
-      constexpr int C2 = PF64 ? 2 : 0, C4 = PF64 ? 4 : 0;
+      constexpr bool PFC = KIND == 0;
+      constexpr int C2 = PFC ? 2 : 0, C4 = PFC ? 4 : 0;
       if (MAXR >= 2 && ring_rows == 2) {
-        if (PF64 && lv.nx <= 128) {
+        if (PFC && lv.nx <= 128) {
           if (t == 0)
             op_post_fused<NT, KIND, T, true, MAXR, C2>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
           else
@@ -1080,16 +869,11 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
           op_post_fused<NT, KIND, T, true, MAXR>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
         else
           op_post_fused<NT, KIND, T, false, MAXR>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
-      } else if (PF64 && lv.nx <= 256) {
+      } else if (PFC && lv.nx <= 256) {
         if (t == 0)
           op_post_fused<NT, KIND, T, true, 1, C4>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
         else
           op_post_fused<NT, KIND, T, false, 1, C4>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
-      } else if (pf) {
-        if (t == 0)
-          op_post_fused_pf<NT, KIND, T, true>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
-        else
-          op_post_fused_pf<NT, KIND, T, false>(P, lc, lv, zc, b, za, omega, omega2, ring, nullptr);
       } else {
         if (t == 0)
           op_post_fused<NT, KIND, T, true, 1>(P, lc, lv, zc, b, za, omega, omega2, ring, rz);
