@@ -38,9 +38,10 @@ __global__ __launch_bounds__(NT) void k_local_pcg64(const ProbDev* probs, const 
   FOR_TILE(l0) {
     const unsigned i = (unsigned)(iy * l0.nx + ix);
     // right-hand side: the global residual window, or (adjoint solves) already in R; x is
-    // not cleared (the first update writes it)
+    // cleared only where the first update reads it
     const double v = rhs_in_tile ? R[i] : bglob[(int64_t)(l0.gy0 + iy) * n1 + (l0.gx0 + ix)];
     R[i] = v;
+    if constexpr (!SKIP_X0<double, KIND>) X[i] = 0.0;
     acc[0] += v * v;
   }
   block_sum<NT, 2>(acc, red);

@@ -902,11 +902,12 @@ __device__ T* vcycle(const ProbDev& P, const Levels& lev, T* base, int m, const 
   return zc;
 }
 
-// FP64 solves do not clear x before the first update, which writes x_1 = alpha p without
-// reading x; FP32 inner solves keep reading their cleared x (the same change there made
-// config 3 mixed 4% slower).
-template <typename T>
-constexpr bool SKIP_X0 = sizeof(T) == 8;
+// FP64 solves with a constant or a tensor coefficient do not clear x before the first
+// update, which writes x_1 = alpha p without reading x; the others keep reading a cleared
+// x (the same change made config 3 mixed 4% slower in FP32 and config 5's fine-cell
+// coefficient 2.5% slower in FP64).
+template <typename T, int KIND>
+constexpr bool SKIP_X0 = sizeof(T) == 8 && (KIND == 0 || KIND == 3);
 
 // x += alpha p, r -= alpha A p and this thread's share of ||r||^2 over the tile, software
 // pipelined: each wave walks its row chunks (rows w, w + NW, ..., 64 nodes per chunk) and
@@ -930,7 +931,7 @@ __device__ void pass_xr(const ProbDev& P, const LevelDesc& l0, T* X, T* R, const
     L.w = Pn[hw ? i - 1 : i];
     L.n = Pn[hn ? i + nx : i];
     L.s = Pn[hs ? i - nx : i];
-    L.x = (SKIP_X0<T> && first) ? T(0) : X[i];  // x_0 = 0 is not read
+    L.x = (SKIP_X0<T, KIND> && first) ? T(0) : X[i];  // x_0 = 0 is not read
     L.r = R[i];
   };
   int iy = w, cix = 0;
@@ -1109,7 +1110,7 @@ __device__ void pass_xr_banded(const ProbDev& P, const LevelDesc& l0, T* X, T* R
         const int jx = ix < nx ? ix : nx - 1;
         pv[c] = Pn[inA ? (unsigned)(ya * nx + jx) : 0u];
         const unsigned ib = inB ? (unsigned)(yb * nx + jx) : 0u;
-        xv[c] = (SKIP_X0<T> && first) ? T(0) : X[ib];  // x_0 = 0 is not read
+        xv[c] = (SKIP_X0<T, KIND> && first) ? T(0) : X[ib];  // x_0 = 0 is not read
         rv[c] = R[ib];
       }
     }
@@ -1187,7 +1188,7 @@ __device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R,
       T d;
       q = stencil<KIND, T>(P, l0, Pn, ix, iy, i, d);
     }
-    X[i] = ((SKIP_X0<T> && first) ? T(0) : X[i]) + alpha * Pn[i];  // x_0 = 0 is not read
+    X[i] = ((SKIP_X0<T, KIND> && first) ? T(0) : X[i]) + alpha * Pn[i];  // x_0 = 0 is not read
     const T r = R[i] - alpha * q;
     R[i] = r;
     *acc += (double)r * (double)r;
@@ -1196,9 +1197,9 @@ __device__ void pass_xr_plain(const ProbDev& P, const LevelDesc& l0, T* X, T* R,
 
 // Preconditioned conjugate gradients on K_j x = r with the V-cycle preconditioner, in
 // the vector type T of the tile buffers (reductions in FP64).  On entry R (level-0
-// right-hand side buffer) holds r; in FP64 X need not be set: the first update writes
-// x_1 = alpha p without reading it (with r = 0 the iteration runs once with p = 0 and
-// alpha = 0, so x_1 = 0); in FP32 X is zero.  bb = ||r||^2.  Iterates until
+// right-hand side buffer) holds r; where SKIP_X0 holds X need not be set: the first
+// update writes x_1 = alpha p without reading it (with r = 0 the iteration runs once with
+// p = 0 and alpha = 0, so x_1 = 0); elsewhere X is zero.  bb = ||r||^2.  Iterates until
 // ||r_k||^2 <= tol2 or max_it; returns the iteration count and the final ||r_k||^2 in rr.
 // MAXR: the most band rows per wave the caller's rings may ask for (1 or 2).
 // The search direction alternates between two buffers (the new one is formed from the
@@ -1217,7 +1218,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
   const T om = T(omega), om2 = T(omega2);
   int iters = 0;
   rr = bb;
-  if constexpr (!SKIP_X0<T>) {
+  if constexpr (!SKIP_X0<T, KIND>) {
     if (!(bb > 0.0)) return 0;
   }
   double acc[2];
@@ -1242,7 +1243,7 @@ __device__ int pcg_solve(const ProbDev& P, const Levels& lev, T* base, int m, co
         pass_dir_plain<NT, KIND, T>(P, l0, Z, Po, Pn, beta, first, &acc[0]);
       block_sum<NT, 2>(acc, red);
       // (FP64) a zero right-hand side gives p = 0: alpha = 0 writes x_1 = 0, r stays 0
-      const T alpha = SKIP_X0<T> ? (acc[0] > 0.0 ? T(rho / acc[0]) : T(0)) : T(rho / acc[0]);
+      const T alpha = SKIP_X0<T, KIND> ? (acc[0] > 0.0 ? T(rho / acc[0]) : T(0)) : T(rho / acc[0]);
       // x += alpha p, r -= alpha A p, ||r||^2
       acc[0] = acc[1] = 0.0;
       if (ring != nullptr && l0.nx <= 64 * RING_CHUNKS)
