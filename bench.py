@@ -585,7 +585,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the subdomain solves of one problem run on one "
-              "MI355X; multi-GPU sharding is a design note, not part of this build.",
+              "MI355X; sharding over several GPUs is described, not implemented.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -14,8 +14,9 @@ correction step) in their own order and notation:
         a(e^j, v) = lambda_{h_k} b(u_{h_k}, v) - a(u_{h_k}, v)   for all v in V_0h_{k+1}(Omega_j),
       and set u~^j = u_{h_k} + e^j;
     step 2: glue the u~^j into one u~ in V_0h_{k+1}(Omega).  The paper glues with
-      the regions G_j and one more boundary value problem on G_{m+1}; this build
-      glues with a partition of unity (chi_j, sum chi_j = 1), u~ = u_{h_k} + sum_j chi_j e^j;
+      the regions G_j and one more boundary value problem on G_{m+1} (interface_gluing
+      below); the default here is a partition of unity (chi_j, sum chi_j = 1),
+      u~ = u_{h_k} + sum_j chi_j e^j;
     step 3, equation (Eigen_Augment_Problem): Rayleigh-Ritz on
         V_{H,h_{k+1}} = V_0H + span{u~}, normalised so that b(u, u) = 1.
 
